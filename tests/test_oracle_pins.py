@@ -1,0 +1,347 @@
+"""Pins of the CPU oracle against facts it does not compute itself.
+
+Every test compares the oracle with something independent of its code: the
+published Philox known-answer vectors, the discrete Hubbard-Stratonovich
+identity on the four site states, analytic G0 functions, a Fock-space trace
+of the time-ordered vertex product, numpy determinants and inverses of N^{-1}
+built from its definition, exact diagonalisation, closed forms of the Hubbard
+atom and the Poisson law of the U -> 0 walk.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from ctaux_inputs import (anderson_bath, anderson_semicircle, dca_square, fermi_weight,
+                          hubbard_atom, hubbard_dimer)
+from ctaux_inputs.workloads import Workload
+from ed import ED, Fock, greens_with_vertices, trace_ratio
+from oracle import OracleChain, draws, gamma_of, philox4x32_10
+from oracle.oracle import OracleError, split_obs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------- RNG
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = philox4x32_10(v[0:4], v[4:6])
+        assert list(out) == v[6:10]
+
+
+def test_draws_are_53bit_uniforms():
+    u = np.array([draws(7, 3, i) for i in range(2000)])
+    assert u.min() >= 0.0 and u.max() < 1.0
+    # multiples of 2^-53
+    assert np.all(np.floor(u * 2.0 ** 53) == u * 2.0 ** 53)
+    # crude uniformity: means near 1/2, independent streams per chain
+    assert abs(u.mean() - 0.5) < 0.02
+    assert not np.allclose(draws(7, 3, 5), draws(7, 4, 5))
+    assert not np.allclose(draws(7, 3, 5), draws(8, 3, 5))
+
+
+# ---------------------------------------------------------------- HS identity
+@pytest.mark.parametrize("beta,U,K,nc", [(10.0, 4.0, 1.0, 1), (8.0, 8.0, 620.0, 16),
+                                         (2.0, 0.5, 3.0, 2)])
+def test_discrete_hs_identity(beta, U, K, nc):
+    """(1/2) sum_s exp(gamma s (n_up - n_dn)) = 1 - beta Nc V_x / K on each site state."""
+    g = gamma_of(beta, U, K, nc)
+    for nu in (0, 1):
+        for nd in (0, 1):
+            lhs = 0.5 * sum(math.exp(g * s * (nu - nd)) for s in (-1, 1))
+            v = U * (nu * nd - 0.5 * (nu + nd))
+            rhs = 1.0 - beta * nc * v / K
+            assert lhs == pytest.approx(rhs, rel=1e-13)
+
+
+# ---------------------------------------------------------------- G0 lookup
+def _exp_workload(beta=3.0, eps=0.7, n_tau=257):
+    from ctaux_inputs import tau_grid
+    g = fermi_weight(eps, tau_grid(beta, n_tau), beta)
+    return Workload("exp", beta, 1.0, 1.0, 1, np.zeros(1, np.int32), g, g.copy()), eps
+
+
+def test_g0_lookup_grid_antiperiodic_and_interpolation_bound():
+    w, eps = _exp_workload()
+    c = OracleChain(w)
+    h = w.beta / (w.n_tau - 1)
+    for m in (0, 1, 100, w.n_tau - 2):
+        assert c.g0(0, 0, 0, m * h) == pytest.approx(w.g0_up[0, m], rel=1e-12)
+    assert c.g0(0, 0, 0, 0.0) == w.g0_up[0, 0]                      # 0+ limit
+    rng = np.random.default_rng(0)
+    # linear interpolation error <= h^2/8 max|f''|, f'' = eps^2 f
+    bound = h * h / 8 * eps * eps * 1.0 + 1e-14
+    for t in rng.uniform(0, w.beta, 200):
+        exact = float(fermi_weight(eps, t, w.beta))
+        assert abs(c.g0(0, 0, 0, t) - exact) <= bound
+        # antiperiodicity: G0(t - beta) = -G0(t)
+        assert c.g0(0, 0, 0, t - w.beta) == pytest.approx(-c.g0(0, 0, 0, t), rel=1e-12, abs=1e-15)
+
+
+# ------------------------------------------------ determinant representation
+def _on_grid_config(rng, w, n):
+    h = w.beta / (w.n_tau - 1)
+    taus = np.sort(rng.choice(w.n_tau - 1, n, replace=False)) * h
+    sites = rng.integers(0, w.n_sites, n)
+    s = rng.choice([-1, 1], n)
+    return taus, sites, s
+
+
+@pytest.mark.parametrize("make", [lambda: hubbard_dimer(beta=2.0, U=2.0, n_tau=2001),
+                                  lambda: anderson_bath(beta=2.0, U=3.0, n_tau=2001)])
+def test_determinant_representation_vs_fock_trace(make):
+    """prod_sigma det N_sigma^{-1} = Z_n / Z_0 (Eqs. Zn_div_Z0, Nmatrix, gamma)."""
+    w = make()
+    f = Fock(w.meta["h1"].shape[0])
+    H0 = f.h0(w.meta["h1"])
+    c = OracleChain(w)
+    rng = np.random.default_rng(11)
+    for n in (1, 2, 3, 4, 4, 3):
+        taus, sites, s = _on_grid_config(rng, w, n)
+        lad, sg = c.set_config(np.arange(n), taus, sites, s)
+        dets = [np.linalg.det(c.Minv(sec)) for sec in (0, 1)]
+        tr = trace_ratio(f, H0, w.beta, c.gamma, list(zip(taus, sites, s)))
+        assert np.prod(dets) == pytest.approx(tr, rel=1e-10)
+        # the bordering used by set_config accumulates the same determinant
+        assert math.exp(lad.sum()) * sg.prod() == pytest.approx(tr, rel=1e-10)
+
+
+def test_green_estimator_vs_fock_trace():
+    w = hubbard_dimer(beta=2.0, U=2.0, n_tau=2001)
+    f = Fock(2)
+    H0 = f.h0(w.meta["h1"])
+    c = OracleChain(w)
+    rng = np.random.default_rng(5)
+    h = w.beta / (w.n_tau - 1)
+    for n in (0, 2, 3):
+        taus, sites, s = _on_grid_config(rng, w, n)
+        c.set_config(np.arange(n), taus, sites, s)
+        verts = list(zip(taus, sites, s))
+        for tau in (h * 137, h * 1501):
+            for sec in (0, 1):
+                for x in (0, 1):
+                    for y in (0, 1):
+                        ge = c.estimate_G(sec, x, y, tau)
+                        gt = greens_with_vertices(f, H0, w.beta, c.gamma, verts, x, y, sec, tau)
+                        assert ge == pytest.approx(gt, rel=1e-9, abs=1e-12)
+
+
+# ----------------------------------------------------- N and ratios vs numpy
+def _plaquette(**kw):
+    args = dict(beta=4.0, U=4.0, K=1.0, n_tau=4096, n_fine=16, superlattice=[[2, 0], [0, 2]])
+    args.update(kw)
+    return dca_square(**args)
+
+
+def test_N_equals_inverse_of_definition():
+    w = _plaquette()
+    c = OracleChain(w, seed=3)
+    for _ in range(4):
+        c.run(3000)
+        assert c.order > 5
+        for sec in (0, 1):
+            N = c.N(sec)
+            ref = np.linalg.inv(c.Minv(sec))
+            assert np.linalg.norm(N - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def _proposed_config(cfg, lp):
+    ids, tau, site, s = (np.array(a) for a in cfg)
+    if lp["type"] == 0:
+        nid = ids.max() + 1 if len(ids) else 0
+        return (np.append(ids, nid), np.append(tau, lp["tau"]), np.append(site, lp["site"]),
+                np.append(s, lp["s_new"]))
+    p = lp["p"]
+    if lp["type"] == 1:
+        keep = np.arange(len(tau)) != p
+        return ids[keep], tau[keep], site[keep], s[keep]
+    s = s.copy()
+    s[p] = lp["s_new"]
+    return ids, tau, site, s
+
+
+def _slogdet_pair(c):
+    out = []
+    for sec in (0, 1):
+        if c.order == 0:
+            out.append((1.0, 0.0))
+        else:
+            out.append(np.linalg.slogdet(c.Minv(sec)))
+    return out
+
+
+@pytest.mark.parametrize("make,seed", [(_plaquette, 1), (lambda: anderson_semicircle(n_tau=4096), 2)])
+def test_every_ratio_matches_determinants(make, seed):
+    """R = {K/(n+1), n/K, 1} * prod_sigma det N'^{-1} / det N^{-1} (Eq. insprob, Sec. II B)."""
+    w = make()
+    c = OracleChain(w, seed=seed)
+    scratch = OracleChain(w, seed=seed)
+    c.run(500)
+    n_types = [0, 0, 0]
+    for _ in range(600):
+        cfg = c.config()
+        n = len(cfg[0])
+        before = _slogdet_pair(c)
+        c.run(1)
+        lp = c.last_proposal()
+        if lp["type"] != 0 and n == 0:
+            assert lp["R"] == 0.0 and lp["acc"] == 0
+            continue
+        n_types[lp["type"]] += 1
+        new = _proposed_config(cfg, lp)
+        scratch.set_config(*new)
+        after = _slogdet_pair(scratch)
+        ratio = 1.0
+        for (s0, l0), (s1, l1) in zip(before, after):
+            ratio *= s0 * s1 * math.exp(l1 - l0)
+        factor = {0: w.K / (n + 1), 1: n / w.K, 2: 1.0}[lp["type"]]
+        assert lp["R"] == pytest.approx(factor * ratio, rel=1e-8)
+    assert min(n_types) > 30
+
+
+# ------------------------------------------------------------ physics pins
+def _bins(make_chain, w, n_chains, bins_per_chain, per_bin, n_therm, nto):
+    """Bin averages from independent chains (seeds 0 .. n_chains-1)."""
+    out = []
+    for seed in range(n_chains):
+        c = make_chain(seed)
+        c.run(n_therm)
+        for _ in range(bins_per_chain):
+            c.reset_obs()
+            c.run(per_bin)
+            out.append(split_obs(c.obs(), w.n_disp, nto))
+    return out
+
+
+def _mean_err(vals):
+    v = np.asarray(vals, dtype=np.float64)
+    return v.mean(axis=0), v.std(axis=0, ddof=1) / np.sqrt(len(v))
+
+
+def _within(mean, err, exact, nsig=3.0):
+    return np.all(np.abs(mean - exact) <= nsig * err + 1e-12)
+
+
+def _family_ok(mean, err, exact):
+    """A vector of estimates (e.g. G(tau_j)): every |z| <= 4 and chi^2/dof <= 2.
+
+    A 3-sigma bound on each of dozens of correlated entries fails by chance
+    far more often than on one scalar; this keeps a comparable false-alarm
+    rate while still catching a systematic deviation of any entry."""
+    z = (np.asarray(mean) - np.asarray(exact)) / np.maximum(np.asarray(err), 1e-15)
+    return bool(np.all(np.abs(z) <= 4.0) and np.mean(z * z) <= 2.0), z
+
+
+@pytest.mark.parametrize("make", [lambda: hubbard_dimer(beta=2.0, U=2.0, n_tau=2001),
+                                  lambda: anderson_bath(beta=4.0, U=3.0, n_tau=2048)])
+def test_walk_against_exact_diagonalisation(make):
+    """D, <n>, G(tau) and <k> = K - beta <V> against ED within 3 sigma."""
+    w = make()
+    nto = 8
+    B = _bins(lambda sd: OracleChain(w, seed=sd, meas_every=4, n_therm=2000, n_tau_out=nto),
+              w, 4, 8, 15000, 4000, nto)
+    sites = list(range(w.n_sites))
+    ed = ED(w.meta["h1"], w.U, w.beta, sites)
+    m, e = _mean_err([b["D"] for b in B])
+    assert _within(m, e, np.mean([ed.double_occ(x) for x in sites]))
+    m, e = _mean_err([b["order"] for b in B])
+    assert _within(m, e, w.K - w.beta * ed.potential())
+    m, e = _mean_err([b["n_up"] for b in B])
+    assert _within(m, e, np.mean([ed.density(x, 0) for x in sites]))
+    G, Ge = _mean_err([b["G"] for b in B])
+    means, errs, exact = [], [], []
+    for x in sites:
+        for y in sites:
+            d = w.site_disp[x * w.n_sites + y]
+            for j in range(nto):
+                tj = (j + 0.5) * w.beta / nto
+                for sec in (0, 1):
+                    means.append(G[sec, d, j])
+                    errs.append(Ge[sec, d, j])
+                    exact.append(ed.greens(x, y, sec, tj))
+    ok, z = _family_ok(means, errs, exact)
+    assert ok, z
+
+
+def test_hubbard_atom_closed_forms():
+    """Isolated atom at half filling: D = 1/(2(1+e^{beta U/2})),
+    G(tau) = (e^{tau U/2} + e^{(beta - tau) U/2}) / (2 + 2 e^{beta U/2})."""
+    beta, U = 1.0, 2.0
+    w = hubbard_atom(beta=beta, U=U, K=1.0)
+    nto = 8
+    B = _bins(lambda sd: OracleChain(w, seed=sd, meas_every=4, n_tau_out=nto),
+              w, 4, 8, 15000, 4000, nto)
+    m, e = _mean_err([b["D"] for b in B])
+    assert _within(m, e, 1.0 / (2.0 * (1.0 + math.exp(beta * U / 2))))
+    G, Ge = _mean_err([b["G"] for b in B])
+    t = (np.arange(nto) + 0.5) * beta / nto
+    exact = (np.exp(t * U / 2) + np.exp((beta - t) * U / 2)) / (2 + 2 * math.exp(beta * U / 2))
+    ok, z = _family_ok(np.concatenate([G[0, 0], G[1, 0]]), np.concatenate([Ge[0, 0], Ge[1, 0]]),
+                       np.concatenate([exact, exact]))
+    assert ok, z
+
+
+def test_u_zero_walk_is_poisson():
+    """At U = 0 every determinant ratio is 1 and the order is Poisson(K)."""
+    K = 3.0
+    w = hubbard_atom(beta=2.0, U=0.0, K=K)
+    B = _bins(lambda sd: OracleChain(w, seed=sd, meas_every=2), w, 4, 10, 10000, 2000, 16)
+    for key, exact in (("order", K), ("order2", K + K * K), ("p0", math.exp(-K))):
+        m, e = _mean_err([b[key] for b in B])
+        assert _within(m, e, exact)
+    assert all(b["D"] == 0.25 for b in B)      # n_up = n_dn = 1/2 exactly, uncorrelated
+
+
+def test_particle_hole_symmetry_semicircle():
+    """Half filling: n_sigma = 1/2 and G(tau) = G(beta - tau) within errors."""
+    w = anderson_semicircle(n_tau=4096)
+    nto = 8
+    B = _bins(lambda sd: OracleChain(w, seed=sd, meas_every=16, n_tau_out=nto),
+              w, 4, 6, 8000, 16000, nto)
+    m, e = _mean_err([0.5 * (b["n_up"] + b["n_dn"]) for b in B])
+    assert _within(m, e, 0.5)
+    G, Ge = _mean_err([b["G"][0, 0] - b["G"][0, 0][::-1] for b in B])
+    ok, z = _family_ok(G[: nto // 2], Ge[: nto // 2], np.zeros(nto // 2))
+    assert ok, z
+    m, e = _mean_err([b["sign"] for b in B])
+    assert m == 1.0
+
+
+# ------------------------------------------------------- bookkeeping and errors
+def test_restore_reproduces_decisions():
+    w = _plaquette()
+    a = OracleChain(w, seed=6)
+    a.set_log(4000)
+    a.run(2000)
+    ids, tau, site, s = a.config()
+    done, next_id, sign = a.get_state()
+    b = OracleChain(w, seed=6)
+    b.set_log(4000)
+    b.set_config(ids, tau, site, s)
+    b.set_state(done, next_id, sign)
+    a.run(1500)
+    b.run(1500)
+    acc_a, R_a = a.get_log(2000, 1500)
+    acc_b, R_b = b.get_log(2000, 1500)
+    assert np.array_equal(acc_a, acc_b)
+    np.testing.assert_allclose(R_b, R_a, rtol=1e-9)
+    for sec in (0, 1):
+        np.testing.assert_allclose(b.N(sec), a.N(sec), rtol=1e-8, atol=1e-10)
+
+
+def test_capacity_and_input_errors():
+    w = _plaquette()
+    c = OracleChain(w, seed=1, n_cap=3)
+    with pytest.raises(OracleError, match="n_cap"):
+        c.run(10000)
+    assert c.order == 3
+    bad = _plaquette()
+    bad.g0_up[0, 5] = np.nan
+    with pytest.raises(OracleError):
+        OracleChain(bad)
