@@ -1,0 +1,168 @@
+/*
+ * ctaux.h — C ABI of the MI355X (gfx950) CT-AUX submatrix-update library.
+ *
+ * The library runs Markov chains of the continuous-time auxiliary-field
+ * (CT-AUX) Monte Carlo method of Gull et al., "Submatrix updates for the
+ * Continuous-Time Auxiliary Field algorithm" (arXiv:1010.3690), on one GPU.
+ * Per chain and per block of k proposals it:
+ *   - draws the proposals from a counter-based Philox4x32-10 stream and
+ *     pre-inserts the block's insertion candidates as spin-0 vertices
+ *     (Sec. IV, "Preparation steps");
+ *   - evaluates insert / remove / spin-flip proposals as spin changes
+ *     0 -> +-1, +-1 -> 0, +-1 -> -+1 with determinant ratios from a growing
+ *     Gamma^{-1} (Sec. III B 2, inversion by partitioning, Eq. ratS);
+ *   - applies the accepted changes with one rank-k update of
+ *     N_sigma = [e^{V_sigma} - G0_sigma (e^{V_sigma} - 1)]^{-1}  (Eq. Nmatrix)
+ *     per spin sector (Eq. Nshermanmorrison) and deletes spin-0 rows and
+ *     columns (Sec. IV C);
+ *   - measures at the end of a block (Sec. IV D) and periodically refines N
+ *     against its definition in FP64.
+ *
+ * Conventions for every entry point:
+ *   - Return value 0 (CTAUX_OK) or a negative CTAUX_E* code.  No exception
+ *     crosses the ABI.  ctaux_last_error() describes the last failure of a
+ *     handle (or of creation, with a NULL handle).
+ *   - Host pointers are read during the call only; the caller keeps them.
+ *   - Device memory: the caller passes one device workspace of at least
+ *     ctaux_workspace_bytes() bytes (256-byte aligned) that must stay valid
+ *     until ctaux_destroy(); the library allocates no device memory itself.
+ *   - Stream: every kernel runs on the caller's HIP stream (NULL = the
+ *     default stream).  Entry points return after the stream has drained,
+ *     except where stated.
+ *   - Handles are not thread-safe; distinct handles may be used concurrently
+ *     on distinct streams.
+ *   - Chains are independent: chain c draws from the stream keyed by
+ *     (opts.seed, c).  Vertex order is canonical: ascending vertex id, ids
+ *     assigned in order of accepted insertions.
+ */
+#ifndef CTAUX_H
+#define CTAUX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CTAUX_OK 0
+#define CTAUX_EINVAL (-1)     /* invalid argument or state                        */
+#define CTAUX_ENOMEM (-2)     /* workspace too small / host allocation failed     */
+#define CTAUX_EDEVICE (-3)    /* HIP runtime error                                */
+#define CTAUX_ENUMERIC (-4)   /* NaN/Inf in a ratio or in N, or refinement failed */
+#define CTAUX_ECAPACITY (-5)  /* an insertion would exceed n_cap                  */
+
+#define CTAUX_FP64 0          /* N stored and updated in FP64 (FP64 MFMA)               */
+#define CTAUX_FP32 1          /* N stored in FP32, rank-k update on FP32 MFMA, FP64 Gamma */
+
+/* Model of one chain (Sec. II A).  U >= 0, K > 0, beta > 0.
+ * gamma is fixed by cosh(gamma) = 1 + beta*U*n_sites/(2K)  (Eq. gamma; the
+ * factor n_sites is the cluster form of the decoupling).
+ * The bare propagator of the pair of sites (x, y) is table site_disp[x*n_sites+y]:
+ * g0_sigma[d*n_tau + m] = G0_sigma,d(tau_m), tau_m = m*beta/(n_tau-1),
+ * with G0(tau) = <T c_x(tau) c_y^dagger(0)>_0 (entry 0 = tau -> 0+, last = beta-).
+ * Between grid points G0 is interpolated linearly; G0(tau - beta) = -G0(tau). */
+typedef struct {
+    double beta, U, K;
+    int32_t n_sites;          /* Nc >= 1                                       */
+    int32_t n_tau;            /* >= 2                                          */
+    int32_t n_disp;           /* number of tables per sector                   */
+    const int32_t *site_disp; /* host, [n_sites*n_sites], values in [0, n_disp) */
+    const double *g0_up;      /* host, [n_disp*n_tau], finite                  */
+    const double *g0_dn;      /* host, [n_disp*n_tau], finite                  */
+} ctaux_model;
+
+/* Run options shared by all chains of a batch. */
+typedef struct {
+    int32_t k_max;            /* proposals per block, 1..128                                  */
+    int32_t k_cap;            /* accepted changes per block (size of Gamma), 1..64; a block
+                                 ends early once Gamma is full (does not change the chain)     */
+    double p_flip;            /* P(flip); P(insert) = P(remove) = (1 - p_flip)/2              */
+    int32_t recompute_every;  /* blocks between FP64 refinements of N (0 = never)             */
+    int32_t precision;        /* CTAUX_FP64 or CTAUX_FP32                                     */
+    int32_t meas_every;       /* measure after every meas_every proposals ...                 */
+    int64_t n_therm;          /* ... once more than n_therm proposals are done                */
+    int32_t n_tau_out;        /* G(tau) output points tau_j = (j+1/2) beta / n_tau_out        */
+    int32_t n_cap;            /* maximum order per chain                                      */
+    uint64_t seed;
+    int64_t log_cap;          /* decisions of proposals with index < log_cap are recorded     */
+} ctaux_opts;
+
+/* Per-chain counters. */
+typedef struct {
+    int64_t proposals;        /* proposals processed                         */
+    int64_t accepted;         /* accepted proposals                          */
+    int64_t blocks;           /* blocks (outer iterations) completed          */
+    int64_t sum_ka;           /* sum over blocks of accepted changes          */
+    int64_t next_id;          /* next vertex id                              */
+    int32_t order;            /* current expansion order n                    */
+    int32_t status;           /* 0 or the CTAUX_E* code that stopped the chain */
+    double sign;              /* sign of the current configuration weight    */
+    double max_drift;         /* largest refinement drift seen (see ctaux_recompute) */
+} ctaux_stats;
+
+/* One vertex of a configuration (tau in [0, beta), site in [0, n_sites), s = +-1). */
+typedef struct {
+    int64_t id;
+    double tau;
+    int32_t site;
+    int32_t s;
+} ctaux_vertex;
+
+typedef struct ctaux_batch ctaux_batch;
+
+/* Device bytes needed for n_chains chains with these models and options
+ * (0 if the arguments are invalid). */
+size_t ctaux_workspace_bytes(const ctaux_model *models, int32_t n_chains, const ctaux_opts *opts);
+
+/* Create a batch of n_chains chains, all starting at order 0.  models is a
+ * host array [n_chains].  The workspace is device memory owned by the caller. */
+int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *opts,
+                 void *dev_workspace, size_t ws_bytes, void *hip_stream, ctaux_batch **out);
+
+/* Advance every chain by n_proposals proposals (propose/accept batch).  Stops
+ * a chain early on CTAUX_ECAPACITY / CTAUX_ENUMERIC and returns that code. */
+int ctaux_run(ctaux_batch *b, int64_t n_proposals);
+
+/* Refine N of every chain against its definition in FP64 (one Newton step
+ * N <- N + N (I - M N) with M = e^V - G0(e^V - 1) built from the tables) and
+ * return the largest relative drift ||N_before - N_after||_F / ||N_after||_F.
+ * Also runs automatically every opts.recompute_every blocks. */
+int ctaux_recompute(ctaux_batch *b, double *max_drift_out);
+
+/* Observable accumulators of a chain (doubles, len >= ctaux_obs_len()):
+ *   [0] measurements   [1] sum sign       [2] sum sign*order   [3] sum sign*order^2
+ *   [4] sum sign*[order==0]               [5] sum sign*D (double occupancy per site)
+ *   [6] sum sign*n_up per site            [7] sum sign*n_dn per site
+ *   [8 ...] sum sign*G_up[d][j]; then sum sign*G_dn[d][j]  (d < n_disp, j < n_tau_out),
+ * G_sigma[d][j] = average of G_sigma(x, tau_j; y, 0) over pairs with table d. */
+int32_t ctaux_obs_len(const ctaux_batch *b);
+int ctaux_get_obs(ctaux_batch *b, int32_t chain, double *out, int32_t len);
+int ctaux_reset_obs(ctaux_batch *b);
+
+int ctaux_get_stats(ctaux_batch *b, int32_t chain, ctaux_stats *out);
+/* Configuration in canonical order; *n_out = order; at most cap vertices copied. */
+int ctaux_get_config(ctaux_batch *b, int32_t chain, int32_t cap, ctaux_vertex *out, int32_t *n_out);
+/* N of one sector (0 up, 1 down) as FP64, row-major with leading dimension ld >= order.
+ * With out == NULL only *n_out is set. */
+int ctaux_get_N(ctaux_batch *b, int32_t chain, int32_t sector, double *out, int32_t ld,
+                int32_t *n_out);
+/* Decisions of proposals [first, first+count) (count <= log_cap - first):
+ * acc[i] = 1 if accepted, R[i] = signed acceptance ratio (0 for a removal or
+ * flip proposed at order 0). */
+int ctaux_get_decisions(ctaux_batch *b, int32_t chain, int64_t first, int64_t count,
+                        uint8_t *acc, double *R);
+/* Per-kernel device time (ms) accumulated since the last reset, measured with
+ * HIP events when opts enable it via ctaux_set_timing(b, 1).  names[i] are
+ * static strings; returns the number of entries written (<= cap). */
+int ctaux_set_timing(ctaux_batch *b, int32_t enable);
+int32_t ctaux_get_timing(ctaux_batch *b, const char **names, double *ms, int64_t *launches,
+                         int32_t cap);
+
+const char *ctaux_last_error(const ctaux_batch *b);
+void ctaux_destroy(ctaux_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,548 @@
+// Host runtime of the C ABI declared in include/ctaux.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ctaux.h"
+#include "ctaux_internal.h"
+
+using namespace ctaux;
+
+namespace {
+
+thread_local char g_create_error[512] = "";
+
+struct TimedEvent {
+  int name;
+  hipEvent_t start, stop;
+};
+
+const char *kKernelNames[] = {"block_begin", "interp", "prep",      "propose", "gamma_inv", "tile_scan",
+                              "assemble",    "rankk",  "block_end", "measure", "refine"};
+constexpr int kNumNames = sizeof(kKernelNames) / sizeof(kKernelNames[0]);
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Sequential carving of the workspace; with base == nullptr it only measures.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t count) {
+    off = align_up(off, 256);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += align_up(count * sizeof(T), 256);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct ctaux_batch {
+  Batch b;
+  hipStream_t stream;
+  std::vector<ChainDesc> desc;        // host copies
+  std::vector<ChainState> state;      // host mirror (refreshed at sync points)
+  std::vector<int32_t> obs_len;
+  int64_t blocks_launched = 0;
+  int32_t recompute_every = 0;
+  int64_t log_cap = 0;
+  int32_t obs_len_max = 0;
+  bool timing = false;
+  std::vector<TimedEvent> pool;       // created events
+  size_t pool_used = 0;
+  double ms[kNumNames] = {0};
+  int64_t launches[kNumNames] = {0};
+  std::string err;
+};
+
+namespace {
+
+int set_err(ctaux_batch *b, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (b) b->err = buf;
+  else snprintf(g_create_error, sizeof g_create_error, "%s", buf);
+  return code;
+}
+
+#define HIPCHECK(b, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return set_err((b), CTAUX_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, ctaux_batch *eb) {
+  if (!models || !o || n_chains < 1) return set_err(eb, CTAUX_EINVAL, "null models/opts or n_chains < 1");
+  if (o->k_max < 1 || o->k_max > kMaxKmax) return set_err(eb, CTAUX_EINVAL, "k_max must be in 1..%d", kMaxKmax);
+  if (o->k_cap < 1 || o->k_cap > kMaxKcap || o->k_cap > o->k_max)
+    return set_err(eb, CTAUX_EINVAL, "k_cap must be in 1..min(k_max, %d)", kMaxKcap);
+  if (!(o->p_flip >= 0.0 && o->p_flip <= 1.0)) return set_err(eb, CTAUX_EINVAL, "p_flip must be in [0,1]");
+  if (o->precision != CTAUX_FP64 && o->precision != CTAUX_FP32)
+    return set_err(eb, CTAUX_EINVAL, "precision must be CTAUX_FP64 or CTAUX_FP32");
+  if (o->meas_every < 1 || o->n_tau_out < 1 || o->n_tau_out > 4096 || o->n_cap < 1 || o->n_cap > 65536 ||
+      o->recompute_every < 0 || o->n_therm < 0 || o->log_cap < 0)
+    return set_err(eb, CTAUX_EINVAL, "invalid meas_every/n_tau_out/n_cap/recompute_every/n_therm/log_cap");
+  for (int c = 0; c < n_chains; ++c) {
+    const ctaux_model &m = models[c];
+    if (!(m.beta > 0) || !(m.U >= 0) || !(m.K > 0) || !isfinite(m.beta) || !isfinite(m.U) || !isfinite(m.K))
+      return set_err(eb, CTAUX_EINVAL, "chain %d: need beta > 0, U >= 0, K > 0", c);
+    if (m.n_sites < 1 || m.n_sites > 128 || m.n_tau < 2 || m.n_disp < 1 || !m.site_disp || !m.g0_up || !m.g0_dn)
+      return set_err(eb, CTAUX_EINVAL, "chain %d: invalid sizes or null tables (n_sites <= 128)", c);
+    for (int i = 0; i < m.n_sites * m.n_sites; ++i)
+      if (m.site_disp[i] < 0 || m.site_disp[i] >= m.n_disp)
+        return set_err(eb, CTAUX_EINVAL, "chain %d: site_disp out of range", c);
+    for (int64_t i = 0; i < static_cast<int64_t>(m.n_disp) * m.n_tau; ++i)
+      if (!isfinite(m.g0_up[i]) || !isfinite(m.g0_dn[i]))
+        return set_err(eb, CTAUX_EINVAL, "chain %d: non-finite G0 table entry %lld", c, (long long)i);
+  }
+  return CTAUX_OK;
+}
+
+// Lays out (and, with a base, assigns) every buffer; returns total bytes.
+size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, char *base, Batch *bt,
+              std::vector<ChainDesc> *descs) {
+  Carver cv{base};
+  const int n_cap = o->n_cap, kmax = o->k_max, kcap = o->k_cap;
+  const int ld = static_cast<int>(align_up(n_cap, 64));
+  const int lda = static_cast<int>(align_up(kcap, 8));
+  const size_t es = o->precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
+  ChainDesc *d_desc = cv.take<ChainDesc>(n_chains);
+  ChainState *d_state = cv.take<ChainState>(n_chains);
+  int32_t *d_prefix = cv.take<int32_t>(n_chains + 1);
+  double *r_M = cv.take<double>(static_cast<size_t>(ld) * ld);
+  double *r_R = cv.take<double>(static_cast<size_t>(ld) * ld);
+  double *r_N = cv.take<double>(static_cast<size_t>(ld) * ld);
+  double *r_red = cv.take<double>(4096);
+  if (bt) {
+    bt->d_desc = d_desc; bt->d_state = d_state; bt->d_tile_prefix = d_prefix;
+    bt->r_M = r_M; bt->r_R = r_R; bt->r_N = r_N; bt->r_red = r_red;
+  }
+  for (int c = 0; c < n_chains; ++c) {
+    const ctaux_model &m = models[c];
+    ChainDesc d;
+    memset(&d, 0, sizeof d);
+    const int nc = m.n_sites;
+    for (int s = 0; s < 2; ++s) d.g0[s] = cv.take<double>(static_cast<size_t>(m.n_disp) * m.n_tau);
+    d.site_disp = cv.take<int32_t>(static_cast<size_t>(nc) * nc);
+    d.cls_off = cv.take<int32_t>(m.n_disp + 1);
+    d.cls_pairs = cv.take<int32_t>(static_cast<size_t>(nc) * nc);
+    for (int p = 0; p < 2; ++p)
+      for (int s = 0; s < 2; ++s) d.N[p][s] = cv.take<char>(es * ld * ld);
+    for (int p = 0; p < 2; ++p) {
+      d.tau[p] = cv.take<double>(n_cap);
+      d.site[p] = cv.take<int32_t>(n_cap);
+      d.s0[p] = cv.take<int32_t>(n_cap);
+      d.id[p] = cv.take<int64_t>(n_cap);
+    }
+    d.ptype = cv.take<int32_t>(kmax);
+    d.pspin = cv.take<int32_t>(kmax);
+    d.pacc = cv.take<double>(kmax);
+    d.ppick = cv.take<double>(kmax);
+    d.ctau = cv.take<double>(kmax);
+    d.csite = cv.take<int32_t>(kmax);
+    d.cid = cv.take<int64_t>(kmax);
+    for (int s = 0; s < 2; ++s) {
+      d.X[s] = cv.take<double>(static_cast<size_t>(kmax) * ld);
+      d.ZT[s] = cv.take<double>(static_cast<size_t>(kmax) * ld);
+      d.YT[s] = cv.take<double>(static_cast<size_t>(kmax) * ld);
+      d.Rt[s] = cv.take<double>(static_cast<size_t>(kmax) * ld);
+      d.G0nn[s] = cv.take<double>(static_cast<size_t>(kmax) * kmax);
+      d.Gnn[s] = cv.take<double>(static_cast<size_t>(kmax) * kmax);
+      d.ghat[s] = cv.take<double>(kcap);
+      d.Gam[s] = cv.take<double>(static_cast<size_t>(kcap) * kcap);
+      d.Ginv[s] = cv.take<double>(static_cast<size_t>(kcap) * kcap);
+      d.Ac[s] = cv.take<char>(es * ld * lda);
+      d.Bc[s] = cv.take<char>(es * lda * ld);
+      d.W[s] = cv.take<double>(static_cast<size_t>(n_cap) * nc);
+      d.gR[s] = cv.take<double>(static_cast<size_t>(n_cap) * nc);
+      d.Gxy[s] = cv.take<double>(static_cast<size_t>(o->n_tau_out + 1) * nc * nc);
+    }
+    d.P = cv.take<int32_t>(kcap);
+    d.map = cv.take<int32_t>(n_cap + kmax);
+    d.obs_len = 8 + 2 * m.n_disp * o->n_tau_out;
+    d.obs = cv.take<double>(d.obs_len);
+    d.log_cap = o->log_cap;
+    d.log_acc = cv.take<uint8_t>(o->log_cap > 0 ? o->log_cap : 1);
+    d.log_R = cv.take<double>(o->log_cap > 0 ? o->log_cap : 1);
+    if (descs) {
+      d.beta = m.beta; d.K = m.K;
+      d.gamma = acosh(1.0 + m.beta * m.U * nc / (2.0 * m.K));
+      d.inv_h = static_cast<double>(m.n_tau - 1) / m.beta;
+      d.p_flip = o->p_flip;
+      for (int s = 0; s < 2; ++s) {
+        const double sigma = s == 0 ? 1.0 : -1.0;
+        for (int k = -2; k <= 2; ++k) d.evd[s][k + 2] = exp(d.gamma * sigma * k);
+      }
+      d.nc = nc; d.n_tau = m.n_tau; d.n_disp = m.n_disp; d.lda = lda;
+      d.n_cap = n_cap; d.ld = ld; d.kmax = kmax; d.kcap = kcap;
+      d.meas_every = o->meas_every; d.n_out = o->n_tau_out; d.n_therm = o->n_therm;
+      d.seed_lo = static_cast<uint32_t>(o->seed);
+      d.seed_hi = static_cast<uint32_t>(o->seed >> 32);
+      d.chain_id = static_cast<uint32_t>(c);
+      d.precision = o->precision;
+      descs->push_back(d);
+    }
+  }
+  return align_up(cv.off, 256);
+}
+
+int enqueue_block(ctaux_batch *h);
+
+struct Timer {
+  ctaux_batch *h;
+  int name;
+  TimedEvent *ev = nullptr;
+  Timer(ctaux_batch *h_, int name_) : h(h_), name(name_) {
+    if (!h->timing) return;
+    if (h->pool_used == h->pool.size()) {
+      TimedEvent e;
+      e.name = name;
+      (void)hipEventCreate(&e.start);
+      (void)hipEventCreate(&e.stop);
+      h->pool.push_back(e);
+    }
+    ev = &h->pool[h->pool_used++];
+    ev->name = name;
+    (void)hipEventRecord(ev->start, h->stream);
+  }
+  ~Timer() {
+    if (ev) (void)hipEventRecord(ev->stop, h->stream);
+  }
+};
+
+void flush_timing(ctaux_batch *h) {
+  for (size_t i = 0; i < h->pool_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->pool[i].start, h->pool[i].stop) == hipSuccess) {
+      h->ms[h->pool[i].name] += ms;
+      h->launches[h->pool[i].name] += 1;
+    }
+  }
+  h->pool_used = 0;
+}
+
+int sync_states(ctaux_batch *h) {
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  if (h->timing) flush_timing(h);
+  HIPCHECK(h, hipMemcpy(h->state.data(), h->b.d_state, sizeof(ChainState) * h->b.n_chains, hipMemcpyDeviceToHost));
+  return CTAUX_OK;
+}
+
+int enqueue_block(ctaux_batch *h) {
+  const Batch &b = h->b;
+  hipStream_t s = h->stream;
+  { Timer t(h, 0); launch_block_begin(b, s); }
+  { Timer t(h, 1); launch_interp(b, s); }
+  { Timer t(h, 2); launch_prep(b, s); }
+  { Timer t(h, 3); launch_propose(b, s); }
+  { Timer t(h, 4); launch_gamma_inv(b, s); }
+  { Timer t(h, 5); launch_tile_scan(b, s); }
+  { Timer t(h, 6); launch_assemble(b, s); }
+  { Timer t(h, 7); launch_rankk(b, s); }
+  { Timer t(h, 8); launch_block_end(b, s); }
+  { Timer t(h, 9); launch_measure(b, s); }
+  h->blocks_launched += 1;
+  if (h->recompute_every > 0 && h->blocks_launched % h->recompute_every == 0) {
+    Timer t(h, 10);
+    for (int c = 0; c < b.n_chains; ++c) launch_refine(b, s, c);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(h, CTAUX_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  if (h->timing && h->pool_used > 16000) {
+    HIPCHECK(h, hipStreamSynchronize(s));
+    flush_timing(h);
+  }
+  return CTAUX_OK;
+}
+
+int chain_error(ctaux_batch *h) {
+  for (int c = 0; c < h->b.n_chains; ++c) {
+    const ChainState &st = h->state[c];
+    if (st.status == CTAUX_ECAPACITY)
+      return set_err(h, CTAUX_ECAPACITY, "chain %d: an insertion at proposal %lld would exceed n_cap=%d", c,
+                     (long long)st.err_index, h->b.n_cap);
+    if (st.status != 0)
+      return set_err(h, st.status, "chain %d: numerical failure (code %d) at proposal %lld, drift %.3g", c,
+                     st.status, (long long)st.err_index, st.last_drift);
+  }
+  return CTAUX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ctaux_workspace_bytes(const ctaux_model *models, int32_t n_chains, const ctaux_opts *opts) {
+  if (validate(models, n_chains, opts, nullptr) != CTAUX_OK) return 0;
+  return layout(models, n_chains, opts, nullptr, nullptr, nullptr);
+}
+
+int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *opts, void *dev_workspace,
+                 size_t ws_bytes, void *hip_stream, ctaux_batch **out) {
+  if (!out) return set_err(nullptr, CTAUX_EINVAL, "out is null");
+  *out = nullptr;
+  int rc = validate(models, n_chains, opts, nullptr);
+  if (rc) return rc;
+  const size_t need = layout(models, n_chains, opts, nullptr, nullptr, nullptr);
+  if (!dev_workspace || ws_bytes < need)
+    return set_err(nullptr, CTAUX_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % 256 != 0)
+    return set_err(nullptr, CTAUX_EINVAL, "workspace must be 256-byte aligned");
+  ctaux_batch *h = new (std::nothrow) ctaux_batch();
+  if (!h) return set_err(nullptr, CTAUX_ENOMEM, "host allocation failed");
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  Batch &b = h->b;
+  b.n_chains = n_chains;
+  b.kmax = opts->k_max;
+  b.kcap = opts->k_cap;
+  b.n_cap = opts->n_cap;
+  b.ld = static_cast<int>(align_up(opts->n_cap, 64));
+  b.precision = opts->precision;
+  b.nc_max = 1;
+  b.n_out_max = opts->n_tau_out;
+  for (int c = 0; c < n_chains; ++c) b.nc_max = models[c].n_sites > b.nc_max ? models[c].n_sites : b.nc_max;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete h;
+    return set_err(nullptr, CTAUX_EDEVICE, "no HIP device");
+  }
+  b.n_cu = prop.multiProcessorCount;
+  b.grid_per_chain = n_chains >= 2048 ? 1 : 2048 / n_chains;
+  if (b.grid_per_chain > 1024) b.grid_per_chain = 1024;
+  h->recompute_every = opts->recompute_every;
+  h->log_cap = opts->log_cap;
+  layout(models, n_chains, opts, static_cast<char *>(dev_workspace), &b, &h->desc);
+  // upload tables, maps and descriptors
+  std::vector<ChainState> st(n_chains);
+  for (int c = 0; c < n_chains; ++c) {
+    const ctaux_model &m = models[c];
+    ChainDesc &d = h->desc[c];
+    const size_t tb = sizeof(double) * m.n_disp * m.n_tau;
+    const int nc = m.n_sites;
+    std::vector<int32_t> off(m.n_disp + 1, 0), pairs;
+    for (int dd = 0; dd < m.n_disp; ++dd) {
+      for (int x = 0; x < nc; ++x)
+        for (int y = 0; y < nc; ++y)
+          if (m.site_disp[x * nc + y] == dd) pairs.push_back(x * nc + y);
+      off[dd + 1] = static_cast<int32_t>(pairs.size());
+    }
+    if (hipMemcpyAsync(const_cast<double *>(d.g0[0]), m.g0_up, tb, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(const_cast<double *>(d.g0[1]), m.g0_dn, tb, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int32_t *>(d.site_disp), m.site_disp, sizeof(int32_t) * nc * nc,
+                       hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int32_t *>(d.cls_off), off.data(), sizeof(int32_t) * off.size(),
+                       hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(const_cast<int32_t *>(d.cls_pairs), pairs.data(), sizeof(int32_t) * pairs.size(),
+                       hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemsetAsync(d.obs, 0, sizeof(double) * d.obs_len, h->stream) != hipSuccess ||
+        (opts->log_cap > 0 &&
+         (hipMemsetAsync(d.log_acc, 0, opts->log_cap, h->stream) != hipSuccess ||
+          hipMemsetAsync(d.log_R, 0, sizeof(double) * opts->log_cap, h->stream) != hipSuccess))) {
+      delete h;
+      return set_err(nullptr, CTAUX_EDEVICE, "upload of chain %d failed", c);
+    }
+    // hipMemcpyAsync of pageable host memory is staged before returning, so the
+    // temporaries above may go out of scope; synchronize per chain to be safe.
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+      delete h;
+      return set_err(nullptr, CTAUX_EDEVICE, "stream synchronisation failed");
+    }
+    h->obs_len.push_back(d.obs_len);
+    if (d.obs_len > h->obs_len_max) h->obs_len_max = d.obs_len;
+    memset(&st[c], 0, sizeof(ChainState));
+    st[c].sign = 1.0;
+  }
+  h->state = st;
+  if (hipMemcpy(b.d_desc, h->desc.data(), sizeof(ChainDesc) * n_chains, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b.d_state, st.data(), sizeof(ChainState) * n_chains, hipMemcpyHostToDevice) != hipSuccess) {
+    delete h;
+    return set_err(nullptr, CTAUX_EDEVICE, "descriptor upload failed");
+  }
+  *out = h;
+  return CTAUX_OK;
+}
+
+int ctaux_run(ctaux_batch *h, int64_t n_proposals) {
+  if (!h) return CTAUX_EINVAL;
+  if (n_proposals < 0) return set_err(h, CTAUX_EINVAL, "n_proposals < 0");
+  int rc = chain_error(h);
+  if (rc) return rc;
+  if (n_proposals == 0) return CTAUX_OK;
+  launch_set_target(h->b, h->stream, n_proposals);
+  int64_t iters = (n_proposals + h->b.kmax - 1) / h->b.kmax;
+  int64_t prev_done = -1;
+  while (true) {
+    for (int64_t i = 0; i < iters; ++i) {
+      rc = enqueue_block(h);
+      if (rc) return rc;
+    }
+    rc = sync_states(h);
+    if (rc) return rc;
+    rc = chain_error(h);
+    if (rc) return rc;
+    int64_t remaining = 0, done_sum = 0;
+    for (const ChainState &st : h->state) {
+      remaining = st.target - st.done > remaining ? st.target - st.done : remaining;
+      done_sum += st.done;
+    }
+    if (remaining == 0) break;
+    if (done_sum == prev_done) return set_err(h, CTAUX_EDEVICE, "no chain progressed");
+    prev_done = done_sum;
+    iters = (remaining + h->b.kmax - 1) / h->b.kmax;
+  }
+  return CTAUX_OK;
+}
+
+int ctaux_recompute(ctaux_batch *h, double *max_drift_out) {
+  if (!h) return CTAUX_EINVAL;
+  {
+    Timer t(h, 10);
+    for (int c = 0; c < h->b.n_chains; ++c) launch_refine(h->b, h->stream, c);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(h, CTAUX_EDEVICE, "refine launch failed: %s", hipGetErrorString(e));
+  int rc = sync_states(h);
+  if (rc) return rc;
+  double m = 0.0;
+  for (const ChainState &st : h->state) m = st.last_drift > m ? st.last_drift : m;
+  if (max_drift_out) *max_drift_out = m;
+  return chain_error(h);
+}
+
+int32_t ctaux_obs_len(const ctaux_batch *h) { return h ? h->obs_len_max : 0; }
+
+int ctaux_get_obs(ctaux_batch *h, int32_t chain, double *out, int32_t len) {
+  if (!h || !out || chain < 0 || chain >= h->b.n_chains) return CTAUX_EINVAL;
+  const int32_t L = h->obs_len[chain];
+  if (len < L) return set_err(h, CTAUX_EINVAL, "obs buffer of %d doubles needed", L);
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  HIPCHECK(h, hipMemcpy(out, h->desc[chain].obs, sizeof(double) * L, hipMemcpyDeviceToHost));
+  for (int32_t i = L; i < len; ++i) out[i] = 0.0;
+  return CTAUX_OK;
+}
+
+int ctaux_reset_obs(ctaux_batch *h) {
+  if (!h) return CTAUX_EINVAL;
+  for (int c = 0; c < h->b.n_chains; ++c)
+    HIPCHECK(h, hipMemsetAsync(h->desc[c].obs, 0, sizeof(double) * h->obs_len[c], h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  return CTAUX_OK;
+}
+
+int ctaux_get_stats(ctaux_batch *h, int32_t chain, ctaux_stats *out) {
+  if (!h || !out || chain < 0 || chain >= h->b.n_chains) return CTAUX_EINVAL;
+  int rc = sync_states(h);
+  if (rc) return rc;
+  const ChainState &st = h->state[chain];
+  out->proposals = st.done;
+  out->accepted = st.accepted;
+  out->blocks = st.blocks;
+  out->sum_ka = st.sum_ka;
+  out->next_id = st.next_id;
+  out->order = st.n;
+  out->status = st.status;
+  out->sign = st.sign;
+  out->max_drift = st.max_drift;
+  return CTAUX_OK;
+}
+
+int ctaux_get_config(ctaux_batch *h, int32_t chain, int32_t cap, ctaux_vertex *out, int32_t *n_out) {
+  if (!h || chain < 0 || chain >= h->b.n_chains || cap < 0 || (cap > 0 && !out)) return CTAUX_EINVAL;
+  int rc = sync_states(h);
+  if (rc) return rc;
+  const ChainState &st = h->state[chain];
+  const ChainDesc &d = h->desc[chain];
+  const int n = st.n, par = st.parity;
+  if (n_out) *n_out = n;
+  const int m = n < cap ? n : cap;
+  if (m == 0) return CTAUX_OK;
+  std::vector<double> tau(m);
+  std::vector<int32_t> site(m), s(m);
+  std::vector<int64_t> id(m);
+  HIPCHECK(h, hipMemcpy(tau.data(), d.tau[par], sizeof(double) * m, hipMemcpyDeviceToHost));
+  HIPCHECK(h, hipMemcpy(site.data(), d.site[par], sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  HIPCHECK(h, hipMemcpy(s.data(), d.s0[par], sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  HIPCHECK(h, hipMemcpy(id.data(), d.id[par], sizeof(int64_t) * m, hipMemcpyDeviceToHost));
+  for (int i = 0; i < m; ++i) out[i] = ctaux_vertex{id[i], tau[i], site[i], s[i]};
+  return CTAUX_OK;
+}
+
+int ctaux_get_N(ctaux_batch *h, int32_t chain, int32_t sector, double *out, int32_t ld, int32_t *n_out) {
+  if (!h || chain < 0 || chain >= h->b.n_chains || sector < 0 || sector > 1) return CTAUX_EINVAL;
+  int rc = sync_states(h);
+  if (rc) return rc;
+  const ChainState &st = h->state[chain];
+  const ChainDesc &d = h->desc[chain];
+  const int n = st.n;
+  if (n_out) *n_out = n;
+  if (n == 0 || !out) return CTAUX_OK;   // out == NULL: query the order only
+  if (ld < n) return set_err(h, CTAUX_EINVAL, "ld < order %d", n);
+  const size_t es = h->b.precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
+  std::vector<char> tmp(es * n * n);
+  HIPCHECK(h, hipMemcpy2D(tmp.data(), es * n, d.N[st.parity][sector], es * d.ld, es * n, n, hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      out[static_cast<size_t>(i) * ld + j] =
+          es == sizeof(double) ? reinterpret_cast<double *>(tmp.data())[static_cast<size_t>(i) * n + j]
+                               : reinterpret_cast<float *>(tmp.data())[static_cast<size_t>(i) * n + j];
+  return CTAUX_OK;
+}
+
+int ctaux_get_decisions(ctaux_batch *h, int32_t chain, int64_t first, int64_t count, uint8_t *acc, double *R) {
+  if (!h || chain < 0 || chain >= h->b.n_chains || first < 0 || count < 0 || first + count > h->log_cap ||
+      (count > 0 && (!acc || !R)))
+    return h ? set_err(h, CTAUX_EINVAL, "decision range outside the log") : CTAUX_EINVAL;
+  if (count == 0) return CTAUX_OK;
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  HIPCHECK(h, hipMemcpy(acc, h->desc[chain].log_acc + first, count, hipMemcpyDeviceToHost));
+  HIPCHECK(h, hipMemcpy(R, h->desc[chain].log_R + first, sizeof(double) * count, hipMemcpyDeviceToHost));
+  return CTAUX_OK;
+}
+
+int ctaux_set_timing(ctaux_batch *h, int32_t enable) {
+  if (!h) return CTAUX_EINVAL;
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  flush_timing(h);
+  h->timing = enable != 0;
+  for (int i = 0; i < kNumNames; ++i) {
+    h->ms[i] = 0.0;
+    h->launches[i] = 0;
+  }
+  return CTAUX_OK;
+}
+
+int32_t ctaux_get_timing(ctaux_batch *h, const char **names, double *ms, int64_t *launches, int32_t cap) {
+  if (!h) return 0;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return 0;
+  flush_timing(h);
+  int32_t k = 0;
+  for (int i = 0; i < kNumNames && k < cap; ++i, ++k) {
+    if (names) names[k] = kKernelNames[i];
+    if (ms) ms[k] = h->ms[i];
+    if (launches) launches[k] = h->launches[i];
+  }
+  return k;
+}
+
+const char *ctaux_last_error(const ctaux_batch *h) { return h ? h->err.c_str() : g_create_error; }
+
+void ctaux_destroy(ctaux_batch *h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (TimedEvent &e : h->pool) {
+    (void)hipEventDestroy(e.start);
+    (void)hipEventDestroy(e.stop);
+  }
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Device helpers: counter-based random numbers, G0 interpolation, G entries.
+#pragma once
+
+#include "ctaux_internal.h"
+
+namespace ctaux {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// multiply-xor bijection with Weyl-sequence key bumps.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    uint32_t lo0 = m0 * c[0], hi0 = __umulhi(m0, c[0]);
+    uint32_t lo1 = m1 * c[2], hi1 = __umulhi(m1, c[2]);
+    uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+}
+
+// 53-bit uniform in [0, 1) from two 32-bit words (high word first).
+__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
+  uint64_t x = (static_cast<uint64_t>(hi) << 32) | lo;
+  return static_cast<double>(x >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// The five uniforms of proposal `index` of a chain: counter (index lo, index
+// hi, chain, tag), key = seed; tag 0 -> (type, accept), 1 -> (tau, pick),
+// 2 -> (spin, unused).
+__device__ __forceinline__ void proposal_uniforms(const ChainDesc &d, uint64_t index, double u[5]) {
+  uint32_t c[4];
+  c[0] = static_cast<uint32_t>(index); c[1] = static_cast<uint32_t>(index >> 32);
+  c[2] = d.chain_id; c[3] = 0;
+  philox4x32_10(c, d.seed_lo, d.seed_hi);
+  u[0] = u53(c[0], c[1]); u[1] = u53(c[2], c[3]);
+  c[0] = static_cast<uint32_t>(index); c[1] = static_cast<uint32_t>(index >> 32);
+  c[2] = d.chain_id; c[3] = 1;
+  philox4x32_10(c, d.seed_lo, d.seed_hi);
+  u[2] = u53(c[0], c[1]); u[3] = u53(c[2], c[3]);
+  c[0] = static_cast<uint32_t>(index); c[1] = static_cast<uint32_t>(index >> 32);
+  c[2] = d.chain_id; c[3] = 2;
+  philox4x32_10(c, d.seed_lo, d.seed_hi);
+  u[4] = u53(c[0], c[1]);
+}
+
+// Bare propagator G0_{xy}(dtau): linear interpolation on the uniform grid,
+// dtau in (-beta, beta); dtau < 0 uses G0(dtau) = -G0(dtau + beta); dtau = 0
+// reads the 0+ entry.
+__device__ __forceinline__ double g0_interp(const ChainDesc &d, int sec, int x, int y, double dtau) {
+  const double *tab = d.g0[sec] + static_cast<int64_t>(d.site_disp[x * d.nc + y]) * d.n_tau;
+  double sgn = 1.0;
+  if (dtau < 0.0) { dtau += d.beta; sgn = -1.0; }
+  double xx = dtau * d.inv_h;
+  int m = static_cast<int>(floor(xx));
+  m = m < 0 ? 0 : (m > d.n_tau - 2 ? d.n_tau - 2 : m);
+  double w = xx - static_cast<double>(m);
+  return sgn * ((1.0 - w) * tab[m] + w * tab[m + 1]);
+}
+
+template <typename T>
+__device__ __forceinline__ double ld_as_double(const T *p) { return static_cast<double>(*p); }
+
+// Entry G_ij of the block-start Green's function matrix G = N_a G0 of the
+// augmented configuration (old vertices 0..n-1, candidates n..n+k_ins-1).
+//  old column j (V_j != 0):  G_ij = (N_a,ij e^{V_j} - delta_ij) / (e^{V_j} - 1)   (Eq. NfromG)
+//     with N_a,ij = N_ij (old row) or Rt_{i-n, j} (candidate row);
+//  candidate column j:       G_ij = (N Z)_{i, j-n} (old row) or (X Y + G0nn)_{i-n, j-n}.
+template <typename T>
+__device__ __forceinline__ double g_entry(const ChainDesc &d, const T *N, const int32_t *s0, int n,
+                                          int sec, int i, int j) {
+  if (j < n) {
+    const double e = d.evd[sec][s0[j] + 2];
+    const double nij = (i < n) ? static_cast<double>(N[static_cast<size_t>(i) * d.ld + j])
+                               : d.Rt[sec][static_cast<size_t>(i - n) * d.ld + j];
+    return (nij * e - (i == j ? 1.0 : 0.0)) / (e - 1.0);
+  }
+  const int jj = j - n;
+  return (i < n) ? d.YT[sec][static_cast<size_t>(jj) * d.ld + i]
+                 : d.Gnn[sec][static_cast<size_t>(i - n) * d.kmax + jj];
+}
+
+// Entry of the augmented block-start N_a = [[N, 0], [Rt, 1]].
+template <typename T>
+__device__ __forceinline__ double na_entry(const ChainDesc &d, const T *N, int n, int sec, int i, int j) {
+  if (i < n) return (j < n) ? static_cast<double>(N[static_cast<size_t>(i) * d.ld + j]) : 0.0;
+  if (j < n) return d.Rt[sec][static_cast<size_t>(i - n) * d.ld + j];
+  return (i == j) ? 1.0 : 0.0;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace ctaux

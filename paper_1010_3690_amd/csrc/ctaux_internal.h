@@ -1,0 +1,136 @@
+// Internal structures of the gfx950 CT-AUX submatrix library.
+//
+// One "chain" is an independent Markov chain.  Every per-chain buffer lives
+// in the caller's device workspace; ChainDesc holds the pointers (fixed at
+// creation) and ChainState the evolving scalars.  All kernels take the batch
+// arrays and find their chain from the grid, so one launch serves every
+// chain of a batch (the batched form) and a single chain alike.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ctaux {
+
+constexpr int kMaxKcap = 64;    // Gamma capacity per block (Gamma^{-1} of both sectors in LDS)
+constexpr int kMaxKmax = 128;   // proposals per block
+constexpr int kTile = 64;       // rank-k output tile edge
+
+enum Precision : int32_t { kFP64 = 0, kFP32 = 1 };
+
+struct ChainDesc {
+  // ---- model (Sec. II A) ----
+  double beta, K, gamma, inv_h, p_flip;
+  double evd[2][5];        // exp(gamma*sigma*d), d = -2..2 (index d+2); sigma = +1 up, -1 down
+  int32_t nc, n_tau, n_disp;
+  int32_t lda;             // leading dimension of Ac rows (k_cap rounded up to 8)
+  const double *g0[2];     // tables [n_disp*n_tau] per sector
+  const int32_t *site_disp;  // [nc*nc]
+  // ---- geometry of the per-chain buffers ----
+  int32_t n_cap;           // max order
+  int32_t ld;              // leading dimension of N, X, ZT, YT, Rt, Bc (>= n_cap)
+  int32_t kmax, kcap;
+  int32_t meas_every, n_out;
+  int64_t n_therm;
+  uint32_t seed_lo, seed_hi, chain_id;
+  int32_t precision;
+  int64_t log_cap;
+  // ---- buffers ----
+  void *N[2][2];           // [parity][sector], ld x ld, double or float
+  double *tau[2];          // [parity][n_cap]
+  int32_t *site[2];
+  int32_t *s0[2];
+  int64_t *id[2];
+  // block proposals (decoded)
+  int32_t *ptype;          // [kmax] 0 ins, 1 rem, 2 flip
+  int32_t *pspin;          // [kmax] spin of an insertion (+-1)
+  double *pacc;            // [kmax] u_acc
+  double *ppick;           // [kmax] u_pick
+  double *ctau;            // [kmax] candidate times
+  int32_t *csite;          // [kmax] candidate sites
+  int64_t *cid;            // [kmax] ids given to accepted candidates
+  // preparation products, FP64, per sector
+  double *X[2];            // [kmax][ld]  X_ji = G0(tau_j^new - tau_i)(e^{V_i} - 1)
+  double *ZT[2];           // [kmax][ld]  ZT_ji = G0(tau_i - tau_j^new)
+  double *G0nn[2];         // [kmax][kmax]
+  double *YT[2];           // [kmax][ld]  (N Z)^T: G of old rows, new columns
+  double *Rt[2];           // [kmax][ld]  X N: rows of the augmented N for new vertices
+  double *Gnn[2];          // [kmax][kmax] X Y + G0nn: G of new rows, new columns
+  // Gamma bookkeeping of the block
+  int32_t *P;              // [kcap] augmented index of each accepted change
+  double *ghat[2];         // [kcap]
+  double *Gam[2];          // [kcap][kcap] Gamma entries of the accepted changes
+  double *Ginv[2];         // [kcap][kcap] Gamma^{-1} (pivoted inversion at block end)
+  int32_t *map;            // [n_cap] new canonical index -> augmented index
+  // rank-k operands (storage type of N)
+  void *Ac[2];             // [ld rows][lda]  (G - I)_{map, P}
+  void *Bc[2];             // [lda][ld]       Gamma^{-1} N_a(P, map)
+  // measurement
+  double *W[2];            // [n_cap][nc]  (e^V - 1) N gR
+  double *gR[2];           // [n_cap][nc]  G0_{x_k y}(tau_k)
+  double *Gxy[2];          // [(n_out+1)][nc*nc]  row 0 = equal time
+  const int32_t *cls_off;  // [n_disp+1] pairs (x*nc+y) of each table, CSR offsets
+  const int32_t *cls_pairs;  // [nc*nc]
+  double *obs;             // accumulators
+  int32_t obs_len;
+  int32_t pad1;
+  // decision log
+  uint8_t *log_acc;        // [log_cap]
+  double *log_R;           // [log_cap]
+};
+
+struct ChainState {
+  int32_t n;           // order at block start
+  int32_t k_ins;       // insertion candidates drawn for this block
+  int32_t L;           // proposals drawn for this block
+  int32_t L_eff;       // proposals processed in this block
+  int32_t k_a;         // accepted changes (size of Gamma)
+  int32_t n_new;       // order after the block
+  int32_t parity;      // current buffer set
+  int32_t status;      // 0 or negative error code
+  int32_t meas_now;    // 1: measure after this block
+  int32_t active;      // 1: the chain runs this block
+  int64_t done;        // proposals processed
+  int64_t target;      // run until done == target
+  int64_t next_id;
+  int64_t accepted;
+  int64_t blocks;
+  int64_t sum_ka;
+  double sign;
+  double max_drift;
+  double last_drift;
+  int64_t err_index;   // proposal index of a failure
+};
+
+// Kernel launchers (each .hip file owns its kernels).
+struct Batch;
+void launch_block_begin(const Batch &b, hipStream_t s);
+void launch_interp(const Batch &b, hipStream_t s);
+void launch_prep(const Batch &b, hipStream_t s);
+void launch_propose(const Batch &b, hipStream_t s);
+void launch_assemble(const Batch &b, hipStream_t s);
+void launch_gamma_inv(const Batch &b, hipStream_t s);
+void launch_tile_scan(const Batch &b, hipStream_t s);
+void launch_rankk(const Batch &b, hipStream_t s);
+void launch_block_end(const Batch &b, hipStream_t s);
+void launch_measure(const Batch &b, hipStream_t s);
+void launch_refine(const Batch &b, hipStream_t s, int32_t chain);
+void launch_set_target(const Batch &b, hipStream_t s, int64_t n_proposals);
+
+// Host-side view of a batch used by the launchers.
+struct Batch {
+  int32_t n_chains;
+  int32_t kmax, kcap, n_cap, ld, nc_max, n_out_max;
+  int32_t precision;
+  int32_t grid_per_chain;    // workgroups per chain for per-chain streaming kernels
+  ChainDesc *d_desc;         // device [n_chains]
+  ChainState *d_state;       // device [n_chains]
+  // rank-k tile scheduler
+  int32_t *d_tile_prefix;    // device [n_chains+1]
+  int32_t n_cu;
+  // refinement scratch (one chain at a time), FP64
+  double *r_M, *r_R, *r_N;   // [ld*ld] each
+  double *r_red;             // [2*1024] partial sums for the drift
+};
+
+}  // namespace ctaux

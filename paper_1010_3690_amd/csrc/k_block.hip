@@ -1,0 +1,158 @@
+// Block set-up and tear-down: proposal draws, pre-insertion of the block's
+// insertion candidates, G0 interpolation for the candidates (Sec. IV A), and
+// the end-of-block bookkeeping.
+#include "ctaux_device.h"
+
+namespace ctaux {
+
+__global__ void k_set_target(ChainState *states, int n_chains, int64_t n_proposals) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n_chains) states[c].target = states[c].done + n_proposals;
+}
+
+void launch_set_target(const Batch &b, hipStream_t s, int64_t n_proposals) {
+  hipLaunchKernelGGL(k_set_target, dim3((b.n_chains + 255) / 256), dim3(256), 0, s, b.d_state,
+                     b.n_chains, n_proposals);
+}
+
+// One workgroup per chain.  Decides the block length (at most k_max, never
+// past a measurement point), decodes the block's proposals and collects the
+// insertion candidates in proposal order.
+__global__ __launch_bounds__(256) void k_block_begin(const ChainDesc *descs, ChainState *states) {
+  const int c = blockIdx.x;
+  const ChainDesc &d = descs[c];
+  ChainState &st = states[c];
+  __shared__ int sh_L, sh_active;
+  __shared__ int scan[256];
+  if (threadIdx.x == 0) {
+    int active = (st.status == 0 && st.done < st.target) ? 1 : 0;
+    int64_t L = 0;
+    if (active) {
+      L = st.target - st.done;
+      if (L > d.kmax) L = d.kmax;
+      int64_t m = (st.done / d.meas_every + 1) * d.meas_every;
+      if (m <= d.n_therm) m = (d.n_therm / d.meas_every + 1) * d.meas_every;
+      if (m - st.done < L) L = m - st.done;
+    }
+    st.active = active;
+    st.L = static_cast<int>(L);
+    st.L_eff = 0;
+    st.k_a = 0;
+    st.meas_now = 0;
+    sh_L = static_cast<int>(L);
+    sh_active = active;
+  }
+  __syncthreads();
+  if (!sh_active) {
+    if (threadIdx.x == 0) st.k_ins = 0;
+    return;
+  }
+  const int L = sh_L;
+  const int t = threadIdx.x;
+  int is_ins = 0;
+  double tau = 0.0;
+  int site = 0;
+  if (t < L) {
+    double u[5];
+    proposal_uniforms(d, static_cast<uint64_t>(st.done + t), u);
+    const double p_ins = 0.5 * (1.0 - d.p_flip);
+    const int type = u[0] < p_ins ? 0 : (u[0] < 2.0 * p_ins ? 1 : 2);
+    d.ptype[t] = type;
+    d.pacc[t] = u[1];
+    d.ppick[t] = u[3];
+    if (type == 0) {
+      tau = d.beta * u[2];
+      site = static_cast<int>(floor(static_cast<double>(d.nc) * u[3]));
+      if (site > d.nc - 1) site = d.nc - 1;
+      d.pspin[t] = u[4] < 0.5 ? -1 : 1;
+      is_ins = 1;
+    } else {
+      d.pspin[t] = 0;
+    }
+  }
+  // exclusive prefix sum of the insertion flags (Hillis-Steele over 256 lanes)
+  scan[t] = is_ins;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int v = (t >= off) ? scan[t - off] : 0;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  if (is_ins) {
+    const int j = scan[t] - 1;
+    d.ctau[j] = tau;
+    d.csite[j] = site;
+  }
+  if (t == 255) st.k_ins = scan[255];
+}
+
+void launch_block_begin(const Batch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_begin, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_state);
+}
+
+// G0 products for the candidates (Sec. IV A, "Preparation steps"), per sector:
+//   X_ji  = G0(tau_j^new - tau_i)(e^{V_i} - 1)   (so that Rt = X N)
+//   ZT_ji = G0(tau_i - tau_j^new)                 (so that YT = (N Z)^T)
+//   G0nn_jj' = G0(tau_j^new - tau_j'^new)          (0+ on the diagonal)
+__global__ __launch_bounds__(256) void k_interp(const ChainDesc *descs, const ChainState *states) {
+  const int c = blockIdx.y;
+  const ChainDesc &d = descs[c];
+  const ChainState &st = states[c];
+  if (!st.active) return;
+  const int n = st.n, k = st.k_ins;
+  const int par = st.parity;
+  const double *tau = d.tau[par];
+  const int32_t *site = d.site[par];
+  const int32_t *s0 = d.s0[par];
+  const int64_t per_sec = 2ll * k * n + static_cast<int64_t>(k) * k;
+  const int64_t total = 2 * per_sec;
+  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
+    const int sec = static_cast<int>(e / per_sec);
+    int64_t r = e - sec * per_sec;
+    if (r < 2ll * k * n) {
+      const int which = static_cast<int>(r / (static_cast<int64_t>(k) * n));
+      r -= static_cast<int64_t>(which) * k * n;
+      const int j = static_cast<int>(r / n), i = static_cast<int>(r - static_cast<int64_t>(j) * n);
+      if (which == 0) {
+        const double ev = d.evd[sec][s0[i] + 2];
+        d.X[sec][static_cast<size_t>(j) * d.ld + i] =
+            g0_interp(d, sec, d.csite[j], site[i], d.ctau[j] - tau[i]) * (ev - 1.0);
+      } else {
+        d.ZT[sec][static_cast<size_t>(j) * d.ld + i] =
+            g0_interp(d, sec, site[i], d.csite[j], tau[i] - d.ctau[j]);
+      }
+    } else {
+      r -= 2ll * k * n;
+      const int j = static_cast<int>(r / k), jj = static_cast<int>(r - static_cast<int64_t>(j) * k);
+      d.G0nn[sec][static_cast<size_t>(j) * d.kmax + jj] =
+          g0_interp(d, sec, d.csite[j], d.csite[jj], d.ctau[j] - d.ctau[jj]);
+    }
+  }
+}
+
+void launch_interp(const Batch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_interp, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s, b.d_desc,
+                     b.d_state);
+}
+
+__global__ void k_block_end(const ChainDesc *descs, ChainState *states, int n_chains) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_chains) return;
+  ChainState &st = states[c];
+  if (!st.active) return;
+  const ChainDesc &d = descs[c];
+  st.n = st.n_new;
+  st.parity ^= 1;
+  st.done += st.L_eff;
+  st.blocks += 1;
+  st.sum_ka += st.k_a;
+  st.meas_now = (st.done % d.meas_every == 0 && st.done > d.n_therm) ? 1 : 0;
+}
+
+void launch_block_end(const Batch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_end, dim3((b.n_chains + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state,
+                     b.n_chains);
+}
+
+}  // namespace ctaux

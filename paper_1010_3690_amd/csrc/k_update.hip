@@ -1,0 +1,224 @@
+// End of a block (Sec. IV C, "Recompute step"): the accepted changes P with
+// Gamma^{-1} are applied to N in one rank-k update per sector,
+//   N' = N_a - (G - I)_{:,P} Gamma^{-1} N_a{P,:}                 (Eq. Nshermanmorrison,
+// equivalently D^{-1}(N - G_{:,P} Gamma^{-1} N_{P,:}) when every vertex changes once),
+// and rows / columns of spin-0 vertices are deleted while storing.
+//
+// k_assemble builds the compacted operands
+//   Ac[i'][a] = (G - I)_{map(i'), P_a}           (n' x k_a)
+//   Bc[a][j'] = sum_b Gamma^{-1}_{ab} N_a(P_b, map(j'))   (k_a x n')
+// and k_rankk computes N'[i'][j'] = N_a(map i', map j') - (Ac Bc)[i'][j'] on
+// MFMA 16x16x4 tiles (FP64, or FP32 for FP32 storage), 64x64 outputs per
+// workgroup, tiles of every chain scheduled from one persistent grid.
+#include "ctaux_device.h"
+
+namespace ctaux {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_assemble(const ChainDesc *descs, const ChainState *states) {
+  const int c = blockIdx.y;
+  const ChainDesc &d = descs[c];
+  const ChainState &st = states[c];
+  if (!st.active) return;
+  const int n = st.n, np = st.n_new, ka = st.k_a;
+  if (ka == 0 || np == 0) return;
+  const int kpad = (ka + 7) & ~7;
+  const int par = st.parity;
+  const int32_t *s0 = d.s0[par];
+  const int64_t per_a = static_cast<int64_t>(np) * kpad;   // Ac entries per sector
+  const int64_t per_sec = 2 * per_a;
+  const int64_t total = 2 * per_sec;
+  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
+    const int sec = static_cast<int>(e / per_sec);
+    int64_t r = e - sec * per_sec;
+    const T *N = static_cast<const T *>(d.N[par][sec]);
+    if (r < per_a) {
+      // Ac: consecutive threads walk the k index of one row, then rows
+      const int i = static_cast<int>(r / kpad), a = static_cast<int>(r - static_cast<int64_t>(i) * kpad);
+      double v = 0.0;
+      if (a < ka) {
+        const int mi = d.map[i], pa = d.P[a];
+        v = g_entry<T>(d, N, s0, n, sec, mi, pa) - (mi == pa ? 1.0 : 0.0);
+      }
+      static_cast<T *>(d.Ac[sec])[static_cast<size_t>(i) * d.lda + a] = static_cast<T>(v);
+    } else {
+      r -= per_a;
+      const int a = static_cast<int>(r / np), j = static_cast<int>(r - static_cast<int64_t>(a) * np);
+      double v = 0.0;
+      if (a < ka) {
+        const int mj = d.map[j];
+        const double *gi = d.Ginv[sec] + static_cast<size_t>(a) * d.kcap;
+        for (int b = 0; b < ka; ++b) v += gi[b] * na_entry<T>(d, N, n, sec, d.P[b], mj);
+      }
+      static_cast<T *>(d.Bc[sec])[static_cast<size_t>(a) * d.ld + j] = static_cast<T>(v);
+    }
+  }
+}
+
+void launch_assemble(const Batch &b, hipStream_t s) {
+  if (b.precision == kFP64)
+    hipLaunchKernelGGL(k_assemble<double>, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s,
+                       b.d_desc, b.d_state);
+  else
+    hipLaunchKernelGGL(k_assemble<float>, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s,
+                       b.d_desc, b.d_state);
+}
+
+// Prefix sums of rank-k tiles over chains: chain c owns tiles
+// [prefix[c], prefix[c+1]), 2 sectors x ceil(n'/64)^2 each.
+__global__ __launch_bounds__(256) void k_tile_scan(const ChainState *states, int n_chains, int32_t *prefix) {
+  __shared__ int sh[256];
+  __shared__ int carry;
+  if (threadIdx.x == 0) { carry = 0; prefix[0] = 0; }
+  __syncthreads();
+  for (int base = 0; base < n_chains; base += 256) {
+    const int c = base + threadIdx.x;
+    int v = 0;
+    if (c < n_chains && states[c].active) {
+      const int nt = (states[c].n_new + kTile - 1) / kTile;
+      v = 2 * nt * nt;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int x = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (c < n_chains) prefix[c + 1] = carry + sh[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 255) carry += sh[255];
+    __syncthreads();
+  }
+}
+
+void launch_tile_scan(const Batch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, s, b.d_state, b.n_chains, b.d_tile_prefix);
+}
+
+template <typename T>
+struct Mfma;
+// Accumulator layouts (checked on gfx950 with a probe of D = A B): lane l holds
+// column l%16 of the 16x16 block; the FP64 instruction puts register q at row
+// l/16 + 4q, the FP32 instruction at row 4(l/16) + q.
+template <>
+struct Mfma<double> {
+  typedef v4d acc_t;
+  __device__ static int row(int lk, int q) { return lk + 4 * q; }
+  __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef v4f acc_t;
+  __device__ static int row(int lk, int q) { return 4 * lk + q; }
+  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// Base value N_a(map i', map j') in the storage type.
+template <typename T>
+__device__ __forceinline__ T base_entry(const ChainDesc &d, const T *N, const double *Rt, int n, int mi, int mj) {
+  if (mi < n) return (mj < n) ? N[static_cast<size_t>(mi) * d.ld + mj] : T(0);
+  if (mj < n) return static_cast<T>(Rt[static_cast<size_t>(mi - n) * d.ld + mj]);
+  return (mi == mj) ? T(1) : T(0);
+}
+
+// MFMA 16x16x4 operand layout (one 16x16 block): lane l supplies A[l%16][k0 + l/16]
+// and B[k0 + l/16][l%16]; accumulator register q holds D[Mfma<T>::row(l/16, q)][l%16].
+template <typename T>
+__global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const ChainState *states,
+                                               const int32_t *prefix, int n_chains) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int total = prefix[n_chains];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    // chain owning tile t (prefix is non-decreasing)
+    int lo = 0, hi = n_chains;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int c = lo;
+    const ChainDesc &d = descs[c];
+    const ChainState &st = states[c];
+    const int n = st.n, np = st.n_new, ka = st.k_a;
+    const int nt = (np + kTile - 1) / kTile;
+    int local = t - prefix[c];
+    const int sec = local / (nt * nt);
+    local -= sec * nt * nt;
+    const int ti = local / nt, tj = local - ti * nt;
+    const int par = st.parity;
+    const T *N = static_cast<const T *>(d.N[par][sec]);
+    T *Nout = static_cast<T *>(d.N[par ^ 1][sec]);
+    const T *Ac = static_cast<const T *>(d.Ac[sec]);
+    const T *Bc = static_cast<const T *>(d.Bc[sec]);
+    const double *Rt = d.Rt[sec];
+    const int row0 = ti * kTile + wr * 32, col0 = tj * kTile + wc * 32;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::zero();
+    if (ka > 0) {
+      const int kpad = (ka + 7) & ~7;
+      for (int k0 = 0; k0 < kpad; k0 += 4) {
+        T af[2], bf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int r = row0 + i * 16 + lr;
+          af[i] = (r < np) ? Ac[static_cast<size_t>(r) * d.lda + k0 + lk] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int cc = col0 + j * 16 + lr;
+          bf[j] = (cc < np) ? Bc[static_cast<size_t>(k0 + lk) * d.ld + cc] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::mma(af[i], bf[j], acc[i][j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int cc = col0 + j * 16 + lr;
+      if (cc >= np) continue;
+      const int mj = d.map[cc];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = row0 + i * 16 + Mfma<T>::row(lk, q);
+          if (r < np) {
+            const int mi = d.map[r];
+            const T base = base_entry<T>(d, N, Rt, n, mi, mj);
+            Nout[static_cast<size_t>(r) * d.ld + cc] = base - acc[i][j][q];
+          }
+        }
+      }
+    }
+  }
+}
+
+void launch_rankk(const Batch &b, hipStream_t s) {
+  const int grid = b.n_cu * 8;
+  if (b.precision == kFP64)
+    hipLaunchKernelGGL(k_rankk<double>, dim3(grid), dim3(256), 0, s, b.d_desc, b.d_state,
+                       b.d_tile_prefix, b.n_chains);
+  else
+    hipLaunchKernelGGL(k_rankk<float>, dim3(grid), dim3(256), 0, s, b.d_desc, b.d_state,
+                       b.d_tile_prefix, b.n_chains);
+}
+
+}  // namespace ctaux

@@ -1,0 +1,228 @@
+"""Python binding of libctaux_hip.so (the C ABI of include/ctaux.h).
+
+Marshalling only: every step of the Monte Carlo path runs in the HIP
+kernels of the library.  PyTorch provides the device workspace and the HIP
+stream.  Importing works without a GPU; creating a batch needs the built
+library and a GPU and raises otherwise (there is no CPU fallback).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libctaux_hip.so")
+
+CTAUX_OK, CTAUX_EINVAL, CTAUX_ENOMEM, CTAUX_EDEVICE, CTAUX_ENUMERIC, CTAUX_ECAPACITY = 0, -1, -2, -3, -4, -5
+CTAUX_FP64, CTAUX_FP32 = 0, 1
+OBS_HEADER = 8
+
+EXPORTED = [
+    "ctaux_workspace_bytes", "ctaux_create", "ctaux_run", "ctaux_recompute", "ctaux_obs_len",
+    "ctaux_get_obs", "ctaux_reset_obs", "ctaux_get_stats", "ctaux_get_config", "ctaux_get_N",
+    "ctaux_get_decisions", "ctaux_set_timing", "ctaux_get_timing", "ctaux_last_error", "ctaux_destroy",
+]
+
+
+class _Model(C.Structure):
+    _fields_ = [("beta", C.c_double), ("U", C.c_double), ("K", C.c_double), ("n_sites", C.c_int32),
+                ("n_tau", C.c_int32), ("n_disp", C.c_int32), ("site_disp", C.c_void_p),
+                ("g0_up", C.c_void_p), ("g0_dn", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("k_max", C.c_int32), ("k_cap", C.c_int32), ("p_flip", C.c_double),
+                ("recompute_every", C.c_int32), ("precision", C.c_int32), ("meas_every", C.c_int32),
+                ("n_therm", C.c_int64), ("n_tau_out", C.c_int32), ("n_cap", C.c_int32),
+                ("seed", C.c_uint64), ("log_cap", C.c_int64)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("proposals", C.c_int64), ("accepted", C.c_int64), ("blocks", C.c_int64),
+                ("sum_ka", C.c_int64), ("next_id", C.c_int64), ("order", C.c_int32),
+                ("status", C.c_int32), ("sign", C.c_double), ("max_drift", C.c_double)]
+
+
+class _Vertex(C.Structure):
+    _fields_ = [("id", C.c_int64), ("tau", C.c_double), ("site", C.c_int32), ("s", C.c_int32)]
+
+
+class CtauxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ctaux error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1010_3690_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.ctaux_workspace_bytes.restype = C.c_size_t
+    lib.ctaux_workspace_bytes.argtypes = [vp, i32, vp]
+    lib.ctaux_create.argtypes = [vp, i32, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.ctaux_run.argtypes = [vp, i64]
+    lib.ctaux_recompute.argtypes = [vp, C.POINTER(d)]
+    lib.ctaux_obs_len.restype = i32
+    lib.ctaux_obs_len.argtypes = [vp]
+    lib.ctaux_get_obs.argtypes = [vp, i32, vp, i32]
+    lib.ctaux_reset_obs.argtypes = [vp]
+    lib.ctaux_get_stats.argtypes = [vp, i32, C.POINTER(_Stats)]
+    lib.ctaux_get_config.argtypes = [vp, i32, i32, vp, C.POINTER(i32)]
+    lib.ctaux_get_N.argtypes = [vp, i32, i32, vp, i32, C.POINTER(i32)]
+    lib.ctaux_get_decisions.argtypes = [vp, i32, i64, i64, vp, vp]
+    lib.ctaux_set_timing.argtypes = [vp, i32]
+    lib.ctaux_get_timing.restype = i32
+    lib.ctaux_get_timing.argtypes = [vp, vp, vp, vp, i32]
+    lib.ctaux_last_error.restype = C.c_char_p
+    lib.ctaux_last_error.argtypes = [vp]
+    lib.ctaux_destroy.argtypes = [vp]
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Options:
+    k_max: int = 64
+    k_cap: int = 64
+    p_flip: float = 0.2
+    recompute_every: int = 64
+    precision: int = CTAUX_FP64
+    meas_every: int = 64
+    n_therm: int = 0
+    n_tau_out: int = 16
+    n_cap: int = 1024
+    seed: int = 0
+    log_cap: int = 0
+
+    def _c(self) -> _Opts:
+        return _Opts(self.k_max, self.k_cap, self.p_flip, self.recompute_every, self.precision,
+                     self.meas_every, self.n_therm, self.n_tau_out, self.n_cap, self.seed, self.log_cap)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class CtauxBatch:
+    """A batch of independent chains on one GPU (one chain is a batch of one)."""
+
+    def __init__(self, workloads, opts: Options, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("CtauxBatch needs a GPU; there is no CPU path")
+        if not isinstance(workloads, (list, tuple)):
+            workloads = [workloads]
+        self.workloads = list(workloads)
+        self.opts = opts
+        self.device = torch.device(device)
+        self._arrays = []
+        models = (_Model * len(workloads))()
+        for i, w in enumerate(workloads):
+            sd = np.ascontiguousarray(w.site_disp, np.int32)
+            gu = np.ascontiguousarray(w.g0_up, np.float64)
+            gd = np.ascontiguousarray(w.g0_dn, np.float64)
+            self._arrays += [sd, gu, gd]
+            models[i] = _Model(w.beta, w.U, w.K, w.n_sites, w.n_tau, w.n_disp, _ptr(sd), _ptr(gu),
+                               _ptr(gd))
+        self._models = models
+        self._copts = opts._c()
+        nbytes = self.lib.ctaux_workspace_bytes(C.byref(models), len(workloads), C.byref(self._copts))
+        if nbytes == 0:
+            raise CtauxError(CTAUX_EINVAL, self.lib.ctaux_last_error(None).decode())
+        self.workspace_bytes = int(nbytes)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = self.lib.ctaux_create(C.byref(models), len(workloads), C.byref(self._copts),
+                                   C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise CtauxError(rc, self.lib.ctaux_last_error(None).decode())
+        self.h = h
+        self.n_chains = len(workloads)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ctaux_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc != 0:
+            raise CtauxError(rc, self.lib.ctaux_last_error(self.h).decode())
+
+    def run(self, n_proposals: int):
+        self._check(self.lib.ctaux_run(self.h, int(n_proposals)))
+
+    def recompute(self) -> float:
+        d = C.c_double()
+        self._check(self.lib.ctaux_recompute(self.h, C.byref(d)))
+        return d.value
+
+    def obs(self, chain: int = 0) -> np.ndarray:
+        n = self.lib.ctaux_obs_len(self.h)
+        out = np.zeros(n)
+        self._check(self.lib.ctaux_get_obs(self.h, chain, _ptr(out), n))
+        w = self.workloads[chain]
+        return out[: OBS_HEADER + 2 * w.n_disp * self.opts.n_tau_out]
+
+    def reset_obs(self):
+        self._check(self.lib.ctaux_reset_obs(self.h))
+
+    def stats(self, chain: int = 0) -> dict:
+        s = _Stats()
+        self._check(self.lib.ctaux_get_stats(self.h, chain, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in _Stats._fields_}
+
+    def config(self, chain: int = 0):
+        n = C.c_int32()
+        self._check(self.lib.ctaux_get_config(self.h, chain, 0, None, C.byref(n)))
+        buf = (_Vertex * max(n.value, 1))()
+        self._check(self.lib.ctaux_get_config(self.h, chain, n.value, buf, C.byref(n)))
+        m = n.value
+        return (np.array([buf[i].id for i in range(m)], np.int64),
+                np.array([buf[i].tau for i in range(m)]),
+                np.array([buf[i].site for i in range(m)], np.int32),
+                np.array([buf[i].s for i in range(m)], np.int32))
+
+    def N(self, chain: int = 0, sector: int = 0) -> np.ndarray:
+        n = C.c_int32()
+        self._check(self.lib.ctaux_get_N(self.h, chain, sector, None, 0, C.byref(n)))
+        out = np.zeros((n.value, n.value))
+        if n.value:
+            self._check(self.lib.ctaux_get_N(self.h, chain, sector, _ptr(out), n.value, C.byref(n)))
+        return out
+
+    def decisions(self, chain: int, first: int, count: int):
+        acc = np.zeros(count, np.uint8)
+        R = np.zeros(count)
+        self._check(self.lib.ctaux_get_decisions(self.h, chain, first, count, _ptr(acc), _ptr(R)))
+        return acc, R
+
+    def set_timing(self, enable: bool):
+        self._check(self.lib.ctaux_set_timing(self.h, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        cap = 32
+        names = (C.c_char_p * cap)()
+        ms = np.zeros(cap)
+        cnt = np.zeros(cap, np.int64)
+        k = self.lib.ctaux_get_timing(self.h, names, _ptr(ms), _ptr(cnt), cap)
+        return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}

@@ -1,0 +1,80 @@
+"""The C-ABI library loads, exports what include/ctaux.h declares and
+validates arguments on the host (no GPU needed, no compute call made)."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from ctaux_inputs import dca_square
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1010_3690_amd import ctaux
+    if not os.path.exists(ctaux.LIB_PATH):
+        from paper_1010_3690_amd.build import build
+        build()
+    return ctaux.load_library()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ctaux.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ctaux_\w+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1010_3690_amd import ctaux
+    out = subprocess.run(["nm", "-D", "--defined-only", ctaux.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (ctaux_\w+)", out))
+    declared = _declared()
+    assert len(declared) >= 15
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    assert set(ctaux.EXPORTED) == set(declared)
+
+
+def _model_and_opts(ctaux, **over):
+    w = dca_square(L=2, beta=2.0, U=4.0, n_tau=256, n_fine=8)
+    sd = np.ascontiguousarray(w.site_disp, np.int32)
+    g = np.ascontiguousarray(w.g0_up)
+    m = ctaux._Model(w.beta, w.U, w.K, w.n_sites, w.n_tau, w.n_disp, sd.ctypes.data, g.ctypes.data,
+                     g.ctypes.data)
+    o = ctaux.Options(**over)._c()
+    return m, o, (sd, g)
+
+
+def test_workspace_bytes_and_validation(lib):
+    from paper_1010_3690_amd import ctaux
+    m, o, keep = _model_and_opts(ctaux, n_cap=256)
+    nb = lib.ctaux_workspace_bytes(C.byref(m), 1, C.byref(o))
+    assert nb > 4 * 256 * 256 * 8          # four FP64 N buffers at least
+    m2, o2, keep2 = _model_and_opts(ctaux, n_cap=256, precision=ctaux.CTAUX_FP32)
+    assert lib.ctaux_workspace_bytes(C.byref(m2), 1, C.byref(o2)) < nb
+    for bad in (dict(k_max=0), dict(k_max=129), dict(k_cap=65), dict(k_cap=8, k_max=4), dict(p_flip=1.5),
+                dict(precision=7), dict(n_cap=0), dict(meas_every=0)):
+        mb, ob, kb = _model_and_opts(ctaux, **bad)
+        assert lib.ctaux_workspace_bytes(C.byref(mb), 1, C.byref(ob)) == 0, bad
+    # a non-finite table entry is rejected
+    g = keep[1].copy()
+    g[0, 3] = np.inf
+    m.g0_up = g.ctypes.data
+    assert lib.ctaux_workspace_bytes(C.byref(m), 1, C.byref(o)) == 0
+    assert b"non-finite" in lib.ctaux_last_error(None)
+
+
+def test_create_rejects_small_workspace(lib):
+    from paper_1010_3690_amd import ctaux
+    m, o, keep = _model_and_opts(ctaux, n_cap=64)
+    h = C.c_void_p()
+    rc = lib.ctaux_create(C.byref(m), 1, C.byref(o), None, 0, None, C.byref(h))
+    assert rc == ctaux.CTAUX_ENOMEM
+    assert not h.value
+    assert b"workspace" in lib.ctaux_last_error(None)
