@@ -1,0 +1,240 @@
+#!/usr/bin/env python
+"""Throughput of the CT-AUX submatrix path on one MI355X.
+
+Workload (step = one block: k_max = 64 proposals, the Gamma inner loop, the
+rank-k update of N in both spin sectors, the measurement, and every 64 blocks
+the FP64 refinement of N): 2D Hubbard DCA cluster 4x4 (Nc = 16), t = 1, U = 8,
+beta = 8, <n> = 0.9, cluster G0(tau) from the coarse-grained square-lattice
+dispersion on 8192 points, one chain, FP64 plain submatrix, K = 600 so that
+the mean order is ~1000.  Inputs are synthetic and resident in HBM before the
+timed region.
+
+Prints one JSON line: vertex updates/s (proposals processed, accepted or not),
+the rank-k TFLOP/s, the roofline of the dominant kernel (per-launch device
+time from HIP events on the library's stream over the timed region), and the
+CPU oracle timed on a bounded sample of the same workload.
+
+Extra legs (--legs): "mixed" runs the same chain with FP32 storage and the FP32
+MFMA rank-k update; "batched" runs 512 independent chains of mixed clusters.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3
+
+METRIC = "vertex updates/s + rank-k TFLOP/s, mixed/batched vs plain FP64, same GPU"
+
+
+def cfg2_workload():
+    from ctaux_inputs import dca_square
+    return dca_square(L=4, beta=8.0, U=8.0, K=600.0, density=0.9, n_tau=8192, t=1.0, n_fine=64)
+
+
+def _opts(ctaux, precision, n_cap=2048, k=64):
+    return ctaux.Options(k_max=k, k_cap=k, p_flip=0.2, recompute_every=64, precision=precision,
+                         meas_every=k, n_therm=0, n_tau_out=16, n_cap=n_cap, seed=0)
+
+
+def timed_run(gb, steps, k, n_chains=1):
+    """Run `steps` blocks on every chain with per-kernel HIP-event timing."""
+    import torch
+    s0 = [gb.stats(c) for c in range(n_chains)]
+    gb.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gb.run(steps * k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = gb.timing()
+    gb.set_timing(False)
+    s1 = [gb.stats(c) for c in range(n_chains)]
+    d = {key: sum(s1[c][key] - s0[c][key] for c in range(n_chains))
+         for key in ("proposals", "accepted", "blocks", "sum_ka", "rankk_flops", "rankk_bytes",
+                     "sum_order")}
+    d["seconds"] = t1 - t0
+    d["timing"] = timing
+    d["order_now"] = [s1[c]["order"] for c in range(n_chains)]
+    d["max_drift"] = max(s1[c]["max_drift"] for c in range(n_chains))
+    return d
+
+
+def roofline(d, precision):
+    """Roofline of the dominant kernel of the timed region."""
+    tm = d["timing"]
+    name = max(tm, key=lambda k: tm[k][0])
+    ms, launches = tm[name]
+    out = {"kernel": name, "share": ms / sum(v[0] for v in tm.values())}
+    if name == "rankk":
+        per_launch_bytes = d["rankk_bytes"] / max(launches, 1)
+        avg_s = ms / 1e3 / max(launches, 1)
+        achieved = per_launch_bytes / avg_s / 1e9
+        out.update({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None})
+    else:
+        # The proposal loop is one workgroup per chain running k dependent
+        # proposals; its work per launch is the gathered G entries and the
+        # O(k_a^2) Gamma^{-1} arithmetic.  Report it against the FP64 vector
+        # peak of the compute units it occupies (one per chain).
+        ka = d["sum_ka"] / max(d["blocks"], 1)
+        k = d["proposals"] / max(d["blocks"], 1)
+        # per proposal and sector: 2 matvecs with Gamma^{-1} (2*ka^2 each) and
+        # one rank-1 growth (2*ka^2) for the accepted fraction
+        acc_frac = ka / max(k, 1)
+        flops_launch = d["proposals"] / max(launches, 1) * 2 * (4 * ka * ka / 4 + acc_frac * 2 * ka * ka / 4)
+        avg_s = ms / 1e3 / max(launches, 1)
+        achieved = flops_launch / avg_s / 1e12
+        n_chains = d.get("n_chains", 1)
+        peak = FP64_PEAK_TFS * n_chains / 256.0
+        out.update({"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "traffic": None})
+    return out
+
+
+def cpu_baseline(w, config, budget_s=15.0):
+    """The oracle (rank-1 CT-AUX, one core) on a bounded sample of the workload:
+    it starts from the GPU chain's thermalised configuration and runs
+    proposals until about budget_s seconds have elapsed."""
+    from oracle import OracleChain
+    ids, tau, site, s = config
+    oc = OracleChain(w, seed=12345, meas_every=64, n_tau_out=16, n_cap=4096)
+    oc.set_config(ids, tau, site, s)
+    oc.set_state(0, int(ids.max()) + 1 if len(ids) else 0, 1.0)
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        oc.run(16)
+        done += 16
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "vertex updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} proposals of the same chain from a thermalised order-{len(ids)} "
+                      f"configuration, {el:.1f} s on one host core"}
+
+
+def leg_plain(args, precision):
+    import torch
+    from paper_1010_3690_amd import ctaux
+    w = cfg2_workload()
+    gb = ctaux.CtauxBatch([w], _opts(ctaux, precision))
+    gb.run(args.warmup * 64)
+    torch.cuda.synchronize()
+    d = timed_run(gb, args.steps, 64)
+    return w, gb, d
+
+
+def leg_batched(args):
+    import torch
+    from ctaux_inputs import batched_mix
+    from paper_1010_3690_amd import ctaux
+    ws = batched_mix(n_chains=args.batch_chains, seed=0, n_tau=2048, n_fine=16)
+    gb = ctaux.CtauxBatch(ws, ctaux.Options(k_max=64, k_cap=64, recompute_every=64,
+                                            precision=ctaux.CTAUX_FP32, meas_every=64,
+                                            n_tau_out=8, n_cap=2048, seed=0))
+    gb.run(args.batch_warmup * 64)
+    torch.cuda.synchronize()
+    d = timed_run(gb, args.batch_steps, 64, n_chains=len(ws))
+    d["n_chains"] = len(ws)
+    return d
+
+
+def summary(d):
+    tm = d["timing"]
+    rk_s = (tm.get("assemble", (0, 0))[0] + tm.get("rankk", (0, 0))[0]) / 1e3
+    return {
+        "updates_per_s": d["proposals"] / d["seconds"],
+        "accepted_per_s": d["accepted"] / d["seconds"],
+        "rankk_tflops": d["rankk_flops"] / rk_s / 1e12 if rk_s > 0 else None,
+        "mean_order": d["sum_order"] / max(d["blocks"], 1),
+        "mean_ka": d["sum_ka"] / max(d["blocks"], 1),
+        "ms_per_block": d["seconds"] * 1e3 / max(d["blocks"], 1),
+        "kernel_ms": {k: round(v[0], 3) for k, v in tm.items()},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--legs", default="plain", help="comma list of plain,mixed,batched")
+    ap.add_argument("--batch-chains", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-warmup", type=int, default=30)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: independent Markov chains shard across GPUs with no "
+              "communication on the hot path, and this build measures one GPU's share.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_1010_3690_amd import ctaux
+
+    legs = [x.strip() for x in args.legs.split(",") if x.strip()]
+    print(f"[bench] plain FP64 leg: warmup {args.warmup} blocks, timed {args.steps} blocks", file=sys.stderr,
+          flush=True)
+    w, gb, d = leg_plain(args, ctaux.CTAUX_FP64)
+    s = summary(d)
+    roof = roofline(d, ctaux.CTAUX_FP64)
+    out = {
+        "metric": METRIC,
+        "value": s["updates_per_s"],
+        "unit": "vertex updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": s["ms_per_block"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D Hubbard DCA 4x4 cluster (Nc=16), t=1, U=8, beta=8, <n>=0.9, "
+                               "coarse-grained G0 on 8192 tau points, K=600, one chain, FP64 plain "
+                               "submatrix, k=64, step = one block of 64 proposals",
+                   "k": 64, "mean_order": s["mean_order"], "mean_accepted_per_block": s["mean_ka"]},
+        "rankk_tflops": s["rankk_tflops"],
+        "accepted_per_s": s["accepted_per_s"],
+        "kernel_ms": s["kernel_ms"],
+        "roofline": roof,
+    }
+    forms = {"plain_fp64": {k: s[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}}
+    if "mixed" in legs:
+        print("[bench] mixed FP32 leg", file=sys.stderr, flush=True)
+        _, gbm, dm = leg_plain(args, ctaux.CTAUX_FP32)
+        sm = summary(dm)
+        forms["mixed_fp32"] = {k: sm[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}
+        forms["mixed_fp32"]["max_refinement_drift"] = dm["max_drift"]
+        gbm.close()
+    if "batched" in legs:
+        print(f"[bench] batched leg: {args.batch_chains} chains", file=sys.stderr, flush=True)
+        db = leg_batched(args)
+        sb = summary(db)
+        forms["batched_fp32"] = {k: sb[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}
+        forms["batched_fp32"]["n_chains"] = args.batch_chains
+        forms["batched_fp32"]["roofline"] = roofline(db, ctaux.CTAUX_FP32)
+        forms["batched_fp32"]["kernel_ms"] = sb["kernel_ms"]
+    out["forms"] = forms
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, gb.config(0), args.cpu_budget)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

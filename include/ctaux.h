@@ -99,6 +99,11 @@ typedef struct {
     int32_t status;           /* 0 or the CTAUX_E* code that stopped the chain */
     double sign;              /* sign of the current configuration weight    */
     double max_drift;         /* largest refinement drift seen (see ctaux_recompute) */
+    double rankk_flops;       /* algorithmic flops of the rank-k updates so far (both sectors:
+                                 2 n'^2 k_a + 2 k_a^2 n' each, n' = order after the block)   */
+    double rankk_bytes;       /* algorithmic HBM bytes of the rank-k updates so far (read and
+                                 write n'^2 entries of N, read the n' x k_a operands)          */
+    double sum_order;         /* sum over blocks of the order after the block                */
 } ctaux_stats;
 
 /* One vertex of a configuration (tau in [0, beta), site in [0, n_sites), s = +-1). */

@@ -452,6 +452,9 @@ int ctaux_get_stats(ctaux_batch *h, int32_t chain, ctaux_stats *out) {
   out->status = st.status;
   out->sign = st.sign;
   out->max_drift = st.max_drift;
+  out->rankk_flops = st.rk_flops;
+  out->rankk_bytes = st.rk_bytes;
+  out->sum_order = st.sum_order;
   return CTAUX_OK;
 }
 

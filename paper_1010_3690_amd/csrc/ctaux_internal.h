@@ -100,6 +100,9 @@ struct ChainState {
   double max_drift;
   double last_drift;
   int64_t err_index;   // proposal index of a failure
+  double rk_flops;     // algorithmic flops of operand assembly + rank-k update, summed over blocks
+  double rk_bytes;     // algorithmic HBM bytes of the rank-k update (read N_a, write N', read Ac, Bc)
+  double sum_order;    // sum over blocks of the order after the block
 };
 
 // Kernel launchers (each .hip file owns its kernels).

@@ -142,6 +142,13 @@ __global__ void k_block_end(const ChainDesc *descs, ChainState *states, int n_ch
   ChainState &st = states[c];
   if (!st.active) return;
   const ChainDesc &d = descs[c];
+  // algorithmic work of the update per sector: Bc = Gamma^{-1} N_P (2 k^2 n') and
+  // N' = N - Ac Bc (2 n'^2 k); bytes: read and write n'^2 entries of N plus Ac and Bc
+  const double np = st.n_new, ka = st.k_a;
+  const double es = d.precision == kFP64 ? 8.0 : 4.0;
+  st.rk_flops += 2.0 * (2.0 * np * np * ka + 2.0 * ka * ka * np);
+  st.rk_bytes += 2.0 * es * (2.0 * np * np + 2.0 * np * ka);
+  st.sum_order += np;
   st.n = st.n_new;
   st.parity ^= 1;
   st.done += st.L_eff;

@@ -44,7 +44,8 @@ class _Opts(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("proposals", C.c_int64), ("accepted", C.c_int64), ("blocks", C.c_int64),
                 ("sum_ka", C.c_int64), ("next_id", C.c_int64), ("order", C.c_int32),
-                ("status", C.c_int32), ("sign", C.c_double), ("max_drift", C.c_double)]
+                ("status", C.c_int32), ("sign", C.c_double), ("max_drift", C.c_double),
+                ("rankk_flops", C.c_double), ("rankk_bytes", C.c_double), ("sum_order", C.c_double)]
 
 
 class _Vertex(C.Structure):
