@@ -33,14 +33,8 @@ def fermi_weight(eps, tau, beta: float) -> np.ndarray:
     """
     eps = np.asarray(eps, dtype=np.float64)
     tau = np.asarray(tau, dtype=np.float64)
-    eps, tau = np.broadcast_arrays(eps, tau)
-    out = np.empty(eps.shape, dtype=np.float64)
-    pos = eps >= 0.0
-    e, t = eps[pos], tau[pos]
-    out[pos] = np.exp(-t * e) / (1.0 + np.exp(-beta * e))
-    e, t = eps[~pos], tau[~pos]
-    out[~pos] = np.exp((beta - t) * e) / (np.exp(beta * e) + 1.0)
-    return out
+    # exponent -tau*eps - log(1 + e^{-beta*eps}) <= 0 for 0 <= tau <= beta
+    return np.exp(-tau * eps - np.logaddexp(0.0, -beta * eps))
 
 
 def semicircle_g0(beta: float, n_tau: int, mu_tilde: float = 0.0,
@@ -105,7 +99,17 @@ def _reduce(points: np.ndarray, a: np.ndarray) -> np.ndarray:
     return np.rint(f @ a).astype(np.int64)
 
 
+_CLUSTER_CACHE: dict = {}
+
+
 def make_cluster(superlattice) -> Cluster:
+    key = tuple(map(tuple, np.asarray(superlattice, dtype=np.int64).tolist()))
+    if key not in _CLUSTER_CACHE:
+        _CLUSTER_CACHE[key] = _make_cluster(superlattice)
+    return _CLUSTER_CACHE[key]
+
+
+def _make_cluster(superlattice) -> Cluster:
     a = np.asarray(superlattice, dtype=np.int64)
     d = a.shape[0]
     nc = int(round(abs(np.linalg.det(a.astype(np.float64)))))
@@ -145,8 +149,18 @@ def _dispersion(k: np.ndarray, t: float) -> np.ndarray:
     return -2.0 * t * np.cos(k).sum(axis=-1)
 
 
+_PATCH_CACHE: dict = {}
+
+
 def _patch_weights(cluster: Cluster, n_fine: int):
     """Fine-mesh k points and their (tie-split) assignment to cluster momenta."""
+    key = (cluster.superlattice.tobytes(), cluster.superlattice.shape, n_fine)
+    if key not in _PATCH_CACHE:
+        _PATCH_CACHE[key] = _patch_weights_uncached(cluster, n_fine)
+    return _PATCH_CACHE[key]
+
+
+def _patch_weights_uncached(cluster: Cluster, n_fine: int):
     d = cluster.sites.shape[1]
     grid = np.array(list(itertools.product(range(n_fine), repeat=d)), dtype=np.float64)
     kf = 2 * np.pi * grid / n_fine

@@ -21,7 +21,7 @@ struct TimedEvent {
   hipEvent_t start, stop;
 };
 
-const char *kKernelNames[] = {"block_begin", "interp", "prep",      "propose", "gamma_inv", "tile_scan",
+const char *kKernelNames[] = {"block_begin", "interp", "prep",    "propose", "gamma_inv",
                               "assemble",    "rankk",  "block_end", "measure", "refine"};
 constexpr int kNumNames = sizeof(kKernelNames) / sizeof(kKernelNames[0]);
 
@@ -80,7 +80,8 @@ int set_err(ctaux_batch *b, int code, const char *fmt, ...) {
   } while (0)
 
 int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, ctaux_batch *eb) {
-  if (!models || !o || n_chains < 1) return set_err(eb, CTAUX_EINVAL, "null models/opts or n_chains < 1");
+  if (!models || !o || n_chains < 1 || n_chains > 8192)
+    return set_err(eb, CTAUX_EINVAL, "null models/opts or n_chains not in 1..8192");
   if (o->k_max < 1 || o->k_max > kMaxKmax) return set_err(eb, CTAUX_EINVAL, "k_max must be in 1..%d", kMaxKmax);
   if (o->k_cap < 1 || o->k_cap > kMaxKcap || o->k_cap > o->k_max)
     return set_err(eb, CTAUX_EINVAL, "k_cap must be in 1..min(k_max, %d)", kMaxKcap);
@@ -116,13 +117,12 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
   const size_t es = o->precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
   ChainDesc *d_desc = cv.take<ChainDesc>(n_chains);
   ChainState *d_state = cv.take<ChainState>(n_chains);
-  int32_t *d_prefix = cv.take<int32_t>(n_chains + 1);
   double *r_M = cv.take<double>(static_cast<size_t>(ld) * ld);
   double *r_R = cv.take<double>(static_cast<size_t>(ld) * ld);
   double *r_N = cv.take<double>(static_cast<size_t>(ld) * ld);
   double *r_red = cv.take<double>(4096);
   if (bt) {
-    bt->d_desc = d_desc; bt->d_state = d_state; bt->d_tile_prefix = d_prefix;
+    bt->d_desc = d_desc; bt->d_state = d_state;
     bt->r_M = r_M; bt->r_R = r_R; bt->r_N = r_N; bt->r_red = r_red;
   }
   for (int c = 0; c < n_chains; ++c) {
@@ -244,14 +244,13 @@ int enqueue_block(ctaux_batch *h) {
   { Timer t(h, 2); launch_prep(b, s); }
   { Timer t(h, 3); launch_propose(b, s); }
   { Timer t(h, 4); launch_gamma_inv(b, s); }
-  { Timer t(h, 5); launch_tile_scan(b, s); }
-  { Timer t(h, 6); launch_assemble(b, s); }
-  { Timer t(h, 7); launch_rankk(b, s); }
-  { Timer t(h, 8); launch_block_end(b, s); }
-  { Timer t(h, 9); launch_measure(b, s); }
+  { Timer t(h, 5); launch_assemble(b, s); }
+  { Timer t(h, 6); launch_rankk(b, s); }
+  { Timer t(h, 7); launch_block_end(b, s); }
+  { Timer t(h, 8); launch_measure(b, s); }
   h->blocks_launched += 1;
   if (h->recompute_every > 0 && h->blocks_launched % h->recompute_every == 0) {
-    Timer t(h, 10);
+    Timer t(h, 9);
     for (int c = 0; c < b.n_chains; ++c) launch_refine(b, s, c);
   }
   hipError_t e = hipGetLastError();
@@ -405,7 +404,7 @@ int ctaux_run(ctaux_batch *h, int64_t n_proposals) {
 int ctaux_recompute(ctaux_batch *h, double *max_drift_out) {
   if (!h) return CTAUX_EINVAL;
   {
-    Timer t(h, 10);
+    Timer t(h, 9);
     for (int c = 0; c < h->b.n_chains; ++c) launch_refine(h->b, h->stream, c);
   }
   hipError_t e = hipGetLastError();

@@ -66,8 +66,8 @@ struct ChainDesc {
   void *Ac[2];             // [ld rows][lda]  (G - I)_{map, P}
   void *Bc[2];             // [lda][ld]       Gamma^{-1} N_a(P, map)
   // measurement
-  double *W[2];            // [n_cap][nc]  (e^V - 1) N gR
-  double *gR[2];           // [n_cap][nc]  G0_{x_k y}(tau_k)
+  double *W[2];            // [n_cap][nc]  N gR
+  double *gR[2];           // [nc][n_cap]  G0_{x_k y}(tau_k), transposed
   double *Gxy[2];          // [(n_out+1)][nc*nc]  row 0 = equal time
   const int32_t *cls_off;  // [n_disp+1] pairs (x*nc+y) of each table, CSR offsets
   const int32_t *cls_pairs;  // [nc*nc]
@@ -113,7 +113,6 @@ void launch_prep(const Batch &b, hipStream_t s);
 void launch_propose(const Batch &b, hipStream_t s);
 void launch_assemble(const Batch &b, hipStream_t s);
 void launch_gamma_inv(const Batch &b, hipStream_t s);
-void launch_tile_scan(const Batch &b, hipStream_t s);
 void launch_rankk(const Batch &b, hipStream_t s);
 void launch_block_end(const Batch &b, hipStream_t s);
 void launch_measure(const Batch &b, hipStream_t s);
@@ -128,8 +127,6 @@ struct Batch {
   int32_t grid_per_chain;    // workgroups per chain for per-chain streaming kernels
   ChainDesc *d_desc;         // device [n_chains]
   ChainState *d_state;       // device [n_chains]
-  // rank-k tile scheduler
-  int32_t *d_tile_prefix;    // device [n_chains+1]
   int32_t n_cu;
   // refinement scratch (one chain at a time), FP64
   double *r_M, *r_R, *r_N;   // [ld*ld] each

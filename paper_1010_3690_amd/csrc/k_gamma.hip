@@ -4,6 +4,10 @@
 // the acceptance ratios during the block; with repeated changes of a vertex
 // Gamma can be ill-conditioned (condition numbers 1e6-1e8 are common), and the
 // unpivoted growth then loses several digits that a pivoted inversion keeps.
+//
+// One workgroup per (chain, sector) on the augmented [Gamma | I] in LDS:
+// thread (row r = tid % 64, column group tid / 64) updates every fourth column
+// of its row, three barriers per eliminated column.
 #include "ctaux_device.h"
 
 namespace ctaux {
@@ -20,11 +24,10 @@ __global__ __launch_bounds__(256) void k_gamma_inv(const ChainDesc *descs, Chain
   __shared__ double prow[2 * kMaxKcap], oldc[2 * kMaxKcap], f[kMaxKcap];
   __shared__ int sh_piv;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane, cg = wave;
   const double *gam = d.Gam[sec];
-  for (int e = tid; e < ka * w2; e += 256) {
-    const int r = e / w2, j = e - r * w2;
-    M[r][j] = j < ka ? gam[r * kcap + j] : ((j - ka) == r ? 1.0 : 0.0);
-  }
+  if (r < ka)
+    for (int j = cg; j < w2; j += 4) M[r][j] = j < ka ? gam[r * kcap + j] : ((j - ka) == r ? 1.0 : 0.0);
   __syncthreads();
   for (int col = 0; col < ka; ++col) {
     if (wave == 0) {
@@ -41,26 +44,41 @@ __global__ __launch_bounds__(256) void k_gamma_inv(const ChainDesc *descs, Chain
     __syncthreads();
     const int p = sh_piv;
     const double pv = M[p][col];
-    for (int j = tid; j < w2; j += 256) {
-      prow[j] = M[p][j] / pv;
-      oldc[j] = M[col][j];
+    if (tid < w2) {
+      prow[tid] = M[p][tid] / pv;
+      oldc[tid] = M[col][tid];
+    } else if (tid >= 128 && tid - 128 < ka) {
+      f[tid - 128] = M[tid - 128][col];
     }
-    if (tid < ka) f[tid] = M[tid][col];
     __syncthreads();
-    for (int e = tid; e < ka * w2; e += 256) {
-      const int r = e / w2, j = e - r * w2;
-      if (r == col) M[r][j] = prow[j];
-      else if (r == p) M[r][j] = oldc[j] - f[col] * prow[j];
-      else M[r][j] -= f[r] * prow[j];
+    if (r < ka) {
+      // loads first, then arithmetic, then stores: the LDS loads of all the
+      // thread's columns are in flight together
+      const double fr = (r == p) ? f[col] : f[r];
+      for (int j1 = cg; j1 < w2; j1 += 32) {   // batches of 8 columns
+        double mv[8], pr[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int j = j1 + 4 * i;
+          pr[i] = (j < w2) ? prow[j] : 0.0;
+          mv[i] = (j < w2) ? ((r == p) ? oldc[j] : M[r][j]) : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int j = j1 + 4 * i;
+          if (j < w2) M[r][j] = (r == col) ? pr[i] : mv[i] - fr * pr[i];
+        }
+      }
     }
     __syncthreads();
   }
   bool bad = false;
-  for (int e = tid; e < ka * ka; e += 256) {
-    const int r = e / ka, j = e - r * ka;
-    const double v = M[r][ka + j];
-    bad |= !isfinite(v);
-    d.Ginv[sec][r * kcap + j] = v;
+  if (r < ka) {
+    for (int j = cg; j < ka; j += 4) {
+      const double v = M[r][ka + j];
+      bad |= !isfinite(v);
+      d.Ginv[sec][r * kcap + j] = v;
+    }
   }
   if (bad) {
     st.status = -4;   // singular Gamma

@@ -67,39 +67,6 @@ void launch_assemble(const Batch &b, hipStream_t s) {
                        b.d_desc, b.d_state);
 }
 
-// Prefix sums of rank-k tiles over chains: chain c owns tiles
-// [prefix[c], prefix[c+1]), 2 sectors x ceil(n'/64)^2 each.
-__global__ __launch_bounds__(256) void k_tile_scan(const ChainState *states, int n_chains, int32_t *prefix) {
-  __shared__ int sh[256];
-  __shared__ int carry;
-  if (threadIdx.x == 0) { carry = 0; prefix[0] = 0; }
-  __syncthreads();
-  for (int base = 0; base < n_chains; base += 256) {
-    const int c = base + threadIdx.x;
-    int v = 0;
-    if (c < n_chains && states[c].active) {
-      const int nt = (states[c].n_new + kTile - 1) / kTile;
-      v = 2 * nt * nt;
-    }
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const int x = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += x;
-      __syncthreads();
-    }
-    if (c < n_chains) prefix[c + 1] = carry + sh[threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x == 255) carry += sh[255];
-    __syncthreads();
-  }
-}
-
-void launch_tile_scan(const Batch &b, hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, s, b.d_state, b.n_chains, b.d_tile_prefix);
-}
-
 template <typename T>
 struct Mfma;
 // Accumulator layouts (checked on gfx950 with a probe of D = A B): lane l holds
@@ -134,10 +101,37 @@ __device__ __forceinline__ T base_entry(const ChainDesc &d, const T *N, const do
 
 // MFMA 16x16x4 operand layout (one 16x16 block): lane l supplies A[l%16][k0 + l/16]
 // and B[k0 + l/16][l%16]; accumulator register q holds D[Mfma<T>::row(l/16, q)][l%16].
+// Persistent over the tiles of all chains: chain c owns tiles [prefix[c],
+// prefix[c+1]), 2 sectors x ceil(n'/64)^2 each; every workgroup builds the
+// prefix in LDS first.
 template <typename T>
-__global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const ChainState *states,
-                                               const int32_t *prefix, int n_chains) {
+__global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const ChainState *states, int n_chains) {
   typedef typename Mfma<T>::acc_t acc_t;
+  extern __shared__ int prefix[];   // [n_chains + 1]
+  __shared__ int scan[256];
+  __shared__ int carry;
+  if (threadIdx.x == 0) { carry = 0; prefix[0] = 0; }
+  __syncthreads();
+  for (int base = 0; base < n_chains; base += 256) {
+    const int cc = base + threadIdx.x;
+    int v = 0;
+    if (cc < n_chains && states[cc].active) {
+      const int nt = (states[cc].n_new + kTile - 1) / kTile;
+      v = 2 * nt * nt;
+    }
+    scan[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int x = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (cc < n_chains) prefix[cc + 1] = carry + scan[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) carry += scan[255];
+    __syncthreads();
+  }
   const int total = prefix[n_chains];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -213,12 +207,11 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
 
 void launch_rankk(const Batch &b, hipStream_t s) {
   const int grid = b.n_cu * 8;
+  const size_t lds = sizeof(int) * (b.n_chains + 1);
   if (b.precision == kFP64)
-    hipLaunchKernelGGL(k_rankk<double>, dim3(grid), dim3(256), 0, s, b.d_desc, b.d_state,
-                       b.d_tile_prefix, b.n_chains);
+    hipLaunchKernelGGL(k_rankk<double>, dim3(grid), dim3(256), lds, s, b.d_desc, b.d_state, b.n_chains);
   else
-    hipLaunchKernelGGL(k_rankk<float>, dim3(grid), dim3(256), 0, s, b.d_desc, b.d_state,
-                       b.d_tile_prefix, b.n_chains);
+    hipLaunchKernelGGL(k_rankk<float>, dim3(grid), dim3(256), lds, s, b.d_desc, b.d_state, b.n_chains);
 }
 
 }  // namespace ctaux

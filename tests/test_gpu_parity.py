@@ -130,8 +130,10 @@ def test_batched_chains_match_their_oracles():
     ws = [_plaquette(), hubbard_dimer(beta=2.0, U=2.0, n_tau=2001), _plaquette(beta=2.0, U=6.0),
           _cluster16(K=5.0), anderson_semicircle(n_tau=4096)]
     n_prop = 3000
+    # ~94 blocks per chain: the FP64 refinement every 16 blocks bounds the
+    # ~1e-12 per-block rounding of the rank-k updates, as in production runs
     opts = ctaux.Options(k_max=32, k_cap=24, n_cap=1024, log_cap=n_prop, meas_every=32, n_tau_out=8,
-                         recompute_every=0, seed=11)
+                         recompute_every=16, seed=11)
     gb = ctaux.CtauxBatch(ws, opts)
     gb.run(n_prop)
     for c, w in enumerate(ws):
