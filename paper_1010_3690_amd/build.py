@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libctaux_hip.so")
-SOURCES = ["api.hip", "k_block.hip", "k_prep.hip", "k_propose.hip", "k_gamma.hip", "k_skinny.hip", "k_update.hip", "k_measure.hip",
+SOURCES = ["api.hip", "k_block.hip", "k_prep.hip", "k_propose.hip", "k_skinny.hip", "k_update.hip", "k_measure.hip",
            "k_refine.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -21,7 +21,7 @@ struct TimedEvent {
   hipEvent_t start, stop;
 };
 
-const char *kKernelNames[] = {"block_begin", "interp", "prep",    "propose", "gamma_inv",
+const char *kKernelNames[] = {"block_begin", "interp", "prep",     "propose",
                               "assemble",    "rankk",  "block_end", "measure", "refine"};
 constexpr int kNumNames = sizeof(kKernelNames) / sizeof(kKernelNames[0]);
 
@@ -243,14 +243,13 @@ int enqueue_block(ctaux_batch *h) {
   { Timer t(h, 1); launch_interp(b, s); }
   { Timer t(h, 2); launch_prep(b, s); }
   { Timer t(h, 3); launch_propose(b, s); }
-  { Timer t(h, 4); launch_gamma_inv(b, s); }
-  { Timer t(h, 5); launch_assemble(b, s); }
-  { Timer t(h, 6); launch_rankk(b, s); }
-  { Timer t(h, 7); launch_block_end(b, s); }
-  { Timer t(h, 8); launch_measure(b, s); }
+  { Timer t(h, 4); launch_assemble(b, s); }
+  { Timer t(h, 5); launch_rankk(b, s); }
+  { Timer t(h, 6); launch_block_end(b, s); }
+  { Timer t(h, 7); launch_measure(b, s); }
   h->blocks_launched += 1;
   if (h->recompute_every > 0 && h->blocks_launched % h->recompute_every == 0) {
-    Timer t(h, 9);
+    Timer t(h, 8);
     for (int c = 0; c < b.n_chains; ++c) launch_refine(b, s, c);
   }
   hipError_t e = hipGetLastError();
@@ -404,7 +403,7 @@ int ctaux_run(ctaux_batch *h, int64_t n_proposals) {
 int ctaux_recompute(ctaux_batch *h, double *max_drift_out) {
   if (!h) return CTAUX_EINVAL;
   {
-    Timer t(h, 9);
+    Timer t(h, 8);
     for (int c = 0; c < h->b.n_chains; ++c) launch_refine(h->b, h->stream, c);
   }
   hipError_t e = hipGetLastError();

@@ -112,7 +112,6 @@ void launch_interp(const Batch &b, hipStream_t s);
 void launch_prep(const Batch &b, hipStream_t s);
 void launch_propose(const Batch &b, hipStream_t s);
 void launch_assemble(const Batch &b, hipStream_t s);
-void launch_gamma_inv(const Batch &b, hipStream_t s);
 void launch_rankk(const Batch &b, hipStream_t s);
 void launch_block_end(const Batch &b, hipStream_t s);
 void launch_measure(const Batch &b, hipStream_t s);

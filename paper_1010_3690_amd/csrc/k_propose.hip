@@ -20,23 +20,36 @@
 // thread reads back only what it wrote itself or what precedes a barrier, and
 // the per-proposal scalars are double-buffered by proposal parity, so no
 // barrier is needed at the end of a proposal.
+//
+// Everything the loop reads from the chain descriptor is copied to registers
+// or LDS first: the loop stores to global memory, so reads through the
+// descriptor could not be hoisted and would sit on the latency-critical path.
 #include "ctaux_device.h"
 
 namespace ctaux {
 
-// G entry with the block-start spins taken from LDS.
+// Pointers and sizes one sector's gathers need.
+struct GView {
+  const double *Rt, *YT, *Gnn;
+  const double *ev;   // LDS: exp(gamma*sigma*s), index s + 2
+  int ld, kmax, n;
+};
+
+// Entry G_ij of the block-start Green's function of the augmented configuration
+// (old vertices 0..n-1, candidates n..):
+//   old column j:       G_ij = (N_a,ij e^{V_j} - delta_ij) / (e^{V_j} - 1)     (Eq. NfromG)
+//   candidate column j: G_ij = (N Z)_{i, j-n} (old row) or (X Y + G0nn)_{i-n, j-n}.
 template <typename T>
-__device__ __forceinline__ double g_entry_l(const ChainDesc &d, const T *N, const int8_t *s0l, int n, int sec,
-                                            int i, int j) {
+__device__ __forceinline__ double g_entry_v(const GView &g, const T *N, const int8_t *s0l, int i, int j) {
+  const int n = g.n;
   if (j < n) {
-    const double e = d.evd[sec][s0l[j] + 2];
-    const double nij = (i < n) ? static_cast<double>(N[static_cast<size_t>(i) * d.ld + j])
-                               : d.Rt[sec][static_cast<size_t>(i - n) * d.ld + j];
+    const double e = g.ev[s0l[j] + 2];
+    const double nij = (i < n) ? static_cast<double>(N[static_cast<size_t>(i) * g.ld + j])
+                               : g.Rt[static_cast<size_t>(i - n) * g.ld + j];
     return (nij * e - (i == j ? 1.0 : 0.0)) / (e - 1.0);
   }
   const int jj = j - n;
-  return (i < n) ? d.YT[sec][static_cast<size_t>(jj) * d.ld + i]
-                 : d.Gnn[sec][static_cast<size_t>(i - n) * d.kmax + jj];
+  return (i < n) ? g.YT[static_cast<size_t>(jj) * g.ld + i] : g.Gnn[static_cast<size_t>(i - n) * g.kmax + jj];
 }
 
 template <typename T>
@@ -48,11 +61,17 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sec = tid >> 7, loc = tid & 127;
   const int n = st.n, kins = st.k_ins, L = st.L;
-  const int kcap = d.kcap, lg = kcap + 1;
   const int par = st.parity;
-  const T *Nsec = static_cast<const T *>(d.N[par][sec]);
-  const bool gz = (d.gamma == 0.0);
   const int64_t done0 = st.done;
+  // descriptor fields used in the loop
+  const int kcap = d.kcap, lg = kcap + 1, n_cap = d.n_cap, kmax = d.kmax;
+  const double Kc = d.K;
+  const bool gz = (d.gamma == 0.0);
+  const T *Nsec = static_cast<const T *>(d.N[par][sec]);
+  double *const gam = d.Gam[sec];
+  uint8_t *const log_acc = d.log_acc;
+  double *const log_R = d.log_R;
+  const int64_t log_cap = d.log_cap;
 
   extern __shared__ double smem[];
   double *Gi = smem;                         // [2][kcap][lg]
@@ -63,15 +82,16 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   int *P = reinterpret_cast<int *>(vu + 2 * kcap);   // [kcap]
   int *dead = P + kcap;                      // [kcap] removed old vertices
   int8_t *scur = reinterpret_cast<int8_t *>(dead + kcap);  // [n + kmax] current spins
-  int8_t *s0l = scur + (d.n_cap + d.kmax);                  // [n + kmax] block-start spins
+  int8_t *s0l = scur + (n_cap + kmax);                      // [n + kmax] block-start spins
   double *Gis = Gi + sec * kcap * lg;
+  __shared__ double sh_ev[2][5];                   // exp(gamma*sigma*d), d = -2..2
   __shared__ double sh_gpp[2][2], sh_beta[2][2];   // [proposal parity][sector]
   __shared__ double sh_gh[2][kMaxKcap];
   __shared__ double sh_pacc[kMaxKmax], sh_ppick[kMaxKmax];
   __shared__ int8_t sh_ptype[kMaxKmax], sh_pspin[kMaxKmax];
-  __shared__ int sh_p;
+  __shared__ int sh_p, sh_bad, sh_nnew;
+  __shared__ int sh_perm[2][kMaxKcap];
   __shared__ int64_t sh_cid[kMaxKmax];
-  __shared__ int sh_scan[256];
 
   int ka = 0, nchg = 0, ncur = n, ndead = 0, next_cand = 0;   // nchg: accepted changes (== ka unless U = 0)
   int64_t next_id = st.next_id, accepted = st.accepted;
@@ -84,6 +104,8 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     scur[i] = v;
     s0l[i] = v;
   }
+  if (tid == 0) sh_bad = 0;
+  if (tid < 10) sh_ev[tid / 5][tid % 5] = d.evd[tid / 5][tid % 5];
   for (int t = tid; t < L; t += 256) {
     sh_ptype[t] = static_cast<int8_t>(d.ptype[t]);
     sh_pspin[t] = static_cast<int8_t>(d.pspin[t]);
@@ -91,6 +113,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     sh_ppick[t] = d.ppick[t];
   }
   __syncthreads();
+  const GView gv{d.Rt[sec], d.YT[sec], d.Gnn[sec], sh_ev[sec], d.ld, kmax, n};
 
   for (int t = 0; t < L; ++t) {
     const int tp = t & 1;
@@ -98,7 +121,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     const double u_acc = sh_pacc[t];
     int p = -1, s_old = 0, s_new = 0, skip = 0;
     if (type == 0) {
-      if (ncur + 1 > d.n_cap) {
+      if (ncur + 1 > n_cap) {
         status = -5;  // CTAUX_ECAPACITY
         L_eff = t;
         err_index = done0 + t;
@@ -154,36 +177,47 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     double gh0 = 0.0, gh1 = 0.0;
     if (!skip && !gz) {
       const int s0p = s0l[p];
-      gh0 = d.evd[0][s_new - s0p + 2] - d.evd[0][s_old - s0p + 2];
-      gh1 = d.evd[1][s_new - s0p + 2] - d.evd[1][s_old - s0p + 2];
+      gh0 = sh_ev[0][s_new - s0p + 2] - sh_ev[0][s_old - s0p + 2];
+      gh1 = sh_ev[1][s_new - s0p + 2] - sh_ev[1][s_old - s0p + 2];
       const double gh = sec == 0 ? gh0 : gh1;
       // gather the new row / column of Gamma and G_pp; each thread also records
       // its entry as row / column ka of Gamma for the pivoted inversion at block
       // end (a rejected proposal's entries are overwritten by the next one)
-      double *gam = d.Gam[sec];
       if (loc < ka) {
         const int pa = P[loc];
-        const double v = g_entry_l<T>(d, Nsec, s0l, n, sec, pa, p) - (pa == p ? 1.0 : 0.0);
+        const double v = g_entry_v<T>(gv, Nsec, s0l, pa, p) - (pa == p ? 1.0 : 0.0);
         vs[sec * kcap + loc] = v;
         gam[loc * kcap + ka] = v;
       } else if (loc < 2 * ka) {
         const int b = loc - ka, pb = P[b];
-        const double v = g_entry_l<T>(d, Nsec, s0l, n, sec, p, pb) - (pb == p ? 1.0 : 0.0);
+        const double v = g_entry_v<T>(gv, Nsec, s0l, p, pb) - (pb == p ? 1.0 : 0.0);
         vw[sec * kcap + b] = v;
         gam[ka * kcap + b] = v;
       } else if (loc == 2 * ka) {
-        const double gpp = g_entry_l<T>(d, Nsec, s0l, n, sec, p, p);
+        const double gpp = g_entry_v<T>(gv, Nsec, s0l, p, p);
         sh_gpp[tp][sec] = gpp;
         gam[ka * kcap + ka] = gpp - 1.0 - 1.0 / gh;
       }
       __syncthreads();
-      // v = Gamma^{-1} s and beta = d - w.v (waves 0 and 2), u = w^T Gamma^{-1} (waves 1 and 3)
+      // v = Gamma^{-1} s and beta = d - w.v (waves 0 and 2), u = w^T Gamma^{-1} (waves 1 and 3);
+      // four accumulators, loads of eight terms in flight together
       if (loc < 64) {
         double acc = 0.0;
         if (loc < ka) {
           const double *row = Gis + loc * lg;
           const double *sv = vs + sec * kcap;
-          for (int b = 0; b < ka; ++b) acc += row[b] * sv[b];
+          double a4[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int b0 = 0; b0 < ka; b0 += 8) {
+            double x[8], y[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              x[i] = (b0 + i < ka) ? row[b0 + i] : 0.0;
+              y[i] = (b0 + i < ka) ? sv[b0 + i] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a4[i & 3] += x[i] * y[i];
+          }
+          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
           vv[sec * kcap + loc] = acc;
         }
         const double x = (loc < ka) ? vw[sec * kcap + loc] * acc : 0.0;
@@ -192,10 +226,19 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       } else {
         const int b = loc - 64;
         if (b < ka) {
-          double acc = 0.0;
           const double *wv = vw + sec * kcap;
-          for (int a = 0; a < ka; ++a) acc += wv[a] * Gis[a * lg + b];
-          vu[sec * kcap + b] = acc;
+          double a4[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int a0 = 0; a0 < ka; a0 += 8) {
+            double x[8], y[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              x[i] = (a0 + i < ka) ? wv[a0 + i] : 0.0;
+              y[i] = (a0 + i < ka) ? Gis[(a0 + i) * lg + b] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a4[i & 3] += x[i] * y[i];
+          }
+          vu[sec * kcap + b] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
       }
       __syncthreads();
@@ -210,8 +253,8 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         r0 = -gh0 * sh_beta[tp][0];
         r1 = -gh1 * sh_beta[tp][1];
       }
-      const double f = (type == 0) ? d.K / static_cast<double>(ncur + 1)
-                                   : (type == 1 ? static_cast<double>(ncur) / d.K : 1.0);
+      const double f = (type == 0) ? Kc / static_cast<double>(ncur + 1)
+                                   : (type == 1 ? static_cast<double>(ncur) / Kc : 1.0);
       R = f * r0 * r1;
     }
     if (!isfinite(R)) {
@@ -223,9 +266,9 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     const int acc = (!skip && u_acc < fabs(R)) ? 1 : 0;
     if (tid == 0) {
       const int64_t idx = done0 + t;
-      if (idx < d.log_cap) {
-        d.log_acc[idx] = static_cast<uint8_t>(acc);
-        d.log_R[idx] = R;
+      if (idx < log_cap) {
+        log_acc[idx] = static_cast<uint8_t>(acc);
+        log_R[idx] = R;
       }
     }
     if (acc) {
@@ -287,36 +330,122 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   }
   __syncthreads();
 
-  // ---- compaction map: interacting vertices in augmented order ----
-  const int na = n + kins;
-  const int chunk = (na + 255) / 256;
-  const int b0 = tid * chunk, b1 = min(b0 + chunk, na);
-  int cnt = 0;
-  for (int i = b0; i < b1; ++i) cnt += (scur[i] != 0);
-  sh_scan[tid] = cnt;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int v = (tid >= off) ? sh_scan[tid - off] : 0;
-    __syncthreads();
-    sh_scan[tid] += v;
-    __syncthreads();
-  }
-  int pos = sh_scan[tid] - cnt;
-  const int np = par ^ 1;
-  for (int i = b0; i < b1; ++i) {
-    if (scur[i] == 0) continue;
-    d.map[pos] = i;
-    if (i < n) {
-      d.tau[np][pos] = d.tau[par][i];
-      d.site[np][pos] = d.site[par][i];
-      d.id[np][pos] = d.id[par][i];
-    } else {
-      d.tau[np][pos] = d.ctau[i - n];
-      d.site[np][pos] = d.csite[i - n];
-      d.id[np][pos] = sh_cid[i - n];
+  if (wave == 1) {
+    // ---- compaction map: interacting vertices in augmented order (one wave, ballot scan) ----
+    const int na = n + kins;
+    const int np = par ^ 1;
+    int running = 0;
+    for (int base = 0; base < na; base += 64) {
+      const int i = base + lane;
+      const bool alive = (i < na) && scur[i] != 0;
+      const unsigned long long m = __ballot(alive);
+      if (alive) {
+        const int pos = running + __popcll(m & ((1ull << lane) - 1ull));
+        d.map[pos] = i;
+        if (i < n) {
+          d.tau[np][pos] = d.tau[par][i];
+          d.site[np][pos] = d.site[par][i];
+          d.id[np][pos] = d.id[par][i];
+        } else {
+          d.tau[np][pos] = d.ctau[i - n];
+          d.site[np][pos] = d.csite[i - n];
+          d.id[np][pos] = sh_cid[i - n];
+        }
+        d.s0[np][pos] = scur[i];
+      }
+      running += __popcll(m);
     }
-    d.s0[np][pos] = scur[i];
-    ++pos;
+    if (lane == 0) sh_nnew = running;
+  } else if (ka > 0 && (wave & 1) == 0) {
+    // ---- Gamma^{-1} for the rank-k update ----
+    // The ratios above came from the unpivoted growth; with repeated changes of
+    // a vertex Gamma can be ill-conditioned (condition numbers 1e6-1e8), so the
+    // N update uses Gamma^{-1} from an in-place Gauss-Jordan elimination with
+    // partial pivoting of the recorded Gamma.  One wave per sector (wave 0: up,
+    // wave 2: down), lane r owns row r; all communication stays inside the
+    // wave, whose LDS operations execute in program order, so no barrier is
+    // needed.
+    double *A = Gis;   // Gamma^{-1} of the growth is no longer needed
+    // Gamma was written by this workgroup before the barriers above
+    // (workgroup-scope visibility); all loads are issued before the first store
+    for (int r0 = 0; r0 < ka; r0 += 16) {
+      double g[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) g[i] = (r0 + i < ka && lane < ka) ? gam[(r0 + i) * kcap + lane] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (r0 + i < ka && lane < ka) A[(r0 + i) * lg + lane] = g[i];
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int col = 0; col < ka; ++col) {
+      // pivot: largest |A[r][col]|, r >= col; |x| bits order like |x|, the low six
+      // mantissa bits carry the row so one 64-bit maximum finds both
+      unsigned long long key = 0ull;
+      if (lane >= col && lane < ka) {
+        const double x = fabs(A[lane * lg + col]);
+        key = (static_cast<unsigned long long>(__double_as_longlong(x)) & ~63ull) |
+              static_cast<unsigned long long>(lane);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        key = o > key ? o : key;
+      }
+      const int p = (ka > col) ? static_cast<int>(key & 63ull) : col;
+      if (lane == 0) sh_perm[sec][col] = p;
+      if (p != col && lane < ka) {   // swap rows p and col (lanes over columns)
+        const double a = A[p * lg + lane], b = A[col * lg + lane];
+        A[p * lg + lane] = b;
+        A[col * lg + lane] = a;
+      }
+      __builtin_amdgcn_wave_barrier();
+      const double ip = 1.0 / A[col * lg + col];
+      __builtin_amdgcn_wave_barrier();
+      if (lane < ka) A[col * lg + lane] = (lane == col ? 1.0 : A[col * lg + lane]) * ip;
+      __builtin_amdgcn_wave_barrier();
+      if (lane < ka && lane != col) {
+        double *row = A + lane * lg;
+        const double *prow = A + col * lg;
+        const double f = row[col];
+        row[col] = 0.0;
+        for (int j1 = 0; j1 < ka; j1 += 8) {   // batches: loads in flight together, then stores
+          double rv[8], pv[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            rv[i] = (j1 + i < ka) ? row[j1 + i] : 0.0;
+            pv[i] = (j1 + i < ka) ? prow[j1 + i] : 0.0;
+          }
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (j1 + i < ka) row[j1 + i] = rv[i] - f * pv[i];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    // undo the row interchanges as column interchanges, last first
+    for (int col = ka - 1; col >= 0; --col) {
+      const int p = sh_perm[sec][col];
+      if (p != col && lane < ka) {
+        const double a = A[lane * lg + col], b = A[lane * lg + p];
+        A[lane * lg + col] = b;
+        A[lane * lg + p] = a;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    bool bad = false;
+    double *gi = d.Ginv[sec];
+    for (int r = 0; r < ka; ++r)
+      for (int j = lane; j < ka; j += 64) {
+        const double x = A[r * lg + j];
+        bad |= !isfinite(x);
+        gi[r * kcap + j] = x;
+      }
+    if (__ballot(bad) != 0ull && lane == 0) sh_bad = 1;   // singular Gamma
+  }
+  __syncthreads();
+  if (sh_bad && status == 0) {
+    status = -4;
+    err_index = -4;
   }
   // ---- P and gh for the rank-k update (Gamma itself was recorded on acceptance) ----
   for (int a = tid; a < ka; a += 256) {
@@ -326,14 +455,14 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   }
   if (tid == 0) {
     st.k_a = ka;
-    st.n_new = sh_scan[255];
+    st.n_new = sh_nnew;
     st.L_eff = L_eff;
     st.sign = sign;
     st.next_id = next_id;
     st.accepted = accepted;
     st.status = status;
     if (status != 0) st.err_index = err_index;
-    if (sh_scan[255] != ncur && status == 0) {
+    if (sh_nnew != ncur && status == 0) {
       st.status = -4;
       st.err_index = -2;   // bookkeeping mismatch
     }

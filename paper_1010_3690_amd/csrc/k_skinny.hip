@@ -1,12 +1,22 @@
-// Skinny products with few rows and long K on MFMA f64 16x16x4:
-//   C[m][c] = sum_k A(m, k) * B(k, c) (+ D[m][c]),  m < M <= 128 per job, k < K, c < Ncols,
-//   B(k, c) = B[k][c] or, transposed, B[c][k].
-// They are the preparation products of a block (Sec. IV A): YT = ZT N^T,
-// Rt = X N (both read N once), Gnn = X YT^T + G0nn; and the measurement
-// (Sec. IV D): W = N gR, then G(x tau_j; y 0) = G0 + gL W with the rows of gL
-// evaluated from the G0 tables inside the loop.  One workgroup owns a
-// 16-column output tile; its 8 waves split K and their partial tiles are
-// summed in LDS in a fixed order (deterministic).
+// Skinny products with few rows on MFMA f64 16x16x4:
+//   C[m][c] = sum_k A(m, k) * B(k, c),  m < M <= 128 per work item, k < K, c < Ncols,
+// with A and B supplied by functors (array reads, G0 table lookups or gathers)
+// and the result handed to an output functor.  They are
+//   - the preparation products of a block (Sec. IV A): YT = ZT N^T, Rt = X N
+//     (each reads N once) and Gnn = X YT^T + G0nn;
+//   - the operand B_c = Gamma^{-1} N_a(P, map) of the rank-k update (Sec. IV C),
+//     with N_a gathered on the fly;
+//   - the measurement (Sec. IV D): W = N gR, then G(x tau_j; y 0) = G0 + gL W
+//     with gL evaluated from the G0 tables inside the loop.
+// A work item is a 16-column tile of one product of one chain; items of all
+// chains are enumerated from a per-chain prefix that every workgroup builds in
+// LDS.  Two execution modes:
+//   - split-K: the 8 waves of a workgroup share one item, each taking every
+//     8th k-step, and their partial tiles are summed in LDS in a fixed order
+//     (few chains with long K: keeps the GPU busy);
+//   - wave: every wave owns items on its own (many chains, short K: no
+//     cross-wave reduction, no barrier per item).
+// Both sum in a fixed order, so results are deterministic.
 #include "ctaux_device.h"
 
 namespace ctaux {
@@ -14,38 +24,41 @@ namespace ctaux {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kSkWaves = 8;
-constexpr int kSkMaxRt = kMaxKmax / 16;   // row tiles per job (M <= 128)
+constexpr int kSkMaxRt = kMaxKmax / 16;   // row tiles per item (M <= 128)
 constexpr int kSkUnroll = 2;
 constexpr int kSkThreads = kSkWaves * 64;
 constexpr int kMeasGRows = 16;           // rows of gL per measurement work item
 
-enum SkinnyKind : int { kSkPrep = 0, kSkGnn = 1, kSkMeasW = 2, kSkMeasG = 3 };
+enum SkinnyKind : int { kSkPrep = 0, kSkGnn = 1, kSkMeasW = 2, kSkMeasG = 3, kSkAsmB = 4 };
+enum SkinnyMode : int { kModeSplitK = 0, kModeWave = 1 };
 
-template <typename T>
-__device__ __forceinline__ double b_load(const T *B, int ldb, int trans, int k, int c) {
-  return trans ? static_cast<double>(B[static_cast<size_t>(c) * ldb + k])
-               : static_cast<double>(B[static_cast<size_t>(k) * ldb + c]);
+// Work items of one chain for a kind (0 when the chain does not take part).
+__device__ __forceinline__ int skinny_items(const ChainDesc &d, const ChainState &st, int kind) {
+  if (!st.active) return 0;
+  const int n = st.n;
+  if (kind == kSkPrep) return st.k_ins > 0 ? 4 * ((n + 15) >> 4) : 0;
+  if (kind == kSkGnn) return st.k_ins > 0 ? 2 * ((st.k_ins + 15) >> 4) : 0;
+  if (kind == kSkAsmB) return (st.k_a > 0 && st.n_new > 0) ? 2 * ((st.n_new + 15) >> 4) : 0;
+  if (!st.meas_now) return 0;
+  if (kind == kSkMeasW) return 2 * ((n + 15) >> 4);
+  const int mtot = d.nc * (d.n_out + 1);
+  return 2 * ((mtot + kMeasGRows - 1) / kMeasGRows) * ((d.nc + 15) >> 4);
 }
 
-// Partial products of this workgroup's waves, reduced into red[nrt*256].
-template <typename T, typename AF>
-__device__ void skinny_core(AF afn, const T *B, int ldb, int trans, int M, int K, int Ncols, int c0,
-                            double *red) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
+// acc += A(m, k) B(k, c) over k = k_first + j * k_step (+ lane's k offset), this wave only.
+// bfn(k) returns B(k, c) for the lane's column c (0 outside).
+template <typename AF, typename BF>
+__device__ __forceinline__ void wave_mma(AF afn, BF bfn, int M, int K, int k_first, int k_step,
+                                         v4d (&acc)[kSkMaxRt]) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
   const int nrt = (M + 15) >> 4;
-  v4d acc[kSkMaxRt];
-#pragma unroll
-  for (int r = 0; r < kSkMaxRt; ++r) acc[r] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int c = c0 + lr;
-  const bool cok = c < Ncols;
-  for (int k0 = wave * 4; k0 < K; k0 += kSkWaves * 4 * kSkUnroll) {
+  for (int k0 = k_first; k0 < K; k0 += k_step * kSkUnroll) {
     double bv[kSkUnroll], av[kSkUnroll][kSkMaxRt];
 #pragma unroll
     for (int u = 0; u < kSkUnroll; ++u) {
-      const int k = k0 + u * kSkWaves * 4 + lk;
+      const int k = k0 + u * k_step + lk;
       const bool kok = k < K;
-      bv[u] = (cok && kok) ? b_load<T>(B, ldb, trans, k, c) : 0.0;
+      bv[u] = kok ? bfn(k) : 0.0;
 #pragma unroll
       for (int r = 0; r < kSkMaxRt; ++r) {
         const int m = r * 16 + lr;
@@ -58,7 +71,33 @@ __device__ void skinny_core(AF afn, const T *B, int ldb, int trans, int M, int K
       for (int r = 0; r < kSkMaxRt; ++r)
         if (r < nrt) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][r], bv[u], acc[r], 0, 0, 0);
   }
-  for (int w = 0; w < kSkWaves; ++w) {
+}
+
+// One item: C tile rows [0, M), columns [c0, c0 + 16), handed to out(m, c, value).
+template <int MODE, typename AF, typename BF, typename OF>
+__device__ __forceinline__ void skinny_item(AF afn, BF bfn, OF out, int M, int K, int Ncols, int c0, double *red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nrt = (M + 15) >> 4;
+  v4d acc[kSkMaxRt];
+#pragma unroll
+  for (int r = 0; r < kSkMaxRt; ++r) acc[r] = v4d{0.0, 0.0, 0.0, 0.0};
+  if (MODE == kModeWave) {
+    wave_mma(afn, bfn, M, K, 0, 4, acc);
+#pragma unroll
+    for (int r = 0; r < kSkMaxRt; ++r) {
+      if (r < nrt) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int m = r * 16 + (lane >> 4) + 4 * q;   // FP64 16x16x4 accumulator: row l/16 + 4q
+          const int cc = c0 + (lane & 15);
+          if (m < M && cc < Ncols) out(m, cc, acc[r][q]);
+        }
+      }
+    }
+    return;
+  }
+  wave_mma(afn, bfn, M, K, wave * 4, kSkWaves * 4, acc);
+  for (int w = 0; w < kSkWaves; ++w) {   // fixed-order reduction of the partial tiles
     if (wave == w) {
 #pragma unroll
       for (int r = 0; r < kSkMaxRt; ++r) {
@@ -73,38 +112,121 @@ __device__ void skinny_core(AF afn, const T *B, int ldb, int trans, int M, int K
     }
     __syncthreads();
   }
+  for (int e = tid; e < nrt * 256; e += kSkThreads) {
+    const int r = e >> 8, l = (e >> 2) & 63, q = e & 3;
+    const int m = r * 16 + (l >> 4) + 4 * q;
+    const int cc = c0 + (l & 15);
+    if (m < M && cc < Ncols) out(m, cc, red[e]);
+  }
+  __syncthreads();   // red is reused by the next item
 }
 
-// Element e of red (after skinny_core) is output row m, column cc.
-__device__ __forceinline__ void red_index(int e, int c0, int &m, int &cc) {
-  const int r = e >> 8, l = (e >> 2) & 63, q = e & 3;
-  m = r * 16 + (l >> 4) + 4 * q;   // FP64 16x16x4 accumulator: row l/16 + 4q
-  cc = c0 + (l & 15);
+template <typename T, int MODE>
+__device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int kind, int local, double *red) {
+  const int lane = threadIdx.x & 63, lr = lane & 15;
+  const int n = st.n, par = st.parity;
+  if (kind == kSkPrep) {
+    // items 0..2nt-1: YT[sec] = ZT N^T, items 2nt..4nt-1: Rt[sec] = X N
+    const int nt = (n + 15) >> 4;
+    const int job = local / nt, c0 = (local - job * nt) * 16, sec = job & 1, ld = d.ld;
+    const double *A = (job < 2) ? d.ZT[sec] : d.X[sec];
+    const T *N = static_cast<const T *>(d.N[par][sec]);
+    double *C = (job < 2) ? d.YT[sec] : d.Rt[sec];
+    const int c = c0 + lr;
+    const bool cok = c < n;
+    auto afn = [=](int m, int k) { return A[static_cast<size_t>(m) * ld + k]; };
+    auto out = [=](int m, int cc, double v) { C[static_cast<size_t>(m) * ld + cc] = v; };
+    if (job < 2) {
+      auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(c) * ld + k]) : 0.0; };
+      skinny_item<MODE>(afn, bfn, out, st.k_ins, n, n, c0, red);
+    } else {
+      auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(k) * ld + c]) : 0.0; };
+      skinny_item<MODE>(afn, bfn, out, st.k_ins, n, n, c0, red);
+    }
+  } else if (kind == kSkGnn) {
+    // Gnn[sec] = X YT^T + G0nn (K = 0 still writes Gnn = G0nn)
+    const int ki = st.k_ins, nt = (ki + 15) >> 4;
+    const int sec = local / nt, c0 = (local - sec * nt) * 16, ld = d.ld, km = d.kmax;
+    const double *X = d.X[sec], *YT = d.YT[sec], *G0nn = d.G0nn[sec];
+    double *Gnn = d.Gnn[sec];
+    const int c = c0 + lr;
+    const bool cok = c < ki;
+    auto afn = [=](int m, int k) { return X[static_cast<size_t>(m) * ld + k]; };
+    auto bfn = [=](int k) { return cok ? YT[static_cast<size_t>(c) * ld + k] : 0.0; };
+    auto out = [=](int m, int cc, double v) {
+      Gnn[static_cast<size_t>(m) * km + cc] = v + G0nn[static_cast<size_t>(m) * km + cc];
+    };
+    skinny_item<MODE>(afn, bfn, out, ki, n, ki, c0, red);
+  } else if (kind == kSkAsmB) {
+    // Bc[sec] = Gamma^{-1} N_a(P, map): rows a < kpad (zero beyond k_a), K = k_a
+    const int np = st.n_new, ka = st.k_a, kpad = (ka + 7) & ~7, nt = (np + 15) >> 4;
+    const int sec = local / nt, c0 = (local - sec * nt) * 16, ld = d.ld, kcap = d.kcap;
+    const double *Gi = d.Ginv[sec], *Rt = d.Rt[sec];
+    const T *N = static_cast<const T *>(d.N[par][sec]);
+    const int32_t *P = d.P;
+    T *Bc = static_cast<T *>(d.Bc[sec]);
+    const int c = c0 + lr;
+    const int mj = c < np ? d.map[c] : -1;
+    auto afn = [=](int m, int k) { return m < ka ? Gi[m * kcap + k] : 0.0; };
+    auto bfn = [=](int k) {
+      if (mj < 0) return 0.0;
+      const int pb = P[k];
+      if (pb < n) return (mj < n) ? static_cast<double>(N[static_cast<size_t>(pb) * ld + mj]) : 0.0;
+      if (mj < n) return Rt[static_cast<size_t>(pb - n) * ld + mj];
+      return pb == mj ? 1.0 : 0.0;
+    };
+    auto out = [=](int m, int cc, double v) { Bc[static_cast<size_t>(m) * ld + cc] = static_cast<T>(v); };
+    skinny_item<MODE>(afn, bfn, out, kpad, ka, np, c0, red);
+  } else if (kind == kSkMeasW) {
+    // W[sec] = N gR as (gRT N^T)^T: C[l][y]
+    const int nt = (n + 15) >> 4;
+    const int sec = local / nt, c0 = (local - sec * nt) * 16, ld = d.ld, ncap = d.n_cap, nc = d.nc;
+    const double *gR = d.gR[sec];
+    const T *N = static_cast<const T *>(d.N[par][sec]);
+    double *W = d.W[sec];
+    const int c = c0 + lr;
+    const bool cok = c < n;
+    auto afn = [=](int m, int k) { return gR[static_cast<size_t>(m) * ncap + k]; };
+    auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(c) * ld + k]) : 0.0; };
+    auto out = [=](int m, int cc, double v) { W[static_cast<size_t>(cc) * nc + m] = v; };
+    skinny_item<MODE>(afn, bfn, out, nc, n, n, c0, red);
+  } else {
+    // Gxy: rows m = j*nc + x (j = 0: tau = 0+, j >= 1: tau_{j-1}); item = 16 rows x 16 columns y
+    const int nc = d.nc, Mtot = nc * (d.n_out + 1);
+    const int ngroups = (Mtot + kMeasGRows - 1) / kMeasGRows, ntiles = (nc + 15) >> 4;
+    const int sec = local / (ngroups * ntiles), rem = local - sec * ngroups * ntiles;
+    const int g = rem / ntiles, c0 = (rem - g * ntiles) * 16;
+    const int m0 = g * kMeasGRows, M = min(kMeasGRows, Mtot - m0);
+    const double *tau = d.tau[par], *W = d.W[sec];
+    const int32_t *site = d.site[par], *s0 = d.s0[par];
+    const double dt = d.beta / d.n_out;
+    double *Gxy = d.Gxy[sec];
+    const int c = c0 + lr;
+    const bool cok = c < nc;
+    auto afn = [&](int m, int l) -> double {
+      const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
+      const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
+      return g0_interp(d, sec, x, site[l], tj - tau[l]) * (d.evd[sec][s0[l] + 2] - 1.0);
+    };
+    auto bfn = [=](int l) { return cok ? W[static_cast<size_t>(l) * nc + c] : 0.0; };
+    auto out = [&](int m, int cc, double v) {
+      const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
+      const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
+      Gxy[static_cast<size_t>(j) * nc * nc + x * nc + cc] = g0_interp(d, sec, x, cc, tj) + v;
+    };
+    skinny_item<MODE>(afn, bfn, out, M, n, nc, c0, red);
+  }
 }
 
-// Work items of one chain for a kind (0 when the chain does not take part).
-__device__ __forceinline__ int skinny_items(const ChainDesc &d, const ChainState &st, int kind) {
-  if (!st.active) return 0;
-  const int n = st.n;
-  if (kind == kSkPrep) return st.k_ins > 0 ? 4 * ((n + 15) >> 4) : 0;
-  if (kind == kSkGnn) return st.k_ins > 0 ? 2 * ((st.k_ins + 15) >> 4) : 0;
-  if (!st.meas_now) return 0;
-  if (kind == kSkMeasW) return 2 * ((n + 15) >> 4);
-  const int mtot = d.nc * (d.n_out + 1);
-  return 2 * ((mtot + kMeasGRows - 1) / kMeasGRows) * ((d.nc + 15) >> 4);
-}
-
-// Persistent over the work items of all chains: every workgroup builds the
-// per-chain prefix of work items in LDS (no separate scan launch), then takes
-// items blockIdx.x, blockIdx.x + gridDim.x, ...
-template <typename T>
+// Persistent over the work items of all chains.
+template <typename T, int MODE>
 __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, const ChainState *states, int kind,
                                                         int n_chains) {
   extern __shared__ int pre[];   // [n_chains + 1]
   __shared__ int scan[kSkThreads];
   __shared__ int carry;
   __shared__ double red[kSkMaxRt * 256];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6;
   if (tid == 0) { carry = 0; pre[0] = 0; }
   __syncthreads();
   for (int base = 0; base < n_chains; base += kSkThreads) {
@@ -123,104 +245,36 @@ __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, c
     __syncthreads();
   }
   const int total = pre[n_chains];
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+  const int first = (MODE == kModeWave) ? blockIdx.x * kSkWaves + wave : blockIdx.x;
+  const int stride = (MODE == kModeWave) ? gridDim.x * kSkWaves : gridDim.x;
+  for (int item = first; item < total; item += stride) {
     int lo = 0, hi = n_chains;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if (pre[mid] <= item) lo = mid; else hi = mid;
     }
-    const int c = lo, local = item - pre[c];
-    const ChainDesc &d = descs[c];
-    const ChainState &st = states[c];
-    const int n = st.n, par = st.parity;
-    if (kind == kSkMeasG) {
-      // rows m = j*nc + x (j = 0: tau = 0+, j >= 1: tau_{j-1}); group g holds rows [16 g, 16 g + 16)
-      const int nc = d.nc, Mtot = nc * (d.n_out + 1);
-      const int ngroups = (Mtot + kMeasGRows - 1) / kMeasGRows, ntiles = (nc + 15) >> 4;
-      const int sec = local / (ngroups * ntiles), rem = local - sec * ngroups * ntiles;
-      const int g = rem / ntiles, c0 = (rem - g * ntiles) * 16;
-      const int m0 = g * kMeasGRows, M = min(kMeasGRows, Mtot - m0);
-      const double *tau = d.tau[par];
-      const int32_t *site = d.site[par], *s0 = d.s0[par];
-      const double dt = d.beta / d.n_out;
-      auto afn = [&](int m, int l) -> double {
-        const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
-        const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
-        return g0_interp(d, sec, x, site[l], tj - tau[l]) * (d.evd[sec][s0[l] + 2] - 1.0);
-      };
-      skinny_core<double>(afn, d.W[sec], nc, 0, M, n, nc, c0, red);
-      for (int e = tid; e < ((M + 15) >> 4) * 256; e += kSkThreads) {
-        int m, cc;
-        red_index(e, c0, m, cc);
-        if (m < M && cc < nc) {
-          const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
-          const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
-          d.Gxy[sec][static_cast<size_t>(j) * nc * nc + x * nc + cc] = g0_interp(d, sec, x, cc, tj) + red[e];
-        }
-      }
-      __syncthreads();
-      continue;
-    }
-    int M, K = n, Ncols, lda, ldb, ldc, ldd = 0, trans, out_trans = 0, job, c0;
-    const double *A, *D = nullptr;
-    const void *B;
-    double *C;
-    if (kind == kSkPrep) {
-      // job 0,1: YT[sec] = ZT N^T ; job 2,3: Rt[sec] = X N
-      const int nt = (n + 15) >> 4;
-      job = local / nt; c0 = (local - job * nt) * 16;
-      const int sec = job & 1;
-      M = st.k_ins; Ncols = n;
-      A = (job < 2) ? d.ZT[sec] : d.X[sec];
-      B = d.N[par][sec];
-      C = (job < 2) ? d.YT[sec] : d.Rt[sec];
-      lda = d.ld; ldb = d.ld; ldc = d.ld;
-      trans = (job < 2);
-    } else if (kind == kSkGnn) {
-      // Gnn[sec] = X YT^T + G0nn  (B = YT is FP64; K = 0 still writes C = D)
-      const int nt = (st.k_ins + 15) >> 4;
-      job = local / nt; c0 = (local - job * nt) * 16;
-      const int sec = job;
-      M = st.k_ins; Ncols = st.k_ins;
-      A = d.X[sec]; B = d.YT[sec]; C = d.Gnn[sec]; D = d.G0nn[sec];
-      lda = d.ld; ldb = d.ld; ldc = d.kmax; ldd = d.kmax;
-      trans = 1;
-    } else {
-      // W[sec] = N gR, computed as (gRT N^T)^T: C[l][y]
-      const int nt = (n + 15) >> 4;
-      job = local / nt; c0 = (local - job * nt) * 16;
-      const int sec = job;
-      M = d.nc; Ncols = n;
-      A = d.gR[sec]; B = d.N[par][sec]; C = d.W[sec];
-      lda = d.n_cap; ldb = d.ld; ldc = d.nc;
-      trans = 1; out_trans = 1;
-    }
-    auto afn = [&](int m, int k) -> double { return A[static_cast<size_t>(m) * lda + k]; };
-    if (kind == kSkGnn)
-      skinny_core<double>(afn, static_cast<const double *>(B), ldb, trans, M, K, Ncols, c0, red);
-    else
-      skinny_core<T>(afn, static_cast<const T *>(B), ldb, trans, M, K, Ncols, c0, red);
-    for (int e = tid; e < ((M + 15) >> 4) * 256; e += kSkThreads) {
-      int m, cc;
-      red_index(e, c0, m, cc);
-      if (m < M && cc < Ncols) {
-        double v = red[e];
-        if (D) v += D[static_cast<size_t>(m) * ldd + cc];
-        if (out_trans) C[static_cast<size_t>(cc) * ldc + m] = v;
-        else C[static_cast<size_t>(m) * ldc + cc] = v;
-      }
-    }
-    __syncthreads();   // red is reused by the next item
+    skinny_dispatch<T, MODE>(descs[lo], states[lo], kind, item - pre[lo], red);
   }
 }
 
-void launch_skinny(const Batch &b, hipStream_t s, int kind) {
-  const dim3 grid(b.n_cu * 2);
+template <typename T>
+static void launch_t(const Batch &b, hipStream_t s, int kind, int mode) {
   const size_t lds = sizeof(int) * (b.n_chains + 1);
-  if (b.precision == kFP32)
-    hipLaunchKernelGGL(k_skinny<float>, grid, dim3(kSkThreads), lds, s, b.d_desc, b.d_state, kind, b.n_chains);
+  const dim3 grid(b.n_cu * 2);
+  if (mode == kModeWave)
+    hipLaunchKernelGGL((k_skinny<T, kModeWave>), grid, dim3(kSkThreads), lds, s, b.d_desc, b.d_state, kind,
+                       b.n_chains);
   else
-    hipLaunchKernelGGL(k_skinny<double>, grid, dim3(kSkThreads), lds, s, b.d_desc, b.d_state, kind, b.n_chains);
+    hipLaunchKernelGGL((k_skinny<T, kModeSplitK>), grid, dim3(kSkThreads), lds, s, b.d_desc, b.d_state, kind,
+                       b.n_chains);
+}
+
+void launch_skinny(const Batch &b, hipStream_t s, int kind) {
+  // Products with K = k_a (B_c) are short: one wave per item.  Otherwise split K
+  // across the waves of a workgroup when few chains run (long K, few items).
+  const int mode = (kind == kSkAsmB || b.n_chains >= 8) ? kModeWave : kModeSplitK;
+  if (b.precision == kFP32) launch_t<float>(b, s, kind, mode);
+  else launch_t<double>(b, s, kind, mode);
 }
 
 }  // namespace ctaux

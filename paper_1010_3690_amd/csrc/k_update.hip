@@ -28,36 +28,28 @@ __global__ __launch_bounds__(256) void k_assemble(const ChainDesc *descs, const 
   const int kpad = (ka + 7) & ~7;
   const int par = st.parity;
   const int32_t *s0 = d.s0[par];
-  const int64_t per_a = static_cast<int64_t>(np) * kpad;   // Ac entries per sector
-  const int64_t per_sec = 2 * per_a;
+  const int64_t per_sec = static_cast<int64_t>(np) * kpad;   // Ac entries per sector
   const int64_t total = 2 * per_sec;
+  const int *map = d.map, *P = d.P;
+  const int lda = d.lda;
   for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
     const int sec = static_cast<int>(e / per_sec);
-    int64_t r = e - sec * per_sec;
+    const int64_t r = e - sec * per_sec;
     const T *N = static_cast<const T *>(d.N[par][sec]);
-    if (r < per_a) {
-      // Ac: consecutive threads walk the k index of one row, then rows
-      const int i = static_cast<int>(r / kpad), a = static_cast<int>(r - static_cast<int64_t>(i) * kpad);
-      double v = 0.0;
-      if (a < ka) {
-        const int mi = d.map[i], pa = d.P[a];
-        v = g_entry<T>(d, N, s0, n, sec, mi, pa) - (mi == pa ? 1.0 : 0.0);
-      }
-      static_cast<T *>(d.Ac[sec])[static_cast<size_t>(i) * d.lda + a] = static_cast<T>(v);
-    } else {
-      r -= per_a;
-      const int a = static_cast<int>(r / np), j = static_cast<int>(r - static_cast<int64_t>(a) * np);
-      double v = 0.0;
-      if (a < ka) {
-        const int mj = d.map[j];
-        const double *gi = d.Ginv[sec] + static_cast<size_t>(a) * d.kcap;
-        for (int b = 0; b < ka; ++b) v += gi[b] * na_entry<T>(d, N, n, sec, d.P[b], mj);
-      }
-      static_cast<T *>(d.Bc[sec])[static_cast<size_t>(a) * d.ld + j] = static_cast<T>(v);
+    // consecutive threads walk the k index of one row, then rows
+    const int i = static_cast<int>(r / kpad), a = static_cast<int>(r - static_cast<int64_t>(i) * kpad);
+    double v = 0.0;
+    if (a < ka) {
+      const int mi = map[i], pa = P[a];
+      v = g_entry<T>(d, N, s0, n, sec, mi, pa) - (mi == pa ? 1.0 : 0.0);
     }
+    static_cast<T *>(d.Ac[sec])[static_cast<size_t>(i) * lda + a] = static_cast<T>(v);
   }
 }
 
+void launch_skinny(const Batch &b, hipStream_t s, int kind);
+
+// Ac = (G - I)_{map, P} here; Bc = Gamma^{-1} N_a(P, map) as a skinny MFMA product.
 void launch_assemble(const Batch &b, hipStream_t s) {
   if (b.precision == kFP64)
     hipLaunchKernelGGL(k_assemble<double>, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s,
@@ -65,6 +57,7 @@ void launch_assemble(const Batch &b, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_assemble<float>, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s,
                        b.d_desc, b.d_state);
+  launch_skinny(b, s, 4);
 }
 
 template <typename T>

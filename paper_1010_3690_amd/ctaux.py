@@ -66,6 +66,9 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: the library must bind to the HIP runtime torch already loaded
+    # (loading it first would bring a second runtime into the process)
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1010_3690_amd.build`")
     lib = C.CDLL(path)
