@@ -164,6 +164,25 @@ int ctaux_set_timing(ctaux_batch *b, int32_t enable);
 int32_t ctaux_get_timing(ctaux_batch *b, const char **names, double *ms, int64_t *launches,
                          int32_t cap);
 
+/* Checkpoint / resume of one chain (the chain state the method carries from
+ * block to block, Sec. IV C: the vertex configuration and N of both sectors,
+ * plus the proposal counter that keys the random stream and the measurement
+ * accumulators).
+ *   ctaux_checkpoint: with buf == NULL stores the needed size in *len; else
+ *     *len is the capacity of buf on entry (CTAUX_EINVAL if too small) and the
+ *     bytes written on return.  The blob is a host byte string of the same
+ *     build (native endianness).
+ *   ctaux_restore: loads a blob into `chain` of this batch, which must have the
+ *     same precision, n_sites, n_tau, beta, K, coupling and observable layout
+ *     (CTAUX_EINVAL otherwise) and n_cap >= the stored order.  The FP64
+ *     refinement runs every recompute_every blocks enqueued on a batch; a
+ *     one-chain batch also takes over that schedule, so continuing with the
+ *     same seed and chain index reproduces the uninterrupted chain bit for bit.
+ *     In a larger batch the refinement phase may differ, which changes N by
+ *     rounding only.  The decision log of the target is not restored. */
+int ctaux_checkpoint(ctaux_batch *b, int32_t chain, void *buf, size_t *len);
+int ctaux_restore(ctaux_batch *b, int32_t chain, const void *buf, size_t len);
+
 const char *ctaux_last_error(const ctaux_batch *b);
 void ctaux_destroy(ctaux_batch *b);
 

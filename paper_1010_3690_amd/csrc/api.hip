@@ -534,6 +534,142 @@ int32_t ctaux_get_timing(ctaux_batch *h, const char **names, double *ms, int64_t
   return k;
 }
 
+// Checkpoint blob: header, then id[n] (int64), tau[n] (double), site[n], s[n]
+// (int32), N of both sectors (n x n each, storage type, row-major), obs.
+struct CkptHeader {
+  char magic[8];
+  int32_t version, precision, nc, n_tau, n, obs_len;
+  double beta, K, gamma;
+  int64_t next_id, done, accepted, blocks, sum_ka;
+  int64_t launches;   // blocks enqueued on the batch (phase of the refinement schedule)
+  double sign, max_drift, last_drift, rk_flops, rk_bytes, sum_order;
+};
+constexpr char kCkptMagic[8] = {'C', 'T', 'A', 'U', 'X', 'C', 'K', '1'};
+
+size_t ckpt_bytes(const ctaux_batch *h, int chain, int n) {
+  const size_t es = h->b.precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
+  return sizeof(CkptHeader) + static_cast<size_t>(n) * (8 + 8 + 4 + 4) + 2 * es * n * n +
+         sizeof(double) * h->obs_len[chain];
+}
+
+int ctaux_checkpoint(ctaux_batch *h, int32_t chain, void *buf, size_t *len) {
+  if (!h || !len || chain < 0 || chain >= h->b.n_chains) return CTAUX_EINVAL;
+  int rc = sync_states(h);
+  if (rc) return rc;
+  const ChainState &st = h->state[chain];
+  const ChainDesc &d = h->desc[chain];
+  const int n = st.n, par = st.parity;
+  const size_t need = ckpt_bytes(h, chain, n);
+  if (!buf) {
+    *len = need;
+    return CTAUX_OK;
+  }
+  if (*len < need) return set_err(h, CTAUX_EINVAL, "checkpoint buffer of %zu bytes needed", need);
+  *len = need;
+  CkptHeader hd;
+  memset(&hd, 0, sizeof hd);
+  memcpy(hd.magic, kCkptMagic, 8);
+  hd.version = 1;
+  hd.precision = h->b.precision;
+  hd.nc = d.nc;
+  hd.n_tau = d.n_tau;
+  hd.n = n;
+  hd.obs_len = h->obs_len[chain];
+  hd.beta = d.beta;
+  hd.K = d.K;
+  hd.gamma = d.gamma;
+  hd.next_id = st.next_id;
+  hd.done = st.done;
+  hd.accepted = st.accepted;
+  hd.blocks = st.blocks;
+  hd.sum_ka = st.sum_ka;
+  hd.launches = h->blocks_launched;
+  hd.sign = st.sign;
+  hd.max_drift = st.max_drift;
+  hd.last_drift = st.last_drift;
+  hd.rk_flops = st.rk_flops;
+  hd.rk_bytes = st.rk_bytes;
+  hd.sum_order = st.sum_order;
+  char *p = static_cast<char *>(buf);
+  memcpy(p, &hd, sizeof hd);
+  p += sizeof hd;
+  const size_t es = h->b.precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
+  if (n > 0) {
+    HIPCHECK(h, hipMemcpy(p, d.id[par], 8 * n, hipMemcpyDeviceToHost));
+    p += 8 * n;
+    HIPCHECK(h, hipMemcpy(p, d.tau[par], 8 * n, hipMemcpyDeviceToHost));
+    p += 8 * n;
+    HIPCHECK(h, hipMemcpy(p, d.site[par], 4 * n, hipMemcpyDeviceToHost));
+    p += 4 * n;
+    HIPCHECK(h, hipMemcpy(p, d.s0[par], 4 * n, hipMemcpyDeviceToHost));
+    p += 4 * n;
+    for (int sec = 0; sec < 2; ++sec) {
+      HIPCHECK(h, hipMemcpy2D(p, es * n, d.N[par][sec], es * d.ld, es * n, n, hipMemcpyDeviceToHost));
+      p += es * n * n;
+    }
+  }
+  HIPCHECK(h, hipMemcpy(p, d.obs, sizeof(double) * h->obs_len[chain], hipMemcpyDeviceToHost));
+  return CTAUX_OK;
+}
+
+int ctaux_restore(ctaux_batch *h, int32_t chain, const void *buf, size_t len) {
+  if (!h || !buf || chain < 0 || chain >= h->b.n_chains) return CTAUX_EINVAL;
+  CkptHeader hd;
+  if (len < sizeof hd) return set_err(h, CTAUX_EINVAL, "checkpoint truncated");
+  memcpy(&hd, buf, sizeof hd);
+  const ChainDesc &d = h->desc[chain];
+  if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1)
+    return set_err(h, CTAUX_EINVAL, "not a version-1 checkpoint");
+  if (hd.precision != h->b.precision || hd.nc != d.nc || hd.n_tau != d.n_tau || hd.beta != d.beta ||
+      hd.K != d.K || hd.gamma != d.gamma || hd.obs_len != h->obs_len[chain])
+    return set_err(h, CTAUX_EINVAL, "checkpoint of another model or precision");
+  if (hd.n < 0 || hd.n > h->b.n_cap) return set_err(h, CTAUX_EINVAL, "checkpoint order %d exceeds n_cap", hd.n);
+  if (len < ckpt_bytes(h, chain, hd.n)) return set_err(h, CTAUX_EINVAL, "checkpoint truncated");
+  int rc = sync_states(h);
+  if (rc) return rc;
+  const int n = hd.n;
+  const size_t es = h->b.precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
+  const char *p = static_cast<const char *>(buf) + sizeof hd;
+  if (n > 0) {
+    HIPCHECK(h, hipMemcpy(d.id[0], p, 8 * n, hipMemcpyHostToDevice));
+    p += 8 * n;
+    HIPCHECK(h, hipMemcpy(d.tau[0], p, 8 * n, hipMemcpyHostToDevice));
+    p += 8 * n;
+    HIPCHECK(h, hipMemcpy(d.site[0], p, 4 * n, hipMemcpyHostToDevice));
+    p += 4 * n;
+    HIPCHECK(h, hipMemcpy(d.s0[0], p, 4 * n, hipMemcpyHostToDevice));
+    p += 4 * n;
+    for (int sec = 0; sec < 2; ++sec) {
+      HIPCHECK(h, hipMemcpy2D(d.N[0][sec], es * d.ld, p, es * n, es * n, n, hipMemcpyHostToDevice));
+      p += es * n * n;
+    }
+  }
+  HIPCHECK(h, hipMemcpy(d.obs, p, sizeof(double) * hd.obs_len, hipMemcpyHostToDevice));
+  ChainState st;
+  memset(&st, 0, sizeof st);
+  st.n = n;
+  st.n_new = n;
+  st.parity = 0;
+  st.done = hd.done;
+  st.target = hd.done;
+  st.next_id = hd.next_id;
+  st.accepted = hd.accepted;
+  st.blocks = hd.blocks;
+  st.sum_ka = hd.sum_ka;
+  st.sign = hd.sign;
+  st.max_drift = hd.max_drift;
+  st.last_drift = hd.last_drift;
+  st.rk_flops = hd.rk_flops;
+  st.rk_bytes = hd.rk_bytes;
+  st.sum_order = hd.sum_order;
+  HIPCHECK(h, hipMemcpy(h->b.d_state + chain, &st, sizeof st, hipMemcpyHostToDevice));
+  h->state[chain] = st;
+  // The refinement runs every recompute_every blocks enqueued on the batch; a
+  // one-chain batch takes over the schedule of the checkpointed one.
+  if (h->b.n_chains == 1) h->blocks_launched = hd.launches;
+  return CTAUX_OK;
+}
+
 const char *ctaux_last_error(const ctaux_batch *h) { return h ? h->err.c_str() : g_create_error; }
 
 void ctaux_destroy(ctaux_batch *h) {

@@ -24,7 +24,8 @@ OBS_HEADER = 8
 EXPORTED = [
     "ctaux_workspace_bytes", "ctaux_create", "ctaux_run", "ctaux_recompute", "ctaux_obs_len",
     "ctaux_get_obs", "ctaux_reset_obs", "ctaux_get_stats", "ctaux_get_config", "ctaux_get_N",
-    "ctaux_get_decisions", "ctaux_set_timing", "ctaux_get_timing", "ctaux_last_error", "ctaux_destroy",
+    "ctaux_get_decisions", "ctaux_set_timing", "ctaux_get_timing", "ctaux_checkpoint", "ctaux_restore",
+    "ctaux_last_error", "ctaux_destroy",
 ]
 
 
@@ -89,6 +90,8 @@ def load_library(path: str = LIB_PATH):
     lib.ctaux_set_timing.argtypes = [vp, i32]
     lib.ctaux_get_timing.restype = i32
     lib.ctaux_get_timing.argtypes = [vp, vp, vp, vp, i32]
+    lib.ctaux_checkpoint.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
+    lib.ctaux_restore.argtypes = [vp, i32, vp, C.c_size_t]
     lib.ctaux_last_error.restype = C.c_char_p
     lib.ctaux_last_error.argtypes = [vp]
     lib.ctaux_destroy.argtypes = [vp]
@@ -219,6 +222,16 @@ class CtauxBatch:
         R = np.zeros(count)
         self._check(self.lib.ctaux_get_decisions(self.h, chain, first, count, _ptr(acc), _ptr(R)))
         return acc, R
+
+    def checkpoint(self, chain: int = 0) -> bytes:
+        n = C.c_size_t(0)
+        self._check(self.lib.ctaux_checkpoint(self.h, chain, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(self.lib.ctaux_checkpoint(self.h, chain, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    def restore(self, blob: bytes, chain: int = 0):
+        self._check(self.lib.ctaux_restore(self.h, chain, C.c_char_p(blob), len(blob)))
 
     def set_timing(self, enable: bool):
         self._check(self.lib.ctaux_set_timing(self.h, 1 if enable else 0))

@@ -240,3 +240,35 @@ def test_full_size_cluster_N_is_inverse_of_definition():
     acc_o, R_o = oc2.get_log(0, 4000)
     assert np.array_equal(acc_g, acc_o)
     np.testing.assert_allclose(R_g, R_o, rtol=R_TOL)
+
+
+def test_checkpoint_restore_continues_the_chain():
+    """A chain restored into a fresh batch takes the decisions of the
+    uninterrupted chain and ends with the same configuration and N (both sides
+    run the same kernels on the same data, so bit for bit)."""
+    ctaux = _ctaux()
+    w = _cluster16()
+    n1, n2 = 2000, 3000
+    opts = ctaux.Options(k_max=64, k_cap=32, n_cap=1024, log_cap=n1 + n2, meas_every=64,
+                         n_tau_out=8, recompute_every=8, seed=5)
+    a = ctaux.CtauxBatch([w], opts)
+    a.run(n1)
+    blob = a.checkpoint(0)
+    b = ctaux.CtauxBatch([w], opts)
+    b.restore(blob, 0)
+    assert b.stats(0)["proposals"] == n1 and b.stats(0)["order"] == a.stats(0)["order"]
+    a.run(n2)
+    b.run(n2)
+    acc_a, R_a = a.decisions(0, n1, n2)
+    acc_b, R_b = b.decisions(0, n1, n2)
+    assert np.array_equal(acc_a, acc_b) and np.array_equal(R_a, R_b)
+    for x, y in zip(a.config(0), b.config(0)):
+        assert np.array_equal(x, y)
+    for sec in (0, 1):
+        assert np.array_equal(a.N(0, sec), b.N(0, sec))
+    assert np.array_equal(a.obs(0), b.obs(0))
+    # a blob of another model is refused
+    other = ctaux.CtauxBatch([_plaquette()], opts)
+    with pytest.raises(ctaux.CtauxError) as e:
+        other.restore(blob, 0)
+    assert e.value.code == ctaux.CTAUX_EINVAL
