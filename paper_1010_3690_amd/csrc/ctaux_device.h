@@ -94,4 +94,53 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wave reductions on the DPP network (VALU lane moves, no LDS round trip).
+// Prefix steps row_shr:1,2,4,8 inside each row of 16 lanes, then row_bcast:15
+// and row_bcast:31 across rows; lane 63 ends with the reduction over all 64
+// lanes (lanes shifted in from outside a row contribute the identity 0).
+// The result is read from lane 63, so it is uniform across the wave.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v) {
+  return static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, dpp_u32<0x111, 0xf>(v));   // row_shr:1
+  v = max(v, dpp_u32<0x112, 0xf>(v));   // row_shr:2
+  v = max(v, dpp_u32<0x114, 0xf>(v));   // row_shr:4
+  v = max(v, dpp_u32<0x118, 0xf>(v));   // row_shr:8
+  v = max(v, dpp_u32<0x142, 0xa>(v));   // row_bcast:15 into rows 1 and 3
+  v = max(v, dpp_u32<0x143, 0xc>(v));   // row_bcast:31 into rows 2 and 3
+  return static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
+}
+
+// Sum over the wave in a fixed order (the same for every call).
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0x111, 0xf>(v);
+  v += dpp_f64<0x112, 0xf>(v);
+  v += dpp_f64<0x114, 0xf>(v);
+  v += dpp_f64<0x118, 0xf>(v);
+  v += dpp_f64<0x142, 0xa>(v);
+  v += dpp_f64<0x143, 0xc>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), 63);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), 63);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// Value of v in lane `src` (src uniform across the wave).
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), src);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
 }  // namespace ctaux

@@ -13,13 +13,15 @@
 // One workgroup (4 waves) per chain; Gamma^{-1} of both sectors lives in LDS.
 // Threads 0..127 serve the up sector, 128..255 the down sector.
 //
-// Synchronisation: an insertion costs two barriers (after the gathers, after
-// Gamma^{-1} s and w^T Gamma^{-1}), a removal or flip three (the rank
-// selection first).  Bookkeeping that the next proposal reads (P, the spins,
-// the removed list) is written by every thread with the same value, each
-// thread reads back only what it wrote itself or what precedes a barrier, and
-// the per-proposal scalars are double-buffered by proposal parity, so no
-// barrier is needed at the end of a proposal.
+// Synchronisation: two barriers per proposal (after the gathers, after
+// Gamma^{-1} s and w^T Gamma^{-1}); they also keep the waves within one
+// proposal of each other.  Bookkeeping that the next proposal reads
+// (P, the spins, the removed list) is written by every thread with the same
+// value and each thread reads back only what it wrote itself or what precedes
+// a barrier, so every wave selects the vertex of a removal or flip on its own;
+// the per-proposal scalars are double-buffered by proposal parity.  The
+// growth of Gamma^{-1} after an acceptance is deferred to the next proposal and
+// runs while that proposal's gathers are in flight.
 //
 // Everything the loop reads from the chain descriptor is copied to registers
 // or LDS first: the loop stores to global memory, so reads through the
@@ -28,29 +30,10 @@
 
 namespace ctaux {
 
-// Pointers and sizes one sector's gathers need.
-struct GView {
-  const double *Rt, *YT, *Gnn;
-  const double *ev;   // LDS: exp(gamma*sigma*s), index s + 2
-  int ld, kmax, n;
-};
-
 // Entry G_ij of the block-start Green's function of the augmented configuration
 // (old vertices 0..n-1, candidates n..):
 //   old column j:       G_ij = (N_a,ij e^{V_j} - delta_ij) / (e^{V_j} - 1)     (Eq. NfromG)
 //   candidate column j: G_ij = (N Z)_{i, j-n} (old row) or (X Y + G0nn)_{i-n, j-n}.
-template <typename T>
-__device__ __forceinline__ double g_entry_v(const GView &g, const T *N, const int8_t *s0l, int i, int j) {
-  const int n = g.n;
-  if (j < n) {
-    const double e = g.ev[s0l[j] + 2];
-    const double nij = (i < n) ? static_cast<double>(N[static_cast<size_t>(i) * g.ld + j])
-                               : g.Rt[static_cast<size_t>(i - n) * g.ld + j];
-    return (nij * e - (i == j ? 1.0 : 0.0)) / (e - 1.0);
-  }
-  const int jj = j - n;
-  return (i < n) ? g.YT[static_cast<size_t>(jj) * g.ld + i] : g.Gnn[static_cast<size_t>(i - n) * g.kmax + jj];
-}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainState *states) {
@@ -64,10 +47,11 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   const int par = st.parity;
   const int64_t done0 = st.done;
   // descriptor fields used in the loop
-  const int kcap = d.kcap, lg = kcap + 1, n_cap = d.n_cap, kmax = d.kmax;
+  const int kcap = d.kcap, lg = kcap + 1, n_cap = d.n_cap, kmax = d.kmax, ld = d.ld;
   const double Kc = d.K;
   const bool gz = (d.gamma == 0.0);
   const T *Nsec = static_cast<const T *>(d.N[par][sec]);
+  const double *Rts = d.Rt[sec], *YTs = d.YT[sec], *Gnns = d.Gnn[sec];
   double *const gam = d.Gam[sec];
   uint8_t *const log_acc = d.log_acc;
   double *const log_R = d.log_R;
@@ -85,11 +69,12 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   int8_t *s0l = scur + (n_cap + kmax);                      // [n + kmax] block-start spins
   double *Gis = Gi + sec * kcap * lg;
   __shared__ double sh_ev[2][5];                   // exp(gamma*sigma*d), d = -2..2
+  __shared__ double sh_rm[2][5];                   // 1 / (exp(gamma*sigma*d) - 1), d = +-1
   __shared__ double sh_gpp[2][2], sh_beta[2][2];   // [proposal parity][sector]
   __shared__ double sh_gh[2][kMaxKcap];
   __shared__ double sh_pacc[kMaxKmax], sh_ppick[kMaxKmax];
   __shared__ int8_t sh_ptype[kMaxKmax], sh_pspin[kMaxKmax];
-  __shared__ int sh_p, sh_bad, sh_nnew;
+  __shared__ int sh_bad, sh_nnew;
   __shared__ int sh_perm[2][kMaxKcap];
   __shared__ int64_t sh_cid[kMaxKmax];
 
@@ -98,6 +83,11 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   double sign = st.sign;
   int status = 0, L_eff = L;
   int64_t err_index = -1;
+  // growth of Gamma^{-1} owed by the last accepted proposal: it runs while the
+  // next proposal's gathers are in flight
+  bool pend = false;
+  int pk = 0;
+  double pbeta = 1.0;
 
   for (int i = tid; i < n + kins; i += 256) {
     const int8_t v = (i < n) ? static_cast<int8_t>(d.s0[par][i]) : 0;
@@ -105,7 +95,11 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     s0l[i] = v;
   }
   if (tid == 0) sh_bad = 0;
-  if (tid < 10) sh_ev[tid / 5][tid % 5] = d.evd[tid / 5][tid % 5];
+  if (tid < 10) {
+    const double e = d.evd[tid / 5][tid % 5];
+    sh_ev[tid / 5][tid % 5] = e;
+    sh_rm[tid / 5][tid % 5] = (tid % 5 == 2) ? 0.0 : 1.0 / (e - 1.0);
+  }
   for (int t = tid; t < L; t += 256) {
     sh_ptype[t] = static_cast<int8_t>(d.ptype[t]);
     sh_pspin[t] = static_cast<int8_t>(d.pspin[t]);
@@ -113,7 +107,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     sh_ppick[t] = d.ppick[t];
   }
   __syncthreads();
-  const GView gv{d.Rt[sec], d.YT[sec], d.Gnn[sec], sh_ev[sec], d.ld, kmax, n};
+  const double *ev = sh_ev[sec], *rm = sh_rm[sec];
 
   for (int t = 0; t < L; ++t) {
     const int tp = t & 1;
@@ -132,38 +126,35 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     } else if (ncur == 0) {
       skip = 1;
     } else {
+      // rank r among interacting vertices in canonical (augmented-index) order;
+      // every wave computes it from the bookkeeping all threads wrote identically
       int r = static_cast<int>(floor(static_cast<double>(ncur) * sh_ppick[t]));
       if (r > ncur - 1) r = ncur - 1;
-      if (wave == 0) {
-        if (lane == 0) sh_p = -1;
-        // rank r among interacting vertices in canonical (augmented-index) order
-        if (r < n - ndead) {
-          // old vertex: least idx with idx = r + #{dead <= idx}
-          int idx = r;
-          while (true) {
-            const bool le = (lane < ndead) && (dead[lane] <= idx);
-            const int nw = r + __popcll(__ballot(le));
-            if (nw == idx) break;
-            idx = nw;
+      if (r < n - ndead) {
+        // old vertex: least idx with idx = r + #{dead <= idx}
+        int idx = r;
+        while (true) {
+          const bool le = (lane < ndead) && (dead[lane] <= idx);
+          const int nw = r + __popcll(__ballot(le));
+          if (nw == idx) break;
+          idx = nw;
+        }
+        p = idx;
+      } else {
+        int r2 = r - (n - ndead);
+        for (int base = 0; base < next_cand; base += 64) {
+          const int j = base + lane;
+          const bool alive = (j < next_cand) && scur[n + j] != 0;
+          const unsigned long long m = __ballot(alive);
+          const int cnt = __popcll(m);
+          if (r2 < cnt) {
+            const unsigned long long hit = __ballot(alive && __popcll(m & ((1ull << lane) - 1ull)) == r2);
+            p = n + base + __ffsll(static_cast<long long>(hit)) - 1;
+            break;
           }
-          if (lane == 0) sh_p = idx;
-        } else {
-          int r2 = r - (n - ndead);
-          for (int base = 0; base < next_cand; base += 64) {
-            const int j = base + lane;
-            const bool alive = (j < next_cand) && scur[n + j] != 0;
-            const unsigned long long m = __ballot(alive);
-            const int cnt = __popcll(m);
-            if (r2 < cnt) {
-              if (alive && __popcll(m & ((1ull << lane) - 1ull)) == r2) sh_p = n + j;
-              break;
-            }
-            r2 -= cnt;
-          }
+          r2 -= cnt;
         }
       }
-      __syncthreads();
-      p = sh_p;
       if (p < 0 || p >= n + next_cand || scur[p] == 0) {   // cannot happen unless bookkeeping is broken
         status = -4;
         L_eff = t;
@@ -179,24 +170,72 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       const int s0p = s0l[p];
       gh0 = sh_ev[0][s_new - s0p + 2] - sh_ev[0][s_old - s0p + 2];
       gh1 = sh_ev[1][s_new - s0p + 2] - sh_ev[1][s_old - s0p + 2];
+      // ---- issue the gathers: thread loc < 64 takes s_loc = G(P_loc, p) (loc == 63: G_pp),
+      // thread 64 + b takes w_b = G(p, P_b) ----
+      int gi = -1, gj = -1;
+      if (loc < 64) {
+        if (loc < ka) { gi = P[loc]; gj = p; }
+        else if (loc == 63) { gi = p; gj = p; }
+      } else if (loc - 64 < ka) {
+        gi = p;
+        gj = P[loc - 64];
+      }
+      double raw = 0.0;
+      if (gi >= 0) {
+        if (gj < n) raw = (gi < n) ? static_cast<double>(Nsec[static_cast<size_t>(gi) * ld + gj])
+                                   : Rts[static_cast<size_t>(gi - n) * ld + gj];
+        else raw = (gi < n) ? YTs[static_cast<size_t>(gj - n) * ld + gi]
+                            : Gnns[static_cast<size_t>(gi - n) * kmax + (gj - n)];
+      }
+      // ---- owed growth of Gamma^{-1} by partitioning (Sec. III B 2), LDS only ----
+      if (pend) {
+        const int k = pk;
+        const double ib = 1.0 / pbeta;
+        const double *v = vv + sec * kcap, *u = vu + sec * kcap;
+        const int b = loc & 63, a0 = loc >> 6;
+        if (b <= k) {
+          // batches of 8 rows: loads first (in flight together), then stores
+          const double ub = (b < k) ? u[b] * ib : 0.0;
+          for (int a1 = a0; a1 <= k; a1 += 16) {
+            double va[8], ga[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const int a = a1 + 2 * i;
+              va[i] = (a < k) ? v[a] : 0.0;
+              ga[i] = (a < k && b < k) ? Gis[a * lg + b] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const int a = a1 + 2 * i;
+              if (a < k) Gis[a * lg + b] = (b < k) ? ga[i] + va[i] * ub : -va[i] * ib;
+              else if (a == k) Gis[k * lg + b] = (b < k) ? -ub : ib;
+            }
+          }
+        }
+        pend = false;
+      }
+      // ---- finish the gathers; each thread also records its entry as row / column ka
+      // of Gamma for the pivoted inversion at block end (a rejected proposal's
+      // entries are overwritten by the next one) ----
       const double gh = sec == 0 ? gh0 : gh1;
-      // gather the new row / column of Gamma and G_pp; each thread also records
-      // its entry as row / column ka of Gamma for the pivoted inversion at block
-      // end (a rejected proposal's entries are overwritten by the next one)
-      if (loc < ka) {
-        const int pa = P[loc];
-        const double v = g_entry_v<T>(gv, Nsec, s0l, pa, p) - (pa == p ? 1.0 : 0.0);
-        vs[sec * kcap + loc] = v;
-        gam[loc * kcap + ka] = v;
-      } else if (loc < 2 * ka) {
-        const int b = loc - ka, pb = P[b];
-        const double v = g_entry_v<T>(gv, Nsec, s0l, p, pb) - (pb == p ? 1.0 : 0.0);
-        vw[sec * kcap + b] = v;
-        gam[ka * kcap + b] = v;
-      } else if (loc == 2 * ka) {
-        const double gpp = g_entry_v<T>(gv, Nsec, s0l, p, p);
-        sh_gpp[tp][sec] = gpp;
-        gam[ka * kcap + ka] = gpp - 1.0 - 1.0 / gh;
+      if (gi >= 0) {
+        double g = raw;
+        if (gj < n) {
+          const int sj = s0l[gj] + 2;
+          g = (raw * ev[sj] - (gi == gj ? 1.0 : 0.0)) * rm[sj];   // Eq. NfromG
+        }
+        if (loc == 63 && gi == gj && loc >= ka) {
+          sh_gpp[tp][sec] = g;
+          gam[ka * kcap + ka] = g - 1.0 - 1.0 / gh;
+        } else if (loc < 64) {
+          const double v = g - (gi == gj ? 1.0 : 0.0);
+          vs[sec * kcap + loc] = v;
+          gam[loc * kcap + ka] = v;
+        } else {
+          const double v = g - (gi == gj ? 1.0 : 0.0);
+          vw[sec * kcap + loc - 64] = v;
+          gam[ka * kcap + loc - 64] = v;
+        }
       }
       __syncthreads();
       // v = Gamma^{-1} s and beta = d - w.v (waves 0 and 2), u = w^T Gamma^{-1} (waves 1 and 3);
@@ -221,7 +260,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           vv[sec * kcap + loc] = acc;
         }
         const double x = (loc < ka) ? vw[sec * kcap + loc] * acc : 0.0;
-        const double s = wave_sum(x);
+        const double s = wave_sum_dpp(x);
         if (lane == 0) sh_beta[tp][sec] = (sh_gpp[tp][sec] - 1.0 - 1.0 / gh) - s;
       } else {
         const int b = loc - 64;
@@ -276,37 +315,15 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       nchg += 1;
       if (R < 0.0) sign = -sign;
       if (!gz) {
-        // Gamma^{-1} grows by partitioning; thread (b = loc % 64, a = loc / 64 + 2i)
-        const int k = ka;
-        const double beta = sh_beta[tp][sec];
-        const double ib = 1.0 / beta;
-        const double *v = vv + sec * kcap, *u = vu + sec * kcap;
-        const int b = loc & 63, a0 = loc >> 6;
-        if (b <= k) {
-          // batches of 8 rows: loads first (in flight together), then stores
-          const double ub = (b < k) ? u[b] * ib : 0.0;
-          for (int a1 = a0; a1 <= k; a1 += 16) {
-            double va[8], ga[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              const int a = a1 + 2 * i;
-              va[i] = (a < k) ? v[a] : 0.0;
-              ga[i] = (a < k && b < k) ? Gis[a * lg + b] : 0.0;
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              const int a = a1 + 2 * i;
-              if (a < k) Gis[a * lg + b] = (b < k) ? ga[i] + va[i] * ub : -va[i] * ib;
-              else if (a == k) Gis[k * lg + b] = (b < k) ? -ub : ib;
-            }
-          }
-        }
-        P[k] = p;           // every thread writes the same value
+        pend = true;
+        pk = ka;
+        pbeta = sh_beta[tp][sec];
+        P[ka] = p;           // every thread writes the same value
         if (tid == 0) {
-          sh_gh[0][k] = gh0;
-          sh_gh[1][k] = gh1;
+          sh_gh[0][ka] = gh0;
+          sh_gh[1][ka] = gh1;
         }
-        ka = k + 1;
+        ka += 1;
       }
       scur[p] = static_cast<int8_t>(s_new);   // every thread writes the same value
       if (type == 0) {
@@ -322,7 +339,9 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       }
     }
     if (type == 0) next_cand += 1;
-    if (gz) __syncthreads();   // U = 0 has no gather barriers; keep the selection scalar safe
+    // with U = 0 there are no gather barriers; without one here a wave could run
+    // ahead and overwrite spins another wave still has to read
+    if (gz) __syncthreads();
     if (nchg == kcap) {   // Gamma (and the removed-vertex list) is full: the block ends here
       L_eff = t + 1;
       break;
@@ -331,29 +350,56 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   __syncthreads();
 
   if (wave == 1) {
-    // ---- compaction map: interacting vertices in augmented order (one wave, ballot scan) ----
+    // ---- compaction map: interacting vertices in augmented order (one wave, ballot
+    // scan); loads of four chunks are in flight together ----
     const int na = n + kins;
     const int np = par ^ 1;
+    const double *tau_o = d.tau[par];
+    const int32_t *site_o = d.site[par];
+    const int64_t *id_o = d.id[par];
+    double *tau_n = d.tau[np];
+    int32_t *site_n = d.site[np], *s0_n = d.s0[np];
+    int64_t *id_n = d.id[np];
+    int *map = d.map;
     int running = 0;
-    for (int base = 0; base < na; base += 64) {
-      const int i = base + lane;
-      const bool alive = (i < na) && scur[i] != 0;
-      const unsigned long long m = __ballot(alive);
-      if (alive) {
-        const int pos = running + __popcll(m & ((1ull << lane) - 1ull));
-        d.map[pos] = i;
-        if (i < n) {
-          d.tau[np][pos] = d.tau[par][i];
-          d.site[np][pos] = d.site[par][i];
-          d.id[np][pos] = d.id[par][i];
-        } else {
-          d.tau[np][pos] = d.ctau[i - n];
-          d.site[np][pos] = d.csite[i - n];
-          d.id[np][pos] = sh_cid[i - n];
+    for (int base = 0; base < na; base += 256) {
+      double tv[4];
+      int sv[4];
+      int64_t iv[4];
+      bool al[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = base + q * 64 + lane;
+        al[q] = (i < na) && scur[i] != 0;
+        tv[q] = 0.0;
+        sv[q] = 0;
+        iv[q] = 0;
+        if (al[q]) {
+          if (i < n) {
+            tv[q] = tau_o[i];
+            sv[q] = site_o[i];
+            iv[q] = id_o[i];
+          } else {
+            tv[q] = d.ctau[i - n];
+            sv[q] = d.csite[i - n];
+            iv[q] = sh_cid[i - n];
+          }
         }
-        d.s0[np][pos] = scur[i];
       }
-      running += __popcll(m);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = base + q * 64 + lane;
+        const unsigned long long m = __ballot(al[q]);
+        if (al[q]) {
+          const int pos = running + __popcll(m & ((1ull << lane) - 1ull));
+          map[pos] = i;
+          tau_n[pos] = tv[q];
+          site_n[pos] = sv[q];
+          id_n[pos] = iv[q];
+          s0_n[pos] = scur[i];
+        }
+        running += __popcll(m);
+      }
     }
     if (lane == 0) sh_nnew = running;
   } else if (ka > 0 && (wave & 1) == 0) {
@@ -362,9 +408,10 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     // a vertex Gamma can be ill-conditioned (condition numbers 1e6-1e8), so the
     // N update uses Gamma^{-1} from an in-place Gauss-Jordan elimination with
     // partial pivoting of the recorded Gamma.  One wave per sector (wave 0: up,
-    // wave 2: down), lane r owns row r; all communication stays inside the
-    // wave, whose LDS operations execute in program order, so no barrier is
-    // needed.
+    // wave 2: down), lane r owns row r; rows are not swapped: a row that has
+    // served as pivot is marked used, and the permutation is undone when the
+    // result is stored.  All communication stays inside the wave, whose LDS
+    // operations execute in program order, so no barrier is needed.
     double *A = Gis;   // Gamma^{-1} of the growth is no longer needed
     // Gamma was written by this workgroup before the barriers above
     // (workgroup-scope visibility); all loads are issued before the first store
@@ -377,69 +424,75 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         if (r0 + i < ka && lane < ka) A[(r0 + i) * lg + lane] = g[i];
     }
     __builtin_amdgcn_wave_barrier();
+    const bool mine = lane < ka;
+    double *row = A + lane * lg;
+    bool used = false;
+    int mypos = 0;
+    double f = mine ? row[0] : 0.0;   // this row's entry in the pivot column
     for (int col = 0; col < ka; ++col) {
-      // pivot: largest |A[r][col]|, r >= col; |x| bits order like |x|, the low six
-      // mantissa bits carry the row so one 64-bit maximum finds both
-      unsigned long long key = 0ull;
-      if (lane >= col && lane < ka) {
-        const double x = fabs(A[lane * lg + col]);
-        key = (static_cast<unsigned long long>(__double_as_longlong(x)) & ~63ull) |
-              static_cast<unsigned long long>(lane);
+      // pivot: largest |A[r][col]| among unused rows; the high word of |x| orders
+      // like |x| to 13 mantissa bits, bit 6 marks a candidate, bits 0-5 carry the row
+      unsigned key = 0u;
+      if (mine && !used) {
+        const unsigned hi = static_cast<unsigned>(__double_as_longlong(fabs(f)) >> 32);
+        key = (hi & ~127u) | 64u | static_cast<unsigned>(lane);
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(key, off, 64);
-        key = o > key ? o : key;
-      }
-      const int p = (ka > col) ? static_cast<int>(key & 63ull) : col;
+      const int p = static_cast<int>(wave_max_u32(key) & 63u);   // uniform
+      const double ip = 1.0 / readlane_f64(f, p);
+      const bool piv = (lane == p);
       if (lane == 0) sh_perm[sec][col] = p;
-      if (p != col && lane < ka) {   // swap rows p and col (lanes over columns)
-        const double a = A[p * lg + lane], b = A[col * lg + lane];
-        A[p * lg + lane] = b;
-        A[col * lg + lane] = a;
+      if (piv) {
+        used = true;
+        mypos = col;
       }
-      __builtin_amdgcn_wave_barrier();
-      const double ip = 1.0 / A[col * lg + col];
-      __builtin_amdgcn_wave_barrier();
-      if (lane < ka) A[col * lg + lane] = (lane == col ? 1.0 : A[col * lg + lane]) * ip;
-      __builtin_amdgcn_wave_barrier();
-      if (lane < ka && lane != col) {
-        double *row = A + lane * lg;
-        const double *prow = A + col * lg;
-        const double f = row[col];
-        row[col] = 0.0;
-        for (int j1 = 0; j1 < ka; j1 += 8) {   // batches: loads in flight together, then stores
-          double rv[8], pv[8];
+      // pivot row: A[p][j] *= ip, A[p][col] = ip; other rows: A[r][j] -= f ip A[p][j],
+      // A[r][col] = -f ip
+      const double scale = piv ? ip : 1.0;
+      const double fi = piv ? 0.0 : f * ip;
+      const double xc = piv ? ip : -fi;
+      const double *prow = A + p * lg;
+      // entry of the next pivot column, from the values before this step
+      double fnext = 0.0;
+      if (mine && col + 1 < ka) fnext = row[col + 1] * scale - fi * prow[col + 1];
+      if (mine) {
+        int j1 = 0;
+        for (; j1 + 16 <= ka; j1 += 16) {   // full batches: loads in flight together, then stores
+          double rv[16], pr[16];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            rv[i] = (j1 + i < ka) ? row[j1 + i] : 0.0;
-            pv[i] = (j1 + i < ka) ? prow[j1 + i] : 0.0;
+          for (int i = 0; i < 16; ++i) {
+            rv[i] = row[j1 + i];
+            pr[i] = prow[j1 + i];
           }
 #pragma unroll
-          for (int i = 0; i < 8; ++i)
-            if (j1 + i < ka) row[j1 + i] = rv[i] - f * pv[i];
+          for (int i = 0; i < 16; ++i) row[j1 + i] = (j1 + i == col) ? xc : rv[i] * scale - fi * pr[i];
+        }
+        if (j1 < ka) {   // last partial batch; loads clamped to the row
+          double rv[16], pr[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int j = min(j1 + i, ka - 1);
+            rv[i] = row[j];
+            pr[i] = prow[j];
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (j1 + i < ka) row[j1 + i] = (j1 + i == col) ? xc : rv[i] * scale - fi * pr[i];
         }
       }
+      f = fnext;
       __builtin_amdgcn_wave_barrier();
     }
-    // undo the row interchanges as column interchanges, last first
-    for (int col = ka - 1; col >= 0; --col) {
-      const int p = sh_perm[sec][col];
-      if (p != col && lane < ka) {
-        const double a = A[lane * lg + col], b = A[lane * lg + p];
-        A[lane * lg + col] = b;
-        A[lane * lg + p] = a;
-      }
-      __builtin_amdgcn_wave_barrier();
-    }
+    // store Gamma^{-1}: row pos(r) of the inverse is row r of A with column m
+    // moved to column perm[m]
     bool bad = false;
     double *gi = d.Ginv[sec];
-    for (int r = 0; r < ka; ++r)
-      for (int j = lane; j < ka; j += 64) {
-        const double x = A[r * lg + j];
+    if (mine) {
+      for (int m = 0; m < ka; ++m) {
+        const double x = row[m];
         bad |= !isfinite(x);
-        gi[r * kcap + j] = x;
+        gi[mypos * kcap + sh_perm[sec][m]] = x;
       }
+    }
     if (__ballot(bad) != 0ull && lane == 0) sh_bad = 1;   // singular Gamma
   }
   __syncthreads();
