@@ -132,13 +132,13 @@ def leg_plain(args, precision):
     return w, gb, d
 
 
-def leg_batched(args):
+def leg_batched(args, precision):
     import torch
     from ctaux_inputs import batched_mix
     from paper_1010_3690_amd import ctaux
     ws = batched_mix(n_chains=args.batch_chains, seed=0, n_tau=2048, n_fine=16)
     gb = ctaux.CtauxBatch(ws, ctaux.Options(k_max=64, k_cap=64, recompute_every=64,
-                                            precision=ctaux.CTAUX_FP32, meas_every=64,
+                                            precision=precision, meas_every=64,
                                             n_tau_out=8, n_cap=2048, seed=0))
     gb.run(args.batch_warmup * 64)
     torch.cuda.synchronize()
@@ -166,7 +166,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--legs", default="plain,mixed,batched", help="comma list of plain,mixed,batched")
+    ap.add_argument("--legs", default="plain,mixed,batched", help="comma list of plain,mixed,batched,batched64")
     ap.add_argument("--batch-chains", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-warmup", type=int, default=30)
@@ -229,14 +229,18 @@ def main():
         forms["mixed_fp32"] = {k: sm[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}
         forms["mixed_fp32"]["max_refinement_drift"] = dm["max_drift"]
         gbm.close()
-    if "batched" in legs:
-        print(f"[bench] batched leg: {args.batch_chains} chains", file=sys.stderr, flush=True)
-        db = leg_batched(args)
+    for leg, name, prec in (("batched", "batched_fp32", ctaux.CTAUX_FP32),
+                            ("batched64", "batched_fp64", ctaux.CTAUX_FP64)):
+        if leg not in legs:
+            continue
+        print(f"[bench] {name} leg: {args.batch_chains} chains", file=sys.stderr, flush=True)
+        db = leg_batched(args, prec)
         sb = summary(db)
-        forms["batched_fp32"] = {k: sb[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}
-        forms["batched_fp32"]["n_chains"] = args.batch_chains
-        forms["batched_fp32"]["roofline"] = roofline(db, ctaux.CTAUX_FP32)
-        forms["batched_fp32"]["kernel_ms"] = sb["kernel_ms"]
+        forms[name] = {k: sb[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}
+        forms[name]["n_chains"] = args.batch_chains
+        forms[name]["max_refinement_drift"] = db["max_drift"]
+        forms[name]["roofline"] = roofline(db, prec)
+        forms[name]["kernel_ms"] = sb["kernel_ms"]
     out["forms"] = forms
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

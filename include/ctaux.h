@@ -104,6 +104,8 @@ typedef struct {
     double rankk_bytes;       /* algorithmic HBM bytes of the rank-k updates so far (read and
                                  write n'^2 entries of N, read the n' x k_a operands)          */
     double sum_order;         /* sum over blocks of the order after the block                */
+    int64_t gj_fallbacks;     /* sector-blocks whose Gamma^{-1} came from the pivoted
+                                 elimination instead of the Newton-refined growth inverse */
 } ctaux_stats;
 
 /* One vertex of a configuration (tau in [0, beta), site in [0, n_sites), s = +-1). */

@@ -159,10 +159,12 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
       d.ghat[s] = cv.take<double>(kcap);
       d.Gam[s] = cv.take<double>(static_cast<size_t>(kcap) * kcap);
       d.Ginv[s] = cv.take<double>(static_cast<size_t>(kcap) * kcap);
+      d.Rg[s] = cv.take<double>(static_cast<size_t>(kcap) * kcap);
       d.Ac[s] = cv.take<char>(es * ld * lda);
       d.Bc[s] = cv.take<char>(es * lda * ld);
       d.W[s] = cv.take<double>(static_cast<size_t>(n_cap) * nc);
       d.gR[s] = cv.take<double>(static_cast<size_t>(n_cap) * nc);
+      d.gL[s] = cv.take<double>(static_cast<size_t>(o->n_tau_out + 1) * nc * ld);
       d.Gxy[s] = cv.take<double>(static_cast<size_t>(o->n_tau_out + 1) * nc * nc);
     }
     d.P = cv.take<int32_t>(kcap);
@@ -453,6 +455,7 @@ int ctaux_get_stats(ctaux_batch *h, int32_t chain, ctaux_stats *out) {
   out->rankk_flops = st.rk_flops;
   out->rankk_bytes = st.rk_bytes;
   out->sum_order = st.sum_order;
+  out->gj_fallbacks = st.gj_fallbacks;
   return CTAUX_OK;
 }
 

@@ -94,6 +94,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
+// wait for this wave's global stores to complete, so stores whose results are
+// read only after a later full barrier stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Wave reductions on the DPP network (VALU lane moves, no LDS round trip).
 // Prefix steps row_shr:1,2,4,8 inside each row of 16 lanes, then row_bcast:15
 // and row_bcast:31 across rows; lane 63 ends with the reduction over all 64

@@ -60,7 +60,8 @@ struct ChainDesc {
   int32_t *P;              // [kcap] augmented index of each accepted change
   double *ghat[2];         // [kcap]
   double *Gam[2];          // [kcap][kcap] Gamma entries of the accepted changes
-  double *Ginv[2];         // [kcap][kcap] Gamma^{-1} (pivoted inversion at block end)
+  double *Ginv[2];         // [kcap][kcap] Gamma^{-1} for the rank-k update
+  double *Rg[2];           // [kcap][kcap] residual I - Gamma X0 of the growth inverse
   int32_t *map;            // [n_cap] new canonical index -> augmented index
   // rank-k operands (storage type of N)
   void *Ac[2];             // [ld rows][lda]  (G - I)_{map, P}
@@ -68,6 +69,7 @@ struct ChainDesc {
   // measurement
   double *W[2];            // [n_cap][nc]  N gR
   double *gR[2];           // [nc][n_cap]  G0_{x_k y}(tau_k), transposed
+  double *gL[2];           // [nc*(n_out+1)][ld]  G0_{x x_l}(tau_j - tau_l)(e^{V_l} - 1), row (j, x)
   double *Gxy[2];          // [(n_out+1)][nc*nc]  row 0 = equal time
   const int32_t *cls_off;  // [n_disp+1] pairs (x*nc+y) of each table, CSR offsets
   const int32_t *cls_pairs;  // [nc*nc]
@@ -103,6 +105,7 @@ struct ChainState {
   double rk_flops;     // algorithmic flops of operand assembly + rank-k update, summed over blocks
   double rk_bytes;     // algorithmic HBM bytes of the rank-k update (read N_a, write N', read Ac, Bc)
   double sum_order;    // sum over blocks of the order after the block
+  int64_t gj_fallbacks;  // sector-blocks whose Gamma^{-1} needed the pivoted elimination
 };
 
 // Kernel launchers (each .hip file owns its kernels).

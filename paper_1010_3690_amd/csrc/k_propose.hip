@@ -15,7 +15,9 @@
 //
 // Synchronisation: two barriers per proposal (after the gathers, after
 // Gamma^{-1} s and w^T Gamma^{-1}); they also keep the waves within one
-// proposal of each other.  Bookkeeping that the next proposal reads
+// proposal of each other.  They order LDS only: the global stores of the loop
+// (the recorded Gamma entries, the decision log) are read only after the
+// full barrier that ends the loop, so they stay in flight.  Bookkeeping that the next proposal reads
 // (P, the spins, the removed list) is written by every thread with the same
 // value and each thread reads back only what it wrote itself or what precedes
 // a barrier, so every wave selects the vertex of a removal or flip on its own;
@@ -75,6 +77,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   __shared__ double sh_pacc[kMaxKmax], sh_ppick[kMaxKmax];
   __shared__ int8_t sh_ptype[kMaxKmax], sh_pspin[kMaxKmax];
   __shared__ int sh_bad, sh_nnew;
+  __shared__ int sh_fallback[2];
   __shared__ int sh_perm[2][kMaxKcap];
   __shared__ int64_t sh_cid[kMaxKmax];
 
@@ -94,7 +97,11 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     scur[i] = v;
     s0l[i] = v;
   }
-  if (tid == 0) sh_bad = 0;
+  if (tid == 0) {
+    sh_bad = 0;
+    sh_fallback[0] = 0;
+    sh_fallback[1] = 0;
+  }
   if (tid < 10) {
     const double e = d.evd[tid / 5][tid % 5];
     sh_ev[tid / 5][tid % 5] = e;
@@ -108,6 +115,34 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   }
   __syncthreads();
   const double *ev = sh_ev[sec], *rm = sh_rm[sec];
+
+  // Gamma^{-1} of size k grows to k + 1 after an acceptance with Schur
+  // complement beta, from v = Gamma^{-1} s and u = w^T Gamma^{-1} (thread
+  // (b = loc % 64, a = loc / 64 + 2i) of the sector)
+  auto grow = [&](int k, double beta) {
+    const double ib = 1.0 / beta;
+    const double *v = vv + sec * kcap, *u = vu + sec * kcap;
+    const int b = loc & 63, a0 = loc >> 6;
+    if (b <= k) {
+      // batches of 8 rows: loads first (in flight together), then stores
+      const double ub = (b < k) ? u[b] * ib : 0.0;
+      for (int a1 = a0; a1 <= k; a1 += 16) {
+        double va[8], ga[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int a = a1 + 2 * i;
+          va[i] = (a < k) ? v[a] : 0.0;
+          ga[i] = (a < k && b < k) ? Gis[a * lg + b] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int a = a1 + 2 * i;
+          if (a < k) Gis[a * lg + b] = (b < k) ? ga[i] + va[i] * ub : -va[i] * ib;
+          else if (a == k) Gis[k * lg + b] = (b < k) ? -ub : ib;
+        }
+      }
+    }
+  };
 
   for (int t = 0; t < L; ++t) {
     const int tp = t & 1;
@@ -189,29 +224,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       }
       // ---- owed growth of Gamma^{-1} by partitioning (Sec. III B 2), LDS only ----
       if (pend) {
-        const int k = pk;
-        const double ib = 1.0 / pbeta;
-        const double *v = vv + sec * kcap, *u = vu + sec * kcap;
-        const int b = loc & 63, a0 = loc >> 6;
-        if (b <= k) {
-          // batches of 8 rows: loads first (in flight together), then stores
-          const double ub = (b < k) ? u[b] * ib : 0.0;
-          for (int a1 = a0; a1 <= k; a1 += 16) {
-            double va[8], ga[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              const int a = a1 + 2 * i;
-              va[i] = (a < k) ? v[a] : 0.0;
-              ga[i] = (a < k && b < k) ? Gis[a * lg + b] : 0.0;
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              const int a = a1 + 2 * i;
-              if (a < k) Gis[a * lg + b] = (b < k) ? ga[i] + va[i] * ub : -va[i] * ib;
-              else if (a == k) Gis[k * lg + b] = (b < k) ? -ub : ib;
-            }
-          }
-        }
+        grow(pk, pbeta);
         pend = false;
       }
       // ---- finish the gathers; each thread also records its entry as row / column ka
@@ -237,7 +250,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           gam[ka * kcap + loc - 64] = v;
         }
       }
-      __syncthreads();
+      lds_barrier();
       // v = Gamma^{-1} s and beta = d - w.v (waves 0 and 2), u = w^T Gamma^{-1} (waves 1 and 3);
       // four accumulators, loads of eight terms in flight together
       if (loc < 64) {
@@ -280,7 +293,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           vu[sec * kcap + b] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
 
     double R;
@@ -341,13 +354,17 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     if (type == 0) next_cand += 1;
     // with U = 0 there are no gather barriers; without one here a wave could run
     // ahead and overwrite spins another wave still has to read
-    if (gz) __syncthreads();
+    if (gz) lds_barrier();
     if (nchg == kcap) {   // Gamma (and the removed-vertex list) is full: the block ends here
       L_eff = t + 1;
       break;
     }
   }
   __syncthreads();
+  // the growth owed by the last acceptance: Gamma^{-1} of the growth is the
+  // starting point of the refinement below
+  if (pend) grow(pk, pbeta);
+  lds_barrier();
 
   if (wave == 1) {
     // ---- compaction map: interacting vertices in augmented order (one wave, ballot
@@ -404,93 +421,164 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     if (lane == 0) sh_nnew = running;
   } else if (ka > 0 && (wave & 1) == 0) {
     // ---- Gamma^{-1} for the rank-k update ----
-    // The ratios above came from the unpivoted growth; with repeated changes of
-    // a vertex Gamma can be ill-conditioned (condition numbers 1e6-1e8), so the
-    // N update uses Gamma^{-1} from an in-place Gauss-Jordan elimination with
-    // partial pivoting of the recorded Gamma.  One wave per sector (wave 0: up,
-    // wave 2: down), lane r owns row r; rows are not swapped: a row that has
-    // served as pivot is marked used, and the permutation is undone when the
-    // result is stored.  All communication stays inside the wave, whose LDS
-    // operations execute in program order, so no barrier is needed.
-    double *A = Gis;   // Gamma^{-1} of the growth is no longer needed
-    // Gamma was written by this workgroup before the barriers above
-    // (workgroup-scope visibility); all loads are issued before the first store
-    for (int r0 = 0; r0 < ka; r0 += 16) {
-      double g[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) g[i] = (r0 + i < ka && lane < ka) ? gam[(r0 + i) * kcap + lane] : 0.0;
-#pragma unroll
-      for (int i = 0; i < 16; ++i)
-        if (r0 + i < ka && lane < ka) A[(r0 + i) * lg + lane] = g[i];
-    }
-    __builtin_amdgcn_wave_barrier();
-    const bool mine = lane < ka;
-    double *row = A + lane * lg;
-    bool used = false;
-    int mypos = 0;
-    double f = mine ? row[0] : 0.0;   // this row's entry in the pivot column
-    for (int col = 0; col < ka; ++col) {
-      // pivot: largest |A[r][col]| among unused rows; the high word of |x| orders
-      // like |x| to 13 mantissa bits, bit 6 marks a candidate, bits 0-5 carry the row
-      unsigned key = 0u;
-      if (mine && !used) {
-        const unsigned hi = static_cast<unsigned>(__double_as_longlong(fabs(f)) >> 32);
-        key = (hi & ~127u) | 64u | static_cast<unsigned>(lane);
-      }
-      const int p = static_cast<int>(wave_max_u32(key) & 63u);   // uniform
-      const double ip = 1.0 / readlane_f64(f, p);
-      const bool piv = (lane == p);
-      if (lane == 0) sh_perm[sec][col] = p;
-      if (piv) {
-        used = true;
-        mypos = col;
-      }
-      // pivot row: A[p][j] *= ip, A[p][col] = ip; other rows: A[r][j] -= f ip A[p][j],
-      // A[r][col] = -f ip
-      const double scale = piv ? ip : 1.0;
-      const double fi = piv ? 0.0 : f * ip;
-      const double xc = piv ? ip : -fi;
-      const double *prow = A + p * lg;
-      // entry of the next pivot column, from the values before this step
-      double fnext = 0.0;
-      if (mine && col + 1 < ka) fnext = row[col + 1] * scale - fi * prow[col + 1];
-      if (mine) {
-        int j1 = 0;
-        for (; j1 + 16 <= ka; j1 += 16) {   // full batches: loads in flight together, then stores
-          double rv[16], pr[16];
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            rv[i] = row[j1 + i];
-            pr[i] = prow[j1 + i];
-          }
-#pragma unroll
-          for (int i = 0; i < 16; ++i) row[j1 + i] = (j1 + i == col) ? xc : rv[i] * scale - fi * pr[i];
-        }
-        if (j1 < ka) {   // last partial batch; loads clamped to the row
-          double rv[16], pr[16];
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int j = min(j1 + i, ka - 1);
-            rv[i] = row[j];
-            pr[i] = prow[j];
-          }
-#pragma unroll
-          for (int i = 0; i < 16; ++i)
-            if (j1 + i < ka) row[j1 + i] = (j1 + i == col) ? xc : rv[i] * scale - fi * pr[i];
-        }
-      }
-      f = fnext;
-      __builtin_amdgcn_wave_barrier();
-    }
-    // store Gamma^{-1}: row pos(r) of the inverse is row r of A with column m
-    // moved to column perm[m]
-    bool bad = false;
+    // The ratios above came from the unpivoted growth, whose inverse X0 loses
+    // accuracy when Gamma is ill-conditioned (repeated changes of one vertex
+    // give condition numbers of 1e6-1e8).  One Newton step on the recorded
+    // Gamma, R = I - Gamma X0, X1 = X0 + X0 R, makes it accurate to
+    // |R|^2 + rounding; it is taken when max|R_ij| <= 1e-8.  Otherwise
+    // Gamma^{-1} comes from an in-place Gauss-Jordan elimination with partial
+    // pivoting of the recorded Gamma.  One wave per sector (wave 0: up,
+    // wave 2: down); the products run on MFMA 16x16x4 tiles, the elimination
+    // has lane r owning row r.
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    const int nt = (ka + 15) >> 4, lr = lane & 15, lk = lane >> 4;
+    double *Rg = d.Rg[sec];
     double *gi = d.Ginv[sec];
-    if (mine) {
-      for (int m = 0; m < ka; ++m) {
-        const double x = row[m];
-        bad |= !isfinite(x);
-        gi[mypos * kcap + sh_perm[sec][m]] = x;
+    bool bad = false;
+    double rmax = 0.0;
+    for (int ti = 0; ti < nt; ++ti) {
+      const int row = ti * 16 + lr;
+      double a[16];   // Gamma[row][4s + lk]
+#pragma unroll
+      for (int s4 = 0; s4 < 16; ++s4) {
+        const int k = 4 * s4 + lk;
+        a[s4] = (row < ka && k < ka) ? gam[row * kcap + k] : 0.0;
+      }
+      for (int tj = 0; tj < nt; ++tj) {
+        const int col = tj * 16 + lr;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4) {
+          const int k = 4 * s4 + lk;
+          const double b = (k < ka && col < ka) ? Gis[k * lg + col] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = ti * 16 + lk + 4 * q;   // FP64 16x16x4 accumulator: row l/16 + 4q
+          if (r < ka && col < ka) {
+            const double x = (r == col ? 1.0 : 0.0) - acc[q];
+            Rg[r * kcap + col] = x;
+            const double ax = fabs(x);
+            rmax = (ax != ax) ? INFINITY : (ax > rmax ? ax : rmax);
+          }
+        }
+      }
+    }
+    // max|R| over the wave (high words of non-negative doubles order like the values)
+    const unsigned rhi = wave_max_u32(static_cast<unsigned>(__double_as_longlong(rmax) >> 32));
+    const bool newton = rhi <= static_cast<unsigned>(__double_as_longlong(1e-8) >> 32);
+    // R was stored by this wave's lanes and is read back by other lanes
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    if (newton) {
+      for (int tj = 0; tj < nt; ++tj) {
+        const int col = tj * 16 + lr;
+        double b[16];   // R[4s + lk][col]
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4) {
+          const int k = 4 * s4 + lk;
+          b[s4] = (k < ka && col < ka) ? Rg[k * kcap + col] : 0.0;
+        }
+        for (int ti = 0; ti < nt; ++ti) {
+          const int row = ti * 16 + lr;
+          v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int s4 = 0; s4 < 16; ++s4) {
+            const int k = 4 * s4 + lk;
+            const double a = (row < ka && k < ka) ? Gis[row * lg + k] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[s4], acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = ti * 16 + lk + 4 * q;
+            if (r < ka && col < ka) {
+              const double x = Gis[r * lg + col] + acc[q];
+              bad |= !isfinite(x);
+              gi[r * kcap + col] = x;
+            }
+          }
+        }
+      }
+    } else {
+      if (lane == 0) sh_fallback[sec] = 1;
+      double *A = Gis;   // the growth inverse is no longer needed
+      // Gamma was written by this workgroup before the full barrier after the
+      // loop (workgroup-scope visibility); all loads are issued before the first store
+      for (int r0 = 0; r0 < ka; r0 += 16) {
+        double g[16];
+  #pragma unroll
+        for (int i = 0; i < 16; ++i) g[i] = (r0 + i < ka && lane < ka) ? gam[(r0 + i) * kcap + lane] : 0.0;
+  #pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (r0 + i < ka && lane < ka) A[(r0 + i) * lg + lane] = g[i];
+      }
+      __builtin_amdgcn_wave_barrier();
+      const bool mine = lane < ka;
+      double *row = A + lane * lg;
+      bool used = false;
+      int mypos = 0;
+      double f = mine ? row[0] : 0.0;   // this row's entry in the pivot column
+      for (int col = 0; col < ka; ++col) {
+        // pivot: largest |A[r][col]| among unused rows; the high word of |x| orders
+        // like |x| to 13 mantissa bits, bit 6 marks a candidate, bits 0-5 carry the row
+        unsigned key = 0u;
+        if (mine && !used) {
+          const unsigned hi = static_cast<unsigned>(__double_as_longlong(fabs(f)) >> 32);
+          key = (hi & ~127u) | 64u | static_cast<unsigned>(lane);
+        }
+        const int p = static_cast<int>(wave_max_u32(key) & 63u);   // uniform
+        const double ip = 1.0 / readlane_f64(f, p);
+        const bool piv = (lane == p);
+        if (lane == 0) sh_perm[sec][col] = p;
+        if (piv) {
+          used = true;
+          mypos = col;
+        }
+        // pivot row: A[p][j] *= ip, A[p][col] = ip; other rows: A[r][j] -= f ip A[p][j],
+        // A[r][col] = -f ip
+        const double scale = piv ? ip : 1.0;
+        const double fi = piv ? 0.0 : f * ip;
+        const double xc = piv ? ip : -fi;
+        const double *prow = A + p * lg;
+        // entry of the next pivot column, from the values before this step
+        double fnext = 0.0;
+        if (mine && col + 1 < ka) fnext = row[col + 1] * scale - fi * prow[col + 1];
+        if (mine) {
+          int j1 = 0;
+          for (; j1 + 16 <= ka; j1 += 16) {   // full batches: loads in flight together, then stores
+            double rv[16], pr[16];
+  #pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              rv[i] = row[j1 + i];
+              pr[i] = prow[j1 + i];
+            }
+  #pragma unroll
+            for (int i = 0; i < 16; ++i) row[j1 + i] = (j1 + i == col) ? xc : rv[i] * scale - fi * pr[i];
+          }
+          if (j1 < ka) {   // last partial batch; loads clamped to the row
+            double rv[16], pr[16];
+  #pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              const int j = min(j1 + i, ka - 1);
+              rv[i] = row[j];
+              pr[i] = prow[j];
+            }
+  #pragma unroll
+            for (int i = 0; i < 16; ++i)
+              if (j1 + i < ka) row[j1 + i] = (j1 + i == col) ? xc : rv[i] * scale - fi * pr[i];
+          }
+        }
+        f = fnext;
+        __builtin_amdgcn_wave_barrier();
+      }
+      // store Gamma^{-1}: row pos(r) of the inverse is row r of A with column m
+      // moved to column perm[m]
+      if (mine) {
+        for (int m = 0; m < ka; ++m) {
+          const double x = row[m];
+          bad |= !isfinite(x);
+          gi[mypos * kcap + sh_perm[sec][m]] = x;
+        }
       }
     }
     if (__ballot(bad) != 0ull && lane == 0) sh_bad = 1;   // singular Gamma
@@ -513,6 +601,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     st.sign = sign;
     st.next_id = next_id;
     st.accepted = accepted;
+    st.gj_fallbacks += sh_fallback[0] + sh_fallback[1];
     st.status = status;
     if (status != 0) st.err_index = err_index;
     if (sh_nnew != ncur && status == 0) {

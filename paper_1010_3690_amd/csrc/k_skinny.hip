@@ -1,22 +1,24 @@
 // Skinny products with few rows on MFMA f64 16x16x4:
-//   C[m][c] = sum_k A(m, k) * B(k, c),  m < M <= 128 per work item, k < K, c < Ncols,
-// with A and B supplied by functors (array reads, G0 table lookups or gathers)
-// and the result handed to an output functor.  They are
+//   C[m][c] = sum_k A(m, k) * B(k, c),  m < M, k < K, c < Ncols,
+// with A and B supplied by functors (array reads or gathers) and the result
+// handed to an output functor.  They are
 //   - the preparation products of a block (Sec. IV A): YT = ZT N^T, Rt = X N
 //     (each reads N once) and Gnn = X YT^T + G0nn;
 //   - the operand B_c = Gamma^{-1} N_a(P, map) of the rank-k update (Sec. IV C),
 //     with N_a gathered on the fly;
-//   - the measurement (Sec. IV D): W = N gR, then G(x tau_j; y 0) = G0 + gL W
-//     with gL evaluated from the G0 tables inside the loop.
-// A work item is a 16-column tile of one product of one chain; items of all
-// chains are enumerated from a per-chain prefix that every workgroup builds in
-// LDS.  Two execution modes:
-//   - split-K: the 8 waves of a workgroup share one item, each taking every
-//     8th k-step, and their partial tiles are summed in LDS in a fixed order
-//     (few chains with long K: keeps the GPU busy);
-//   - wave: every wave owns items on its own (many chains, short K: no
-//     cross-wave reduction, no barrier per item).
-// Both sum in a fixed order, so results are deterministic.
+//   - the measurement (Sec. IV D): W = N gR, then G(x tau_j; y 0) = G0 + gL W.
+// A work item is a tile of 16*NRT rows and 16 columns of one product of one
+// chain (NRT covers the largest row count the product can have in the batch); items of all chains are enumerated from a per-chain prefix that
+// every workgroup builds in LDS.  Two execution modes:
+//   - split-K: the 8 waves of a workgroup share one item, each taking one
+//     contiguous eighth of K, and their partial tiles are summed in LDS in a
+//     fixed order (few chains with long K: keeps the GPU busy);
+//   - wave: every wave owns items on its own (many chains: no cross-wave
+//     reduction, no barrier per item).
+// Both sum in a fixed order, so results are deterministic.  The k loop keeps
+// two batches of U k-steps in flight (operands of the next batch are loaded
+// before the current batch's MFMAs), with U chosen so that NRT*U operand
+// registers stay bounded.
 #include "ctaux_device.h"
 
 namespace ctaux {
@@ -24,10 +26,8 @@ namespace ctaux {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kSkWaves = 8;
-constexpr int kSkMaxRt = kMaxKmax / 16;   // row tiles per item (M <= 128)
-constexpr int kSkUnroll = 2;
 constexpr int kSkThreads = kSkWaves * 64;
-constexpr int kMeasGRows = 16;           // rows of gL per measurement work item
+constexpr int kMeasGRt = 1;               // row tiles per measurement G item
 
 enum SkinnyKind : int { kSkPrep = 0, kSkGnn = 1, kSkMeasW = 2, kSkMeasG = 3, kSkAsmB = 4 };
 enum SkinnyMode : int { kModeSplitK = 0, kModeWave = 1 };
@@ -41,87 +41,100 @@ __device__ __forceinline__ int skinny_items(const ChainDesc &d, const ChainState
   if (kind == kSkAsmB) return (st.k_a > 0 && st.n_new > 0) ? 2 * ((st.n_new + 15) >> 4) : 0;
   if (!st.meas_now) return 0;
   if (kind == kSkMeasW) return 2 * ((n + 15) >> 4);
-  const int mtot = d.nc * (d.n_out + 1);
-  return 2 * ((mtot + kMeasGRows - 1) / kMeasGRows) * ((d.nc + 15) >> 4);
+  const int mtot = d.nc * (d.n_out + 1), rows = 16 * kMeasGRt;
+  return 2 * ((mtot + rows - 1) / rows) * ((d.nc + 15) >> 4);
 }
 
-// acc += A(m, k) B(k, c) over k = k_first + j * k_step (+ lane's k offset), this wave only.
-// bfn(k) returns B(k, c) for the lane's column c (0 outside).
-template <typename AF, typename BF>
-__device__ __forceinline__ void wave_mma(AF afn, BF bfn, int M, int K, int k_first, int k_step,
-                                         v4d (&acc)[kSkMaxRt]) {
+// acc[r] += A(16r + m, k) B(k, c) for k in [k_begin, k_end), this wave only.
+// Lane l supplies A(16r + l%16, k0 + l/16) and B(k0 + l/16, c0 + l%16);
+// bfn(k) returns B(k, c) for the lane's column (0 outside).
+template <int NRT, int U, typename AF, typename BF>
+__device__ __forceinline__ void wave_mma(AF afn, BF bfn, int M, int k_begin, int k_end, v4d (&acc)[NRT]) {
   const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-  const int nrt = (M + 15) >> 4;
-  for (int k0 = k_first; k0 < K; k0 += k_step * kSkUnroll) {
-    double bv[kSkUnroll], av[kSkUnroll][kSkMaxRt];
+  double b0[U], a0[U][NRT], b1[U], a1[U][NRT];
+  auto load = [&](double (&bv)[U], double (&av)[U][NRT], int k0) {
 #pragma unroll
-    for (int u = 0; u < kSkUnroll; ++u) {
-      const int k = k0 + u * k_step + lk;
-      const bool kok = k < K;
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + 4 * u + lk;
+      const bool kok = k < k_end;
       bv[u] = kok ? bfn(k) : 0.0;
 #pragma unroll
-      for (int r = 0; r < kSkMaxRt; ++r) {
+      for (int r = 0; r < NRT; ++r) {
         const int m = r * 16 + lr;
-        av[u][r] = (r < nrt && m < M && kok) ? afn(m, k) : 0.0;
+        av[u][r] = (kok && m < M) ? afn(m, k) : 0.0;
       }
     }
+  };
+  auto mma = [&](const double (&bv)[U], const double (&av)[U][NRT]) {
 #pragma unroll
-    for (int u = 0; u < kSkUnroll; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int r = 0; r < kSkMaxRt; ++r)
-        if (r < nrt) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][r], bv[u], acc[r], 0, 0, 0);
+      for (int r = 0; r < NRT; ++r) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][r], bv[u], acc[r], 0, 0, 0);
+  };
+  constexpr int S = 4 * U;
+  int k0 = k_begin;
+  if (k0 >= k_end) return;
+  load(b0, a0, k0);
+  while (true) {
+    load(b1, a1, k0 + S);
+    mma(b0, a0);
+    k0 += S;
+    if (k0 >= k_end) break;
+    load(b0, a0, k0 + S);
+    mma(b1, a1);
+    k0 += S;
+    if (k0 >= k_end) break;
   }
 }
 
 // One item: C tile rows [0, M), columns [c0, c0 + 16), handed to out(m, c, value).
-template <int MODE, typename AF, typename BF, typename OF>
+template <int MODE, int NRT, typename AF, typename BF, typename OF>
 __device__ __forceinline__ void skinny_item(AF afn, BF bfn, OF out, int M, int K, int Ncols, int c0, double *red) {
+  constexpr int U = NRT == 1 ? 8 : (NRT == 2 ? 4 : (NRT == 4 ? 2 : 1));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nrt = (M + 15) >> 4;
-  v4d acc[kSkMaxRt];
+  v4d acc[NRT];
 #pragma unroll
-  for (int r = 0; r < kSkMaxRt; ++r) acc[r] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int r = 0; r < NRT; ++r) acc[r] = v4d{0.0, 0.0, 0.0, 0.0};
   if (MODE == kModeWave) {
-    wave_mma(afn, bfn, M, K, 0, 4, acc);
+    wave_mma<NRT, U>(afn, bfn, M, 0, K, acc);
 #pragma unroll
-    for (int r = 0; r < kSkMaxRt; ++r) {
-      if (r < nrt) {
+    for (int r = 0; r < NRT; ++r) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int m = r * 16 + (lane >> 4) + 4 * q;   // FP64 16x16x4 accumulator: row l/16 + 4q
-          const int cc = c0 + (lane & 15);
-          if (m < M && cc < Ncols) out(m, cc, acc[r][q]);
-        }
+      for (int q = 0; q < 4; ++q) {
+        const int m = r * 16 + (lane >> 4) + 4 * q;   // FP64 16x16x4 accumulator: row l/16 + 4q
+        const int cc = c0 + (lane & 15);
+        if (m < M && cc < Ncols) out(m, cc, acc[r][q]);
       }
     }
     return;
   }
-  wave_mma(afn, bfn, M, K, wave * 4, kSkWaves * 4, acc);
+  // contiguous eighths of K, rounded to whole k-steps
+  const int chunk = (((K + kSkWaves - 1) / kSkWaves) + 3) & ~3;
+  const int kb = wave * chunk;
+  wave_mma<NRT, U>(afn, bfn, M, kb, min(K, kb + chunk), acc);
   for (int w = 0; w < kSkWaves; ++w) {   // fixed-order reduction of the partial tiles
     if (wave == w) {
 #pragma unroll
-      for (int r = 0; r < kSkMaxRt; ++r) {
-        if (r < nrt) {
+      for (int r = 0; r < NRT; ++r) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            double *p = red + (r * 64 + lane) * 4 + q;
-            *p = (w == 0) ? acc[r][q] : *p + acc[r][q];
-          }
+        for (int q = 0; q < 4; ++q) {
+          double *p = red + (r * 64 + lane) * 4 + q;
+          *p = (w == 0) ? acc[r][q] : *p + acc[r][q];
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
-  for (int e = tid; e < nrt * 256; e += kSkThreads) {
+  for (int e = tid; e < NRT * 256; e += kSkThreads) {
     const int r = e >> 8, l = (e >> 2) & 63, q = e & 3;
     const int m = r * 16 + (l >> 4) + 4 * q;
     const int cc = c0 + (l & 15);
     if (m < M && cc < Ncols) out(m, cc, red[e]);
   }
-  __syncthreads();   // red is reused by the next item
+  lds_barrier();   // red is reused by the next item
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int NRT>
 __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int kind, int local, double *red) {
   const int lane = threadIdx.x & 63, lr = lane & 15;
   const int n = st.n, par = st.parity;
@@ -138,10 +151,10 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int ki
     auto out = [=](int m, int cc, double v) { C[static_cast<size_t>(m) * ld + cc] = v; };
     if (job < 2) {
       auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(c) * ld + k]) : 0.0; };
-      skinny_item<MODE>(afn, bfn, out, st.k_ins, n, n, c0, red);
+      skinny_item<MODE, NRT>(afn, bfn, out, st.k_ins, n, n, c0, red);
     } else {
       auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(k) * ld + c]) : 0.0; };
-      skinny_item<MODE>(afn, bfn, out, st.k_ins, n, n, c0, red);
+      skinny_item<MODE, NRT>(afn, bfn, out, st.k_ins, n, n, c0, red);
     }
   } else if (kind == kSkGnn) {
     // Gnn[sec] = X YT^T + G0nn (K = 0 still writes Gnn = G0nn)
@@ -156,7 +169,7 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int ki
     auto out = [=](int m, int cc, double v) {
       Gnn[static_cast<size_t>(m) * km + cc] = v + G0nn[static_cast<size_t>(m) * km + cc];
     };
-    skinny_item<MODE>(afn, bfn, out, ki, n, ki, c0, red);
+    skinny_item<MODE, NRT>(afn, bfn, out, ki, n, ki, c0, red);
   } else if (kind == kSkAsmB) {
     // Bc[sec] = Gamma^{-1} N_a(P, map): rows a < kpad (zero beyond k_a), K = k_a
     const int np = st.n_new, ka = st.k_a, kpad = (ka + 7) & ~7, nt = (np + 15) >> 4;
@@ -176,7 +189,7 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int ki
       return pb == mj ? 1.0 : 0.0;
     };
     auto out = [=](int m, int cc, double v) { Bc[static_cast<size_t>(m) * ld + cc] = static_cast<T>(v); };
-    skinny_item<MODE>(afn, bfn, out, kpad, ka, np, c0, red);
+    skinny_item<MODE, NRT>(afn, bfn, out, kpad, ka, np, c0, red);
   } else if (kind == kSkMeasW) {
     // W[sec] = N gR as (gRT N^T)^T: C[l][y]
     const int nt = (n + 15) >> 4;
@@ -189,43 +202,38 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int ki
     auto afn = [=](int m, int k) { return gR[static_cast<size_t>(m) * ncap + k]; };
     auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(c) * ld + k]) : 0.0; };
     auto out = [=](int m, int cc, double v) { W[static_cast<size_t>(cc) * nc + m] = v; };
-    skinny_item<MODE>(afn, bfn, out, nc, n, n, c0, red);
+    skinny_item<MODE, NRT>(afn, bfn, out, nc, n, n, c0, red);
   } else {
-    // Gxy: rows m = j*nc + x (j = 0: tau = 0+, j >= 1: tau_{j-1}); item = 16 rows x 16 columns y
-    const int nc = d.nc, Mtot = nc * (d.n_out + 1);
-    const int ngroups = (Mtot + kMeasGRows - 1) / kMeasGRows, ntiles = (nc + 15) >> 4;
+    // Gxy: rows m = j*nc + x (j = 0: tau = 0+, j >= 1: tau_{j-1}); item = 16*kMeasGRt rows x 16 columns y
+    const int nc = d.nc, Mtot = nc * (d.n_out + 1), rows = 16 * kMeasGRt;
+    const int ngroups = (Mtot + rows - 1) / rows, ntiles = (nc + 15) >> 4;
     const int sec = local / (ngroups * ntiles), rem = local - sec * ngroups * ntiles;
     const int g = rem / ntiles, c0 = (rem - g * ntiles) * 16;
-    const int m0 = g * kMeasGRows, M = min(kMeasGRows, Mtot - m0);
-    const double *tau = d.tau[par], *W = d.W[sec];
-    const int32_t *site = d.site[par], *s0 = d.s0[par];
+    const int m0 = g * rows, M = min(rows, Mtot - m0), ld = d.ld;
+    const double *gL = d.gL[sec] + static_cast<size_t>(m0) * ld, *W = d.W[sec];
     const double dt = d.beta / d.n_out;
     double *Gxy = d.Gxy[sec];
     const int c = c0 + lr;
     const bool cok = c < nc;
-    auto afn = [&](int m, int l) -> double {
-      const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
-      const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
-      return g0_interp(d, sec, x, site[l], tj - tau[l]) * (d.evd[sec][s0[l] + 2] - 1.0);
-    };
+    auto afn = [=](int m, int l) { return gL[static_cast<size_t>(m) * ld + l]; };
     auto bfn = [=](int l) { return cok ? W[static_cast<size_t>(l) * nc + c] : 0.0; };
     auto out = [&](int m, int cc, double v) {
       const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
       const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
       Gxy[static_cast<size_t>(j) * nc * nc + x * nc + cc] = g0_interp(d, sec, x, cc, tj) + v;
     };
-    skinny_item<MODE>(afn, bfn, out, M, n, nc, c0, red);
+    skinny_item<MODE, NRT>(afn, bfn, out, M, n, nc, c0, red);
   }
 }
 
 // Persistent over the work items of all chains.
-template <typename T, int MODE>
+template <typename T, int MODE, int NRT>
 __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, const ChainState *states, int kind,
                                                         int n_chains) {
   extern __shared__ int pre[];   // [n_chains + 1]
   __shared__ int scan[kSkThreads];
   __shared__ int carry;
-  __shared__ double red[kSkMaxRt * 256];
+  __shared__ double red[NRT * 256];
   const int tid = threadIdx.x, wave = tid >> 6;
   if (tid == 0) { carry = 0; pre[0] = 0; }
   __syncthreads();
@@ -253,28 +261,49 @@ __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, c
       const int mid = (lo + hi) >> 1;
       if (pre[mid] <= item) lo = mid; else hi = mid;
     }
-    skinny_dispatch<T, MODE>(descs[lo], states[lo], kind, item - pre[lo], red);
+    skinny_dispatch<T, MODE, NRT>(descs[lo], states[lo], kind, item - pre[lo], red);
   }
 }
 
-template <typename T>
-static void launch_t(const Batch &b, hipStream_t s, int kind, int mode) {
+template <typename T, int MODE, int NRT>
+static void launch_k(const Batch &b, hipStream_t s, int kind) {
   const size_t lds = sizeof(int) * (b.n_chains + 1);
-  const dim3 grid(b.n_cu * 2);
-  if (mode == kModeWave)
-    hipLaunchKernelGGL((k_skinny<T, kModeWave>), grid, dim3(kSkThreads), lds, s, b.d_desc, b.d_state, kind,
-                       b.n_chains);
-  else
-    hipLaunchKernelGGL((k_skinny<T, kModeSplitK>), grid, dim3(kSkThreads), lds, s, b.d_desc, b.d_state, kind,
-                       b.n_chains);
+  hipLaunchKernelGGL((k_skinny<T, MODE, NRT>), dim3(b.n_cu * 2), dim3(kSkThreads), lds, s, b.d_desc, b.d_state, kind,
+                     b.n_chains);
+}
+
+template <typename T, int MODE>
+static void launch_m(const Batch &b, hipStream_t s, int kind, int nrt) {
+  switch (nrt) {
+    case 1: launch_k<T, MODE, 1>(b, s, kind); break;
+    case 2: launch_k<T, MODE, 2>(b, s, kind); break;
+    case 4: launch_k<T, MODE, 4>(b, s, kind); break;
+    default: launch_k<T, MODE, 8>(b, s, kind); break;
+  }
+}
+
+static int host_row_tiles(int M) {
+  const int t = (M + 15) / 16;
+  return t <= 1 ? 1 : (t <= 2 ? 2 : (t <= 4 ? 4 : 8));
 }
 
 void launch_skinny(const Batch &b, hipStream_t s, int kind) {
+  // Row tiles per item cover the largest M the kind can have in this batch:
+  // k_ins <= k_max (preparation), nc (W), k_a <= k_cap (B_c), one tile (G).
+  const int M = kind == kSkPrep || kind == kSkGnn ? b.kmax
+              : kind == kSkMeasW ? b.nc_max
+              : kind == kSkAsmB ? ((b.kcap + 7) & ~7) : 16 * kMeasGRt;
+  const int nrt = host_row_tiles(M);
   // Products with K = k_a (B_c) are short: one wave per item.  Otherwise split K
   // across the waves of a workgroup when few chains run (long K, few items).
-  const int mode = (kind == kSkAsmB || b.n_chains >= 8) ? kModeWave : kModeSplitK;
-  if (b.precision == kFP32) launch_t<float>(b, s, kind, mode);
-  else launch_t<double>(b, s, kind, mode);
+  const bool wave = (kind == kSkAsmB || b.n_chains >= 8);
+  if (b.precision == kFP32) {
+    if (wave) launch_m<float, kModeWave>(b, s, kind, nrt);
+    else launch_m<float, kModeSplitK>(b, s, kind, nrt);
+  } else {
+    if (wave) launch_m<double, kModeWave>(b, s, kind, nrt);
+    else launch_m<double, kModeSplitK>(b, s, kind, nrt);
+  }
 }
 
 }  // namespace ctaux

@@ -46,7 +46,8 @@ class _Stats(C.Structure):
     _fields_ = [("proposals", C.c_int64), ("accepted", C.c_int64), ("blocks", C.c_int64),
                 ("sum_ka", C.c_int64), ("next_id", C.c_int64), ("order", C.c_int32),
                 ("status", C.c_int32), ("sign", C.c_double), ("max_drift", C.c_double),
-                ("rankk_flops", C.c_double), ("rankk_bytes", C.c_double), ("sum_order", C.c_double)]
+                ("rankk_flops", C.c_double), ("rankk_bytes", C.c_double), ("sum_order", C.c_double),
+                ("gj_fallbacks", C.c_int64)]
 
 
 class _Vertex(C.Structure):
