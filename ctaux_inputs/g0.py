@@ -128,17 +128,30 @@ def _make_cluster(superlattice) -> Cluster:
         dif = _reduce(sites[x][None, :] - sites, a)
         for y in range(nc):
             disp[x, y] = index[tuple(dif[y])]
-    # cluster momenta: K = 2 pi a^{-1} m, reduced mod 2 pi
+    # cluster momenta: K = 2 pi a^{-1} m (m integer), reduced mod 2 pi.  They form
+    # a group of order nc generated by the unit vectors m = e_i: breadth-first
+    # closure under adding e_i.
     ainv = np.linalg.inv(a.astype(np.float64))
-    span = range(-nc, nc + 1)
-    ks = set()
-    for m in itertools.product(span, repeat=d):
+
+    def _k_of(m):
         k = 2 * np.pi * (ainv @ np.array(m, dtype=np.float64))
         k = np.mod(k, 2 * np.pi)
         k[np.isclose(k, 2 * np.pi, atol=1e-9)] = 0.0
-        ks.add(tuple(np.round(k, 9)))
-        if len(ks) > nc:
-            break
+        return tuple(np.round(k, 9))
+
+    ks = {_k_of([0] * d)}
+    frontier = [[0] * d]
+    while frontier and len(ks) <= nc:
+        nxt = []
+        for m in frontier:
+            for i in range(d):
+                m2 = list(m)
+                m2[i] += 1
+                key = _k_of(m2)
+                if key not in ks:
+                    ks.add(key)
+                    nxt.append(m2)
+        frontier = nxt
     momenta = np.array(sorted(ks), dtype=np.float64)
     if momenta.shape[0] != nc:
         raise ValueError("cluster momentum enumeration failed")

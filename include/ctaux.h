@@ -86,6 +86,11 @@ typedef struct {
     int32_t n_cap;            /* maximum order per chain                                      */
     uint64_t seed;
     int64_t log_cap;          /* decisions of proposals with index < log_cap are recorded     */
+    double gamma_tol;         /* Gamma^{-1} for the N update: the growth inverse X0 refined by
+                                 one Newton step is used when max|(I - Gamma X0)_ij| <=
+                                 gamma_tol (1e-8 is a good value); otherwise, and always when
+                                 gamma_tol < 0, a Gauss-Jordan elimination with partial
+                                 pivoting of Gamma (Sec. IV C).                               */
 } ctaux_opts;
 
 /* Per-chain counters. */

@@ -503,6 +503,17 @@ int oc_build_Minv(const oc_chain *c, int32_t sector, double *out) {
     return OC_OK;
 }
 
+int oc_build_M_of(const oc_chain *c, int32_t sector, int32_t n, const double *tau,
+                  const int32_t *site, const int32_t *s, double *out) {
+    if (sector < 0 || sector > 1 || n < 0) return OC_EINVAL;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            out[(size_t)i * n + j] =
+                (i == j ? expV(c, sector, s[i]) : 0.0) -
+                oc_g0_lookup(c, sector, site[i], site[j], tau[i] - tau[j]) * (expV(c, sector, s[j]) - 1.0);
+    return OC_OK;
+}
+
 int oc_set_config(oc_chain *c, int32_t n, const int64_t *id, const double *tau,
                   const int32_t *site, const int32_t *s, double *logabsdet, double *sgn) {
     if (n < 0 || n > c->n_cap) return fail(c, OC_ECAPACITY, "order %d exceeds n_cap", n);

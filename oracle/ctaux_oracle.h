@@ -82,6 +82,10 @@ int oc_get_config(const oc_chain *c, int64_t *id, double *tau, int32_t *site, in
 int oc_get_N(const oc_chain *c, int32_t sector, double *out);
 /* M = N^{-1} of the current configuration built from its definition (Eq. Nmatrix). */
 int oc_build_Minv(const oc_chain *c, int32_t sector, double *out);
+/* The same definition for a configuration given by its arrays (the chain only
+ * supplies the model); O(n^2), no inversion. */
+int oc_build_M_of(const oc_chain *c, int32_t sector, int32_t n, const double *tau,
+                  const int32_t *site, const int32_t *s, double *out);
 
 /* Replace the configuration (used for restore and for brute-force pins);
  * N is rebuilt by successive bordering.  log|det N_sigma^{-1}| and its sign

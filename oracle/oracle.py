@@ -57,6 +57,7 @@ def _load():
     lib.oc_get_config.argtypes = [vp, vp, vp, vp, vp]
     lib.oc_get_N.argtypes = [vp, i32, vp]
     lib.oc_build_Minv.argtypes = [vp, i32, vp]
+    lib.oc_build_M_of.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     lib.oc_set_config.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     lib.oc_get_state.argtypes = [vp, P(i64), P(i64), P(d)]
     lib.oc_set_state.argtypes = [vp, i64, i64, d]
@@ -179,6 +180,16 @@ class OracleChain:
         n = self.order
         out = np.zeros((n, n))
         self._check(self.lib.oc_build_Minv(self.h, sector, _ptr(out)))
+        return out
+
+    def M_of(self, sector: int, tau, site, s) -> np.ndarray:
+        """N^{-1} = e^V - G0 (e^V - 1) of a given configuration, from its definition."""
+        tau = np.ascontiguousarray(tau, np.float64)
+        site = np.ascontiguousarray(site, np.int32)
+        s = np.ascontiguousarray(s, np.int32)
+        n = len(tau)
+        out = np.zeros((n, n))
+        self._check(self.lib.oc_build_M_of(self.h, sector, n, _ptr(tau), _ptr(site), _ptr(s), _ptr(out)))
         return out
 
     def set_config(self, ids, tau, site, s):

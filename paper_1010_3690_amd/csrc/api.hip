@@ -86,6 +86,7 @@ int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, c
   if (o->k_cap < 1 || o->k_cap > kMaxKcap || o->k_cap > o->k_max)
     return set_err(eb, CTAUX_EINVAL, "k_cap must be in 1..min(k_max, %d)", kMaxKcap);
   if (!(o->p_flip >= 0.0 && o->p_flip <= 1.0)) return set_err(eb, CTAUX_EINVAL, "p_flip must be in [0,1]");
+  if (!isfinite(o->gamma_tol)) return set_err(eb, CTAUX_EINVAL, "gamma_tol must be finite");
   if (o->precision != CTAUX_FP64 && o->precision != CTAUX_FP32)
     return set_err(eb, CTAUX_EINVAL, "precision must be CTAUX_FP64 or CTAUX_FP32");
   if (o->meas_every < 1 || o->n_tau_out < 1 || o->n_tau_out > 4096 || o->n_cap < 1 || o->n_cap > 65536 ||
@@ -179,6 +180,7 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
       d.gamma = acosh(1.0 + m.beta * m.U * nc / (2.0 * m.K));
       d.inv_h = static_cast<double>(m.n_tau - 1) / m.beta;
       d.p_flip = o->p_flip;
+      d.gamma_tol = o->gamma_tol;
       for (int s = 0; s < 2; ++s) {
         const double sigma = s == 0 ? 1.0 : -1.0;
         for (int k = -2; k <= 2; ++k) d.evd[s][k + 2] = exp(d.gamma * sigma * k);

@@ -21,6 +21,7 @@ enum Precision : int32_t { kFP64 = 0, kFP32 = 1 };
 struct ChainDesc {
   // ---- model (Sec. II A) ----
   double beta, K, gamma, inv_h, p_flip;
+  double gamma_tol;        // Newton-refined growth inverse accepted below this residual
   double evd[2][5];        // exp(gamma*sigma*d), d = -2..2 (index d+2); sigma = +1 up, -1 down
   int32_t nc, n_tau, n_disp;
   int32_t lda;             // leading dimension of Ac rows (k_cap rounded up to 8)

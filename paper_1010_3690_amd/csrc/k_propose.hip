@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   const int64_t done0 = st.done;
   // descriptor fields used in the loop
   const int kcap = d.kcap, lg = kcap + 1, n_cap = d.n_cap, kmax = d.kmax, ld = d.ld;
-  const double Kc = d.K;
+  const double Kc = d.K, gtol = d.gamma_tol;
   const bool gz = (d.gamma == 0.0);
   const T *Nsec = static_cast<const T *>(d.N[par][sec]);
   const double *Rts = d.Rt[sec], *YTs = d.YT[sec], *Gnns = d.Gnn[sec];
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     // accuracy when Gamma is ill-conditioned (repeated changes of one vertex
     // give condition numbers of 1e6-1e8).  One Newton step on the recorded
     // Gamma, R = I - Gamma X0, X1 = X0 + X0 R, makes it accurate to
-    // |R|^2 + rounding; it is taken when max|R_ij| <= 1e-8.  Otherwise
+    // |R|^2 + rounding; it is taken when max|R_ij| <= gamma_tol.  Otherwise
     // Gamma^{-1} comes from an in-place Gauss-Jordan elimination with partial
     // pivoting of the recorded Gamma.  One wave per sector (wave 0: up,
     // wave 2: down); the products run on MFMA 16x16x4 tiles, the elimination
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     }
     // max|R| over the wave (high words of non-negative doubles order like the values)
     const unsigned rhi = wave_max_u32(static_cast<unsigned>(__double_as_longlong(rmax) >> 32));
-    const bool newton = rhi <= static_cast<unsigned>(__double_as_longlong(1e-8) >> 32);
+    const bool newton = gtol >= 0.0 && rhi <= static_cast<unsigned>(__double_as_longlong(gtol) >> 32);
     // R was stored by this wave's lanes and is read back by other lanes
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     if (newton) {

@@ -39,7 +39,7 @@ class _Opts(C.Structure):
     _fields_ = [("k_max", C.c_int32), ("k_cap", C.c_int32), ("p_flip", C.c_double),
                 ("recompute_every", C.c_int32), ("precision", C.c_int32), ("meas_every", C.c_int32),
                 ("n_therm", C.c_int64), ("n_tau_out", C.c_int32), ("n_cap", C.c_int32),
-                ("seed", C.c_uint64), ("log_cap", C.c_int64)]
+                ("seed", C.c_uint64), ("log_cap", C.c_int64), ("gamma_tol", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -113,10 +113,12 @@ class Options:
     n_cap: int = 1024
     seed: int = 0
     log_cap: int = 0
+    gamma_tol: float = 1e-8
 
     def _c(self) -> _Opts:
         return _Opts(self.k_max, self.k_cap, self.p_flip, self.recompute_every, self.precision,
-                     self.meas_every, self.n_therm, self.n_tau_out, self.n_cap, self.seed, self.log_cap)
+                     self.meas_every, self.n_therm, self.n_tau_out, self.n_cap, self.seed, self.log_cap,
+                     self.gamma_tol)
 
 
 def _ptr(a: np.ndarray):

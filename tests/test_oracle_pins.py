@@ -345,3 +345,16 @@ def test_capacity_and_input_errors():
     bad.g0_up[0, 5] = np.nan
     with pytest.raises(OracleError):
         OracleChain(bad)
+
+
+def test_M_of_configuration_equals_chain_definition():
+    """The configuration-level builder gives the chain's own N^{-1}, and N is
+    its inverse."""
+    w = hubbard_dimer(beta=2.0, U=2.0, n_tau=2001)
+    oc = OracleChain(w, seed=4)
+    oc.run(2000)
+    ids, tau, site, s = oc.config()
+    for sec in (0, 1):
+        M = oc.M_of(sec, tau, site, s)
+        assert np.array_equal(M, oc.Minv(sec))
+        assert np.abs(M @ oc.N(sec) - np.eye(len(tau))).max() < 1e-10
