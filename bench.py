@@ -15,7 +15,10 @@ time from HIP events on the library's stream over the timed region), and the
 CPU oracle timed on a bounded sample of the same workload.
 
 Extra legs (--legs): "mixed" runs the same chain with FP32 storage and the FP32
-MFMA rank-k update; "batched" runs 512 independent chains of mixed clusters.
+MFMA rank-k update; "batched" runs 512 independent chains of mixed clusters
+(Nc in {4, 8, 16, 32}, beta in [4, 12], U in [4, 8]) in FP64; "batched32" the
+same with FP32 storage, which stops with an error when a chain's refinement
+drift shows that FP32 cannot hold its N.
 """
 
 from __future__ import annotations
@@ -46,11 +49,31 @@ def _opts(ctaux, precision, n_cap=2048, k=64):
                          meas_every=k, n_therm=0, n_tau_out=16, n_cap=n_cap, seed=0)
 
 
-def timed_run(gb, steps, k, n_chains=1):
-    """Run `steps` blocks on every chain with per-kernel HIP-event timing."""
+STAT_KEYS = ("proposals", "accepted", "blocks", "sum_ka", "rankk_flops", "rankk_bytes", "sum_order",
+             "prep_flops", "prep_bytes", "meas_flops", "meas_bytes")
+
+
+def _delta(gb, s0, n_chains):
+    s1 = [gb.stats(c) for c in range(n_chains)]
+    d = {key: sum(s1[c][key] - s0[c][key] for c in range(n_chains)) for key in STAT_KEYS}
+    return d, s1
+
+
+def timed_run(gb, steps, k, n_chains=1, profile_blocks=40):
+    """Per-kernel shares from a short run with HIP events around every kernel,
+    then `steps` blocks with events around the dominant kernel only (each event
+    pair adds device time), timed on the host between synchronisations."""
     import torch
     s0 = [gb.stats(c) for c in range(n_chains)]
     gb.set_timing(True)
+    gb.run(profile_blocks * k)
+    prof = gb.timing()
+    dprof, _ = _delta(gb, s0, n_chains)
+    # the kernel with the largest device time per block; the periodic
+    # refinement does not run every block and is excluded
+    dominant = max((n for n in prof if n != "refine"), key=lambda name: prof[name][0])
+    gb.set_timing(False, kernels=[dominant])
+    s0 = [gb.stats(c) for c in range(n_chains)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gb.run(steps * k)
@@ -58,44 +81,47 @@ def timed_run(gb, steps, k, n_chains=1):
     t1 = time.perf_counter()
     timing = gb.timing()
     gb.set_timing(False)
-    s1 = [gb.stats(c) for c in range(n_chains)]
-    d = {key: sum(s1[c][key] - s0[c][key] for c in range(n_chains))
-         for key in ("proposals", "accepted", "blocks", "sum_ka", "rankk_flops", "rankk_bytes",
-                     "sum_order")}
+    d, s1 = _delta(gb, s0, n_chains)
     d["seconds"] = t1 - t0
+    d["dominant"] = dominant
     d["timing"] = timing
+    d["profile"] = {"blocks": dprof["blocks"], "timing": prof, "stats": dprof}
     d["order_now"] = [s1[c]["order"] for c in range(n_chains)]
     d["max_drift"] = max(s1[c]["max_drift"] for c in range(n_chains))
     return d
 
 
 def roofline(d, precision):
-    """Roofline of the dominant kernel of the timed region."""
-    tm = d["timing"]
-    name = max(tm, key=lambda k: tm[k][0])
-    ms, launches = tm[name]
-    out = {"kernel": name, "share": ms / sum(v[0] for v in tm.values())}
-    if name == "rankk":
-        per_launch_bytes = d["rankk_bytes"] / max(launches, 1)
-        avg_s = ms / 1e3 / max(launches, 1)
-        achieved = per_launch_bytes / avg_s / 1e9
+    """Roofline of the dominant kernel of the timed region: its algorithmic work
+    per launch over its average launch duration (HIP events on the library's
+    stream around each launch of that kernel)."""
+    name = d["dominant"]
+    ms, launches = d["timing"][name]
+    if launches == 0 or ms <= 0.0:
+        return {"kernel": name, "error": "no timed launch"}
+    avg_s = ms / 1e3 / max(launches, 1)
+    prof = d["profile"]["timing"]
+    out = {"kernel": name, "share": prof[name][0] / sum(v[0] for v in prof.values()),
+           "launches": launches, "avg_launch_us": avg_s * 1e6}
+    if name in ("rankk", "prep", "measure"):
+        key = {"rankk": "rankk_bytes", "prep": "prep_bytes", "measure": "meas_bytes"}[name]
+        achieved = d[key] / max(launches, 1) / avg_s / 1e9
         out.update({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": None})
     else:
         # The proposal loop is one workgroup per chain running k dependent
-        # proposals; its work per launch is the gathered G entries and the
-        # O(k_a^2) Gamma^{-1} arithmetic.  Report it against the FP64 vector
-        # peak of the compute units it occupies (one per chain).
+        # proposals; its work per launch is the O(k_a^2) Gamma^{-1} arithmetic
+        # (per proposal and sector two matrix-vector products with Gamma^{-1},
+        # 4 k_a^2 flops, and for an accepted proposal the growth, 2 k_a^2),
+        # reported against the FP64 vector peak of the compute units it
+        # occupies (one per chain).
         ka = d["sum_ka"] / max(d["blocks"], 1)
         k = d["proposals"] / max(d["blocks"], 1)
-        # per proposal and sector: 2 matvecs with Gamma^{-1} (2*ka^2 each) and
-        # one rank-1 growth (2*ka^2) for the accepted fraction
         acc_frac = ka / max(k, 1)
         flops_launch = d["proposals"] / max(launches, 1) * 2 * (4 * ka * ka / 4 + acc_frac * 2 * ka * ka / 4)
-        avg_s = ms / 1e3 / max(launches, 1)
         achieved = flops_launch / avg_s / 1e12
         n_chains = d.get("n_chains", 1)
-        peak = FP64_PEAK_TFS * n_chains / 256.0
+        peak = FP64_PEAK_TFS * min(n_chains, 256) / 256.0
         out.update({"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                     "frac": achieved / peak, "traffic": None})
     return out
@@ -142,22 +168,24 @@ def leg_batched(args, precision):
                                             n_tau_out=8, n_cap=2048, seed=0))
     gb.run(args.batch_warmup * 64)
     torch.cuda.synchronize()
-    d = timed_run(gb, args.batch_steps, 64, n_chains=len(ws))
+    d = timed_run(gb, args.batch_steps, 64, n_chains=len(ws), profile_blocks=4)
     d["n_chains"] = len(ws)
     return d
 
 
 def summary(d):
-    tm = d["timing"]
-    rk_s = (tm.get("assemble", (0, 0))[0] + tm.get("rankk", (0, 0))[0]) / 1e3
+    prof = d["profile"]
+    pb = max(prof["blocks"], 1)
+    rk = prof["timing"].get("rankk")
     return {
         "updates_per_s": d["proposals"] / d["seconds"],
         "accepted_per_s": d["accepted"] / d["seconds"],
-        "rankk_tflops": d["rankk_flops"] / rk_s / 1e12 if rk_s > 0 else None,
+        # rank-k TFLOP/s of the update kernel alone (operand assembly reported in kernel_us)
+        "rankk_tflops": (prof["stats"]["rankk_flops"] / (rk[0] / 1e3) / 1e12) if rk and rk[0] > 0 else None,
         "mean_order": d["sum_order"] / max(d["blocks"], 1),
         "mean_ka": d["sum_ka"] / max(d["blocks"], 1),
         "ms_per_block": d["seconds"] * 1e3 / max(d["blocks"], 1),
-        "kernel_ms": {k: round(v[0], 3) for k, v in tm.items()},
+        "kernel_us_per_block": {k: round(v[0] * 1e3 / pb, 2) for k, v in prof["timing"].items()},
     }
 
 
@@ -166,10 +194,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--legs", default="plain,mixed,batched", help="comma list of plain,mixed,batched,batched64")
+    ap.add_argument("--legs", default="plain,mixed,batched",
+                    help="comma list of plain (FP64, one chain), mixed (FP32 storage, one chain), "
+                         "batched (FP64, many chains), batched32 (FP32 storage, many chains)")
     ap.add_argument("--batch-chains", type=int, default=512)
-    ap.add_argument("--batch-steps", type=int, default=20)
-    ap.add_argument("--batch-warmup", type=int, default=30)
+    ap.add_argument("--batch-steps", type=int, default=64)
+    ap.add_argument("--batch-warmup", type=int, default=60)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -218,29 +248,35 @@ def main():
                    "k": 64, "mean_order": s["mean_order"], "mean_accepted_per_block": s["mean_ka"]},
         "rankk_tflops": s["rankk_tflops"],
         "accepted_per_s": s["accepted_per_s"],
-        "kernel_ms": s["kernel_ms"],
+        "kernel_us_per_block": s["kernel_us_per_block"],
         "roofline": roof,
     }
     forms = {"plain_fp64": {k: s[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}}
+    forms["plain_fp64"]["max_refinement_drift"] = d["max_drift"]
     if "mixed" in legs:
-        print("[bench] mixed FP32 leg", file=sys.stderr, flush=True)
+        print("[bench] mixed leg: FP32 storage, same chain", file=sys.stderr, flush=True)
         _, gbm, dm = leg_plain(args, ctaux.CTAUX_FP32)
         sm = summary(dm)
         forms["mixed_fp32"] = {k: sm[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}
         forms["mixed_fp32"]["max_refinement_drift"] = dm["max_drift"]
+        forms["mixed_fp32"]["kernel_us_per_block"] = sm["kernel_us_per_block"]
         gbm.close()
-    for leg, name, prec in (("batched", "batched_fp32", ctaux.CTAUX_FP32),
-                            ("batched64", "batched_fp64", ctaux.CTAUX_FP64)):
+    for leg, name, prec in (("batched", "batched_fp64", ctaux.CTAUX_FP64),
+                            ("batched32", "batched_fp32", ctaux.CTAUX_FP32)):
         if leg not in legs:
             continue
         print(f"[bench] {name} leg: {args.batch_chains} chains", file=sys.stderr, flush=True)
-        db = leg_batched(args, prec)
+        try:
+            db = leg_batched(args, prec)
+        except ctaux.CtauxError as e:   # FP32 storage cannot hold every chain of the mix
+            forms[name] = {"error": str(e)}
+            continue
         sb = summary(db)
         forms[name] = {k: sb[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}
         forms[name]["n_chains"] = args.batch_chains
         forms[name]["max_refinement_drift"] = db["max_drift"]
         forms[name]["roofline"] = roofline(db, prec)
-        forms[name]["kernel_ms"] = sb["kernel_ms"]
+        forms[name]["kernel_us_per_block"] = sb["kernel_us_per_block"]
     out["forms"] = forms
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

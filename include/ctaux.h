@@ -91,6 +91,9 @@ typedef struct {
                                  gamma_tol (1e-8 is a good value); otherwise, and always when
                                  gamma_tol < 0, a Gauss-Jordan elimination with partial
                                  pivoting of Gamma (Sec. IV C).                               */
+    double drift_tol;         /* a refinement whose drift exceeds drift_tol stops the chain
+                                 with CTAUX_ENUMERIC (N no longer represents the inverse of
+                                 its definition); <= 0 disables the check                     */
 } ctaux_opts;
 
 /* Per-chain counters. */
@@ -111,6 +114,13 @@ typedef struct {
     double sum_order;         /* sum over blocks of the order after the block                */
     int64_t gj_fallbacks;     /* sector-blocks whose Gamma^{-1} came from the pivoted
                                  elimination instead of the Newton-refined growth inverse */
+    double prep_flops;        /* algorithmic flops of the preparation products: per sector
+                                 4 n^2 k_ins (YT, Rt) + 2 k_ins^2 n (Gnn)                      */
+    double prep_bytes;        /* their algorithmic HBM bytes: N read twice, X, ZT, YT, Rt once */
+    double meas_flops;        /* algorithmic flops of the measurements: per sector
+                                 2 n^2 nc (W) + 2 nc^2 (n_out+1) n (G)                         */
+    double meas_bytes;        /* their algorithmic bytes: N read once, gL written and read,
+                                 two table reads per gL entry, gR                              */
 } ctaux_stats;
 
 /* One vertex of a configuration (tau in [0, beta), site in [0, n_sites), s = +-1). */
@@ -165,9 +175,11 @@ int ctaux_get_N(ctaux_batch *b, int32_t chain, int32_t sector, double *out, int3
 int ctaux_get_decisions(ctaux_batch *b, int32_t chain, int64_t first, int64_t count,
                         uint8_t *acc, double *R);
 /* Per-kernel device time (ms) accumulated since the last reset, measured with
- * HIP events when opts enable it via ctaux_set_timing(b, 1).  names[i] are
+ * HIP events around the launches selected by ctaux_set_timing(b, mask): bit i
+ * of mask selects entry i of the names ctaux_get_timing reports (-1: all,
+ * 0: off; every event pair adds a little time to the stream).  names[i] are
  * static strings; returns the number of entries written (<= cap). */
-int ctaux_set_timing(ctaux_batch *b, int32_t enable);
+int ctaux_set_timing(ctaux_batch *b, int32_t mask);
 int32_t ctaux_get_timing(ctaux_batch *b, const char **names, double *ms, int64_t *launches,
                          int32_t cap);
 

@@ -52,7 +52,7 @@ struct ctaux_batch {
   int32_t recompute_every = 0;
   int64_t log_cap = 0;
   int32_t obs_len_max = 0;
-  bool timing = false;
+  int32_t timing = 0;                 // bit i: time kernel i (kKernelNames)
   std::vector<TimedEvent> pool;       // created events
   size_t pool_used = 0;
   double ms[kNumNames] = {0};
@@ -86,7 +86,8 @@ int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, c
   if (o->k_cap < 1 || o->k_cap > kMaxKcap || o->k_cap > o->k_max)
     return set_err(eb, CTAUX_EINVAL, "k_cap must be in 1..min(k_max, %d)", kMaxKcap);
   if (!(o->p_flip >= 0.0 && o->p_flip <= 1.0)) return set_err(eb, CTAUX_EINVAL, "p_flip must be in [0,1]");
-  if (!isfinite(o->gamma_tol)) return set_err(eb, CTAUX_EINVAL, "gamma_tol must be finite");
+  if (!isfinite(o->gamma_tol) || !isfinite(o->drift_tol))
+    return set_err(eb, CTAUX_EINVAL, "gamma_tol and drift_tol must be finite");
   if (o->precision != CTAUX_FP64 && o->precision != CTAUX_FP32)
     return set_err(eb, CTAUX_EINVAL, "precision must be CTAUX_FP64 or CTAUX_FP32");
   if (o->meas_every < 1 || o->n_tau_out < 1 || o->n_tau_out > 4096 || o->n_cap < 1 || o->n_cap > 65536 ||
@@ -118,13 +119,18 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
   const size_t es = o->precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
   ChainDesc *d_desc = cv.take<ChainDesc>(n_chains);
   ChainState *d_state = cv.take<ChainState>(n_chains);
-  double *r_M = cv.take<double>(static_cast<size_t>(ld) * ld);
-  double *r_R = cv.take<double>(static_cast<size_t>(ld) * ld);
-  double *r_N = cv.take<double>(static_cast<size_t>(ld) * ld);
-  double *r_red = cv.take<double>(4096);
+  // refinement pool: room for one chain at n_cap, and for all chains at n_cap
+  // up to 4 GiB; chains are refined in groups that fit
+  const size_t need_cap = 2ull * refine_slots(o->precision) * static_cast<size_t>(n_cap) * n_cap;
+  size_t pool = static_cast<size_t>(n_chains) * need_cap;
+  const size_t pool_limit = (size_t{4} << 30) / sizeof(double);
+  if (pool > pool_limit) pool = pool_limit > need_cap ? pool_limit : need_cap;
+  double *r_pool = cv.take<double>(pool);
+  RefineItem *r_items = cv.take<RefineItem>(n_chains);
+  double *r_red = cv.take<double>(refine_red_doubles(n_chains));
   if (bt) {
     bt->d_desc = d_desc; bt->d_state = d_state;
-    bt->r_M = r_M; bt->r_R = r_R; bt->r_N = r_N; bt->r_red = r_red;
+    bt->r_pool = r_pool; bt->r_pool_doubles = pool; bt->r_items = r_items; bt->r_red = r_red;
   }
   for (int c = 0; c < n_chains; ++c) {
     const ctaux_model &m = models[c];
@@ -181,6 +187,7 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
       d.inv_h = static_cast<double>(m.n_tau - 1) / m.beta;
       d.p_flip = o->p_flip;
       d.gamma_tol = o->gamma_tol;
+      d.drift_tol = o->drift_tol;
       for (int s = 0; s < 2; ++s) {
         const double sigma = s == 0 ? 1.0 : -1.0;
         for (int k = -2; k <= 2; ++k) d.evd[s][k + 2] = exp(d.gamma * sigma * k);
@@ -205,7 +212,7 @@ struct Timer {
   int name;
   TimedEvent *ev = nullptr;
   Timer(ctaux_batch *h_, int name_) : h(h_), name(name_) {
-    if (!h->timing) return;
+    if (!(h->timing & (1 << name))) return;
     if (h->pool_used == h->pool.size()) {
       TimedEvent e;
       e.name = name;
@@ -240,6 +247,36 @@ int sync_states(ctaux_batch *h) {
   return CTAUX_OK;
 }
 
+// Refines every healthy chain: reads the orders (one synchronisation), packs
+// the chains into groups whose scratch fits the pool, and launches each group.
+int refine_all(ctaux_batch *h) {
+  int rc = sync_states(h);
+  if (rc) return rc;
+  const Batch &b = h->b;
+  const size_t slots = static_cast<size_t>(refine_slots(b.precision));
+  std::vector<RefineItem> items;
+  std::vector<int> starts;
+  size_t used = 0;
+  for (int c = 0; c < b.n_chains; ++c) {
+    const ChainState &st = h->state[c];
+    if (st.status != 0) continue;
+    const size_t need = 2 * slots * static_cast<size_t>(st.n) * st.n;
+    if (starts.empty() || used + need > b.r_pool_doubles) {
+      starts.push_back(static_cast<int>(items.size()));
+      used = 0;
+    }
+    items.push_back(RefineItem{c, st.n, static_cast<int64_t>(used)});
+    used += need;
+  }
+  if (items.empty()) return CTAUX_OK;
+  HIPCHECK(h, hipMemcpy(b.r_items, items.data(), sizeof(RefineItem) * items.size(), hipMemcpyHostToDevice));
+  starts.push_back(static_cast<int>(items.size()));
+  Timer t(h, 8);
+  for (size_t g = 0; g + 1 < starts.size(); ++g)
+    launch_refine_group(b, h->stream, b.r_items + starts[g], starts[g + 1] - starts[g]);
+  return CTAUX_OK;
+}
+
 int enqueue_block(ctaux_batch *h) {
   const Batch &b = h->b;
   hipStream_t s = h->stream;
@@ -253,8 +290,8 @@ int enqueue_block(ctaux_batch *h) {
   { Timer t(h, 7); launch_measure(b, s); }
   h->blocks_launched += 1;
   if (h->recompute_every > 0 && h->blocks_launched % h->recompute_every == 0) {
-    Timer t(h, 8);
-    for (int c = 0; c < b.n_chains; ++c) launch_refine(b, s, c);
+    int rc = refine_all(h);
+    if (rc) return rc;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(h, CTAUX_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -271,6 +308,9 @@ int chain_error(ctaux_batch *h) {
     if (st.status == CTAUX_ECAPACITY)
       return set_err(h, CTAUX_ECAPACITY, "chain %d: an insertion at proposal %lld would exceed n_cap=%d", c,
                      (long long)st.err_index, h->b.n_cap);
+    if (st.status != 0 && st.err_index == -5)
+      return set_err(h, st.status, "chain %d: refinement drift %.3g exceeds drift_tol (N is no longer the "
+                     "inverse of its definition; FP32 storage cannot hold this model)", c, st.last_drift);
     if (st.status != 0)
       return set_err(h, st.status, "chain %d: numerical failure (code %d) at proposal %lld, drift %.3g", c,
                      st.status, (long long)st.err_index, st.last_drift);
@@ -406,10 +446,8 @@ int ctaux_run(ctaux_batch *h, int64_t n_proposals) {
 
 int ctaux_recompute(ctaux_batch *h, double *max_drift_out) {
   if (!h) return CTAUX_EINVAL;
-  {
-    Timer t(h, 8);
-    for (int c = 0; c < h->b.n_chains; ++c) launch_refine(h->b, h->stream, c);
-  }
+  int rc0 = refine_all(h);
+  if (rc0) return rc0;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(h, CTAUX_EDEVICE, "refine launch failed: %s", hipGetErrorString(e));
   int rc = sync_states(h);
@@ -458,6 +496,10 @@ int ctaux_get_stats(ctaux_batch *h, int32_t chain, ctaux_stats *out) {
   out->rankk_bytes = st.rk_bytes;
   out->sum_order = st.sum_order;
   out->gj_fallbacks = st.gj_fallbacks;
+  out->prep_flops = st.prep_flops;
+  out->prep_bytes = st.prep_bytes;
+  out->meas_flops = st.meas_flops;
+  out->meas_bytes = st.meas_bytes;
   return CTAUX_OK;
 }
 
@@ -514,11 +556,11 @@ int ctaux_get_decisions(ctaux_batch *h, int32_t chain, int64_t first, int64_t co
   return CTAUX_OK;
 }
 
-int ctaux_set_timing(ctaux_batch *h, int32_t enable) {
+int ctaux_set_timing(ctaux_batch *h, int32_t mask) {
   if (!h) return CTAUX_EINVAL;
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   flush_timing(h);
-  h->timing = enable != 0;
+  h->timing = mask;
   for (int i = 0; i < kNumNames; ++i) {
     h->ms[i] = 0.0;
     h->launches[i] = 0;

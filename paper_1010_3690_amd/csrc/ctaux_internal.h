@@ -22,6 +22,7 @@ struct ChainDesc {
   // ---- model (Sec. II A) ----
   double beta, K, gamma, inv_h, p_flip;
   double gamma_tol;        // Newton-refined growth inverse accepted below this residual
+  double drift_tol;        // refinement drift above this stops the chain (<= 0: no check)
   double evd[2][5];        // exp(gamma*sigma*d), d = -2..2 (index d+2); sigma = +1 up, -1 down
   int32_t nc, n_tau, n_disp;
   int32_t lda;             // leading dimension of Ac rows (k_cap rounded up to 8)
@@ -107,6 +108,8 @@ struct ChainState {
   double rk_bytes;     // algorithmic HBM bytes of the rank-k update (read N_a, write N', read Ac, Bc)
   double sum_order;    // sum over blocks of the order after the block
   int64_t gj_fallbacks;  // sector-blocks whose Gamma^{-1} needed the pivoted elimination
+  double prep_flops, prep_bytes;   // algorithmic work of the preparation products
+  double meas_flops, meas_bytes;   // algorithmic work of the measurements
 };
 
 // Kernel launchers (each .hip file owns its kernels).
@@ -119,7 +122,16 @@ void launch_assemble(const Batch &b, hipStream_t s);
 void launch_rankk(const Batch &b, hipStream_t s);
 void launch_block_end(const Batch &b, hipStream_t s);
 void launch_measure(const Batch &b, hipStream_t s);
-void launch_refine(const Batch &b, hipStream_t s, int32_t chain);
+// Refinement of a group of chains: each item names a chain, its order and the
+// offset (in doubles) of its scratch in the refinement pool.
+struct RefineItem {
+  int32_t chain;
+  int32_t n;
+  int64_t off;
+};
+int refine_slots(int precision);           // n x n scratch blocks per sector
+size_t refine_red_doubles(int n_items);    // partial sums for the drift of n_items chains
+void launch_refine_group(const Batch &b, hipStream_t s, const RefineItem *items, int n_items);
 void launch_set_target(const Batch &b, hipStream_t s, int64_t n_proposals);
 
 // Host-side view of a batch used by the launchers.
@@ -131,9 +143,11 @@ struct Batch {
   ChainDesc *d_desc;         // device [n_chains]
   ChainState *d_state;       // device [n_chains]
   int32_t n_cu;
-  // refinement scratch (one chain at a time), FP64
-  double *r_M, *r_R, *r_N;   // [ld*ld] each
-  double *r_red;             // [2*1024] partial sums for the drift
+  // refinement: scratch pool for a group of chains, the group's items, drift partial sums
+  double *r_pool;
+  size_t r_pool_doubles;
+  RefineItem *r_items;       // [n_chains]
+  double *r_red;             // [refine_red_doubles(n_chains)]
 };
 
 }  // namespace ctaux

@@ -149,12 +149,27 @@ __global__ void k_block_end(const ChainDesc *descs, ChainState *states, int n_ch
   st.rk_flops += 2.0 * (2.0 * np * np * ka + 2.0 * ka * ka * np);
   st.rk_bytes += 2.0 * es * (2.0 * np * np + 2.0 * np * ka);
   st.sum_order += np;
+  // preparation of this block (per sector): YT = ZT N^T and Rt = X N read N once
+  // each (2 n^2 k_ins flops each), Gnn = X YT^T + G0nn (2 k_ins^2 n)
+  {
+    const double n0 = st.n, ki = st.k_ins;
+    st.prep_flops += 2.0 * (4.0 * n0 * n0 * ki + 2.0 * ki * ki * n0);
+    st.prep_bytes += 2.0 * (2.0 * es * n0 * n0 + 8.0 * 4.0 * ki * n0);
+  }
   st.n = st.n_new;
   st.parity ^= 1;
   st.done += st.L_eff;
   st.blocks += 1;
   st.sum_ka += st.k_a;
   st.meas_now = (st.done % d.meas_every == 0 && st.done > d.n_therm) ? 1 : 0;
+  if (st.meas_now) {
+    // measurement (per sector): W = N gR reads N once (2 n^2 nc flops); gL has
+    // nc (n_out + 1) n entries, each two table reads, written and read once;
+    // G = G0 + gL W (2 nc (n_out + 1) n nc flops)
+    const double m = static_cast<double>(d.nc) * (d.n_out + 1), nc = d.nc;
+    st.meas_flops += 2.0 * (2.0 * np * np * nc + 2.0 * m * np * nc);
+    st.meas_bytes += 2.0 * (es * np * np + 8.0 * (2.0 + 2.0) * m * np + 8.0 * 2.0 * np * nc);
+  }
 }
 
 void launch_block_end(const Batch &b, hipStream_t s) {

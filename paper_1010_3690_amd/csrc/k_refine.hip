@@ -6,130 +6,237 @@
 // the current configuration from an updated N whose error is small (FP64
 // rounding drift, or the ~1e-7 error of FP32 storage), and the drift is the
 // relative error N had before the step, to first order.
+//
+// All chains of a batch are refined together: the host packs chains into
+// groups whose scratch (M and R per sector, plus an FP64 copy of N for FP32
+// storage, n x n each, packed) fits the refinement pool, and each group costs
+// five launches whatever its size.  The products run persistent over the
+// 64x64 tiles of every chain and sector of the group.
 #include "ctaux_device.h"
 
 namespace ctaux {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_build_M(const ChainDesc *descs, const ChainState *states, int c,
-                                                 int sec, double *M) {
-  const ChainDesc &d = descs[c];
-  const ChainState &st = states[c];
-  const int n = st.n, par = st.parity;
+constexpr int kRefBlocks = 64;   // workgroups per chain for the elementwise kernels
+
+// Per-chain scratch of a group: [sector][M, R, Nd] blocks of n*n doubles.
+__device__ __forceinline__ double *ref_slot(double *pool, const RefineItem &it, int sec, int which, int nslots) {
+  const size_t nn = static_cast<size_t>(it.n) * it.n;
+  return pool + it.off + (static_cast<size_t>(sec) * nslots + which) * nn;
+}
+
+// M (and, for FP32 storage, an FP64 copy of N) of both sectors.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ref_build(const ChainDesc *descs, const ChainState *states,
+                                                   const RefineItem *items, double *pool) {
+  const RefineItem it = items[blockIdx.y];
+  const ChainDesc &d = descs[it.chain];
+  const ChainState &st = states[it.chain];
+  const int n = it.n, par = st.parity;
+  const int nslots = (sizeof(T) == sizeof(double)) ? 2 : 3;
   const double *tau = d.tau[par];
   const int32_t *site = d.site[par], *s0 = d.s0[par];
-  const int64_t total = static_cast<int64_t>(n) * n;
-  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
-    const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<int64_t>(i) * n);
+  const int64_t per = static_cast<int64_t>(n) * n;
+  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < 2 * per; e += gridDim.x * 256ll) {
+    const int sec = e >= per ? 1 : 0;
+    const int64_t r = e - sec * per;
+    const int i = static_cast<int>(r / n), j = static_cast<int>(r - static_cast<int64_t>(i) * n);
     const double evj = d.evd[sec][s0[j] + 2];
     double v = -g0_interp(d, sec, site[i], site[j], tau[i] - tau[j]) * (evj - 1.0);
     if (i == j) v += d.evd[sec][s0[i] + 2];
-    M[static_cast<size_t>(i) * d.ld + j] = v;
+    ref_slot(pool, it, sec, 0, nslots)[r] = v;
+    if (sizeof(T) != sizeof(double)) {
+      const T *N = static_cast<const T *>(d.N[par][sec]);
+      ref_slot(pool, it, sec, 2, nslots)[r] = static_cast<double>(N[static_cast<size_t>(i) * d.ld + j]);
+    }
   }
 }
 
+// C = alpha A B + diag I on 64x64 tiles, FP64 MFMA 16x16x4, K staged through LDS
+// in chunks of 32 with the next chunk's loads in flight during the current
+// chunk's MFMAs.  mode 0: R = I - M N;  mode 1: T = N R (into M's slot).
+constexpr int kGK = 32;
 template <typename T>
-__global__ __launch_bounds__(256) void k_to_f64(const ChainDesc *descs, const ChainState *states, int c,
-                                                int sec, double *out) {
-  const ChainDesc &d = descs[c];
-  const ChainState &st = states[c];
-  const int n = st.n;
-  const T *N = static_cast<const T *>(d.N[st.parity][sec]);
-  const int64_t total = static_cast<int64_t>(n) * n;
-  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
-    const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<int64_t>(i) * n);
-    out[static_cast<size_t>(i) * d.ld + j] = static_cast<double>(N[static_cast<size_t>(i) * d.ld + j]);
-  }
-}
-
-// C = alpha * A B + diag * I   (n x n, leading dimension ld), FP64 MFMA 16x16x4,
-// 64x64 tile per workgroup, K staged through LDS in chunks of 16.
-constexpr int kGK = 16;
-__global__ __launch_bounds__(256) void k_gemm_f64(const ChainState *states, int c, int ld, const double *A,
-                                                  const double *B, double *C, double alpha, double diag) {
-  const int n = states[c].n;
-  const int tiles = (n + 63) / 64;
-  const int tti = blockIdx.y, tj = blockIdx.x;
-  if (tti >= tiles || tj >= tiles) return;
-  __shared__ double As[64][kGK + 1];
-  __shared__ double Bs[kGK][64 + 1];
+__global__ __launch_bounds__(256) void k_ref_gemm(const ChainDesc *descs, const ChainState *states,
+                                                  const RefineItem *items, int n_items, double *pool, int mode) {
+  extern __shared__ int pre[];   // [n_items + 1]
+  __shared__ double As[2][64][kGK + 1];
+  __shared__ double Bs[2][kGK][64 + 1];
+  __shared__ int scan[256];
+  __shared__ int carry;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1, lr = lane & 15, lk = lane >> 4;
-  const int r0 = tti * 64, c0 = tj * 64;
-  v4d acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < n; k0 += kGK) {
-    for (int e = tid; e < 64 * kGK; e += 256) {
-      const int r = e / kGK, q = e % kGK;
-      As[r][q] = (r0 + r < n && k0 + q < n) ? A[static_cast<size_t>(r0 + r) * ld + k0 + q] : 0.0;
-      const int qb = e / 64, cb = e % 64;
-      Bs[qb][cb] = (k0 + qb < n && c0 + cb < n) ? B[static_cast<size_t>(k0 + qb) * ld + c0 + cb] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kGK; kk += 4) {
-      double af[2], bf[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) af[i] = As[wr * 32 + i * 16 + lr][kk + lk];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) bf[j] = Bs[kk + lk][wc * 32 + j * 16 + lr];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      for (int q = 0; q < 4; ++q) {
-        const int r = r0 + wr * 32 + i * 16 + lk + 4 * q;   // FP64 16x16x4 accumulator: row l/16 + 4q
-        const int cc = c0 + wc * 32 + j * 16 + lr;
-        if (r < n && cc < n) C[static_cast<size_t>(r) * ld + cc] = alpha * acc[i][j][q] + (r == cc ? diag : 0.0);
-      }
-}
-
-// N <- N + T (T = N R held in `t`), and per-workgroup partial sums of T^2 and N'^2.
-template <typename T>
-__global__ __launch_bounds__(256) void k_refine_apply(const ChainDesc *descs, const ChainState *states, int c,
-                                                      int sec, const double *nd, const double *t, double *red) {
-  const ChainDesc &d = descs[c];
-  const ChainState &st = states[c];
-  const int n = st.n;
-  T *N = static_cast<T *>(d.N[st.parity][sec]);
-  const int64_t total = static_cast<int64_t>(n) * n;
-  double s_t = 0.0, s_n = 0.0;
-  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
-    const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<int64_t>(i) * n);
-    const size_t o = static_cast<size_t>(i) * d.ld + j;
-    const double tv = t[o];
-    const double nv = nd[o] + tv;
-    N[o] = static_cast<T>(nv);
-    s_t += tv * tv;
-    s_n += nv * nv;
-  }
-  __shared__ double sh[2][4];
-  s_t = wave_sum(s_t);
-  s_n = wave_sum(s_n);
-  if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = s_t; sh[1][threadIdx.x >> 6] = s_n; }
+  const int nslots = (sizeof(T) == sizeof(double)) ? 2 : 3;
+  if (tid == 0) { carry = 0; pre[0] = 0; }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    red[2 * (sec * gridDim.x + blockIdx.x)] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-    red[2 * (sec * gridDim.x + blockIdx.x) + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+  for (int base = 0; base < n_items; base += 256) {
+    const int q = base + tid;
+    int v = 0;
+    if (q < n_items) {
+      const int nt = (items[q].n + 63) / 64;
+      v = 2 * nt * nt;
+    }
+    scan[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int x = tid >= off ? scan[tid - off] : 0;
+      __syncthreads();
+      scan[tid] += x;
+      __syncthreads();
+    }
+    if (q < n_items) pre[q + 1] = carry + scan[tid];
+    __syncthreads();
+    if (tid == 0) carry += scan[255];
+    __syncthreads();
+  }
+  const int total = pre[n_items];
+  const int wr = wave >> 1, wc = wave & 1, lr = lane & 15, lk = lane >> 4;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = n_items;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pre[mid] <= t) lo = mid; else hi = mid;
+    }
+    const RefineItem it = items[lo];
+    const ChainDesc &d = descs[it.chain];
+    const ChainState &st = states[it.chain];
+    const int n = it.n, nt = (n + 63) / 64;
+    int local = t - pre[lo];
+    const int sec = local / (nt * nt);
+    local -= sec * nt * nt;
+    const int r0 = (local / nt) * 64, c0 = (local % nt) * 64;
+    double *Ms = ref_slot(pool, it, sec, 0, nslots);
+    double *Rs = ref_slot(pool, it, sec, 1, nslots);
+    // N as an FP64 operand: the storage itself (FP64) or its copy (FP32)
+    const double *Nd;
+    int ldn;
+    if (sizeof(T) == sizeof(double)) {
+      Nd = static_cast<const double *>(d.N[st.parity][sec]);
+      ldn = d.ld;
+    } else {
+      Nd = ref_slot(pool, it, sec, 2, nslots);
+      ldn = n;
+    }
+    const double *A = mode == 0 ? Ms : Nd;
+    const int lda = mode == 0 ? n : ldn;
+    const double *B = mode == 0 ? Nd : Rs;
+    const int ldb = mode == 0 ? ldn : n;
+    double *C = mode == 0 ? Rs : Ms;
+    const double alpha = mode == 0 ? -1.0 : 1.0, diag = mode == 0 ? 1.0 : 0.0;
+    // staging: thread tid loads row tid/4 of the A chunk (8 consecutive k) and
+    // row tid/8 of the B chunk (8 consecutive columns)
+    const int ar = tid >> 2, ak = (tid & 3) * 8;
+    const int bk = tid >> 3, bc = (tid & 7) * 8;
+    double ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = r0 + ar, k = k0 + ak + i;
+        ra[i] = (r < n && k < n) ? A[static_cast<size_t>(r) * lda + k] : 0.0;
+        const int kb = k0 + bk, cc = c0 + bc + i;
+        rb[i] = (kb < n && cc < n) ? B[static_cast<size_t>(kb) * ldb + cc] : 0.0;
+      }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        As[buf][ar][ak + i] = ra[i];
+        Bs[buf][bk][bc + i] = rb[i];
+      }
+    };
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < n; k0 += kGK) {
+      const bool more = k0 + kGK < n;
+      if (more) load(k0 + kGK);   // in flight during this chunk's MFMAs
+#pragma unroll
+      for (int kk = 0; kk < kGK; kk += 4) {
+        double af[2], bf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[i] = As[buf][wr * 32 + i * 16 + lr][kk + lk];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bf[j] = Bs[buf][kk + lk][wc * 32 + j * 16 + lr];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = r0 + wr * 32 + i * 16 + lk + 4 * q;   // FP64 16x16x4 accumulator: row l/16 + 4q
+          const int cc = c0 + wc * 32 + j * 16 + lr;
+          if (r < n && cc < n) C[static_cast<size_t>(r) * n + cc] = alpha * acc[i][j][q] + (r == cc ? diag : 0.0);
+        }
   }
 }
 
-__global__ void k_refine_reduce(ChainState *states, int c, const double *red, int nblk) {
-  if (threadIdx.x != 0) return;
+// N <- N + T (T = N R in M's slot), and per-workgroup partial sums of T^2 and N'^2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ref_apply(const ChainDesc *descs, const ChainState *states,
+                                                   const RefineItem *items, double *pool, double *red) {
+  const RefineItem it = items[blockIdx.y];
+  const ChainDesc &d = descs[it.chain];
+  const ChainState &st = states[it.chain];
+  const int n = it.n, nslots = (sizeof(T) == sizeof(double)) ? 2 : 3;
+  __shared__ double sh[2][4];
+  for (int sec = 0; sec < 2; ++sec) {
+    T *N = static_cast<T *>(d.N[st.parity][sec]);
+    const double *t = ref_slot(pool, it, sec, 0, nslots);
+    const double *nd = (sizeof(T) == sizeof(double)) ? nullptr : ref_slot(pool, it, sec, 2, nslots);
+    const int64_t total = static_cast<int64_t>(n) * n;
+    double s_t = 0.0, s_n = 0.0;
+    for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
+      const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<int64_t>(i) * n);
+      const size_t o = static_cast<size_t>(i) * d.ld + j;
+      const double tv = t[e];
+      const double nv = (nd ? nd[e] : static_cast<double>(N[o])) + tv;
+      N[o] = static_cast<T>(nv);
+      s_t += tv * tv;
+      s_n += nv * nv;
+    }
+    s_t = wave_sum(s_t);
+    s_n = wave_sum(s_n);
+    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = s_t; sh[1][threadIdx.x >> 6] = s_n; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double *r = red + ((static_cast<size_t>(blockIdx.y) * 2 + sec) * gridDim.x + blockIdx.x) * 2;
+      r[0] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+      r[1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    }
+    __syncthreads();
+  }
+}
+
+// Drift of every chain of the group (partial sums in a fixed order).
+__global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const RefineItem *items, int n_items,
+                             const double *red) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_items) return;
+  const int c = items[q].chain;
   ChainState &st = states[c];
   double drift = 0.0;
   for (int sec = 0; sec < 2; ++sec) {
     double a = 0.0, b = 0.0;
-    for (int i = 0; i < nblk; ++i) {
-      a += red[2 * (sec * nblk + i)];
-      b += red[2 * (sec * nblk + i) + 1];
+    const double *r = red + (static_cast<size_t>(q) * 2 + sec) * kRefBlocks * 2;
+    for (int i = 0; i < kRefBlocks; ++i) {
+      a += r[2 * i];
+      b += r[2 * i + 1];
     }
     const double dr = (b > 0.0) ? sqrt(a / b) : 0.0;
     if (!isfinite(dr)) drift = INFINITY;
@@ -138,37 +245,37 @@ __global__ void k_refine_reduce(ChainState *states, int c, const double *red, in
   st.last_drift = drift;
   if (!(drift <= st.max_drift)) st.max_drift = drift;
   if (!isfinite(drift) && st.status == 0) st.status = -4;
+  if (st.status == 0 && descs[c].drift_tol > 0.0 && drift > descs[c].drift_tol) {
+    st.status = -4;   // N no longer represents the inverse of its definition
+    st.err_index = -5;
+  }
 }
 
-constexpr int kApplyBlocks = 512;
+int refine_slots(int precision) { return precision == kFP64 ? 2 : 3; }
 
-void launch_refine(const Batch &b, hipStream_t s, int32_t c) {
-  const int tiles = (b.n_cap + 63) / 64;
-  const dim3 ggrid(tiles, tiles);
-  const int eblocks = 1024;
-  for (int sec = 0; sec < 2; ++sec) {
-    hipLaunchKernelGGL(k_build_M, dim3(eblocks), dim3(256), 0, s, b.d_desc, b.d_state, c, sec, b.r_M);
-    // N (current parity, known only on the device) is copied into r_N as the FP64 GEMM
-    // operand: n^2 traffic, negligible next to the two n^3 products.
-    const double *nd;
-    if (b.precision == kFP64) {
-      hipLaunchKernelGGL(k_to_f64<double>, dim3(eblocks), dim3(256), 0, s, b.d_desc, b.d_state, c, sec, b.r_N);
-    } else {
-      hipLaunchKernelGGL(k_to_f64<float>, dim3(eblocks), dim3(256), 0, s, b.d_desc, b.d_state, c, sec, b.r_N);
-    }
-    nd = b.r_N;
-    // R = I - M N
-    hipLaunchKernelGGL(k_gemm_f64, ggrid, dim3(256), 0, s, b.d_state, c, b.ld, b.r_M, nd, b.r_R, -1.0, 1.0);
-    // T = N R  (into r_M)
-    hipLaunchKernelGGL(k_gemm_f64, ggrid, dim3(256), 0, s, b.d_state, c, b.ld, nd, b.r_R, b.r_M, 1.0, 0.0);
-    if (b.precision == kFP64)
-      hipLaunchKernelGGL(k_refine_apply<double>, dim3(kApplyBlocks), dim3(256), 0, s, b.d_desc, b.d_state, c,
-                         sec, nd, b.r_M, b.r_red);
-    else
-      hipLaunchKernelGGL(k_refine_apply<float>, dim3(kApplyBlocks), dim3(256), 0, s, b.d_desc, b.d_state, c,
-                         sec, nd, b.r_M, b.r_red);
-  }
-  hipLaunchKernelGGL(k_refine_reduce, dim3(1), dim3(64), 0, s, b.d_state, c, b.r_red, kApplyBlocks);
+size_t refine_red_doubles(int n_items) { return static_cast<size_t>(n_items) * 2 * kRefBlocks * 2; }
+
+template <typename T>
+static void launch_group_t(const Batch &b, hipStream_t s, const RefineItem *items, int n_items) {
+  hipLaunchKernelGGL(k_ref_build<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
+                     b.r_pool);
+  const size_t lds = sizeof(int) * (n_items + 1);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ref_gemm<T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  for (int mode = 0; mode < 2; ++mode)
+    hipLaunchKernelGGL(k_ref_gemm<T>, dim3(b.n_cu * 2), dim3(256), lds, s, b.d_desc, b.d_state, items, n_items,
+                       b.r_pool, mode);
+  hipLaunchKernelGGL(k_ref_apply<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
+                     b.r_pool, b.r_red);
+  hipLaunchKernelGGL(k_ref_reduce, dim3((n_items + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items,
+                     b.r_red);
+}
+
+// One group of chains (items in device memory, scratch offsets within the pool).
+void launch_refine_group(const Batch &b, hipStream_t s, const RefineItem *items, int n_items) {
+  if (n_items <= 0) return;
+  if (b.precision == kFP64) launch_group_t<double>(b, s, items, n_items);
+  else launch_group_t<float>(b, s, items, n_items);
 }
 
 }  // namespace ctaux

@@ -20,6 +20,9 @@ LIB_PATH = os.path.join(_HERE, "lib", "libctaux_hip.so")
 CTAUX_OK, CTAUX_EINVAL, CTAUX_ENOMEM, CTAUX_EDEVICE, CTAUX_ENUMERIC, CTAUX_ECAPACITY = 0, -1, -2, -3, -4, -5
 CTAUX_FP64, CTAUX_FP32 = 0, 1
 OBS_HEADER = 8
+# order of the per-kernel timing entries (ctaux_get_timing)
+TIMED_KERNELS = ["block_begin", "interp", "prep", "propose", "assemble", "rankk", "block_end", "measure",
+                 "refine"]
 
 EXPORTED = [
     "ctaux_workspace_bytes", "ctaux_create", "ctaux_run", "ctaux_recompute", "ctaux_obs_len",
@@ -39,7 +42,8 @@ class _Opts(C.Structure):
     _fields_ = [("k_max", C.c_int32), ("k_cap", C.c_int32), ("p_flip", C.c_double),
                 ("recompute_every", C.c_int32), ("precision", C.c_int32), ("meas_every", C.c_int32),
                 ("n_therm", C.c_int64), ("n_tau_out", C.c_int32), ("n_cap", C.c_int32),
-                ("seed", C.c_uint64), ("log_cap", C.c_int64), ("gamma_tol", C.c_double)]
+                ("seed", C.c_uint64), ("log_cap", C.c_int64), ("gamma_tol", C.c_double),
+                ("drift_tol", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -47,7 +51,8 @@ class _Stats(C.Structure):
                 ("sum_ka", C.c_int64), ("next_id", C.c_int64), ("order", C.c_int32),
                 ("status", C.c_int32), ("sign", C.c_double), ("max_drift", C.c_double),
                 ("rankk_flops", C.c_double), ("rankk_bytes", C.c_double), ("sum_order", C.c_double),
-                ("gj_fallbacks", C.c_int64)]
+                ("gj_fallbacks", C.c_int64), ("prep_flops", C.c_double), ("prep_bytes", C.c_double),
+                ("meas_flops", C.c_double), ("meas_bytes", C.c_double)]
 
 
 class _Vertex(C.Structure):
@@ -114,11 +119,12 @@ class Options:
     seed: int = 0
     log_cap: int = 0
     gamma_tol: float = 1e-8
+    drift_tol: float = 1e-2
 
     def _c(self) -> _Opts:
         return _Opts(self.k_max, self.k_cap, self.p_flip, self.recompute_every, self.precision,
                      self.meas_every, self.n_therm, self.n_tau_out, self.n_cap, self.seed, self.log_cap,
-                     self.gamma_tol)
+                     self.gamma_tol, self.drift_tol)
 
 
 def _ptr(a: np.ndarray):
@@ -236,8 +242,16 @@ class CtauxBatch:
     def restore(self, blob: bytes, chain: int = 0):
         self._check(self.lib.ctaux_restore(self.h, chain, C.c_char_p(blob), len(blob)))
 
-    def set_timing(self, enable: bool):
-        self._check(self.lib.ctaux_set_timing(self.h, 1 if enable else 0))
+    def set_timing(self, enable, kernels=None):
+        """Time every kernel (enable True), none (False), or only the named ones."""
+        mask = 0
+        if kernels is not None:
+            names = TIMED_KERNELS
+            for k in kernels:
+                mask |= 1 << names.index(k)
+        elif enable:
+            mask = -1
+        self._check(self.lib.ctaux_set_timing(self.h, mask))
 
     def timing(self) -> dict:
         cap = 32
