@@ -91,6 +91,24 @@ def timed_run(gb, steps, k, n_chains=1, profile_blocks=40):
     return d
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel's source has changed since the counters
+    were taken (the summary records the source's SHA-256)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_bytes_per_launch.txt")
+    src = {"propose": "k_propose.hip", "rankk": "k_update.hip"}.get(kernel)
+    if src is None or not os.path.exists(path):
+        return None
+    with open(os.path.join(ROOT, "paper_1010_3690_amd", "csrc", src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 3 and not line.startswith("#") and parts[0] == kernel and parts[2] == sha:
+            return float(parts[1])
+    return None
+
+
 def roofline(d, precision):
     """Roofline of the dominant kernel of the timed region: its algorithmic work
     per launch over its average launch duration (HIP events on the library's
@@ -123,7 +141,7 @@ def roofline(d, precision):
         n_chains = d.get("n_chains", 1)
         peak = FP64_PEAK_TFS * min(n_chains, 256) / 256.0
         out.update({"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                    "frac": achieved / peak, "traffic": None})
+                    "frac": achieved / peak, "traffic": measured_traffic(name) if n_chains == 1 else None})
     return out
 
 
@@ -159,17 +177,26 @@ def leg_plain(args, precision):
 
 
 def leg_batched(args, precision):
+    """512 chains; with --autotune the block length and rank-k tile come from
+    paper_1010_3690_amd.autotune (trials continue the same thermalised chains)."""
     import torch
     from ctaux_inputs import batched_mix
     from paper_1010_3690_amd import ctaux
     ws = batched_mix(n_chains=args.batch_chains, seed=0, n_tau=2048, n_fine=16)
-    gb = ctaux.CtauxBatch(ws, ctaux.Options(k_max=64, k_cap=64, recompute_every=64,
-                                            precision=precision, meas_every=64,
-                                            n_tau_out=8, n_cap=2048, seed=0))
+    opts = ctaux.Options(k_max=64, k_cap=64, recompute_every=64, precision=precision, meas_every=64,
+                         n_tau_out=8, n_cap=2048, seed=0)
+    tuning = None
+    if args.autotune:
+        from paper_1010_3690_amd.autotune import autotune
+        print("[bench] autotuning the batched form", file=sys.stderr, flush=True)
+        opts, tuning = autotune(ws, opts, warmup_proposals=args.batch_warmup * 64, trial_proposals=32 * 64)
+    gb = ctaux.CtauxBatch(ws, opts)
     gb.run(args.batch_warmup * 64)
     torch.cuda.synchronize()
     d = timed_run(gb, args.batch_steps, 64, n_chains=len(ws), profile_blocks=4)
     d["n_chains"] = len(ws)
+    d["options"] = {"k_max": opts.k_max, "k_cap": opts.k_cap, "rankk_tile": opts.rankk_tile}
+    d["tuning"] = tuning
     return d
 
 
@@ -202,6 +229,8 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=60)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=True,
+                    help="choose k and the rank-k tile of the batched legs with the autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 10 device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -277,6 +306,10 @@ def main():
         forms[name]["max_refinement_drift"] = db["max_drift"]
         forms[name]["roofline"] = roofline(db, prec)
         forms[name]["kernel_us_per_block"] = sb["kernel_us_per_block"]
+        forms[name]["options"] = db["options"]
+        if db["tuning"]:
+            forms[name]["autotune"] = [{k: (round(v, 1) if isinstance(v, float) else v) for k, v in r.items()}
+                                       for r in db["tuning"]]
     out["forms"] = forms
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

@@ -94,6 +94,8 @@ typedef struct {
     double drift_tol;         /* a refinement whose drift exceeds drift_tol stops the chain
                                  with CTAUX_ENUMERIC (N no longer represents the inverse of
                                  its definition); <= 0 disables the check                     */
+    int32_t rankk_tile;       /* output tile edge of the rank-k update: 64, 32, or 0 for 64;
+                                 smaller tiles waste less of the ragged edge at small orders  */
 } ctaux_opts;
 
 /* Per-chain counters. */

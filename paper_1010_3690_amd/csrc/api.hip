@@ -88,6 +88,8 @@ int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, c
   if (!(o->p_flip >= 0.0 && o->p_flip <= 1.0)) return set_err(eb, CTAUX_EINVAL, "p_flip must be in [0,1]");
   if (!isfinite(o->gamma_tol) || !isfinite(o->drift_tol))
     return set_err(eb, CTAUX_EINVAL, "gamma_tol and drift_tol must be finite");
+  if (o->rankk_tile != 0 && o->rankk_tile != 32 && o->rankk_tile != 64)
+    return set_err(eb, CTAUX_EINVAL, "rankk_tile must be 0, 32 or 64");
   if (o->precision != CTAUX_FP64 && o->precision != CTAUX_FP32)
     return set_err(eb, CTAUX_EINVAL, "precision must be CTAUX_FP64 or CTAUX_FP32");
   if (o->meas_every < 1 || o->n_tau_out < 1 || o->n_tau_out > 4096 || o->n_cap < 1 || o->n_cap > 65536 ||
@@ -350,7 +352,11 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
   b.precision = opts->precision;
   b.nc_max = 1;
   b.n_out_max = opts->n_tau_out;
-  for (int c = 0; c < n_chains; ++c) b.nc_max = models[c].n_sites > b.nc_max ? models[c].n_sites : b.nc_max;
+  b.n_tau_max = 2;
+  for (int c = 0; c < n_chains; ++c) {
+    b.nc_max = models[c].n_sites > b.nc_max ? models[c].n_sites : b.nc_max;
+    b.n_tau_max = models[c].n_tau > b.n_tau_max ? models[c].n_tau : b.n_tau_max;
+  }
   int dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -358,6 +364,7 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
     return set_err(nullptr, CTAUX_EDEVICE, "no HIP device");
   }
   b.n_cu = prop.multiProcessorCount;
+  b.rankk_tile = opts->rankk_tile == 32 ? 32 : 64;
   b.grid_per_chain = n_chains >= 2048 ? 1 : 2048 / n_chains;
   if (b.grid_per_chain > 1024) b.grid_per_chain = 1024;
   h->recompute_every = opts->recompute_every;
@@ -404,6 +411,8 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
     st[c].sign = 1.0;
   }
   h->state = st;
+  setup_propose(b);
+  setup_refine(b);
   if (hipMemcpy(b.d_desc, h->desc.data(), sizeof(ChainDesc) * n_chains, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b.d_state, st.data(), sizeof(ChainState) * n_chains, hipMemcpyHostToDevice) != hipSuccess) {
     delete h;

@@ -14,7 +14,7 @@ namespace ctaux {
 
 constexpr int kMaxKcap = 64;    // Gamma capacity per block (Gamma^{-1} of both sectors in LDS)
 constexpr int kMaxKmax = 128;   // proposals per block
-constexpr int kTile = 64;       // rank-k output tile edge
+
 
 enum Precision : int32_t { kFP64 = 0, kFP32 = 1 };
 
@@ -133,13 +133,17 @@ int refine_slots(int precision);           // n x n scratch blocks per sector
 size_t refine_red_doubles(int n_items);    // partial sums for the drift of n_items chains
 void launch_refine_group(const Batch &b, hipStream_t s, const RefineItem *items, int n_items);
 void launch_set_target(const Batch &b, hipStream_t s, int64_t n_proposals);
+// per-batch kernel attributes (dynamic LDS limits), once at creation
+void setup_propose(const Batch &b);
+void setup_refine(const Batch &b);
 
 // Host-side view of a batch used by the launchers.
 struct Batch {
   int32_t n_chains;
-  int32_t kmax, kcap, n_cap, ld, nc_max, n_out_max;
+  int32_t kmax, kcap, n_cap, ld, nc_max, n_out_max, n_tau_max;
   int32_t precision;
   int32_t grid_per_chain;    // workgroups per chain for per-chain streaming kernels
+  int32_t rankk_tile;        // rank-k output tile edge, 64 or 32
   ChainDesc *d_desc;         // device [n_chains]
   ChainState *d_state;       // device [n_chains]
   int32_t n_cu;

@@ -616,17 +616,22 @@ size_t propose_lds_bytes(const Batch &b) {
          2ull * static_cast<size_t>(b.n_cap + b.kmax) + 16;
 }
 
+// Dynamic LDS limits are set once per batch: the call costs host time that would
+// otherwise sit between the launches of every block.
+void setup_propose(const Batch &b) {
+  const int lds = static_cast<int>(propose_lds_bytes(b));
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_propose<double>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_propose<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
 void launch_propose(const Batch &b, hipStream_t s) {
   const size_t lds = propose_lds_bytes(b);
-  if (b.precision == kFP64) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_propose<double>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (b.precision == kFP64)
     hipLaunchKernelGGL(k_propose<double>, dim3(b.n_chains), dim3(256), lds, s, b.d_desc, b.d_state);
-  } else {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_propose<float>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  else
     hipLaunchKernelGGL(k_propose<float>, dim3(b.n_chains), dim3(256), lds, s, b.d_desc, b.d_state);
-  }
 }
 
 }  // namespace ctaux

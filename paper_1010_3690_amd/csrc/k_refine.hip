@@ -260,8 +260,6 @@ static void launch_group_t(const Batch &b, hipStream_t s, const RefineItem *item
   hipLaunchKernelGGL(k_ref_build<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
                      b.r_pool);
   const size_t lds = sizeof(int) * (n_items + 1);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ref_gemm<T>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   for (int mode = 0; mode < 2; ++mode)
     hipLaunchKernelGGL(k_ref_gemm<T>, dim3(b.n_cu * 2), dim3(256), lds, s, b.d_desc, b.d_state, items, n_items,
                        b.r_pool, mode);
@@ -269,6 +267,14 @@ static void launch_group_t(const Batch &b, hipStream_t s, const RefineItem *item
                      b.r_pool, b.r_red);
   hipLaunchKernelGGL(k_ref_reduce, dim3((n_items + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items,
                      b.r_red);
+}
+
+void setup_refine(const Batch &b) {
+  const int lds = static_cast<int>(sizeof(int) * (b.n_chains + 1));
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ref_gemm<double>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ref_gemm<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 // One group of chains (items in device memory, scratch offsets within the pool).

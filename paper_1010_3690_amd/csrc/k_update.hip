@@ -8,8 +8,8 @@
 //   Ac[i'][a] = (G - I)_{map(i'), P_a}           (n' x k_a)
 //   Bc[a][j'] = sum_b Gamma^{-1}_{ab} N_a(P_b, map(j'))   (k_a x n')
 // and k_rankk computes N'[i'][j'] = N_a(map i', map j') - (Ac Bc)[i'][j'] on
-// MFMA 16x16x4 tiles (FP64, or FP32 for FP32 storage), 64x64 outputs per
-// workgroup, tiles of every chain scheduled from one persistent grid.
+// MFMA 16x16x4 tiles (FP64, or FP32 for FP32 storage), 64x64 or 32x32 outputs
+// per workgroup, tiles of every chain scheduled from one persistent grid.
 #include "ctaux_device.h"
 
 namespace ctaux {
@@ -94,12 +94,14 @@ __device__ __forceinline__ T base_entry(const ChainDesc &d, const T *N, const do
 
 // MFMA 16x16x4 operand layout (one 16x16 block): lane l supplies A[l%16][k0 + l/16]
 // and B[k0 + l/16][l%16]; accumulator register q holds D[Mfma<T>::row(l/16, q)][l%16].
-// Persistent over the tiles of all chains: chain c owns tiles [prefix[c],
-// prefix[c+1]), 2 sectors x ceil(n'/64)^2 each; every workgroup builds the
-// prefix in LDS first.
-template <typename T>
+// Output tiles of TILE x TILE (64 or 32), each of the four waves owning a
+// TILE/2 square of NB x NB MFMA blocks.  Persistent over the tiles of all
+// chains: chain c owns tiles [prefix[c], prefix[c+1]), 2 sectors x
+// ceil(n'/TILE)^2 each; every workgroup builds the prefix in LDS first.
+template <typename T, int TILE>
 __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const ChainState *states, int n_chains) {
   typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int SUB = TILE / 2, NB = SUB / 16;
   extern __shared__ int prefix[];   // [n_chains + 1]
   __shared__ int scan[256];
   __shared__ int carry;
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
     const int cc = base + threadIdx.x;
     int v = 0;
     if (cc < n_chains && states[cc].active) {
-      const int nt = (states[cc].n_new + kTile - 1) / kTile;
+      const int nt = (states[cc].n_new + TILE - 1) / TILE;
       v = 2 * nt * nt;
     }
     scan[threadIdx.x] = v;
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
     const ChainDesc &d = descs[c];
     const ChainState &st = states[c];
     const int n = st.n, np = st.n_new, ka = st.k_a;
-    const int nt = (np + kTile - 1) / kTile;
+    const int nt = (np + TILE - 1) / TILE;
     int local = t - prefix[c];
     const int sec = local / (nt * nt);
     local -= sec * nt * nt;
@@ -151,60 +153,76 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
     const T *Ac = static_cast<const T *>(d.Ac[sec]);
     const T *Bc = static_cast<const T *>(d.Bc[sec]);
     const double *Rt = d.Rt[sec];
-    const int row0 = ti * kTile + wr * 32, col0 = tj * kTile + wc * 32;
-    acc_t acc[2][2];
+    const int row0 = ti * TILE + wr * SUB, col0 = tj * TILE + wc * SUB;
+    // the N_a entries this lane updates, loaded before the k loop so that their
+    // latency overlaps the products
+    T base[NB][NB][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < NB; ++j) {
+      const int cc = col0 + j * 16 + lr;
+      const int mj = cc < np ? d.map[cc] : 0;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::zero();
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = row0 + i * 16 + Mfma<T>::row(lk, q);
+          base[i][j][q] = (r < np && cc < np) ? base_entry<T>(d, N, Rt, n, d.map[r], mj) : T(0);
+        }
+    }
+    acc_t acc[NB][NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[i][j] = Mfma<T>::zero();
     if (ka > 0) {
       const int kpad = (ka + 7) & ~7;
       for (int k0 = 0; k0 < kpad; k0 += 4) {
-        T af[2], bf[2];
+        T af[NB], bf[NB];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < NB; ++i) {
           const int r = row0 + i * 16 + lr;
           af[i] = (r < np) ? Ac[static_cast<size_t>(r) * d.lda + k0 + lk] : T(0);
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NB; ++j) {
           const int cc = col0 + j * 16 + lr;
           bf[j] = (cc < np) ? Bc[static_cast<size_t>(k0 + lk) * d.ld + cc] : T(0);
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::mma(af[i], bf[j], acc[i][j]);
+          for (int j = 0; j < NB; ++j) acc[i][j] = Mfma<T>::mma(af[i], bf[j], acc[i][j]);
       }
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NB; ++j) {
       const int cc = col0 + j * 16 + lr;
       if (cc >= np) continue;
-      const int mj = d.map[cc];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < NB; ++i) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = row0 + i * 16 + Mfma<T>::row(lk, q);
-          if (r < np) {
-            const int mi = d.map[r];
-            const T base = base_entry<T>(d, N, Rt, n, mi, mj);
-            Nout[static_cast<size_t>(r) * d.ld + cc] = base - acc[i][j][q];
-          }
+          if (r < np) Nout[static_cast<size_t>(r) * d.ld + cc] = base[i][j][q] - acc[i][j][q];
         }
       }
     }
   }
 }
 
-void launch_rankk(const Batch &b, hipStream_t s) {
+template <typename T>
+static void launch_rankk_t(const Batch &b, hipStream_t s) {
   const int grid = b.n_cu * 8;
   const size_t lds = sizeof(int) * (b.n_chains + 1);
-  if (b.precision == kFP64)
-    hipLaunchKernelGGL(k_rankk<double>, dim3(grid), dim3(256), lds, s, b.d_desc, b.d_state, b.n_chains);
+  if (b.rankk_tile == 32)
+    hipLaunchKernelGGL((k_rankk<T, 32>), dim3(grid), dim3(256), lds, s, b.d_desc, b.d_state, b.n_chains);
   else
-    hipLaunchKernelGGL(k_rankk<float>, dim3(grid), dim3(256), lds, s, b.d_desc, b.d_state, b.n_chains);
+    hipLaunchKernelGGL((k_rankk<T, 64>), dim3(grid), dim3(256), lds, s, b.d_desc, b.d_state, b.n_chains);
+}
+
+void launch_rankk(const Batch &b, hipStream_t s) {
+  if (b.precision == kFP64) launch_rankk_t<double>(b, s);
+  else launch_rankk_t<float>(b, s);
 }
 
 }  // namespace ctaux

@@ -43,7 +43,7 @@ class _Opts(C.Structure):
                 ("recompute_every", C.c_int32), ("precision", C.c_int32), ("meas_every", C.c_int32),
                 ("n_therm", C.c_int64), ("n_tau_out", C.c_int32), ("n_cap", C.c_int32),
                 ("seed", C.c_uint64), ("log_cap", C.c_int64), ("gamma_tol", C.c_double),
-                ("drift_tol", C.c_double)]
+                ("drift_tol", C.c_double), ("rankk_tile", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -120,11 +120,12 @@ class Options:
     log_cap: int = 0
     gamma_tol: float = 1e-8
     drift_tol: float = 1e-2
+    rankk_tile: int = 64
 
     def _c(self) -> _Opts:
         return _Opts(self.k_max, self.k_cap, self.p_flip, self.recompute_every, self.precision,
                      self.meas_every, self.n_therm, self.n_tau_out, self.n_cap, self.seed, self.log_cap,
-                     self.gamma_tol, self.drift_tol)
+                     self.gamma_tol, self.drift_tol, self.rankk_tile)
 
 
 def _ptr(a: np.ndarray):

@@ -99,12 +99,15 @@ def _compare_obs(og, oo):
     # Gamma^{-1} always from the pivoted Gauss-Jordan elimination
     ("plaquette_gj", _plaquette, 6000, 64, 64, -1.0),
     ("cluster16_gj", _cluster16, 6000, 64, 32, -1.0),
+    # rank-k update on 32x32 output tiles
+    ("cluster16_tile32", _cluster16, 6000, 64, 32, 1e-8),
 ])
 def test_decisions_and_N_match_oracle(name, make, n_prop, kmax, kcap, gamma_tol):
     ctaux = _ctaux()
     w = make()
     opts = ctaux.Options(k_max=kmax, k_cap=kcap, n_cap=2048, log_cap=n_prop, meas_every=kmax,
-                         n_tau_out=8, recompute_every=0, seed=3, gamma_tol=gamma_tol)
+                         n_tau_out=8, recompute_every=0, seed=3, gamma_tol=gamma_tol,
+                         rankk_tile=32 if name.endswith("tile32") else 64)
     gb, oc = _run_pair(ctaux, w, n_prop, opts, steps=2)
     st = _compare(gb, oc, n_prop)
     assert st["accepted"] > 50
@@ -341,3 +344,16 @@ def test_config5_cubic_nc100_eight_chains():
     oc = OracleChain(w, n_cap=8192)
     errs = _n_vs_definition(ctaux, gb, oc, 3, 1e-6)
     print(f"[config5] chain 3 N error after recompute {max(errs):.3e}", flush=True)
+
+
+def test_autotune_keeps_the_chain():
+    """The autotuner's candidates continue the same thermalised chains; the
+    chosen options are one of the candidates and the trial rates are positive."""
+    ctaux = _ctaux()
+    from paper_1010_3690_amd.autotune import autotune
+    ws = [_plaquette(beta=3.0 + 0.25 * i) for i in range(6)]
+    opts = ctaux.Options(k_max=64, k_cap=64, n_cap=512, recompute_every=16, seed=2, meas_every=64)
+    best, results = autotune(ws, opts, candidates=((32, 64), (64, 32)), warmup_proposals=64 * 20,
+                             trial_proposals=64 * 8)
+    assert len(results) == 2 and all(r["updates_per_s"] > 0 for r in results)
+    assert (best.k_max, best.rankk_tile) in ((32, 64), (64, 32))
