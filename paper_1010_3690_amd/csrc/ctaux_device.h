@@ -94,6 +94,20 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Pointers read from the chain descriptor are generic, and generic (flat)
+// accesses are counted by both the vector-memory and the LDS wait counters, so
+// any wait for an LDS result would also wait for every global load or store in
+// flight.  Accesses through these global-address-space views are counted by
+// the vector-memory counter only.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gview(const T *p) {
+  return (const __attribute__((address_space(1))) T *)(p);
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gview_w(T *p) {
+  return (__attribute__((address_space(1))) T *)(p);
+}
+
 // Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
 // wait for this wave's global stores to complete, so stores whose results are
 // read only after a later full barrier stay in flight across it.

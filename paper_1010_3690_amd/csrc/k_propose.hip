@@ -52,11 +52,11 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   const int kcap = d.kcap, lg = kcap + 1, n_cap = d.n_cap, kmax = d.kmax, ld = d.ld;
   const double Kc = d.K, gtol = d.gamma_tol;
   const bool gz = (d.gamma == 0.0);
-  const T *Nsec = static_cast<const T *>(d.N[par][sec]);
-  const double *Rts = d.Rt[sec], *YTs = d.YT[sec], *Gnns = d.Gnn[sec];
-  double *const gam = d.Gam[sec];
-  uint8_t *const log_acc = d.log_acc;
-  double *const log_R = d.log_R;
+  const auto Nsec = gview(static_cast<const T *>(d.N[par][sec]));
+  const auto Rts = gview(d.Rt[sec]), YTs = gview(d.YT[sec]), Gnns = gview(d.Gnn[sec]);
+  const auto gam = gview_w(d.Gam[sec]);
+  const auto log_acc = gview_w(d.log_acc);
+  const auto log_R = gview_w(d.log_R);
   const int64_t log_cap = d.log_cap;
 
   extern __shared__ double smem[];
@@ -432,8 +432,8 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     // has lane r owning row r.
     typedef double v4d __attribute__((ext_vector_type(4)));
     const int nt = (ka + 15) >> 4, lr = lane & 15, lk = lane >> 4;
-    double *Rg = d.Rg[sec];
-    double *gi = d.Ginv[sec];
+    const auto Rg = gview_w(d.Rg[sec]);
+    const auto gi = gview_w(d.Ginv[sec]);
     bool bad = false;
     double rmax = 0.0;
     for (int ti = 0; ti < nt; ++ti) {

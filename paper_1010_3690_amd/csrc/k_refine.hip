@@ -117,11 +117,11 @@ __global__ __launch_bounds__(256) void k_ref_gemm(const ChainDesc *descs, const 
       Nd = ref_slot(pool, it, sec, 2, nslots);
       ldn = n;
     }
-    const double *A = mode == 0 ? Ms : Nd;
+    const auto A = gview(mode == 0 ? Ms : Nd);
     const int lda = mode == 0 ? n : ldn;
-    const double *B = mode == 0 ? Nd : Rs;
+    const auto B = gview(mode == 0 ? Nd : Rs);
     const int ldb = mode == 0 ? ldn : n;
-    double *C = mode == 0 ? Rs : Ms;
+    const auto C = gview_w(mode == 0 ? Rs : Ms);
     const double alpha = mode == 0 ? -1.0 : 1.0, diag = mode == 0 ? 1.0 : 0.0;
     // staging: thread tid loads row tid/4 of the A chunk (8 consecutive k) and
     // row tid/8 of the B chunk (8 consecutive columns)

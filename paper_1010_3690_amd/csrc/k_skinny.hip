@@ -28,6 +28,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kSkWaves = 8;
 constexpr int kSkThreads = kSkWaves * 64;
 constexpr int kMeasGRt = 1;               // row tiles per measurement G item
+constexpr int kPrepRows = 32;             // rows (candidates) per preparation item
 
 enum SkinnyKind : int { kSkPrep = 0, kSkGnn = 1, kSkMeasW = 2, kSkMeasG = 3, kSkAsmB = 4 };
 enum SkinnyMode : int { kModeSplitK = 0, kModeWave = 1 };
@@ -36,8 +37,9 @@ enum SkinnyMode : int { kModeSplitK = 0, kModeWave = 1 };
 __device__ __forceinline__ int skinny_items(const ChainDesc &d, const ChainState &st, int kind) {
   if (!st.active) return 0;
   const int n = st.n;
-  if (kind == kSkPrep) return st.k_ins > 0 ? 4 * ((n + 15) >> 4) : 0;
-  if (kind == kSkGnn) return st.k_ins > 0 ? 2 * ((st.k_ins + 15) >> 4) : 0;
+  const int rg = (st.k_ins + kPrepRows - 1) / kPrepRows;   // row groups of the candidates
+  if (kind == kSkPrep) return st.k_ins > 0 ? 4 * rg * ((n + 15) >> 4) : 0;
+  if (kind == kSkGnn) return st.k_ins > 0 ? 2 * rg * ((st.k_ins + 15) >> 4) : 0;
   if (kind == kSkAsmB) return (st.k_a > 0 && st.n_new > 0) ? 2 * ((st.n_new + 15) >> 4) : 0;
   if (!st.meas_now) return 0;
   if (kind == kSkMeasW) return 2 * ((n + 15) >> 4);
@@ -139,29 +141,36 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int ki
   const int lane = threadIdx.x & 63, lr = lane & 15;
   const int n = st.n, par = st.parity;
   if (kind == kSkPrep) {
-    // items 0..2nt-1: YT[sec] = ZT N^T, items 2nt..4nt-1: Rt[sec] = X N
+    // per row group of candidates: items 0..2nt-1 YT[sec] = ZT N^T, 2nt..4nt-1 Rt[sec] = X N
     const int nt = (n + 15) >> 4;
-    const int job = local / nt, c0 = (local - job * nt) * 16, sec = job & 1, ld = d.ld;
-    const double *A = (job < 2) ? d.ZT[sec] : d.X[sec];
-    const T *N = static_cast<const T *>(d.N[par][sec]);
-    double *C = (job < 2) ? d.YT[sec] : d.Rt[sec];
+    const int grp = local / (4 * nt), r0 = grp * kPrepRows;
+    const int loc2 = local - grp * 4 * nt;
+    const int job = loc2 / nt, c0 = (loc2 - job * nt) * 16, sec = job & 1, ld = d.ld;
+    const auto A = gview(((job < 2) ? d.ZT[sec] : d.X[sec]) + static_cast<size_t>(r0) * ld);
+    const auto N = gview(static_cast<const T *>(d.N[par][sec]));
+    const auto C = gview_w(((job < 2) ? d.YT[sec] : d.Rt[sec]) + static_cast<size_t>(r0) * ld);
+    const int M = min(kPrepRows, st.k_ins - r0);
     const int c = c0 + lr;
     const bool cok = c < n;
     auto afn = [=](int m, int k) { return A[static_cast<size_t>(m) * ld + k]; };
     auto out = [=](int m, int cc, double v) { C[static_cast<size_t>(m) * ld + cc] = v; };
     if (job < 2) {
       auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(c) * ld + k]) : 0.0; };
-      skinny_item<MODE, NRT>(afn, bfn, out, st.k_ins, n, n, c0, red);
+      skinny_item<MODE, NRT>(afn, bfn, out, M, n, n, c0, red);
     } else {
       auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(k) * ld + c]) : 0.0; };
-      skinny_item<MODE, NRT>(afn, bfn, out, st.k_ins, n, n, c0, red);
+      skinny_item<MODE, NRT>(afn, bfn, out, M, n, n, c0, red);
     }
   } else if (kind == kSkGnn) {
-    // Gnn[sec] = X YT^T + G0nn (K = 0 still writes Gnn = G0nn)
+    // Gnn[sec] = X YT^T + G0nn (K = 0 still writes Gnn = G0nn), per row group
     const int ki = st.k_ins, nt = (ki + 15) >> 4;
-    const int sec = local / nt, c0 = (local - sec * nt) * 16, ld = d.ld, km = d.kmax;
-    const double *X = d.X[sec], *YT = d.YT[sec], *G0nn = d.G0nn[sec];
-    double *Gnn = d.Gnn[sec];
+    const int grp = local / (2 * nt), r0 = grp * kPrepRows;
+    const int loc2 = local - grp * 2 * nt;
+    const int sec = loc2 / nt, c0 = (loc2 - sec * nt) * 16, ld = d.ld, km = d.kmax;
+    const auto X = gview(d.X[sec] + static_cast<size_t>(r0) * ld), YT = gview(d.YT[sec]);
+    const auto G0nn = gview(d.G0nn[sec] + static_cast<size_t>(r0) * km);
+    const auto Gnn = gview_w(d.Gnn[sec] + static_cast<size_t>(r0) * km);
+    const int M = min(kPrepRows, ki - r0);
     const int c = c0 + lr;
     const bool cok = c < ki;
     auto afn = [=](int m, int k) { return X[static_cast<size_t>(m) * ld + k]; };
@@ -169,7 +178,7 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int ki
     auto out = [=](int m, int cc, double v) {
       Gnn[static_cast<size_t>(m) * km + cc] = v + G0nn[static_cast<size_t>(m) * km + cc];
     };
-    skinny_item<MODE, NRT>(afn, bfn, out, ki, n, ki, c0, red);
+    skinny_item<MODE, NRT>(afn, bfn, out, M, n, ki, c0, red);
   } else if (kind == kSkAsmB) {
     // Bc[sec] = Gamma^{-1} N_a(P, map): rows a < kpad (zero beyond k_a), K = k_a
     const int np = st.n_new, ka = st.k_a, kpad = (ka + 7) & ~7, nt = (np + 15) >> 4;
@@ -289,8 +298,9 @@ static int host_row_tiles(int M) {
 
 void launch_skinny(const Batch &b, hipStream_t s, int kind) {
   // Row tiles per item cover the largest M the kind can have in this batch:
-  // k_ins <= k_max (preparation), nc (W), k_a <= k_cap (B_c), one tile (G).
-  const int M = kind == kSkPrep || kind == kSkGnn ? b.kmax
+  // up to 32 candidates per row group (preparation), nc (W), k_a <= k_cap (B_c),
+  // one tile (G).
+  const int M = kind == kSkPrep || kind == kSkGnn ? (b.kmax < kPrepRows ? b.kmax : kPrepRows)
               : kind == kSkMeasW ? b.nc_max
               : kind == kSkAsmB ? ((b.kcap + 7) & ~7) : 16 * kMeasGRt;
   const int nrt = host_row_tiles(M);
