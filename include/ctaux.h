@@ -182,6 +182,9 @@ int ctaux_get_decisions(ctaux_batch *b, int32_t chain, int64_t first, int64_t co
  * 0: off; every event pair adds a little time to the stream).  names[i] are
  * static strings; returns the number of entries written (<= cap). */
 int ctaux_set_timing(ctaux_batch *b, int32_t mask);
+/* Time only one launch in `every` of each selected kernel (default 1), which
+ * keeps the events' own device time out of most launches. */
+int ctaux_set_timing_every(ctaux_batch *b, int32_t every);
 int32_t ctaux_get_timing(ctaux_batch *b, const char **names, double *ms, int64_t *launches,
                          int32_t cap);
 

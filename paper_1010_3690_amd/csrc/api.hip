@@ -53,6 +53,8 @@ struct ctaux_batch {
   int64_t log_cap = 0;
   int32_t obs_len_max = 0;
   int32_t timing = 0;                 // bit i: time kernel i (kKernelNames)
+  int32_t timing_every = 1;           // time one launch in timing_every of each selected kernel
+  int64_t timing_seen[16] = {0};      // launches of each kernel since timing was set
   std::vector<TimedEvent> pool;       // created events
   size_t pool_used = 0;
   double ms[kNumNames] = {0};
@@ -215,6 +217,7 @@ struct Timer {
   TimedEvent *ev = nullptr;
   Timer(ctaux_batch *h_, int name_) : h(h_), name(name_) {
     if (!(h->timing & (1 << name))) return;
+    if (h->timing_seen[name]++ % h->timing_every != 0) return;
     if (h->pool_used == h->pool.size()) {
       TimedEvent e;
       e.name = name;
@@ -570,6 +573,7 @@ int ctaux_set_timing(ctaux_batch *h, int32_t mask) {
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   flush_timing(h);
   h->timing = mask;
+  for (int i = 0; i < 16; ++i) h->timing_seen[i] = 0;
   for (int i = 0; i < kNumNames; ++i) {
     h->ms[i] = 0.0;
     h->launches[i] = 0;
@@ -723,6 +727,12 @@ int ctaux_restore(ctaux_batch *h, int32_t chain, const void *buf, size_t len) {
   // The refinement runs every recompute_every blocks enqueued on the batch; a
   // one-chain batch takes over the schedule of the checkpointed one.
   if (h->b.n_chains == 1) h->blocks_launched = hd.launches;
+  return CTAUX_OK;
+}
+
+int ctaux_set_timing_every(ctaux_batch *h, int32_t every) {
+  if (!h || every < 1) return CTAUX_EINVAL;
+  h->timing_every = every;
   return CTAUX_OK;
 }
 

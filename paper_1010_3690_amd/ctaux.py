@@ -27,7 +27,8 @@ TIMED_KERNELS = ["block_begin", "interp", "prep", "propose", "assemble", "rankk"
 EXPORTED = [
     "ctaux_workspace_bytes", "ctaux_create", "ctaux_run", "ctaux_recompute", "ctaux_obs_len",
     "ctaux_get_obs", "ctaux_reset_obs", "ctaux_get_stats", "ctaux_get_config", "ctaux_get_N",
-    "ctaux_get_decisions", "ctaux_set_timing", "ctaux_get_timing", "ctaux_checkpoint", "ctaux_restore",
+    "ctaux_get_decisions", "ctaux_set_timing", "ctaux_set_timing_every", "ctaux_get_timing",
+    "ctaux_checkpoint", "ctaux_restore",
     "ctaux_last_error", "ctaux_destroy",
 ]
 
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     lib.ctaux_get_N.argtypes = [vp, i32, i32, vp, i32, C.POINTER(i32)]
     lib.ctaux_get_decisions.argtypes = [vp, i32, i64, i64, vp, vp]
     lib.ctaux_set_timing.argtypes = [vp, i32]
+    lib.ctaux_set_timing_every.argtypes = [vp, i32]
     lib.ctaux_get_timing.restype = i32
     lib.ctaux_get_timing.argtypes = [vp, vp, vp, vp, i32]
     lib.ctaux_checkpoint.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
@@ -243,8 +245,10 @@ class CtauxBatch:
     def restore(self, blob: bytes, chain: int = 0):
         self._check(self.lib.ctaux_restore(self.h, chain, C.c_char_p(blob), len(blob)))
 
-    def set_timing(self, enable, kernels=None):
-        """Time every kernel (enable True), none (False), or only the named ones."""
+    def set_timing(self, enable, kernels=None, every=1):
+        """Time every kernel (enable True), none (False), or only the named ones,
+        one launch in `every`."""
+        self._check(self.lib.ctaux_set_timing_every(self.h, int(every)))
         mask = 0
         if kernels is not None:
             names = TIMED_KERNELS
