@@ -86,11 +86,13 @@ typedef struct {
     int32_t n_cap;            /* maximum order per chain                                      */
     uint64_t seed;
     int64_t log_cap;          /* decisions of proposals with index < log_cap are recorded     */
-    double gamma_tol;         /* Gamma^{-1} for the N update: the growth inverse X0 refined by
-                                 one Newton step is used when max|(I - Gamma X0)_ij| <=
-                                 gamma_tol (1e-8 is a good value); otherwise, and always when
+    double gamma_tol;         /* Gamma^{-1} for the N update: the growth inverse X0 (built
+                                 while proposing, Sec. IV C) is used when
+                                 max|(I - Gamma X0)_ij| <= gamma_tol (1e-8 is a good value),
+                                 with one Newton step when that residual lies above its own
+                                 FP64 rounding floor; otherwise, and always when
                                  gamma_tol < 0, a Gauss-Jordan elimination with partial
-                                 pivoting of Gamma (Sec. IV C).                               */
+                                 pivoting of Gamma.                                           */
     double drift_tol;         /* a refinement whose drift exceeds drift_tol stops the chain
                                  with CTAUX_ENUMERIC (N no longer represents the inverse of
                                  its definition); <= 0 disables the check                     */
@@ -115,7 +117,7 @@ typedef struct {
                                  write n'^2 entries of N, read the n' x k_a operands)          */
     double sum_order;         /* sum over blocks of the order after the block                */
     int64_t gj_fallbacks;     /* sector-blocks whose Gamma^{-1} came from the pivoted
-                                 elimination instead of the Newton-refined growth inverse */
+                                 elimination instead of the growth inverse                */
     double prep_flops;        /* algorithmic flops of the preparation products: per sector
                                  4 n^2 k_ins (YT, Rt) + 2 k_ins^2 n (Gnn)                      */
     double prep_bytes;        /* their algorithmic HBM bytes: N read twice, X, ZT, YT, Rt once */
@@ -149,8 +151,10 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
 int ctaux_run(ctaux_batch *b, int64_t n_proposals);
 
 /* Refine N of every chain against its definition in FP64 (one Newton step
- * N <- N + N (I - M N) with M = e^V - G0(e^V - 1) built from the tables) and
- * return the largest relative drift ||N_before - N_after||_F / ||N_after||_F.
+ * N <- N + N (I - M N) with M = e^V - G0(e^V - 1) built from the tables; up to
+ * two more steps for a chain whose drift exceeded 1e-9 with FP64 storage, 1e-4
+ * with FP32) and return the largest relative drift of the first step,
+ * ||N_before - N_after||_F / ||N_after||_F, over the chains.
  * Also runs automatically every opts.recompute_every blocks. */
 int ctaux_recompute(ctaux_batch *b, double *max_drift_out);
 

@@ -254,31 +254,43 @@ int sync_states(ctaux_batch *h) {
 
 // Refines every healthy chain: reads the orders (one synchronisation), packs
 // the chains into groups whose scratch fits the pool, and launches each group.
+// One Newton step squares the error of N; a chain whose drift exceeded the
+// storage's threshold gets further steps (up to kRefinePasses in all), each
+// preceded by one more synchronisation, so that a strongly coupled chain whose
+// block updates lost several digits starts the next interval at the accuracy
+// of its storage (FP32 storage holds N only to ~1e-7 relative: its threshold
+// is set far above that floor).
+constexpr int kRefinePasses = 3;
+
 int refine_all(ctaux_batch *h) {
-  int rc = sync_states(h);
-  if (rc) return rc;
   const Batch &b = h->b;
   const size_t slots = static_cast<size_t>(refine_slots(b.precision));
-  std::vector<RefineItem> items;
-  std::vector<int> starts;
-  size_t used = 0;
-  for (int c = 0; c < b.n_chains; ++c) {
-    const ChainState &st = h->state[c];
-    if (st.status != 0) continue;
-    const size_t need = 2 * slots * static_cast<size_t>(st.n) * st.n;
-    if (starts.empty() || used + need > b.r_pool_doubles) {
-      starts.push_back(static_cast<int>(items.size()));
-      used = 0;
+  const double again = b.precision == kFP64 ? 1e-9 : 1e-4;
+  for (int pass = 0; pass < kRefinePasses; ++pass) {
+    int rc = sync_states(h);
+    if (rc) return rc;
+    std::vector<RefineItem> items;
+    std::vector<int> starts;
+    size_t used = 0;
+    for (int c = 0; c < b.n_chains; ++c) {
+      const ChainState &st = h->state[c];
+      if (st.status != 0) continue;
+      if (pass > 0 && !(st.pass_drift > again)) continue;
+      const size_t need = 2 * slots * static_cast<size_t>(st.n) * st.n;
+      if (starts.empty() || used + need > b.r_pool_doubles) {
+        starts.push_back(static_cast<int>(items.size()));
+        used = 0;
+      }
+      items.push_back(RefineItem{c, st.n, static_cast<int64_t>(used)});
+      used += need;
     }
-    items.push_back(RefineItem{c, st.n, static_cast<int64_t>(used)});
-    used += need;
+    if (items.empty()) return CTAUX_OK;
+    HIPCHECK(h, hipMemcpy(b.r_items, items.data(), sizeof(RefineItem) * items.size(), hipMemcpyHostToDevice));
+    starts.push_back(static_cast<int>(items.size()));
+    Timer t(h, 8);
+    for (size_t g = 0; g + 1 < starts.size(); ++g)
+      launch_refine_group(b, h->stream, b.r_items + starts[g], starts[g + 1] - starts[g], pass);
   }
-  if (items.empty()) return CTAUX_OK;
-  HIPCHECK(h, hipMemcpy(b.r_items, items.data(), sizeof(RefineItem) * items.size(), hipMemcpyHostToDevice));
-  starts.push_back(static_cast<int>(items.size()));
-  Timer t(h, 8);
-  for (size_t g = 0; g + 1 < starts.size(); ++g)
-    launch_refine_group(b, h->stream, b.r_items + starts[g], starts[g + 1] - starts[g]);
   return CTAUX_OK;
 }
 
@@ -315,7 +327,7 @@ int chain_error(ctaux_batch *h) {
                      (long long)st.err_index, h->b.n_cap);
     if (st.status != 0 && st.err_index == -5)
       return set_err(h, st.status, "chain %d: refinement drift %.3g exceeds drift_tol (N is no longer the "
-                     "inverse of its definition; FP32 storage cannot hold this model)", c, st.last_drift);
+                     "inverse of its definition: refine more often, or use FP64 storage)", c, st.last_drift);
     if (st.status != 0)
       return set_err(h, st.status, "chain %d: numerical failure (code %d) at proposal %lld, drift %.3g", c,
                      st.status, (long long)st.err_index, st.last_drift);

@@ -21,7 +21,7 @@ enum Precision : int32_t { kFP64 = 0, kFP32 = 1 };
 struct ChainDesc {
   // ---- model (Sec. II A) ----
   double beta, K, gamma, inv_h, p_flip;
-  double gamma_tol;        // Newton-refined growth inverse accepted below this residual
+  double gamma_tol;        // growth inverse of Gamma (Newton-refined where that gains) accepted below this residual
   double drift_tol;        // refinement drift above this stops the chain (<= 0: no check)
   double evd[2][5];        // exp(gamma*sigma*d), d = -2..2 (index d+2); sigma = +1 up, -1 down
   int32_t nc, n_tau, n_disp;
@@ -103,6 +103,7 @@ struct ChainState {
   double sign;
   double max_drift;
   double last_drift;
+  double pass_drift;       // drift measured by the latest refinement pass
   int64_t err_index;   // proposal index of a failure
   double rk_flops;     // algorithmic flops of operand assembly + rank-k update, summed over blocks
   double rk_bytes;     // algorithmic HBM bytes of the rank-k update (read N_a, write N', read Ac, Bc)
@@ -131,7 +132,7 @@ struct RefineItem {
 };
 int refine_slots(int precision);           // n x n scratch blocks per sector
 size_t refine_red_doubles(int n_items);    // partial sums for the drift of n_items chains
-void launch_refine_group(const Batch &b, hipStream_t s, const RefineItem *items, int n_items);
+void launch_refine_group(const Batch &b, hipStream_t s, const RefineItem *items, int n_items, int pass);
 void launch_set_target(const Batch &b, hipStream_t s, int64_t n_proposals);
 // per-batch kernel attributes (dynamic LDS limits), once at creation
 void setup_propose(const Batch &b);

@@ -422,20 +422,25 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   } else if (ka > 0 && (wave & 1) == 0) {
     // ---- Gamma^{-1} for the rank-k update ----
     // The ratios above came from the unpivoted growth, whose inverse X0 loses
-    // accuracy when Gamma is ill-conditioned (repeated changes of one vertex
-    // give condition numbers of 1e6-1e8).  One Newton step on the recorded
-    // Gamma, R = I - Gamma X0, X1 = X0 + X0 R, makes it accurate to
-    // |R|^2 + rounding; it is taken when max|R_ij| <= gamma_tol.  Otherwise
-    // Gamma^{-1} comes from an in-place Gauss-Jordan elimination with partial
-    // pivoting of the recorded Gamma.  One wave per sector (wave 0: up,
-    // wave 2: down); the products run on MFMA 16x16x4 tiles, the elimination
-    // has lane r owning row r.
+    // accuracy when an intermediate Schur complement of Gamma is small
+    // (repeated changes of one vertex give condition numbers of 1e6-1e8).  The
+    // residual R = I - Gamma X0 on the recorded Gamma decides:
+    //  * max|R_ij| > gamma_tol: Gamma^{-1} comes from an in-place Gauss-Jordan
+    //    elimination with partial pivoting of the recorded Gamma;
+    //  * max|R_ij| above the FP64 rounding floor of the residual itself,
+    //    rho = 16 k_a eps max|Gamma| max|X0|: one Newton step X1 = X0 + X0 R
+    //    makes X0 accurate to |R|^2 + rounding;
+    //  * otherwise X0 is used as it is: a Newton step would add rounding of
+    //    order rho |X0| (on strongly coupled models Gamma^{-1} has entries of
+    //    1e6 that the update cancels, and that rounding then dominates N's error).
+    // One wave per sector (wave 0: up, wave 2: down); the products run on MFMA
+    // 16x16x4 tiles, the elimination has lane r owning row r.
     typedef double v4d __attribute__((ext_vector_type(4)));
     const int nt = (ka + 15) >> 4, lr = lane & 15, lk = lane >> 4;
     const auto Rg = gview_w(d.Rg[sec]);
     const auto gi = gview_w(d.Ginv[sec]);
     bool bad = false;
-    double rmax = 0.0;
+    double rmax = 0.0, gmax = 0.0, xmax = 0.0;
     for (int ti = 0; ti < nt; ++ti) {
       const int row = ti * 16 + lr;
       double a[16];   // Gamma[row][4s + lk]
@@ -443,6 +448,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       for (int s4 = 0; s4 < 16; ++s4) {
         const int k = 4 * s4 + lk;
         a[s4] = (row < ka && k < ka) ? gam[row * kcap + k] : 0.0;
+        gmax = fmax(gmax, fabs(a[s4]));
       }
       for (int tj = 0; tj < nt; ++tj) {
         const int col = tj * 16 + lr;
@@ -451,6 +457,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         for (int s4 = 0; s4 < 16; ++s4) {
           const int k = 4 * s4 + lk;
           const double b = (k < ka && col < ka) ? Gis[k * lg + col] : 0.0;
+          if (ti == 0) xmax = fmax(xmax, fabs(b));
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], b, acc, 0, 0, 0);
         }
 #pragma unroll
@@ -467,10 +474,25 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     }
     // max|R| over the wave (high words of non-negative doubles order like the values)
     const unsigned rhi = wave_max_u32(static_cast<unsigned>(__double_as_longlong(rmax) >> 32));
-    const bool newton = gtol >= 0.0 && rhi <= static_cast<unsigned>(__double_as_longlong(gtol) >> 32);
+    const bool growth_ok = gtol >= 0.0 && rhi <= static_cast<unsigned>(__double_as_longlong(gtol) >> 32);
+    // rounding floor (maxima to within a factor 2 from the high words; NaN/inf in
+    // Gamma or X0 already make rmax infinite)
+    const double gm = __longlong_as_double(static_cast<long long>(
+        wave_max_u32(static_cast<unsigned>(__double_as_longlong(gmax) >> 32))) << 32);
+    const double xm = __longlong_as_double(static_cast<long long>(
+        wave_max_u32(static_cast<unsigned>(__double_as_longlong(xmax) >> 32))) << 32);
+    const double rho = 16.0 * ka * 2.220446049250313e-16 * gm * xm;
+    const bool newton = growth_ok && __longlong_as_double(static_cast<long long>(rhi) << 32) > rho;
     // R was stored by this wave's lanes and is read back by other lanes
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    if (newton) {
+    if (growth_ok && !newton) {
+      for (int e = lane; e < ka * ka; e += 64) {
+        const int r = e / ka, col = e - r * ka;
+        const double x = Gis[r * lg + col];
+        bad |= !isfinite(x);
+        gi[r * kcap + col] = x;
+      }
+    } else if (newton) {
       for (int tj = 0; tj < nt; ++tj) {
         const int col = tj * 16 + lr;
         double b[16];   // R[4s + lk][col]

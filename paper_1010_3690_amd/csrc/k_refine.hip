@@ -224,8 +224,11 @@ __global__ __launch_bounds__(256) void k_ref_apply(const ChainDesc *descs, const
 }
 
 // Drift of every chain of the group (partial sums in a fixed order).
+// pass 0 records the drift the chain accumulated since its last refinement
+// (last_drift, max_drift, the drift_tol check); every pass leaves its drift in
+// pass_drift for the host's decision on one more step.
 __global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const RefineItem *items, int n_items,
-                             const double *red) {
+                             const double *red, int pass) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_items) return;
   const int c = items[q].chain;
@@ -242,9 +245,11 @@ __global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const R
     if (!isfinite(dr)) drift = INFINITY;
     else if (dr > drift) drift = dr;
   }
+  st.pass_drift = drift;
+  if (!isfinite(drift) && st.status == 0) st.status = -4;
+  if (pass > 0) return;
   st.last_drift = drift;
   if (!(drift <= st.max_drift)) st.max_drift = drift;
-  if (!isfinite(drift) && st.status == 0) st.status = -4;
   if (st.status == 0 && descs[c].drift_tol > 0.0 && drift > descs[c].drift_tol) {
     st.status = -4;   // N no longer represents the inverse of its definition
     st.err_index = -5;
@@ -256,7 +261,7 @@ int refine_slots(int precision) { return precision == kFP64 ? 2 : 3; }
 size_t refine_red_doubles(int n_items) { return static_cast<size_t>(n_items) * 2 * kRefBlocks * 2; }
 
 template <typename T>
-static void launch_group_t(const Batch &b, hipStream_t s, const RefineItem *items, int n_items) {
+static void launch_group_t(const Batch &b, hipStream_t s, const RefineItem *items, int n_items, int pass) {
   hipLaunchKernelGGL(k_ref_build<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
                      b.r_pool);
   const size_t lds = sizeof(int) * (n_items + 1);
@@ -266,7 +271,7 @@ static void launch_group_t(const Batch &b, hipStream_t s, const RefineItem *item
   hipLaunchKernelGGL(k_ref_apply<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
                      b.r_pool, b.r_red);
   hipLaunchKernelGGL(k_ref_reduce, dim3((n_items + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items,
-                     b.r_red);
+                     b.r_red, pass);
 }
 
 void setup_refine(const Batch &b) {
@@ -278,10 +283,10 @@ void setup_refine(const Batch &b) {
 }
 
 // One group of chains (items in device memory, scratch offsets within the pool).
-void launch_refine_group(const Batch &b, hipStream_t s, const RefineItem *items, int n_items) {
+void launch_refine_group(const Batch &b, hipStream_t s, const RefineItem *items, int n_items, int pass) {
   if (n_items <= 0) return;
-  if (b.precision == kFP64) launch_group_t<double>(b, s, items, n_items);
-  else launch_group_t<float>(b, s, items, n_items);
+  if (b.precision == kFP64) launch_group_t<double>(b, s, items, n_items, pass);
+  else launch_group_t<float>(b, s, items, n_items, pass);
 }
 
 }  // namespace ctaux
