@@ -45,6 +45,17 @@ struct Carver {
 struct ctaux_batch {
   Batch b;
   hipStream_t stream;
+  // The measurement of a block runs on a stream of its own beside the next
+  // block's proposals (it reads the block's N, configuration and state copy,
+  // which the next block does not write before its k_block_end); the next
+  // block's k_block_end waits for it.  For a few chains it is launched once the
+  // next block's preparation is enqueued, so that it shares the GPU with the
+  // one-workgroup-per-chain proposal kernel rather than with the preparation
+  // products.
+  hipStream_t mstream = nullptr;
+  hipEvent_t ev_end = nullptr, ev_meas = nullptr;
+  bool meas_owed = false;      // a block ended and its measurement is not launched yet
+  bool meas_pending = false;   // ev_meas marks the end of the last launched measurement
   std::vector<ChainDesc> desc;        // host copies
   std::vector<ChainState> state;      // host mirror (refreshed at sync points)
   std::vector<int32_t> obs_len;
@@ -123,6 +134,7 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
   const size_t es = o->precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
   ChainDesc *d_desc = cv.take<ChainDesc>(n_chains);
   ChainState *d_state = cv.take<ChainState>(n_chains);
+  ChainState *d_mstate = cv.take<ChainState>(n_chains);
   // refinement pool: room for one chain at n_cap, and for all chains at n_cap
   // up to 4 GiB; chains are refined in groups that fit
   const size_t need_cap = 2ull * refine_slots(o->precision) * static_cast<size_t>(n_cap) * n_cap;
@@ -133,7 +145,7 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
   RefineItem *r_items = cv.take<RefineItem>(n_chains);
   double *r_red = cv.take<double>(refine_red_doubles(n_chains));
   if (bt) {
-    bt->d_desc = d_desc; bt->d_state = d_state;
+    bt->d_desc = d_desc; bt->d_state = d_state; bt->d_mstate = d_mstate;
     bt->r_pool = r_pool; bt->r_pool_doubles = pool; bt->r_items = r_items; bt->r_red = r_red;
   }
   for (int c = 0; c < n_chains; ++c) {
@@ -214,8 +226,9 @@ int enqueue_block(ctaux_batch *h);
 struct Timer {
   ctaux_batch *h;
   int name;
+  hipStream_t s;
   TimedEvent *ev = nullptr;
-  Timer(ctaux_batch *h_, int name_) : h(h_), name(name_) {
+  Timer(ctaux_batch *h_, int name_, hipStream_t s_ = nullptr) : h(h_), name(name_), s(s_ ? s_ : h_->stream) {
     if (!(h->timing & (1 << name))) return;
     if (h->timing_seen[name]++ % h->timing_every != 0) return;
     if (h->pool_used == h->pool.size()) {
@@ -227,10 +240,10 @@ struct Timer {
     }
     ev = &h->pool[h->pool_used++];
     ev->name = name;
-    (void)hipEventRecord(ev->start, h->stream);
+    (void)hipEventRecord(ev->start, s);
   }
   ~Timer() {
-    if (ev) (void)hipEventRecord(ev->stop, h->stream);
+    if (ev) (void)hipEventRecord(ev->stop, s);
   }
 };
 
@@ -245,8 +258,31 @@ void flush_timing(ctaux_batch *h) {
   h->pool_used = 0;
 }
 
-int sync_states(ctaux_batch *h) {
+// Launches the measurement owed by the last block on the measurement stream,
+// ordered after everything enqueued so far on the batch's stream.
+int launch_owed_measure(ctaux_batch *h) {
+  if (!h->meas_owed) return CTAUX_OK;
+  HIPCHECK(h, hipEventRecord(h->ev_end, h->stream));
+  HIPCHECK(h, hipStreamWaitEvent(h->mstream, h->ev_end, 0));
+  { Timer t(h, 7, h->mstream); launch_measure(h->b, h->mstream); }
+  HIPCHECK(h, hipEventRecord(h->ev_meas, h->mstream));
+  h->meas_owed = false;
+  h->meas_pending = true;
+  return CTAUX_OK;
+}
+
+// Launches any owed measurement and waits for both streams of the batch.
+int sync_all(ctaux_batch *h) {
+  int rc = launch_owed_measure(h);
+  if (rc) return rc;
   HIPCHECK(h, hipStreamSynchronize(h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->mstream));
+  return CTAUX_OK;
+}
+
+int sync_states(ctaux_batch *h) {
+  int rc = sync_all(h);
+  if (rc) return rc;
   if (h->timing) flush_timing(h);
   HIPCHECK(h, hipMemcpy(h->state.data(), h->b.d_state, sizeof(ChainState) * h->b.n_chains, hipMemcpyDeviceToHost));
   return CTAUX_OK;
@@ -300,11 +336,21 @@ int enqueue_block(ctaux_batch *h) {
   { Timer t(h, 0); launch_block_begin(b, s); }
   { Timer t(h, 1); launch_interp(b, s); }
   { Timer t(h, 2); launch_prep(b, s); }
+  int rc = launch_owed_measure(h);   // the previous block's, beside this block's proposals
+  if (rc) return rc;
   { Timer t(h, 3); launch_propose(b, s); }
   { Timer t(h, 4); launch_assemble(b, s); }
   { Timer t(h, 5); launch_rankk(b, s); }
+  // k_block_end rewrites the state copy the previous measurement reads
+  if (h->meas_pending) HIPCHECK(h, hipStreamWaitEvent(s, h->ev_meas, 0));
   { Timer t(h, 6); launch_block_end(b, s); }
-  { Timer t(h, 7); launch_measure(b, s); }
+  h->meas_owed = true;
+  // many chains: the measurement is the longest step of a block and the next
+  // block's k_block_end waits for it, so it starts at once
+  if (b.n_chains >= 8) {
+    int rc2 = launch_owed_measure(h);
+    if (rc2) return rc2;
+  }
   h->blocks_launched += 1;
   if (h->recompute_every > 0 && h->blocks_launched % h->recompute_every == 0) {
     int rc = refine_all(h);
@@ -313,7 +359,8 @@ int enqueue_block(ctaux_batch *h) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(h, CTAUX_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   if (h->timing && h->pool_used > 16000) {
-    HIPCHECK(h, hipStreamSynchronize(s));
+    int rc = sync_all(h);
+    if (rc) return rc;
     flush_timing(h);
   }
   return CTAUX_OK;
@@ -429,9 +476,18 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
   setup_propose(b);
   setup_refine(b);
   if (hipMemcpy(b.d_desc, h->desc.data(), sizeof(ChainDesc) * n_chains, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b.d_state, st.data(), sizeof(ChainState) * n_chains, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(b.d_state, st.data(), sizeof(ChainState) * n_chains, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b.d_mstate, st.data(), sizeof(ChainState) * n_chains, hipMemcpyHostToDevice) != hipSuccess) {
     delete h;
     return set_err(nullptr, CTAUX_EDEVICE, "descriptor upload failed");
+  }
+  // measurement stream (default priority, no implicit synchronisation with the
+  // null stream) and the two events that order it against the caller's stream
+  if (hipStreamCreateWithFlags(&h->mstream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_end, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_meas, hipEventDisableTiming) != hipSuccess) {
+    ctaux_destroy(h);
+    return set_err(nullptr, CTAUX_EDEVICE, "measurement stream creation failed");
   }
   *out = h;
   return CTAUX_OK;
@@ -488,7 +544,10 @@ int ctaux_get_obs(ctaux_batch *h, int32_t chain, double *out, int32_t len) {
   if (!h || !out || chain < 0 || chain >= h->b.n_chains) return CTAUX_EINVAL;
   const int32_t L = h->obs_len[chain];
   if (len < L) return set_err(h, CTAUX_EINVAL, "obs buffer of %d doubles needed", L);
-  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  {
+    int rc_ = sync_all(h);
+    if (rc_) return rc_;
+  }
   HIPCHECK(h, hipMemcpy(out, h->desc[chain].obs, sizeof(double) * L, hipMemcpyDeviceToHost));
   for (int32_t i = L; i < len; ++i) out[i] = 0.0;
   return CTAUX_OK;
@@ -496,9 +555,16 @@ int ctaux_get_obs(ctaux_batch *h, int32_t chain, double *out, int32_t len) {
 
 int ctaux_reset_obs(ctaux_batch *h) {
   if (!h) return CTAUX_EINVAL;
+  {
+    int rc_ = sync_all(h);   // a measurement in flight writes obs
+    if (rc_) return rc_;
+  }
   for (int c = 0; c < h->b.n_chains; ++c)
     HIPCHECK(h, hipMemsetAsync(h->desc[c].obs, 0, sizeof(double) * h->obs_len[c], h->stream));
-  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  {
+    int rc_ = sync_all(h);
+    if (rc_) return rc_;
+  }
   return CTAUX_OK;
 }
 
@@ -574,7 +640,10 @@ int ctaux_get_decisions(ctaux_batch *h, int32_t chain, int64_t first, int64_t co
       (count > 0 && (!acc || !R)))
     return h ? set_err(h, CTAUX_EINVAL, "decision range outside the log") : CTAUX_EINVAL;
   if (count == 0) return CTAUX_OK;
-  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  {
+    int rc_ = sync_all(h);
+    if (rc_) return rc_;
+  }
   HIPCHECK(h, hipMemcpy(acc, h->desc[chain].log_acc + first, count, hipMemcpyDeviceToHost));
   HIPCHECK(h, hipMemcpy(R, h->desc[chain].log_R + first, sizeof(double) * count, hipMemcpyDeviceToHost));
   return CTAUX_OK;
@@ -582,7 +651,10 @@ int ctaux_get_decisions(ctaux_batch *h, int32_t chain, int64_t first, int64_t co
 
 int ctaux_set_timing(ctaux_batch *h, int32_t mask) {
   if (!h) return CTAUX_EINVAL;
-  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  {
+    int rc_ = sync_all(h);
+    if (rc_) return rc_;
+  }
   flush_timing(h);
   h->timing = mask;
   for (int i = 0; i < 16; ++i) h->timing_seen[i] = 0;
@@ -595,7 +667,7 @@ int ctaux_set_timing(ctaux_batch *h, int32_t mask) {
 
 int32_t ctaux_get_timing(ctaux_batch *h, const char **names, double *ms, int64_t *launches, int32_t cap) {
   if (!h) return 0;
-  if (hipStreamSynchronize(h->stream) != hipSuccess) return 0;
+  if (sync_all(h) != CTAUX_OK) return 0;
   flush_timing(h);
   int32_t k = 0;
   for (int i = 0; i < kNumNames && k < cap; ++i, ++k) {
@@ -753,6 +825,12 @@ const char *ctaux_last_error(const ctaux_batch *h) { return h ? h->err.c_str() :
 void ctaux_destroy(ctaux_batch *h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  if (h->mstream) {
+    (void)hipStreamSynchronize(h->mstream);
+    (void)hipStreamDestroy(h->mstream);
+  }
+  if (h->ev_end) (void)hipEventDestroy(h->ev_end);
+  if (h->ev_meas) (void)hipEventDestroy(h->ev_meas);
   for (TimedEvent &e : h->pool) {
     (void)hipEventDestroy(e.start);
     (void)hipEventDestroy(e.stop);

@@ -147,6 +147,8 @@ struct Batch {
   int32_t rankk_tile;        // rank-k output tile edge, 64 or 32
   ChainDesc *d_desc;         // device [n_chains]
   ChainState *d_state;       // device [n_chains]
+  ChainState *d_mstate;      // device [n_chains]: the state as the last block left it, read by
+                             // the measurement, which runs beside the next block
   int32_t n_cu;
   // refinement: scratch pool for a group of chains, the group's items, drift partial sums
   double *r_pool;

@@ -136,11 +136,16 @@ void launch_interp(const Batch &b, hipStream_t s) {
                      b.d_state);
 }
 
-__global__ void k_block_end(const ChainDesc *descs, ChainState *states, int n_chains) {
+// Ends a block and leaves a copy of the chain's state for the measurement
+// (mstates), which runs on a stream of its own beside the next block.
+__global__ void k_block_end(const ChainDesc *descs, ChainState *states, ChainState *mstates, int n_chains) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_chains) return;
   ChainState &st = states[c];
-  if (!st.active) return;
+  if (!st.active) {
+    mstates[c] = st;
+    return;
+  }
   const ChainDesc &d = descs[c];
   // algorithmic work of the update per sector: Bc = Gamma^{-1} N_P (2 k^2 n') and
   // N' = N - Ac Bc (2 n'^2 k); bytes: read and write n'^2 entries of N plus Ac and Bc
@@ -170,11 +175,12 @@ __global__ void k_block_end(const ChainDesc *descs, ChainState *states, int n_ch
     st.meas_flops += 2.0 * (2.0 * np * np * nc + 2.0 * m * np * nc);
     st.meas_bytes += 2.0 * (es * np * np + 8.0 * (2.0 + 2.0) * m * np + 8.0 * 2.0 * np * nc);
   }
+  mstates[c] = st;
 }
 
 void launch_block_end(const Batch &b, hipStream_t s) {
   hipLaunchKernelGGL(k_block_end, dim3((b.n_chains + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state,
-                     b.n_chains);
+                     b.d_mstate, b.n_chains);
 }
 
 }  // namespace ctaux

@@ -106,11 +106,11 @@ __global__ __launch_bounds__(256) void k_meas_acc(const ChainDesc *descs, const 
 }
 
 void launch_measure(const Batch &b, hipStream_t s) {
-  hipLaunchKernelGGL(k_meas_gR, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s, b.d_desc, b.d_state);
-  hipLaunchKernelGGL(k_meas_gL, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s, b.d_desc, b.d_state);
+  hipLaunchKernelGGL(k_meas_gR, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);
+  hipLaunchKernelGGL(k_meas_gL, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);
   launch_skinny(b, s, 2);   // W = N gR
   launch_skinny(b, s, 3);   // Gxy = G0 + gL W, gL_{(x,tau), l} = G0_{x x_l}(tau - tau_l)(e^{V_l} - 1)
-  hipLaunchKernelGGL(k_meas_acc, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_state);
+  hipLaunchKernelGGL(k_meas_acc, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);
 }
 
 }  // namespace ctaux

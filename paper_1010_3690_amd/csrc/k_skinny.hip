@@ -277,7 +277,9 @@ __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, c
 template <typename T, int MODE, int NRT>
 static void launch_k(const Batch &b, hipStream_t s, int kind) {
   const size_t lds = sizeof(int) * (b.n_chains + 1);
-  hipLaunchKernelGGL((k_skinny<T, MODE, NRT>), dim3(b.n_cu * 2), dim3(kSkThreads), lds, s, b.d_desc, b.d_state, kind,
+  // the measurement products read the state the last block left (d_mstate)
+  const ChainState *states = (kind == kSkMeasW || kind == kSkMeasG) ? b.d_mstate : b.d_state;
+  hipLaunchKernelGGL((k_skinny<T, MODE, NRT>), dim3(b.n_cu * 2), dim3(kSkThreads), lds, s, b.d_desc, states, kind,
                      b.n_chains);
 }
 

@@ -346,6 +346,31 @@ def test_config5_cubic_nc100_eight_chains():
     print(f"[config5] chain 3 N error after recompute {max(errs):.3e}", flush=True)
 
 
+def test_refinement_restores_a_strongly_coupled_chain():
+    """Nc = 32, beta = 7.08, U = 7.13, K = 1 (gamma ~ 7.4): the FP64 block
+    updates lose digits (Gamma^{-1} has entries of ~1e6 that the update
+    cancels), so 60 blocks without refinement leave a drift well above FP64
+    rounding.  One refinement call takes as many Newton steps as needed: a
+    second call right after it measures a drift at the rounding level, and N
+    then matches the inverse of its definition."""
+    from ctaux_inputs.workloads import _MIX_LATTICES
+    ctaux = _ctaux()
+    w = dca_square(beta=7.0812185938101795, U=7.13460658748971, K=1.0, n_tau=2048, n_fine=16,
+                   superlattice=_MIX_LATTICES[32])
+    opts = ctaux.Options(k_max=64, k_cap=64, n_cap=2048, recompute_every=0, seed=0, drift_tol=0.0,
+                         meas_every=64, n_tau_out=8)
+    print(f"[strong] nc={w.n_sites} K={w.K}", flush=True)
+    gb = ctaux.CtauxBatch([w], opts)
+    gb.run(64 * 60)
+    d1 = gb.recompute()
+    d2 = gb.recompute()
+    print(f"[strong] order {gb.stats(0)['order']} drift {d1:.3e} then {d2:.3e}", flush=True)
+    assert d1 > 1e-9          # the interval drifted past the extra-step threshold
+    assert d2 < 1e-10
+    oc = OracleChain(w, n_cap=2048)
+    _n_vs_definition(ctaux, gb, oc, 0, 1e-8)
+
+
 def test_autotune_keeps_the_chain():
     """The autotuner's candidates continue the same thermalised chains; the
     chosen options are one of the candidates and the trial rates are positive."""
