@@ -124,21 +124,23 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     const double *v = vv + sec * kcap, *u = vu + sec * kcap;
     const int b = loc & 63, a0 = loc >> 6;
     if (b <= k) {
-      // batches of 8 rows: loads first (in flight together), then stores
+      // batches of 8 rows: loads first (in flight together), then stores.  Load
+      // addresses are clamped into the matrix and the values beyond k never used,
+      // so the loads need no per-element branch.
       const double ub = (b < k) ? u[b] * ib : 0.0;
       for (int a1 = a0; a1 <= k; a1 += 16) {
         double va[8], ga[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const int a = a1 + 2 * i;
-          va[i] = (a < k) ? v[a] : 0.0;
-          ga[i] = (a < k && b < k) ? Gis[a * lg + b] : 0.0;
+          const int ac = min(a1 + 2 * i, kcap - 1);
+          va[i] = v[ac];
+          ga[i] = Gis[ac * lg + b];
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const int a = a1 + 2 * i;
-          if (a < k) Gis[a * lg + b] = (b < k) ? ga[i] + va[i] * ub : -va[i] * ib;
-          else if (a == k) Gis[k * lg + b] = (b < k) ? -ub : ib;
+          if (a <= k)
+            Gis[a * lg + b] = (a < k) ? ((b < k) ? ga[i] + va[i] * ub : -va[i] * ib) : ((b < k) ? -ub : ib);
         }
       }
     }
@@ -259,15 +261,19 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           const double *row = Gis + loc * lg;
           const double *sv = vs + sec * kcap;
           double a4[4] = {0.0, 0.0, 0.0, 0.0};
-          for (int b0 = 0; b0 < ka; b0 += 8) {
+          for (int b0 = 0; b0 < ka; b0 += 8) {   // clamped addresses, masked operands
             double x[8], y[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-              x[i] = (b0 + i < ka) ? row[b0 + i] : 0.0;
-              y[i] = (b0 + i < ka) ? sv[b0 + i] : 0.0;
+              const int bc = min(b0 + i, kcap - 1);
+              x[i] = row[bc];
+              y[i] = sv[bc];
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) a4[i & 3] += x[i] * y[i];
+            for (int i = 0; i < 8; ++i) {
+              const bool in = b0 + i < ka;
+              a4[i & 3] = fma(in ? x[i] : 0.0, in ? y[i] : 0.0, a4[i & 3]);
+            }
           }
           acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
           vv[sec * kcap + loc] = acc;
@@ -280,15 +286,19 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         if (b < ka) {
           const double *wv = vw + sec * kcap;
           double a4[4] = {0.0, 0.0, 0.0, 0.0};
-          for (int a0 = 0; a0 < ka; a0 += 8) {
+          for (int a0 = 0; a0 < ka; a0 += 8) {   // clamped addresses, masked operands
             double x[8], y[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-              x[i] = (a0 + i < ka) ? wv[a0 + i] : 0.0;
-              y[i] = (a0 + i < ka) ? Gis[(a0 + i) * lg + b] : 0.0;
+              const int ac = min(a0 + i, kcap - 1);
+              x[i] = wv[ac];
+              y[i] = Gis[ac * lg + b];
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) a4[i & 3] += x[i] * y[i];
+            for (int i = 0; i < 8; ++i) {
+              const bool in = a0 + i < ka;
+              a4[i & 3] = fma(in ? x[i] : 0.0, in ? y[i] : 0.0, a4[i & 3]);
+            }
           }
           vu[sec * kcap + b] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
