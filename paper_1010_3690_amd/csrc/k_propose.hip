@@ -49,7 +49,9 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   const int par = st.parity;
   const int64_t done0 = st.done;
   // descriptor fields used in the loop
-  const int kcap = d.kcap, lg = kcap + 1, n_cap = d.n_cap, kmax = d.kmax, ld = d.ld;
+  const int kcap = d.kcap, n_cap = d.n_cap, kmax = d.kmax, ld = d.ld;
+  // LDS layout per sector: k_cap rounded up to 8 (kp) rows of lg = kp + 1 entries
+  const int kp = (kcap + 7) & ~7, lg = kp + 1;
   const double Kc = d.K, gtol = d.gamma_tol;
   const bool gz = (d.gamma == 0.0);
   const auto Nsec = gview(static_cast<const T *>(d.N[par][sec]));
@@ -60,16 +62,16 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   const int64_t log_cap = d.log_cap;
 
   extern __shared__ double smem[];
-  double *Gi = smem;                         // [2][kcap][lg]
-  double *vs = Gi + 2 * kcap * lg;           // [2][kcap]   s vectors
-  double *vw = vs + 2 * kcap;                // [2][kcap]   w vectors
-  double *vv = vw + 2 * kcap;                // [2][kcap]   Gamma^{-1} s
-  double *vu = vv + 2 * kcap;                // [2][kcap]   w^T Gamma^{-1}
-  int *P = reinterpret_cast<int *>(vu + 2 * kcap);   // [kcap]
+  double *Gi = smem;                         // [2][kp][lg]
+  double *vs = Gi + 2 * kp * lg;             // [2][kp]   s vectors
+  double *vw = vs + 2 * kp;                  // [2][kp]   w vectors
+  double *vv = vw + 2 * kp;                  // [2][kp]   Gamma^{-1} s
+  double *vu = vv + 2 * kp;                  // [2][kp]   w^T Gamma^{-1}
+  int *P = reinterpret_cast<int *>(vu + 2 * kp);   // [kcap]
   int *dead = P + kcap;                      // [kcap] removed old vertices
   int8_t *scur = reinterpret_cast<int8_t *>(dead + kcap);  // [n + kmax] current spins
   int8_t *s0l = scur + (n_cap + kmax);                      // [n + kmax] block-start spins
-  double *Gis = Gi + sec * kcap * lg;
+  double *Gis = Gi + sec * kp * lg;
   __shared__ double sh_ev[2][5];                   // exp(gamma*sigma*d), d = -2..2
   __shared__ double sh_rm[2][5];                   // 1 / (exp(gamma*sigma*d) - 1), d = +-1
   __shared__ double sh_gpp[2][2], sh_beta[2][2];   // [proposal parity][sector]
@@ -92,6 +94,10 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   int pk = 0;
   double pbeta = 1.0;
 
+  // Gamma^{-1} of both sectors (with the padding rows) and the s, w vectors start
+  // at zero: entries beyond k_a stay zero for the whole block, so the
+  // matrix-vector products below can read whole batches of 8 without masks.
+  for (int i = tid; i < static_cast<int>(vv - Gi); i += 256) Gi[i] = 0.0;
   for (int i = tid; i < n + kins; i += 256) {
     const int8_t v = (i < n) ? static_cast<int8_t>(d.s0[par][i]) : 0;
     scur[i] = v;
@@ -121,7 +127,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   // (b = loc % 64, a = loc / 64 + 2i) of the sector)
   auto grow = [&](int k, double beta) {
     const double ib = 1.0 / beta;
-    const double *v = vv + sec * kcap, *u = vu + sec * kcap;
+    const double *v = vv + sec * kp, *u = vu + sec * kp;
     const int b = loc & 63, a0 = loc >> 6;
     if (b <= k) {
       // batches of 8 rows: loads first (in flight together), then stores.  Load
@@ -244,11 +250,11 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           gam[ka * kcap + ka] = g - 1.0 - 1.0 / gh;
         } else if (loc < 64) {
           const double v = g - (gi == gj ? 1.0 : 0.0);
-          vs[sec * kcap + loc] = v;
+          vs[sec * kp + loc] = v;
           gam[loc * kcap + ka] = v;
         } else {
           const double v = g - (gi == gj ? 1.0 : 0.0);
-          vw[sec * kcap + loc - 64] = v;
+          vw[sec * kp + loc - 64] = v;
           gam[ka * kcap + loc - 64] = v;
         }
       }
@@ -259,48 +265,41 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         double acc = 0.0;
         if (loc < ka) {
           const double *row = Gis + loc * lg;
-          const double *sv = vs + sec * kcap;
+          const double *sv = vs + sec * kp;
           double a4[4] = {0.0, 0.0, 0.0, 0.0};
-          for (int b0 = 0; b0 < ka; b0 += 8) {   // clamped addresses, masked operands
+          for (int b0 = 0; b0 < ka; b0 += 8) {   // whole batches of 8: entries beyond k_a are zero
             double x[8], y[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-              const int bc = min(b0 + i, kcap - 1);
-              x[i] = row[bc];
-              y[i] = sv[bc];
+              x[i] = row[b0 + i];
+              y[i] = sv[b0 + i];
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              const bool in = b0 + i < ka;
-              a4[i & 3] = fma(in ? x[i] : 0.0, in ? y[i] : 0.0, a4[i & 3]);
-            }
+            for (int i = 0; i < 8; ++i) a4[i & 3] = fma(x[i], y[i], a4[i & 3]);
           }
           acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-          vv[sec * kcap + loc] = acc;
+          vv[sec * kp + loc] = acc;
         }
-        const double x = (loc < ka) ? vw[sec * kcap + loc] * acc : 0.0;
+        const double x = (loc < ka) ? vw[sec * kp + loc] * acc : 0.0;
         const double s = wave_sum_dpp(x);
         if (lane == 0) sh_beta[tp][sec] = (sh_gpp[tp][sec] - 1.0 - 1.0 / gh) - s;
       } else {
         const int b = loc - 64;
         if (b < ka) {
-          const double *wv = vw + sec * kcap;
+          const double *wv = vw + sec * kp;
           double a4[4] = {0.0, 0.0, 0.0, 0.0};
-          for (int a0 = 0; a0 < ka; a0 += 8) {   // clamped addresses, masked operands
+          for (int a0 = 0; a0 < ka; a0 += 8) {   // whole batches of 8: entries beyond k_a are zero
             double x[8], y[8];
+            const double *col = Gis + a0 * lg + b;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-              const int ac = min(a0 + i, kcap - 1);
-              x[i] = wv[ac];
-              y[i] = Gis[ac * lg + b];
+              x[i] = wv[a0 + i];
+              y[i] = col[i * lg];
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              const bool in = a0 + i < ka;
-              a4[i & 3] = fma(in ? x[i] : 0.0, in ? y[i] : 0.0, a4[i & 3]);
-            }
+            for (int i = 0; i < 8; ++i) a4[i & 3] = fma(x[i], y[i], a4[i & 3]);
           }
-          vu[sec * kcap + b] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+          vu[sec * kp + b] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
       }
       lds_barrier();
@@ -643,8 +642,12 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   }
 }
 
+// LDS: Gamma^{-1} of both sectors as k_cap rounded up to 8 rows (the
+// matrix-vector products read whole batches of 8) of that many plus one
+// entries, the four vectors, P, the removed list and the spins.
 size_t propose_lds_bytes(const Batch &b) {
-  return sizeof(double) * (2ull * b.kcap * (b.kcap + 1) + 8ull * b.kcap) + sizeof(int) * 2ull * b.kcap +
+  const size_t kp = (static_cast<size_t>(b.kcap) + 7) & ~size_t{7};
+  return sizeof(double) * (2 * kp * (kp + 1) + 8 * kp) + sizeof(int) * 2ull * b.kcap +
          2ull * static_cast<size_t>(b.n_cap + b.kmax) + 16;
 }
 
