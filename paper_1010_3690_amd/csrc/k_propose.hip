@@ -68,8 +68,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   double *vv = vw + 2 * kp;                  // [2][kp]   Gamma^{-1} s
   double *vu = vv + 2 * kp;                  // [2][kp]   w^T Gamma^{-1}
   int *P = reinterpret_cast<int *>(vu + 2 * kp);   // [kcap]
-  int *dead = P + kcap;                      // [kcap] removed old vertices
-  int8_t *scur = reinterpret_cast<int8_t *>(dead + kcap);  // [n + kmax] current spins
+  int8_t *scur = reinterpret_cast<int8_t *>(P + kcap);  // [n + kmax] current spins
   int8_t *s0l = scur + (n_cap + kmax);                      // [n + kmax] block-start spins
   double *Gis = Gi + sec * kp * lg;
   __shared__ double sh_ev[2][5];                   // exp(gamma*sigma*d), d = -2..2
@@ -121,6 +120,19 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   }
   __syncthreads();
   const double *ev = sh_ev[sec], *rm = sh_rm[sec];
+  // The proposals' draws live in registers (proposal t in lane t % 64 of slot
+  // t / 64) and are read with readlane; lane b of each wave holds P_b and the
+  // b-th removed old vertex.  The loop then reads them without LDS round trips.
+  double r_pacc[2], r_ppick[2];
+  int r_tspin[2];   // type | (spin + 1) << 8
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int t = 64 * j + lane;
+    r_pacc[j] = (t < L) ? sh_pacc[t] : 0.0;
+    r_ppick[j] = (t < L) ? sh_ppick[t] : 0.0;
+    r_tspin[j] = (t < L) ? (static_cast<int>(sh_ptype[t]) | ((static_cast<int>(sh_pspin[t]) + 1) << 8)) : 0;
+  }
+  int myP = 0, myDead = 0x7fffffff;
 
   // Gamma^{-1} of size k grows to k + 1 after an acceptance with Schur
   // complement beta, from v = Gamma^{-1} s and u = w^T Gamma^{-1} (thread
@@ -153,9 +165,10 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   };
 
   for (int t = 0; t < L; ++t) {
-    const int tp = t & 1;
-    const int type = sh_ptype[t];
-    const double u_acc = sh_pacc[t];
+    const int tp = t & 1, tj = t >> 6, tl = t & 63;
+    const int tspin = __builtin_amdgcn_readlane(tj ? r_tspin[1] : r_tspin[0], tl);
+    const int type = tspin & 0xff;
+    const double u_acc = readlane_f64(tj ? r_pacc[1] : r_pacc[0], tl);
     int p = -1, s_old = 0, s_new = 0, skip = 0;
     if (type == 0) {
       if (ncur + 1 > n_cap) {
@@ -165,19 +178,19 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         break;
       }
       p = n + next_cand;
-      s_new = sh_pspin[t];
+      s_new = (tspin >> 8) - 1;
     } else if (ncur == 0) {
       skip = 1;
     } else {
       // rank r among interacting vertices in canonical (augmented-index) order;
       // every wave computes it from the bookkeeping all threads wrote identically
-      int r = static_cast<int>(floor(static_cast<double>(ncur) * sh_ppick[t]));
+      int r = static_cast<int>(floor(static_cast<double>(ncur) * readlane_f64(tj ? r_ppick[1] : r_ppick[0], tl)));
       if (r > ncur - 1) r = ncur - 1;
       if (r < n - ndead) {
         // old vertex: least idx with idx = r + #{dead <= idx}
         int idx = r;
         while (true) {
-          const bool le = (lane < ndead) && (dead[lane] <= idx);
+          const bool le = myDead <= idx;   // lanes past the list hold INT_MAX
           const int nw = r + __popcll(__ballot(le));
           if (nw == idx) break;
           idx = nw;
@@ -208,20 +221,21 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       s_new = (type == 1) ? 0 : -s_old;
     }
 
+    // prefactor of the acceptance ratio (Eq. insprob), computed while the
+    // gathers below are in flight
+    const double fpre = (type == 0) ? Kc / static_cast<double>(ncur + 1)
+                                    : (type == 1 ? static_cast<double>(ncur) / Kc : 1.0);
     double gh0 = 0.0, gh1 = 0.0;
     if (!skip && !gz) {
-      const int s0p = s0l[p];
-      gh0 = sh_ev[0][s_new - s0p + 2] - sh_ev[0][s_old - s0p + 2];
-      gh1 = sh_ev[1][s_new - s0p + 2] - sh_ev[1][s_old - s0p + 2];
       // ---- issue the gathers: thread loc < 64 takes s_loc = G(P_loc, p) (loc == 63: G_pp),
       // thread 64 + b takes w_b = G(p, P_b) ----
       int gi = -1, gj = -1;
       if (loc < 64) {
-        if (loc < ka) { gi = P[loc]; gj = p; }
+        if (loc < ka) { gi = myP; gj = p; }
         else if (loc == 63) { gi = p; gj = p; }
       } else if (loc - 64 < ka) {
         gi = p;
-        gj = P[loc - 64];
+        gj = myP;
       }
       double raw = 0.0;
       if (gi >= 0) {
@@ -229,6 +243,11 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
                                    : Rts[static_cast<size_t>(gi - n) * ld + gj];
         else raw = (gi < n) ? YTs[static_cast<size_t>(gj - n) * ld + gi]
                             : Gnns[static_cast<size_t>(gi - n) * kmax + (gj - n)];
+      }
+      {
+        const int s0p = s0l[p];
+        gh0 = sh_ev[0][s_new - s0p + 2] - sh_ev[0][s_old - s0p + 2];
+        gh1 = sh_ev[1][s_new - s0p + 2] - sh_ev[1][s_old - s0p + 2];
       }
       // ---- owed growth of Gamma^{-1} by partitioning (Sec. III B 2), LDS only ----
       if (pend) {
@@ -314,9 +333,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         r0 = -gh0 * sh_beta[tp][0];
         r1 = -gh1 * sh_beta[tp][1];
       }
-      const double f = (type == 0) ? Kc / static_cast<double>(ncur + 1)
-                                   : (type == 1 ? static_cast<double>(ncur) / Kc : 1.0);
-      R = f * r0 * r1;
+      R = fpre * r0 * r1;
     }
     if (!isfinite(R)) {
       status = -4;  // CTAUX_ENUMERIC
@@ -341,6 +358,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         pk = ka;
         pbeta = sh_beta[tp][sec];
         P[ka] = p;           // every thread writes the same value
+        if (lane == ka) myP = p;
         if (tid == 0) {
           sh_gh[0][ka] = gh0;
           sh_gh[1][ka] = gh1;
@@ -355,7 +373,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       } else if (type == 1) {
         ncur -= 1;
         if (p < n) {
-          dead[ndead] = p;   // every thread writes the same value
+          if (lane == ndead) myDead = p;
           ndead += 1;
         }
       }
@@ -644,10 +662,10 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
 
 // LDS: Gamma^{-1} of both sectors as k_cap rounded up to 8 rows (the
 // matrix-vector products read whole batches of 8) of that many plus one
-// entries, the four vectors, P, the removed list and the spins.
+// entries, the four vectors, P and the spins.
 size_t propose_lds_bytes(const Batch &b) {
   const size_t kp = (static_cast<size_t>(b.kcap) + 7) & ~size_t{7};
-  return sizeof(double) * (2 * kp * (kp + 1) + 8 * kp) + sizeof(int) * 2ull * b.kcap +
+  return sizeof(double) * (2 * kp * (kp + 1) + 8 * kp) + sizeof(int) * static_cast<size_t>(b.kcap) +
          2ull * static_cast<size_t>(b.n_cap + b.kmax) + 16;
 }
 
