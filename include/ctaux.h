@@ -78,7 +78,11 @@ typedef struct {
     int32_t k_cap;            /* accepted changes per block (size of Gamma), 1..64; a block
                                  ends early once Gamma is full (does not change the chain)     */
     double p_flip;            /* P(flip); P(insert) = P(remove) = (1 - p_flip)/2              */
-    int32_t recompute_every;  /* blocks between FP64 refinements of N (0 = never)             */
+    int32_t recompute_every;  /* most blocks between FP64 refinements of N (0 = never).  The
+                                 interval starts at min(8, recompute_every); after each
+                                 refinement it is quartered (down to 1) when a chain's drift
+                                 exceeded 1e-3 and doubled (up to recompute_every) when
+                                 every drift stayed below 1e-4                               */
     int32_t precision;        /* CTAUX_FP64 or CTAUX_FP32                                     */
     int32_t meas_every;       /* measure after every meas_every proposals ...                 */
     int64_t n_therm;          /* ... once more than n_therm proposals are done                */
@@ -155,7 +159,7 @@ int ctaux_run(ctaux_batch *b, int64_t n_proposals);
  * two more steps for a chain whose drift exceeded 1e-9 with FP64 storage, 1e-4
  * with FP32) and return the largest relative drift of the first step,
  * ||N_before - N_after||_F / ||N_after||_F, over the chains.
- * Also runs automatically every opts.recompute_every blocks. */
+ * Also runs automatically, at most every opts.recompute_every blocks. */
 int ctaux_recompute(ctaux_batch *b, double *max_drift_out);
 
 /* Observable accumulators of a chain (doubles, len >= ctaux_obs_len()):
@@ -203,8 +207,8 @@ int32_t ctaux_get_timing(ctaux_batch *b, const char **names, double *ms, int64_t
  *   ctaux_restore: loads a blob into `chain` of this batch, which must have the
  *     same precision, n_sites, n_tau, beta, K, coupling and observable layout
  *     (CTAUX_EINVAL otherwise) and n_cap >= the stored order.  The FP64
- *     refinement runs every recompute_every blocks enqueued on a batch; a
- *     one-chain batch also takes over that schedule, so continuing with the
+ *     refinement schedule belongs to the batch; a one-chain batch with the same
+ *     recompute_every also takes over that schedule, so continuing with the
  *     same seed and chain index reproduces the uninterrupted chain bit for bit.
  *     In a larger batch the refinement phase may differ, which changes N by
  *     rounding only.  The decision log of the target is not restored. */

@@ -61,6 +61,10 @@ struct ctaux_batch {
   std::vector<int32_t> obs_len;
   int64_t blocks_launched = 0;
   int32_t recompute_every = 0;
+  // adaptive refinement schedule: refine_interval starts at min(8, recompute_every)
+  // and moves within [1, recompute_every] with the drift the refinements measure
+  int32_t refine_interval = 0;
+  int64_t since_refine = 0;
   int64_t log_cap = 0;
   int32_t obs_len_max = 0;
   int32_t timing = 0;                 // bit i: time kernel i (kKernelNames)
@@ -298,13 +302,26 @@ int sync_states(ctaux_batch *h) {
 // is set far above that floor).
 constexpr int kRefinePasses = 3;
 
-int refine_all(ctaux_batch *h) {
+int refine_all(ctaux_batch *h, bool adapt) {
   const Batch &b = h->b;
   const size_t slots = static_cast<size_t>(refine_slots(b.precision));
   const double again = b.precision == kFP64 ? 1e-9 : 1e-4;
   for (int pass = 0; pass < kRefinePasses; ++pass) {
     int rc = sync_states(h);
     if (rc) return rc;
+    if (pass == 1 && adapt) {
+      // the first step's drift over the chains sets the next interval: a
+      // quarter of it when a chain drifted far (well before drift_tol stops it),
+      // twice it (up to recompute_every) when every chain stayed a factor 10
+      // below that
+      double m = 0.0;
+      for (const ChainState &st : h->state)
+        if (st.status == 0 && st.last_drift > m) m = st.last_drift;
+      const double hi = 1e-3;
+      if (m > hi) h->refine_interval = h->refine_interval > 4 ? h->refine_interval / 4 : 1;
+      else if (m < 0.1 * hi)
+        h->refine_interval = 2 * h->refine_interval < h->recompute_every ? 2 * h->refine_interval : h->recompute_every;
+    }
     std::vector<RefineItem> items;
     std::vector<int> starts;
     size_t used = 0;
@@ -352,8 +369,9 @@ int enqueue_block(ctaux_batch *h) {
     if (rc2) return rc2;
   }
   h->blocks_launched += 1;
-  if (h->recompute_every > 0 && h->blocks_launched % h->recompute_every == 0) {
-    int rc = refine_all(h);
+  if (h->recompute_every > 0 && ++h->since_refine >= h->refine_interval) {
+    h->since_refine = 0;
+    int rc = refine_all(h, true);
     if (rc) return rc;
   }
   hipError_t e = hipGetLastError();
@@ -430,6 +448,7 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
   b.grid_per_chain = n_chains >= 2048 ? 1 : 2048 / n_chains;
   if (b.grid_per_chain > 1024) b.grid_per_chain = 1024;
   h->recompute_every = opts->recompute_every;
+  h->refine_interval = opts->recompute_every < 8 ? opts->recompute_every : 8;
   h->log_cap = opts->log_cap;
   layout(models, n_chains, opts, static_cast<char *>(dev_workspace), &b, &h->desc);
   // upload tables, maps and descriptors
@@ -526,7 +545,7 @@ int ctaux_run(ctaux_batch *h, int64_t n_proposals) {
 
 int ctaux_recompute(ctaux_batch *h, double *max_drift_out) {
   if (!h) return CTAUX_EINVAL;
-  int rc0 = refine_all(h);
+  int rc0 = refine_all(h, false);
   if (rc0) return rc0;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(h, CTAUX_EDEVICE, "refine launch failed: %s", hipGetErrorString(e));
@@ -685,7 +704,8 @@ struct CkptHeader {
   int32_t version, precision, nc, n_tau, n, obs_len;
   double beta, K, gamma;
   int64_t next_id, done, accepted, blocks, sum_ka;
-  int64_t launches;   // blocks enqueued on the batch (phase of the refinement schedule)
+  int64_t launches;   // blocks enqueued on the batch
+  int64_t refine_interval, since_refine;   // state of the adaptive refinement schedule
   double sign, max_drift, last_drift, rk_flops, rk_bytes, sum_order;
 };
 constexpr char kCkptMagic[8] = {'C', 'T', 'A', 'U', 'X', 'C', 'K', '1'};
@@ -728,6 +748,8 @@ int ctaux_checkpoint(ctaux_batch *h, int32_t chain, void *buf, size_t *len) {
   hd.blocks = st.blocks;
   hd.sum_ka = st.sum_ka;
   hd.launches = h->blocks_launched;
+  hd.refine_interval = h->refine_interval;
+  hd.since_refine = h->since_refine;
   hd.sign = st.sign;
   hd.max_drift = st.max_drift;
   hd.last_drift = st.last_drift;
@@ -808,9 +830,15 @@ int ctaux_restore(ctaux_batch *h, int32_t chain, const void *buf, size_t len) {
   st.sum_order = hd.sum_order;
   HIPCHECK(h, hipMemcpy(h->b.d_state + chain, &st, sizeof st, hipMemcpyHostToDevice));
   h->state[chain] = st;
-  // The refinement runs every recompute_every blocks enqueued on the batch; a
-  // one-chain batch takes over the schedule of the checkpointed one.
-  if (h->b.n_chains == 1) h->blocks_launched = hd.launches;
+  // The refinement schedule belongs to the batch; a one-chain batch takes over
+  // the schedule of the checkpointed one (when both use the same recompute_every).
+  if (h->b.n_chains == 1) {
+    h->blocks_launched = hd.launches;
+    if (h->recompute_every > 0 && hd.refine_interval >= 1 && hd.refine_interval <= h->recompute_every) {
+      h->refine_interval = static_cast<int32_t>(hd.refine_interval);
+      h->since_refine = hd.since_refine;
+    }
+  }
   return CTAUX_OK;
 }
 
