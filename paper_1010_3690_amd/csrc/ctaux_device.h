@@ -44,11 +44,25 @@ __device__ __forceinline__ void proposal_uniforms(const ChainDesc &d, uint64_t i
   u[4] = u53(c[0], c[1]);
 }
 
+// Pointers read from the chain descriptor are generic, and generic (flat)
+// accesses are counted by both the vector-memory and the LDS wait counters, so
+// any wait for an LDS result would also wait for every global load or store in
+// flight.  Accesses through these global-address-space views are counted by
+// the vector-memory counter only.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gview(const T *p) {
+  return (const __attribute__((address_space(1))) T *)(p);
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gview_w(T *p) {
+  return (__attribute__((address_space(1))) T *)(p);
+}
+
 // Bare propagator G0_{xy}(dtau): linear interpolation on the uniform grid,
 // dtau in (-beta, beta); dtau < 0 uses G0(dtau) = -G0(dtau + beta); dtau = 0
 // reads the 0+ entry.
 __device__ __forceinline__ double g0_interp(const ChainDesc &d, int sec, int x, int y, double dtau) {
-  const double *tab = d.g0[sec] + static_cast<int64_t>(d.site_disp[x * d.nc + y]) * d.n_tau;
+  const auto tab = gview(d.g0[sec] + static_cast<int64_t>(gview(d.site_disp)[x * d.nc + y]) * d.n_tau);
   double sgn = 1.0;
   if (dtau < 0.0) { dtau += d.beta; sgn = -1.0; }
   double xx = dtau * d.inv_h;
@@ -57,6 +71,7 @@ __device__ __forceinline__ double g0_interp(const ChainDesc &d, int sec, int x, 
   double w = xx - static_cast<double>(m);
   return sgn * ((1.0 - w) * tab[m] + w * tab[m + 1]);
 }
+
 
 template <typename T>
 __device__ __forceinline__ double ld_as_double(const T *p) { return static_cast<double>(*p); }
@@ -70,14 +85,14 @@ template <typename T>
 __device__ __forceinline__ double g_entry(const ChainDesc &d, const T *N, const int32_t *s0, int n,
                                           int sec, int i, int j) {
   if (j < n) {
-    const double e = d.evd[sec][s0[j] + 2];
-    const double nij = (i < n) ? static_cast<double>(N[static_cast<size_t>(i) * d.ld + j])
-                               : d.Rt[sec][static_cast<size_t>(i - n) * d.ld + j];
+    const double e = gview(d.evd[sec])[gview(s0)[j] + 2];
+    const double nij = (i < n) ? static_cast<double>(gview(N)[static_cast<size_t>(i) * d.ld + j])
+                               : gview(d.Rt[sec])[static_cast<size_t>(i - n) * d.ld + j];
     return (nij * e - (i == j ? 1.0 : 0.0)) / (e - 1.0);
   }
   const int jj = j - n;
-  return (i < n) ? d.YT[sec][static_cast<size_t>(jj) * d.ld + i]
-                 : d.Gnn[sec][static_cast<size_t>(i - n) * d.kmax + jj];
+  return (i < n) ? gview(d.YT[sec])[static_cast<size_t>(jj) * d.ld + i]
+                 : gview(d.Gnn[sec])[static_cast<size_t>(i - n) * d.kmax + jj];
 }
 
 // Entry of the augmented block-start N_a = [[N, 0], [Rt, 1]].
@@ -94,19 +109,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Pointers read from the chain descriptor are generic, and generic (flat)
-// accesses are counted by both the vector-memory and the LDS wait counters, so
-// any wait for an LDS result would also wait for every global load or store in
-// flight.  Accesses through these global-address-space views are counted by
-// the vector-memory counter only.
-template <typename T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T *gview(const T *p) {
-  return (const __attribute__((address_space(1))) T *)(p);
-}
-template <typename T>
-__device__ __forceinline__ __attribute__((address_space(1))) T *gview_w(T *p) {
-  return (__attribute__((address_space(1))) T *)(p);
-}
 
 // Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
 // wait for this wave's global stores to complete, so stores whose results are

@@ -24,7 +24,8 @@ __global__ __launch_bounds__(256) void k_meas_gR(const ChainDesc *descs, const C
     const int sec = static_cast<int>(e / per);
     const int64_t r = e - sec * per;
     const int k = static_cast<int>(r / nc), y = static_cast<int>(r - static_cast<int64_t>(k) * nc);
-    d.gR[sec][static_cast<size_t>(y) * d.n_cap + k] = g0_interp(d, sec, d.site[par][k], y, d.tau[par][k]);
+    gview_w(d.gR[sec])[static_cast<size_t>(y) * d.n_cap + k] =
+        g0_interp(d, sec, gview(d.site[par])[k], y, gview(d.tau[par])[k]);
   }
 }
 
@@ -39,16 +40,16 @@ __global__ __launch_bounds__(256) void k_meas_gL(const ChainDesc *descs, const C
   const int rows = nc * (d.n_out + 1);
   const double dt = d.beta / d.n_out;
   const int64_t per = static_cast<int64_t>(rows) * n;
-  const double *tau = d.tau[par];
-  const int32_t *site = d.site[par], *s0 = d.s0[par];
+  const auto tau = gview(d.tau[par]);
+  const auto site = gview(d.site[par]), s0 = gview(d.s0[par]);
   for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < 2 * per; e += gridDim.x * 256ll) {
     const int sec = static_cast<int>(e / per);
     const int64_t r = e - sec * per;
     const int m = static_cast<int>(r / n), l = static_cast<int>(r - static_cast<int64_t>(m) * n);
     const int j = m / nc, x = m - j * nc;
     const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
-    d.gL[sec][static_cast<size_t>(m) * ld + l] =
-        g0_interp(d, sec, x, site[l], tj - tau[l]) * (d.evd[sec][s0[l] + 2] - 1.0);
+    gview_w(d.gL[sec])[static_cast<size_t>(m) * ld + l] =
+        g0_interp(d, sec, x, site[l], tj - tau[l]) * (gview(d.evd[sec])[s0[l] + 2] - 1.0);
   }
 }
 

@@ -90,9 +90,10 @@ __device__ __forceinline__ void wave_mma(AF afn, BF bfn, int M, int k_begin, int
 }
 
 // One item: C tile rows [0, M), columns [c0, c0 + 16), handed to out(m, c, value).
-template <int MODE, int NRT, typename AF, typename BF, typename OF>
+// UO overrides the k-steps per batch (0: the default for NRT).
+template <int MODE, int NRT, int UO = 0, typename AF, typename BF, typename OF>
 __device__ __forceinline__ void skinny_item(AF afn, BF bfn, OF out, int M, int K, int Ncols, int c0, double *red) {
-  constexpr int U = NRT == 1 ? 8 : (NRT == 2 ? 4 : (NRT == 4 ? 2 : 1));
+  constexpr int U = UO ? UO : (NRT == 1 ? 8 : (NRT == 2 ? 4 : (NRT == 4 ? 2 : 1)));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   v4d acc[NRT];
 #pragma unroll
@@ -136,11 +137,11 @@ __device__ __forceinline__ void skinny_item(AF afn, BF bfn, OF out, int M, int K
   lds_barrier();   // red is reused by the next item
 }
 
-template <typename T, int MODE, int NRT>
-__device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int kind, int local, double *red) {
+template <typename T, int MODE, int NRT, int KIND>
+__device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int local, double *red) {
   const int lane = threadIdx.x & 63, lr = lane & 15;
   const int n = st.n, par = st.parity;
-  if (kind == kSkPrep) {
+  if constexpr (KIND == kSkPrep) {
     // per row group of candidates: items 0..2nt-1 YT[sec] = ZT N^T, 2nt..4nt-1 Rt[sec] = X N
     const int nt = (n + 15) >> 4;
     const int grp = local / (4 * nt), r0 = grp * kPrepRows;
@@ -161,7 +162,7 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int ki
       auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(k) * ld + c]) : 0.0; };
       skinny_item<MODE, NRT>(afn, bfn, out, M, n, n, c0, red);
     }
-  } else if (kind == kSkGnn) {
+  } else if constexpr (KIND == kSkGnn) {
     // Gnn[sec] = X YT^T + G0nn (K = 0 still writes Gnn = G0nn), per row group
     const int ki = st.k_ins, nt = (ki + 15) >> 4;
     const int grp = local / (2 * nt), r0 = grp * kPrepRows;
@@ -179,33 +180,39 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int ki
       Gnn[static_cast<size_t>(m) * km + cc] = v + G0nn[static_cast<size_t>(m) * km + cc];
     };
     skinny_item<MODE, NRT>(afn, bfn, out, M, n, ki, c0, red);
-  } else if (kind == kSkAsmB) {
+  } else if constexpr (KIND == kSkAsmB) {
     // Bc[sec] = Gamma^{-1} N_a(P, map): rows a < kpad (zero beyond k_a), K = k_a
     const int np = st.n_new, ka = st.k_a, kpad = (ka + 7) & ~7, nt = (np + 15) >> 4;
     const int sec = local / nt, c0 = (local - sec * nt) * 16, ld = d.ld, kcap = d.kcap;
-    const double *Gi = d.Ginv[sec], *Rt = d.Rt[sec];
-    const T *N = static_cast<const T *>(d.N[par][sec]);
-    const int32_t *P = d.P;
-    T *Bc = static_cast<T *>(d.Bc[sec]);
+    const auto Gi = gview(d.Ginv[sec]), Rt = gview(d.Rt[sec]);
+    const auto N = gview(static_cast<const T *>(d.N[par][sec]));
+    const auto Bc = gview_w(static_cast<T *>(d.Bc[sec]));
     const int c = c0 + lr;
-    const int mj = c < np ? d.map[c] : -1;
+    const int mj = c < np ? gview(d.map)[c] : -1;
+    // P (k_a <= 64 entries) is copied once per item into this wave's part of
+    // red (which wave mode leaves unused), so the gathers of N_a need no
+    // dependent global load; batches of k-steps are as long as registers allow
+    int *Ps = reinterpret_cast<int *>(red) + (threadIdx.x >> 6) * 64;
+    Ps[lane] = lane < ka ? gview(d.P)[lane] : 0;
+    __builtin_amdgcn_wave_barrier();
     auto afn = [=](int m, int k) { return m < ka ? Gi[m * kcap + k] : 0.0; };
     auto bfn = [=](int k) {
       if (mj < 0) return 0.0;
-      const int pb = P[k];
+      const int pb = Ps[k];
       if (pb < n) return (mj < n) ? static_cast<double>(N[static_cast<size_t>(pb) * ld + mj]) : 0.0;
       if (mj < n) return Rt[static_cast<size_t>(pb - n) * ld + mj];
       return pb == mj ? 1.0 : 0.0;
     };
     auto out = [=](int m, int cc, double v) { Bc[static_cast<size_t>(m) * ld + cc] = static_cast<T>(v); };
-    skinny_item<MODE, NRT>(afn, bfn, out, kpad, ka, np, c0, red);
-  } else if (kind == kSkMeasW) {
+    constexpr int UB = NRT <= 2 ? 8 : (NRT == 4 ? 4 : 1);   // bounded by the operand registers
+    skinny_item<MODE, NRT, UB>(afn, bfn, out, kpad, ka, np, c0, red);
+  } else if constexpr (KIND == kSkMeasW) {
     // W[sec] = N gR as (gRT N^T)^T: C[l][y]
     const int nt = (n + 15) >> 4;
     const int sec = local / nt, c0 = (local - sec * nt) * 16, ld = d.ld, ncap = d.n_cap, nc = d.nc;
-    const double *gR = d.gR[sec];
-    const T *N = static_cast<const T *>(d.N[par][sec]);
-    double *W = d.W[sec];
+    const auto gR = gview(d.gR[sec]);
+    const auto N = gview(static_cast<const T *>(d.N[par][sec]));
+    const auto W = gview_w(d.W[sec]);
     const int c = c0 + lr;
     const bool cok = c < n;
     auto afn = [=](int m, int k) { return gR[static_cast<size_t>(m) * ncap + k]; };
@@ -219,9 +226,9 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int ki
     const int sec = local / (ngroups * ntiles), rem = local - sec * ngroups * ntiles;
     const int g = rem / ntiles, c0 = (rem - g * ntiles) * 16;
     const int m0 = g * rows, M = min(rows, Mtot - m0), ld = d.ld;
-    const double *gL = d.gL[sec] + static_cast<size_t>(m0) * ld, *W = d.W[sec];
+    const auto gL = gview(d.gL[sec] + static_cast<size_t>(m0) * ld), W = gview(d.W[sec]);
     const double dt = d.beta / d.n_out;
-    double *Gxy = d.Gxy[sec];
+    const auto Gxy = gview_w(d.Gxy[sec]);
     const int c = c0 + lr;
     const bool cok = c < nc;
     auto afn = [=](int m, int l) { return gL[static_cast<size_t>(m) * ld + l]; };
@@ -235,9 +242,10 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int ki
   }
 }
 
-// Persistent over the work items of all chains.
-template <typename T, int MODE, int NRT>
-__global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, const ChainState *states, int kind,
+// Persistent over the work items of all chains; one instantiation per product
+// kind, so that each gets the registers of its own operands.
+template <typename T, int MODE, int NRT, int KIND>
+__global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, const ChainState *states,
                                                         int n_chains) {
   extern __shared__ int pre[];   // [n_chains + 1]
   __shared__ int scan[kSkThreads];
@@ -248,7 +256,7 @@ __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, c
   __syncthreads();
   for (int base = 0; base < n_chains; base += kSkThreads) {
     const int cc = base + tid;
-    scan[tid] = cc < n_chains ? skinny_items(descs[cc], states[cc], kind) : 0;
+    scan[tid] = cc < n_chains ? skinny_items(descs[cc], states[cc], KIND) : 0;
     __syncthreads();
     for (int off = 1; off < kSkThreads; off <<= 1) {
       const int v = tid >= off ? scan[tid - off] : 0;
@@ -270,17 +278,41 @@ __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, c
       const int mid = (lo + hi) >> 1;
       if (pre[mid] <= item) lo = mid; else hi = mid;
     }
-    skinny_dispatch<T, MODE, NRT>(descs[lo], states[lo], kind, item - pre[lo], red);
+    skinny_dispatch<T, MODE, NRT, KIND>(descs[lo], states[lo], item - pre[lo], red);
   }
 }
 
-template <typename T, int MODE, int NRT>
-static void launch_k(const Batch &b, hipStream_t s, int kind) {
+template <typename T, int MODE, int NRT, int KIND>
+static void launch_kk(const Batch &b, hipStream_t s) {
   const size_t lds = sizeof(int) * (b.n_chains + 1);
   // the measurement products read the state the last block left (d_mstate)
-  const ChainState *states = (kind == kSkMeasW || kind == kSkMeasG) ? b.d_mstate : b.d_state;
-  hipLaunchKernelGGL((k_skinny<T, MODE, NRT>), dim3(b.n_cu * 2), dim3(kSkThreads), lds, s, b.d_desc, states, kind,
+  const ChainState *states = (KIND == kSkMeasW || KIND == kSkMeasG) ? b.d_mstate : b.d_state;
+  hipLaunchKernelGGL((k_skinny<T, MODE, NRT, KIND>), dim3(b.n_cu * 2), dim3(kSkThreads), lds, s, b.d_desc, states,
                      b.n_chains);
+}
+
+// Only the (kind, row tiles, mode) combinations launch_skinny can choose are
+// instantiated: preparation and G_nn take at most 2 row tiles (32 candidates),
+// G one, B_c at most 4 (k_cap <= 64) and always one wave per item.
+template <typename T, int MODE, int NRT>
+static void launch_k(const Batch &b, hipStream_t s, int kind) {
+  switch (kind) {
+    case kSkPrep:
+      if constexpr (NRT <= 2) launch_kk<T, MODE, NRT, kSkPrep>(b, s);
+      break;
+    case kSkGnn:
+      if constexpr (NRT <= 2) launch_kk<T, MODE, NRT, kSkGnn>(b, s);
+      break;
+    case kSkMeasW:
+      launch_kk<T, MODE, NRT, kSkMeasW>(b, s);
+      break;
+    case kSkMeasG:
+      if constexpr (NRT == kMeasGRt) launch_kk<T, MODE, NRT, kSkMeasG>(b, s);
+      break;
+    default:
+      if constexpr (MODE == kModeWave && NRT <= 4) launch_kk<T, MODE, NRT, kSkAsmB>(b, s);
+      break;
+  }
 }
 
 template <typename T, int MODE>

@@ -40,10 +40,10 @@ __global__ __launch_bounds__(256) void k_assemble(const ChainDesc *descs, const 
     const int i = static_cast<int>(r / kpad), a = static_cast<int>(r - static_cast<int64_t>(i) * kpad);
     double v = 0.0;
     if (a < ka) {
-      const int mi = map[i], pa = P[a];
+      const int mi = gview(map)[i], pa = gview(P)[a];
       v = g_entry<T>(d, N, s0, n, sec, mi, pa) - (mi == pa ? 1.0 : 0.0);
     }
-    static_cast<T *>(d.Ac[sec])[static_cast<size_t>(i) * lda + a] = static_cast<T>(v);
+    gview_w(static_cast<T *>(d.Ac[sec]))[static_cast<size_t>(i) * lda + a] = static_cast<T>(v);
   }
 }
 
@@ -87,8 +87,8 @@ struct Mfma<float> {
 // Base value N_a(map i', map j') in the storage type.
 template <typename T>
 __device__ __forceinline__ T base_entry(const ChainDesc &d, const T *N, const double *Rt, int n, int mi, int mj) {
-  if (mi < n) return (mj < n) ? N[static_cast<size_t>(mi) * d.ld + mj] : T(0);
-  if (mj < n) return static_cast<T>(Rt[static_cast<size_t>(mi - n) * d.ld + mj]);
+  if (mi < n) return (mj < n) ? gview(N)[static_cast<size_t>(mi) * d.ld + mj] : T(0);
+  if (mj < n) return static_cast<T>(gview(Rt)[static_cast<size_t>(mi - n) * d.ld + mj]);
   return (mi == mj) ? T(1) : T(0);
 }
 
@@ -149,10 +149,12 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
     const int ti = local / nt, tj = local - ti * nt;
     const int par = st.parity;
     const T *N = static_cast<const T *>(d.N[par][sec]);
-    T *Nout = static_cast<T *>(d.N[par ^ 1][sec]);
-    const T *Ac = static_cast<const T *>(d.Ac[sec]);
-    const T *Bc = static_cast<const T *>(d.Bc[sec]);
+    const auto Nout = gview_w(static_cast<T *>(d.N[par ^ 1][sec]));
+    const auto Ac = gview(static_cast<const T *>(d.Ac[sec]));
+    const auto Bc = gview(static_cast<const T *>(d.Bc[sec]));
     const double *Rt = d.Rt[sec];
+    const auto map = gview(d.map);
+    const int lda = d.lda, ldn = d.ld;
     const int row0 = ti * TILE + wr * SUB, col0 = tj * TILE + wc * SUB;
     // the N_a entries this lane updates, loaded before the k loop so that their
     // latency overlaps the products
@@ -160,13 +162,13 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int cc = col0 + j * 16 + lr;
-      const int mj = cc < np ? d.map[cc] : 0;
+      const int mj = cc < np ? map[cc] : 0;
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = row0 + i * 16 + Mfma<T>::row(lk, q);
-          base[i][j][q] = (r < np && cc < np) ? base_entry<T>(d, N, Rt, n, d.map[r], mj) : T(0);
+          base[i][j][q] = (r < np && cc < np) ? base_entry<T>(d, N, Rt, n, map[r], mj) : T(0);
         }
     }
     acc_t acc[NB][NB];
@@ -175,23 +177,50 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
 #pragma unroll
       for (int j = 0; j < NB; ++j) acc[i][j] = Mfma<T>::zero();
     if (ka > 0) {
+      // k in batches of KS k-steps; the next batch's operands are loaded before
+      // the current batch's products (two batches in flight).  Ac and Bc are zero
+      // between k_a and kpad; steps past kpad load nothing.
+      constexpr int KS = TILE == 64 ? 2 : 4;   // bounded by the operand registers
       const int kpad = (ka + 7) & ~7;
-      for (int k0 = 0; k0 < kpad; k0 += 4) {
-        T af[NB], bf[NB];
+      T a0[KS][NB], b0[KS][NB], a1[KS][NB], b1[KS][NB];
+      auto load = [&](T (&av)[KS][NB], T (&bv)[KS][NB], int k0) {
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          const int r = row0 + i * 16 + lr;
-          af[i] = (r < np) ? Ac[static_cast<size_t>(r) * d.lda + k0 + lk] : T(0);
+        for (int u = 0; u < KS; ++u) {
+          const bool kok = k0 + 4 * u < kpad;
+          const int k = k0 + 4 * u + lk;
+#pragma unroll
+          for (int i = 0; i < NB; ++i) {
+            const int r = row0 + i * 16 + lr;
+            av[u][i] = (kok && r < np) ? Ac[static_cast<size_t>(r) * lda + k] : T(0);
+          }
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const int cc = col0 + j * 16 + lr;
+            bv[u][j] = (kok && cc < np) ? Bc[static_cast<size_t>(k) * ldn + cc] : T(0);
+          }
         }
+      };
+      auto mma = [&](const T (&av)[KS][NB], const T (&bv)[KS][NB], int k0) {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int cc = col0 + j * 16 + lr;
-          bf[j] = (cc < np) ? Bc[static_cast<size_t>(k0 + lk) * d.ld + cc] : T(0);
+        for (int u = 0; u < KS; ++u) {
+          if (k0 + 4 * u >= kpad) break;
+#pragma unroll
+          for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[i][j] = Mfma<T>::mma(av[u][i], bv[u][j], acc[i][j]);
         }
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) acc[i][j] = Mfma<T>::mma(af[i], bf[j], acc[i][j]);
+      };
+      int k0 = 0;
+      load(a0, b0, k0);
+      while (true) {
+        if (k0 + 4 * KS < kpad) load(a1, b1, k0 + 4 * KS);
+        mma(a0, b0, k0);
+        k0 += 4 * KS;
+        if (k0 >= kpad) break;
+        if (k0 + 4 * KS < kpad) load(a0, b0, k0 + 4 * KS);
+        mma(a1, b1, k0);
+        k0 += 4 * KS;
+        if (k0 >= kpad) break;
       }
     }
 #pragma unroll
@@ -203,7 +232,7 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = row0 + i * 16 + Mfma<T>::row(lk, q);
-          if (r < np) Nout[static_cast<size_t>(r) * d.ld + cc] = base[i][j][q] - acc[i][j][q];
+          if (r < np) Nout[static_cast<size_t>(r) * ldn + cc] = base[i][j][q] - acc[i][j][q];
         }
       }
     }
