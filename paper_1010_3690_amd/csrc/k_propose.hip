@@ -135,30 +135,36 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   int myP = 0, myDead = 0x7fffffff;
 
   // Gamma^{-1} of size k grows to k + 1 after an acceptance with Schur
-  // complement beta, from v = Gamma^{-1} s and u = w^T Gamma^{-1} (thread
-  // (b = loc % 64, a = loc / 64 + 2i) of the sector)
+  // complement beta, from v = Gamma^{-1} s and u = w^T Gamma^{-1}:
+  //   [[X + v u^T / beta, -v / beta], [-u^T / beta, 1 / beta]].
+  // Thread (cp = loc % 32, rg = loc / 32) of the sector owns columns 2cp, 2cp+1
+  // (adjacent doubles: paired LDS accesses) of rows rg + 4i; batches of four
+  // rows are loaded before they are stored.  Load addresses are clamped into the
+  // matrix and values beyond k never used, so the loads need no branch.
   auto grow = [&](int k, double beta) {
     const double ib = 1.0 / beta;
     const double *v = vv + sec * kp, *u = vu + sec * kp;
-    const int b = loc & 63, a0 = loc >> 6;
-    if (b <= k) {
-      // batches of 8 rows: loads first (in flight together), then stores.  Load
-      // addresses are clamped into the matrix and the values beyond k never used,
-      // so the loads need no per-element branch.
-      const double ub = (b < k) ? u[b] * ib : 0.0;
-      for (int a1 = a0; a1 <= k; a1 += 16) {
-        double va[8], ga[8];
+    const int cp = loc & 31, rg = loc >> 5, b0 = 2 * cp, b1 = b0 + 1;
+    if (b0 <= k) {
+      const double ub0 = (b0 < k) ? u[b0] * ib : 0.0;
+      const double ub1 = (b1 < k) ? u[b1] * ib : 0.0;
+      for (int a1 = rg; a1 <= k; a1 += 16) {
+        double va[4], g0[4], g1[4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int ac = min(a1 + 2 * i, kcap - 1);
+        for (int i = 0; i < 4; ++i) {
+          const int ac = min(a1 + 4 * i, kcap - 1);
           va[i] = v[ac];
-          ga[i] = Gis[ac * lg + b];
+          g0[i] = Gis[ac * lg + b0];
+          g1[i] = Gis[ac * lg + b1];
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int a = a1 + 2 * i;
-          if (a <= k)
-            Gis[a * lg + b] = (a < k) ? ((b < k) ? ga[i] + va[i] * ub : -va[i] * ib) : ((b < k) ? -ub : ib);
+        for (int i = 0; i < 4; ++i) {
+          const int a = a1 + 4 * i;
+          if (a <= k) {
+            Gis[a * lg + b0] = (a < k) ? ((b0 < k) ? g0[i] + va[i] * ub0 : -va[i] * ib) : ((b0 < k) ? -ub0 : ib);
+            if (b1 <= k)
+              Gis[a * lg + b1] = (a < k) ? ((b1 < k) ? g1[i] + va[i] * ub1 : -va[i] * ib) : ((b1 < k) ? -ub1 : ib);
+          }
         }
       }
     }
