@@ -193,6 +193,8 @@ def leg_batched(args, precision):
         from paper_1010_3690_amd.autotune import autotune
         print("[bench] autotuning the batched form", file=sys.stderr, flush=True)
         opts, tuning = autotune(ws, opts, warmup_proposals=args.batch_warmup * 64, trial_proposals=32 * 64)
+        print(f"[bench] autotuned: k_max={opts.k_max} k_cap={opts.k_cap} rankk_tile={opts.rankk_tile}",
+              file=sys.stderr, flush=True)
     gb = ctaux.CtauxBatch(ws, opts)
     gb.run(args.batch_warmup * 64)
     torch.cuda.synchronize()

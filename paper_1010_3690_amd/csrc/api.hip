@@ -288,7 +288,33 @@ int sync_states(ctaux_batch *h) {
   int rc = sync_all(h);
   if (rc) return rc;
   if (h->timing) flush_timing(h);
-  HIPCHECK(h, hipMemcpy(h->state.data(), h->b.d_state, sizeof(ChainState) * h->b.n_chains, hipMemcpyDeviceToHost));
+  // device-to-host copies are ordered on the batch's stream and waited for
+  HIPCHECK(h, hipMemcpyAsync(h->state.data(), h->b.d_state, sizeof(ChainState) * h->b.n_chains,
+                             hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  return CTAUX_OK;
+}
+
+// N of a chain between the device (rows of ld entries) and a compact host
+// array of n x n entries.  Whole padded rows move in one contiguous copy on the
+// batch's stream; the (un)packing is done on the host.  (Two-dimensional copies
+// between pageable host memory and the device have been seen to deliver zeros
+// when the process runs under the ROCm kernel tracer.)
+int n_to_host(ctaux_batch *h, void *dst, const void *src, int n, size_t es) {
+  const size_t ld = static_cast<size_t>(h->b.ld);
+  std::vector<char> rows(es * ld * n);
+  HIPCHECK(h, hipMemcpyAsync(rows.data(), src, rows.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  for (int i = 0; i < n; ++i) memcpy(static_cast<char *>(dst) + es * n * i, rows.data() + es * ld * i, es * n);
+  return CTAUX_OK;
+}
+
+int n_to_device(ctaux_batch *h, void *dst, const void *src, int n, size_t es) {
+  const size_t ld = static_cast<size_t>(h->b.ld);
+  std::vector<char> rows(es * ld * n, 0);
+  for (int i = 0; i < n; ++i) memcpy(rows.data() + es * ld * i, static_cast<const char *>(src) + es * n * i, es * n);
+  HIPCHECK(h, hipMemcpyAsync(dst, rows.data(), rows.size(), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));   // rows is freed on return
   return CTAUX_OK;
 }
 
@@ -338,7 +364,12 @@ int refine_all(ctaux_batch *h, bool adapt) {
       used += need;
     }
     if (items.empty()) return CTAUX_OK;
-    HIPCHECK(h, hipMemcpy(b.r_items, items.data(), sizeof(RefineItem) * items.size(), hipMemcpyHostToDevice));
+    // host-to-device copies go on the batch's stream and are waited for: a
+    // synchronous hipMemcpy from pageable memory may return before its DMA has
+    // landed, and is not ordered with a stream other than the null stream
+    HIPCHECK(h, hipMemcpyAsync(b.r_items, items.data(), sizeof(RefineItem) * items.size(), hipMemcpyHostToDevice,
+                               h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
     starts.push_back(static_cast<int>(items.size()));
     Timer t(h, 8);
     for (size_t g = 0; g + 1 < starts.size(); ++g)
@@ -494,9 +525,13 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
   h->state = st;
   setup_propose(b);
   setup_refine(b);
-  if (hipMemcpy(b.d_desc, h->desc.data(), sizeof(ChainDesc) * n_chains, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b.d_state, st.data(), sizeof(ChainState) * n_chains, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b.d_mstate, st.data(), sizeof(ChainState) * n_chains, hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpyAsync(b.d_desc, h->desc.data(), sizeof(ChainDesc) * n_chains, hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(b.d_state, st.data(), sizeof(ChainState) * n_chains, hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(b.d_mstate, st.data(), sizeof(ChainState) * n_chains, hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
     delete h;
     return set_err(nullptr, CTAUX_EDEVICE, "descriptor upload failed");
   }
@@ -567,7 +602,8 @@ int ctaux_get_obs(ctaux_batch *h, int32_t chain, double *out, int32_t len) {
     int rc_ = sync_all(h);
     if (rc_) return rc_;
   }
-  HIPCHECK(h, hipMemcpy(out, h->desc[chain].obs, sizeof(double) * L, hipMemcpyDeviceToHost));
+  HIPCHECK(h, hipMemcpyAsync(out, h->desc[chain].obs, sizeof(double) * L, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
   for (int32_t i = L; i < len; ++i) out[i] = 0.0;
   return CTAUX_OK;
 }
@@ -625,10 +661,11 @@ int ctaux_get_config(ctaux_batch *h, int32_t chain, int32_t cap, ctaux_vertex *o
   std::vector<double> tau(m);
   std::vector<int32_t> site(m), s(m);
   std::vector<int64_t> id(m);
-  HIPCHECK(h, hipMemcpy(tau.data(), d.tau[par], sizeof(double) * m, hipMemcpyDeviceToHost));
-  HIPCHECK(h, hipMemcpy(site.data(), d.site[par], sizeof(int32_t) * m, hipMemcpyDeviceToHost));
-  HIPCHECK(h, hipMemcpy(s.data(), d.s0[par], sizeof(int32_t) * m, hipMemcpyDeviceToHost));
-  HIPCHECK(h, hipMemcpy(id.data(), d.id[par], sizeof(int64_t) * m, hipMemcpyDeviceToHost));
+  HIPCHECK(h, hipMemcpyAsync(tau.data(), d.tau[par], sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipMemcpyAsync(site.data(), d.site[par], sizeof(int32_t) * m, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipMemcpyAsync(s.data(), d.s0[par], sizeof(int32_t) * m, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipMemcpyAsync(id.data(), d.id[par], sizeof(int64_t) * m, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
   for (int i = 0; i < m; ++i) out[i] = ctaux_vertex{id[i], tau[i], site[i], s[i]};
   return CTAUX_OK;
 }
@@ -645,7 +682,8 @@ int ctaux_get_N(ctaux_batch *h, int32_t chain, int32_t sector, double *out, int3
   if (ld < n) return set_err(h, CTAUX_EINVAL, "ld < order %d", n);
   const size_t es = h->b.precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
   std::vector<char> tmp(es * n * n);
-  HIPCHECK(h, hipMemcpy2D(tmp.data(), es * n, d.N[st.parity][sector], es * d.ld, es * n, n, hipMemcpyDeviceToHost));
+  int rc2 = n_to_host(h, tmp.data(), d.N[st.parity][sector], n, es);
+  if (rc2) return rc2;
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j)
       out[static_cast<size_t>(i) * ld + j] =
@@ -663,8 +701,10 @@ int ctaux_get_decisions(ctaux_batch *h, int32_t chain, int64_t first, int64_t co
     int rc_ = sync_all(h);
     if (rc_) return rc_;
   }
-  HIPCHECK(h, hipMemcpy(acc, h->desc[chain].log_acc + first, count, hipMemcpyDeviceToHost));
-  HIPCHECK(h, hipMemcpy(R, h->desc[chain].log_R + first, sizeof(double) * count, hipMemcpyDeviceToHost));
+  HIPCHECK(h, hipMemcpyAsync(acc, h->desc[chain].log_acc + first, count, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipMemcpyAsync(R, h->desc[chain].log_R + first, sizeof(double) * count, hipMemcpyDeviceToHost,
+                             h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
   return CTAUX_OK;
 }
 
@@ -761,20 +801,22 @@ int ctaux_checkpoint(ctaux_batch *h, int32_t chain, void *buf, size_t *len) {
   p += sizeof hd;
   const size_t es = h->b.precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
   if (n > 0) {
-    HIPCHECK(h, hipMemcpy(p, d.id[par], 8 * n, hipMemcpyDeviceToHost));
+    HIPCHECK(h, hipMemcpyAsync(p, d.id[par], 8 * n, hipMemcpyDeviceToHost, h->stream));
     p += 8 * n;
-    HIPCHECK(h, hipMemcpy(p, d.tau[par], 8 * n, hipMemcpyDeviceToHost));
+    HIPCHECK(h, hipMemcpyAsync(p, d.tau[par], 8 * n, hipMemcpyDeviceToHost, h->stream));
     p += 8 * n;
-    HIPCHECK(h, hipMemcpy(p, d.site[par], 4 * n, hipMemcpyDeviceToHost));
+    HIPCHECK(h, hipMemcpyAsync(p, d.site[par], 4 * n, hipMemcpyDeviceToHost, h->stream));
     p += 4 * n;
-    HIPCHECK(h, hipMemcpy(p, d.s0[par], 4 * n, hipMemcpyDeviceToHost));
+    HIPCHECK(h, hipMemcpyAsync(p, d.s0[par], 4 * n, hipMemcpyDeviceToHost, h->stream));
     p += 4 * n;
     for (int sec = 0; sec < 2; ++sec) {
-      HIPCHECK(h, hipMemcpy2D(p, es * n, d.N[par][sec], es * d.ld, es * n, n, hipMemcpyDeviceToHost));
+      rc = n_to_host(h, p, d.N[par][sec], n, es);
+      if (rc) return rc;
       p += es * n * n;
     }
   }
-  HIPCHECK(h, hipMemcpy(p, d.obs, sizeof(double) * h->obs_len[chain], hipMemcpyDeviceToHost));
+  HIPCHECK(h, hipMemcpyAsync(p, d.obs, sizeof(double) * h->obs_len[chain], hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
   return CTAUX_OK;
 }
 
@@ -797,20 +839,21 @@ int ctaux_restore(ctaux_batch *h, int32_t chain, const void *buf, size_t len) {
   const size_t es = h->b.precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
   const char *p = static_cast<const char *>(buf) + sizeof hd;
   if (n > 0) {
-    HIPCHECK(h, hipMemcpy(d.id[0], p, 8 * n, hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpyAsync(d.id[0], p, 8 * n, hipMemcpyHostToDevice, h->stream));
     p += 8 * n;
-    HIPCHECK(h, hipMemcpy(d.tau[0], p, 8 * n, hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpyAsync(d.tau[0], p, 8 * n, hipMemcpyHostToDevice, h->stream));
     p += 8 * n;
-    HIPCHECK(h, hipMemcpy(d.site[0], p, 4 * n, hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpyAsync(d.site[0], p, 4 * n, hipMemcpyHostToDevice, h->stream));
     p += 4 * n;
-    HIPCHECK(h, hipMemcpy(d.s0[0], p, 4 * n, hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpyAsync(d.s0[0], p, 4 * n, hipMemcpyHostToDevice, h->stream));
     p += 4 * n;
     for (int sec = 0; sec < 2; ++sec) {
-      HIPCHECK(h, hipMemcpy2D(d.N[0][sec], es * d.ld, p, es * n, es * n, n, hipMemcpyHostToDevice));
+      rc = n_to_device(h, d.N[0][sec], p, n, es);
+      if (rc) return rc;
       p += es * n * n;
     }
   }
-  HIPCHECK(h, hipMemcpy(d.obs, p, sizeof(double) * hd.obs_len, hipMemcpyHostToDevice));
+  HIPCHECK(h, hipMemcpyAsync(d.obs, p, sizeof(double) * hd.obs_len, hipMemcpyHostToDevice, h->stream));
   ChainState st;
   memset(&st, 0, sizeof st);
   st.n = n;
@@ -828,7 +871,10 @@ int ctaux_restore(ctaux_batch *h, int32_t chain, const void *buf, size_t len) {
   st.rk_flops = hd.rk_flops;
   st.rk_bytes = hd.rk_bytes;
   st.sum_order = hd.sum_order;
-  HIPCHECK(h, hipMemcpy(h->b.d_state + chain, &st, sizeof st, hipMemcpyHostToDevice));
+  HIPCHECK(h, hipMemcpyAsync(h->b.d_state + chain, &st, sizeof st, hipMemcpyHostToDevice, h->stream));
+  // the copies above read the caller's buffer and st: wait for them on the
+  // batch's stream (see refine_all on synchronous copies from pageable memory)
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
   h->state[chain] = st;
   // The refinement schedule belongs to the batch; a one-chain batch takes over
   // the schedule of the checkpointed one (when both use the same recompute_every).
