@@ -56,6 +56,7 @@ struct ctaux_batch {
   hipEvent_t ev_end = nullptr, ev_meas = nullptr;
   bool meas_owed = false;      // a block ended and its measurement is not launched yet
   bool meas_pending = false;   // ev_meas marks the end of the last launched measurement
+  bool begun = false;          // the next block's start already ran (fused into the last block's end)
   std::vector<ChainDesc> desc;        // host copies
   std::vector<ChainState> state;      // host mirror (refreshed at sync points)
   std::vector<int32_t> obs_len;
@@ -225,7 +226,7 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
   return align_up(cv.off, 256);
 }
 
-int enqueue_block(ctaux_batch *h);
+int enqueue_block(ctaux_batch *h, bool next_follows);
 
 struct Timer {
   ctaux_batch *h;
@@ -378,10 +379,16 @@ int refine_all(ctaux_batch *h, bool adapt) {
   return CTAUX_OK;
 }
 
-int enqueue_block(ctaux_batch *h) {
+// next_follows: another block is enqueued right after this one, so its start
+// is fused into this block's end (k_block_turn).
+int enqueue_block(ctaux_batch *h, bool next_follows) {
   const Batch &b = h->b;
   hipStream_t s = h->stream;
-  { Timer t(h, 0); launch_block_begin(b, s); }
+  if (!h->begun) {
+    Timer t(h, 0);
+    launch_block_begin(b, s);
+  }
+  h->begun = false;
   { Timer t(h, 1); launch_interp(b, s); }
   { Timer t(h, 2); launch_prep(b, s); }
   int rc = launch_owed_measure(h);   // the previous block's, beside this block's proposals
@@ -391,7 +398,14 @@ int enqueue_block(ctaux_batch *h) {
   { Timer t(h, 5); launch_rankk(b, s); }
   // k_block_end rewrites the state copy the previous measurement reads
   if (h->meas_pending) HIPCHECK(h, hipStreamWaitEvent(s, h->ev_meas, 0));
-  { Timer t(h, 6); launch_block_end(b, s); }
+  if (next_follows) {
+    Timer t(h, 6);
+    launch_block_turn(b, s);
+    h->begun = true;
+  } else {
+    Timer t(h, 6);
+    launch_block_end(b, s);
+  }
   h->meas_owed = true;
   // many chains: the measurement is the longest step of a block and the next
   // block's k_block_end waits for it, so it starts at once
@@ -558,7 +572,7 @@ int ctaux_run(ctaux_batch *h, int64_t n_proposals) {
   int64_t prev_done = -1;
   while (true) {
     for (int64_t i = 0; i < iters; ++i) {
-      rc = enqueue_block(h);
+      rc = enqueue_block(h, i + 1 < iters);
       if (rc) return rc;
     }
     rc = sync_states(h);

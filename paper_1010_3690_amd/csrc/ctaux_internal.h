@@ -122,6 +122,7 @@ void launch_propose(const Batch &b, hipStream_t s);
 void launch_assemble(const Batch &b, hipStream_t s);
 void launch_rankk(const Batch &b, hipStream_t s);
 void launch_block_end(const Batch &b, hipStream_t s);
+void launch_block_turn(const Batch &b, hipStream_t s);   // block end + next block begin
 void launch_measure(const Batch &b, hipStream_t s);
 // Refinement of a group of chains: each item names a chain, its order and the
 // offset (in doubles) of its scratch in the refinement pool.

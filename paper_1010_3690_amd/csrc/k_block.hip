@@ -18,10 +18,7 @@ void launch_set_target(const Batch &b, hipStream_t s, int64_t n_proposals) {
 // One workgroup per chain.  Decides the block length (at most k_max, never
 // past a measurement point), decodes the block's proposals and collects the
 // insertion candidates in proposal order.
-__global__ __launch_bounds__(256) void k_block_begin(const ChainDesc *descs, ChainState *states) {
-  const int c = blockIdx.x;
-  const ChainDesc &d = descs[c];
-  ChainState &st = states[c];
+__device__ void block_begin_chain(const ChainDesc &d, ChainState &st) {
   __shared__ int sh_L, sh_active;
   __shared__ int scan[256];
   if (threadIdx.x == 0) {
@@ -87,6 +84,10 @@ __global__ __launch_bounds__(256) void k_block_begin(const ChainDesc *descs, Cha
   if (t == 255) st.k_ins = scan[255];
 }
 
+__global__ __launch_bounds__(256) void k_block_begin(const ChainDesc *descs, ChainState *states) {
+  block_begin_chain(descs[blockIdx.x], states[blockIdx.x]);
+}
+
 void launch_block_begin(const Batch &b, hipStream_t s) {
   hipLaunchKernelGGL(k_block_begin, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_state);
 }
@@ -138,15 +139,11 @@ void launch_interp(const Batch &b, hipStream_t s) {
 
 // Ends a block and leaves a copy of the chain's state for the measurement
 // (mstates), which runs on a stream of its own beside the next block.
-__global__ void k_block_end(const ChainDesc *descs, ChainState *states, ChainState *mstates, int n_chains) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_chains) return;
-  ChainState &st = states[c];
+__device__ void block_end_chain(const ChainDesc &d, ChainState &st, ChainState &mst) {
   if (!st.active) {
-    mstates[c] = st;
+    mst = st;
     return;
   }
-  const ChainDesc &d = descs[c];
   // algorithmic work of the update per sector: Bc = Gamma^{-1} N_P (2 k^2 n') and
   // N' = N - Ac Bc (2 n'^2 k); bytes: read and write n'^2 entries of N plus Ac and Bc
   const double np = st.n_new, ka = st.k_a;
@@ -175,12 +172,31 @@ __global__ void k_block_end(const ChainDesc *descs, ChainState *states, ChainSta
     st.meas_flops += 2.0 * (2.0 * np * np * nc + 2.0 * m * np * nc);
     st.meas_bytes += 2.0 * (es * np * np + 8.0 * (2.0 + 2.0) * m * np + 8.0 * 2.0 * np * nc);
   }
-  mstates[c] = st;
+  mst = st;
+}
+
+__global__ void k_block_end(const ChainDesc *descs, ChainState *states, ChainState *mstates, int n_chains) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n_chains) block_end_chain(descs[c], states[c], mstates[c]);
+}
+
+// The end of one block and the start of the next in one launch (one workgroup
+// per chain): saves a kernel, and its launch gap, on the critical path of every
+// block but the last of a run.
+__global__ __launch_bounds__(256) void k_block_turn(const ChainDesc *descs, ChainState *states, ChainState *mstates) {
+  const int c = blockIdx.x;
+  if (threadIdx.x == 0) block_end_chain(descs[c], states[c], mstates[c]);
+  __syncthreads();   // the state thread 0 wrote is read by the whole workgroup below
+  block_begin_chain(descs[c], states[c]);
 }
 
 void launch_block_end(const Batch &b, hipStream_t s) {
   hipLaunchKernelGGL(k_block_end, dim3((b.n_chains + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state,
                      b.d_mstate, b.n_chains);
+}
+
+void launch_block_turn(const Batch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_turn, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_state, b.d_mstate);
 }
 
 }  // namespace ctaux

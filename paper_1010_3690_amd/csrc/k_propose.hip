@@ -657,8 +657,10 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     st.next_id = next_id;
     st.accepted = accepted;
     st.gj_fallbacks += sh_fallback[0] + sh_fallback[1];
-    st.status = status;
-    if (status != 0) st.err_index = err_index;
+    if (status != 0) {   // never clears a status set elsewhere (a refinement between blocks)
+      st.status = status;
+      st.err_index = err_index;
+    }
     if (sh_nnew != ncur && status == 0) {
       st.status = -4;
       st.err_index = -2;   // bookkeeping mismatch

@@ -246,13 +246,20 @@ __global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const R
     else if (dr > drift) drift = dr;
   }
   st.pass_drift = drift;
-  if (!isfinite(drift) && st.status == 0) st.status = -4;
+  // A failing chain is also deactivated: the next block may already have been
+  // started (its start is fused into the previous block's end), and its kernels
+  // then skip the chain.
+  if (!isfinite(drift) && st.status == 0) {
+    st.status = -4;
+    st.active = 0;
+  }
   if (pass > 0) return;
   st.last_drift = drift;
   if (!(drift <= st.max_drift)) st.max_drift = drift;
   if (st.status == 0 && descs[c].drift_tol > 0.0 && drift > descs[c].drift_tol) {
     st.status = -4;   // N no longer represents the inverse of its definition
     st.err_index = -5;
+    st.active = 0;
   }
 }
 
