@@ -218,6 +218,37 @@ def test_capacity_error_matches_oracle():
     _compare(gb, oc, done)
 
 
+def test_drift_tol_stops_the_chains():
+    """A refinement whose drift exceeds drift_tol stops the chain with
+    CTAUX_ENUMERIC.  A tolerance below any FP64 drift forces it at the first
+    refinement (after block 4): both chains of the batch stop there, although
+    the next block's start has already been launched, their decisions up to
+    there equal the oracle's, and a further run reports the same error."""
+    ctaux = _ctaux()
+    w = _plaquette()
+    n_prop = 64 * 12
+    opts = ctaux.Options(k_max=64, k_cap=64, n_cap=512, log_cap=n_prop, recompute_every=4, seed=3,
+                         drift_tol=1e-300)
+    gb = ctaux.CtauxBatch([w, w], opts)
+    with pytest.raises(ctaux.CtauxError) as e:
+        gb.run(n_prop)
+    assert e.value.code == ctaux.CTAUX_ENUMERIC and "drift_tol" in str(e.value)
+    for c in range(2):
+        st = gb.stats(c)
+        assert st["status"] == ctaux.CTAUX_ENUMERIC
+        # the first refinement follows block 4 (interval min(8, 4)); nothing runs after it
+        assert st["proposals"] == 4 * 64, st["proposals"]
+        oc = OracleChain(w, seed=3, chain_id=c, n_cap=512)
+        oc.set_log(st["proposals"])
+        oc.run(st["proposals"])
+        acc_g, _ = gb.decisions(c, 0, st["proposals"])
+        acc_o, _ = oc.get_log(0, st["proposals"])
+        assert np.array_equal(acc_g, acc_o)
+    with pytest.raises(ctaux.CtauxError) as e2:
+        gb.run(64)
+    assert e2.value.code == ctaux.CTAUX_ENUMERIC
+
+
 def test_full_size_cluster_N_is_inverse_of_definition():
     """4x4 cluster at order ~1000 (k = 64): N equals the FP64 inverse of its definition."""
     ctaux = _ctaux()
