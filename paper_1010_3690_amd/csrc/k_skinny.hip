@@ -89,17 +89,96 @@ __device__ __forceinline__ void wave_mma(AF afn, BF bfn, int M, int k_begin, int
   }
 }
 
+// As wave_mma, with the k index permuted inside groups of 16: in step i of a
+// group starting at k0, lane l supplies A(16r + l%16, k0 + 4(l/16) + i) and
+// B(k0 + 4(l/16) + i, c).  The four steps of a group then read four
+// consecutive k per lane, so operands stored along k (rows of N, of X, Zt,
+// YT, gR, gL) load as whole 32-byte pieces, four lanes covering one 128-byte
+// line.  The products are the same; only the order of the k terms changes.
+// afn and bfn must accept any row below M and any k below k_end, and bfn any
+// k for the lane's column (the caller clamps addresses and masks values).
+template <int NRT, int U, typename AF, typename BF>
+__device__ __forceinline__ void wave_mma_kv(AF afn, BF bfn, int M, int k_begin, int k_end, v4d (&acc)[NRT]) {
+  static_assert(U % 4 == 0, "whole groups of four k-steps");
+  constexpr int G = U / 4;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  double b0[G][4], a0[G][4][NRT], b1[G][4], a1[G][4][NRT];
+  auto load = [&](double (&bv)[G][4], double (&av)[G][4][NRT], int k0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int kb = k0 + 16 * g + 4 * lk;
+      if (kb + 3 < k_end) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[g][i] = bfn(kb + i);
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) {
+          const int m = r * 16 + lr;
+          const bool mok = m < M;
+          const int mc = mok ? m : 0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double v = afn(mc, kb + i);
+            av[g][i][r] = mok ? v : 0.0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = kb + i;
+          const bool kok = k < k_end;
+          bv[g][i] = kok ? bfn(k) : 0.0;
+#pragma unroll
+          for (int r = 0; r < NRT; ++r) {
+            const int m = r * 16 + lr;
+            av[g][i][r] = (kok && m < M) ? afn(m, k) : 0.0;
+          }
+        }
+      }
+    }
+  };
+  auto mma = [&](const double (&bv)[G][4], const double (&av)[G][4][NRT]) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < NRT; ++r)
+          acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g][i][r], bv[g][i], acc[r], 0, 0, 0);
+  };
+  constexpr int S = 16 * G;
+  int k0 = k_begin;
+  if (k0 >= k_end) return;
+  load(b0, a0, k0);
+  while (true) {
+    load(b1, a1, k0 + S);
+    mma(b0, a0);
+    k0 += S;
+    if (k0 >= k_end) break;
+    load(b0, a0, k0 + S);
+    mma(b1, a1);
+    k0 += S;
+    if (k0 >= k_end) break;
+  }
+}
+
 // One item: C tile rows [0, M), columns [c0, c0 + 16), handed to out(m, c, value).
 // UO overrides the k-steps per batch (0: the default for NRT).
-template <int MODE, int NRT, int UO = 0, typename AF, typename BF, typename OF>
+// KV: operands stored along k, loaded four k at a time (wave_mma_kv; up to four
+// row tiles).
+template <int MODE, int NRT, int UO = 0, bool KV = false, typename AF, typename BF, typename OF>
 __device__ __forceinline__ void skinny_item(AF afn, BF bfn, OF out, int M, int K, int Ncols, int c0, double *red) {
-  constexpr int U = UO ? UO : (NRT == 1 ? 8 : (NRT == 2 ? 4 : (NRT == 4 ? 2 : 1)));
+  constexpr bool kv = KV && NRT <= 4;
+  constexpr int U = kv ? (NRT == 1 ? 8 : 4) : (UO ? UO : (NRT == 1 ? 8 : (NRT == 2 ? 4 : (NRT == 4 ? 2 : 1))));
+  auto mma = [&](int kbeg, int kend, v4d (&acc)[NRT]) {
+    if constexpr (kv) wave_mma_kv<NRT, U>(afn, bfn, M, kbeg, kend, acc);
+    else wave_mma<NRT, U>(afn, bfn, M, kbeg, kend, acc);
+  };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   v4d acc[NRT];
 #pragma unroll
   for (int r = 0; r < NRT; ++r) acc[r] = v4d{0.0, 0.0, 0.0, 0.0};
   if (MODE == kModeWave) {
-    wave_mma<NRT, U>(afn, bfn, M, 0, K, acc);
+    mma(0, K, acc);
 #pragma unroll
     for (int r = 0; r < NRT; ++r) {
 #pragma unroll
@@ -114,7 +193,7 @@ __device__ __forceinline__ void skinny_item(AF afn, BF bfn, OF out, int M, int K
   // contiguous eighths of K, rounded to whole k-steps
   const int chunk = (((K + kSkWaves - 1) / kSkWaves) + 3) & ~3;
   const int kb = wave * chunk;
-  wave_mma<NRT, U>(afn, bfn, M, kb, min(K, kb + chunk), acc);
+  mma(kb, min(K, kb + chunk), acc);
   for (int w = 0; w < kSkWaves; ++w) {   // fixed-order reduction of the partial tiles
     if (wave == w) {
 #pragma unroll
@@ -153,14 +232,21 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
     const int M = min(kPrepRows, st.k_ins - r0);
     const int c = c0 + lr;
     const bool cok = c < n;
+    const int cc0 = cok ? c : 0;   // in-bounds address; the value is masked
     auto afn = [=](int m, int k) { return A[static_cast<size_t>(m) * ld + k]; };
     auto out = [=](int m, int cc, double v) { C[static_cast<size_t>(m) * ld + cc] = v; };
     if (job < 2) {
-      auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(c) * ld + k]) : 0.0; };
-      skinny_item<MODE, NRT>(afn, bfn, out, M, n, n, c0, red);
+      auto bfn = [=](int k) {
+        const double v = static_cast<double>(N[static_cast<size_t>(cc0) * ld + k]);
+        return cok ? v : 0.0;
+      };
+      skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, n, c0, red);
     } else {
-      auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(k) * ld + c]) : 0.0; };
-      skinny_item<MODE, NRT>(afn, bfn, out, M, n, n, c0, red);
+      auto bfn = [=](int k) {
+        const double v = static_cast<double>(N[static_cast<size_t>(k) * ld + cc0]);
+        return cok ? v : 0.0;
+      };
+      skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, n, c0, red);
     }
   } else if constexpr (KIND == kSkGnn) {
     // Gnn[sec] = X YT^T + G0nn (K = 0 still writes Gnn = G0nn), per row group
@@ -174,12 +260,16 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
     const int M = min(kPrepRows, ki - r0);
     const int c = c0 + lr;
     const bool cok = c < ki;
+    const int cc0 = cok ? c : 0;
     auto afn = [=](int m, int k) { return X[static_cast<size_t>(m) * ld + k]; };
-    auto bfn = [=](int k) { return cok ? YT[static_cast<size_t>(c) * ld + k] : 0.0; };
+    auto bfn = [=](int k) {
+      const double v = YT[static_cast<size_t>(cc0) * ld + k];
+      return cok ? v : 0.0;
+    };
     auto out = [=](int m, int cc, double v) {
       Gnn[static_cast<size_t>(m) * km + cc] = v + G0nn[static_cast<size_t>(m) * km + cc];
     };
-    skinny_item<MODE, NRT>(afn, bfn, out, M, n, ki, c0, red);
+    skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, ki, c0, red);
   } else if constexpr (KIND == kSkAsmB) {
     // Bc[sec] = Gamma^{-1} N_a(P, map): rows a < kpad (zero beyond k_a), K = k_a
     const int np = st.n_new, ka = st.k_a, kpad = (ka + 7) & ~7, nt = (np + 15) >> 4;
@@ -215,10 +305,14 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
     const auto W = gview_w(d.W[sec]);
     const int c = c0 + lr;
     const bool cok = c < n;
+    const int cc0 = cok ? c : 0;
     auto afn = [=](int m, int k) { return gR[static_cast<size_t>(m) * ncap + k]; };
-    auto bfn = [=](int k) { return cok ? static_cast<double>(N[static_cast<size_t>(c) * ld + k]) : 0.0; };
+    auto bfn = [=](int k) {
+      const double v = static_cast<double>(N[static_cast<size_t>(cc0) * ld + k]);
+      return cok ? v : 0.0;
+    };
     auto out = [=](int m, int cc, double v) { W[static_cast<size_t>(cc) * nc + m] = v; };
-    skinny_item<MODE, NRT>(afn, bfn, out, nc, n, n, c0, red);
+    skinny_item<MODE, NRT, 0, true>(afn, bfn, out, nc, n, n, c0, red);
   } else {
     // Gxy: rows m = j*nc + x (j = 0: tau = 0+, j >= 1: tau_{j-1}); item = 16*kMeasGRt rows x 16 columns y
     const int nc = d.nc, Mtot = nc * (d.n_out + 1), rows = 16 * kMeasGRt;
@@ -231,14 +325,18 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
     const auto Gxy = gview_w(d.Gxy[sec]);
     const int c = c0 + lr;
     const bool cok = c < nc;
+    const int cc0 = cok ? c : 0;
     auto afn = [=](int m, int l) { return gL[static_cast<size_t>(m) * ld + l]; };
-    auto bfn = [=](int l) { return cok ? W[static_cast<size_t>(l) * nc + c] : 0.0; };
+    auto bfn = [=](int l) {
+      const double v = W[static_cast<size_t>(l) * nc + cc0];
+      return cok ? v : 0.0;
+    };
     auto out = [&](int m, int cc, double v) {
       const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
       const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
       Gxy[static_cast<size_t>(j) * nc * nc + x * nc + cc] = g0_interp(d, sec, x, cc, tj) + v;
     };
-    skinny_item<MODE, NRT>(afn, bfn, out, M, n, nc, c0, red);
+    skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, nc, c0, red);
   }
 }
 
