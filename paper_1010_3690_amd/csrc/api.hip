@@ -119,6 +119,9 @@ int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, c
       return set_err(eb, CTAUX_EINVAL, "chain %d: need beta > 0, U >= 0, K > 0", c);
     if (m.n_sites < 1 || m.n_sites > 128 || m.n_tau < 2 || m.n_disp < 1 || !m.site_disp || !m.g0_up || !m.g0_dn)
       return set_err(eb, CTAUX_EINVAL, "chain %d: invalid sizes or null tables (n_sites <= 128)", c);
+    // the table kernels index a chain's elements with 32-bit integers
+    if (2ll * (o->n_tau_out + 1) * m.n_sites * o->n_cap >= (1ll << 31))
+      return set_err(eb, CTAUX_EINVAL, "chain %d: 2 (n_tau_out + 1) n_sites n_cap must stay below 2^31", c);
     for (int i = 0; i < m.n_sites * m.n_sites; ++i)
       if (m.site_disp[i] < 0 || m.site_disp[i] >= m.n_disp)
         return set_err(eb, CTAUX_EINVAL, "chain %d: site_disp out of range", c);

@@ -59,7 +59,10 @@ def test_workspace_bytes_and_validation(lib):
     m2, o2, keep2 = _model_and_opts(ctaux, n_cap=256, precision=ctaux.CTAUX_FP32)
     assert lib.ctaux_workspace_bytes(C.byref(m2), 1, C.byref(o2)) < nb
     for bad in (dict(k_max=0), dict(k_max=129), dict(k_cap=65), dict(k_cap=8, k_max=4), dict(p_flip=1.5),
-                dict(precision=7), dict(n_cap=0), dict(meas_every=0)):
+                dict(precision=7), dict(n_cap=0), dict(meas_every=0), dict(rankk_tile=16),
+                dict(gamma_tol=float("nan")),
+                # 2 (n_tau_out + 1) n_sites n_cap >= 2^31 (32-bit table indices): 2 * 4097 * 4 * 65536
+                dict(n_tau_out=4096, n_cap=65536)):
         mb, ob, kb = _model_and_opts(ctaux, **bad)
         assert lib.ctaux_workspace_bytes(C.byref(mb), 1, C.byref(ob)) == 0, bad
     # a non-finite table entry is rejected
