@@ -26,9 +26,12 @@
  *   - Device memory: the caller passes one device workspace of at least
  *     ctaux_workspace_bytes() bytes (256-byte aligned) that must stay valid
  *     until ctaux_destroy(); the library allocates no device memory itself.
- *   - Stream: every kernel runs on the caller's HIP stream (NULL = the
- *     default stream).  Entry points return after the stream has drained,
- *     except where stated.
+ *   - Streams: the block kernels and every copy run on the caller's HIP
+ *     stream (NULL = the default stream).  The measurement kernels run on a
+ *     stream the library creates at ctaux_create (default priority,
+ *     non-blocking), ordered against the caller's stream with two events per
+ *     block; ctaux_destroy releases them.  Entry points return after both
+ *     streams have drained, except where stated.
  *   - Handles are not thread-safe; distinct handles may be used concurrently
  *     on distinct streams.
  *   - Chains are independent: chain c draws from the stream keyed by
