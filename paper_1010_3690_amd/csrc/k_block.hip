@@ -106,15 +106,15 @@ __global__ __launch_bounds__(256) void k_interp(const ChainDesc *descs, const Ch
   const double *tau = d.tau[par];
   const int32_t *site = d.site[par];
   const int32_t *s0 = d.s0[par];
-  const int64_t per_sec = 2ll * k * n + static_cast<int64_t>(k) * k;
-  const int64_t total = 2 * per_sec;
-  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
-    const int sec = static_cast<int>(e / per_sec);
-    int64_t r = e - sec * per_sec;
-    if (r < 2ll * k * n) {
-      const int which = static_cast<int>(r / (static_cast<int64_t>(k) * n));
-      r -= static_cast<int64_t>(which) * k * n;
-      const int j = static_cast<int>(r / n), i = static_cast<int>(r - static_cast<int64_t>(j) * n);
+  // 32-bit index arithmetic: 2 (2 k n + k^2) < 2^31 for k <= 128, n <= 8192
+  const int kn = k * n, per_sec = 2 * kn + k * k, total = 2 * per_sec;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+    const int sec = e >= per_sec ? 1 : 0;
+    int r = e - sec * per_sec;
+    if (r < 2 * kn) {
+      const int which = r >= kn ? 1 : 0;
+      r -= which * kn;
+      const int j = r / n, i = r - j * n;
       if (which == 0) {
         const double ev = d.evd[sec][s0[i] + 2];
         d.X[sec][static_cast<size_t>(j) * d.ld + i] =
@@ -124,8 +124,8 @@ __global__ __launch_bounds__(256) void k_interp(const ChainDesc *descs, const Ch
             g0_interp(d, sec, site[i], d.csite[j], tau[i] - d.ctau[j]);
       }
     } else {
-      r -= 2ll * k * n;
-      const int j = static_cast<int>(r / k), jj = static_cast<int>(r - static_cast<int64_t>(j) * k);
+      r -= 2 * kn;
+      const int j = r / k, jj = r - j * k;
       d.G0nn[sec][static_cast<size_t>(j) * d.kmax + jj] =
           g0_interp(d, sec, d.csite[j], d.csite[jj], d.ctau[j] - d.ctau[jj]);
     }

@@ -19,11 +19,12 @@ __global__ __launch_bounds__(256) void k_meas_gR(const ChainDesc *descs, const C
   const ChainState &st = states[c];
   if (!st.active || !st.meas_now) return;
   const int n = st.n, nc = d.nc, par = st.parity;
-  const int64_t per = static_cast<int64_t>(n) * nc;
-  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < 2 * per; e += gridDim.x * 256ll) {
-    const int sec = static_cast<int>(e / per);
-    const int64_t r = e - sec * per;
-    const int k = static_cast<int>(r / nc), y = static_cast<int>(r - static_cast<int64_t>(k) * nc);
+  // rows y, columns k (consecutive threads write consecutive k); 32-bit indices
+  const int per = n * nc;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < 2 * per; e += gridDim.x * 256) {
+    const int sec = e >= per ? 1 : 0;
+    const int r = e - sec * per;
+    const int y = r / n, k = r - y * n;
     gview_w(d.gR[sec])[static_cast<size_t>(y) * d.n_cap + k] =
         g0_interp(d, sec, gview(d.site[par])[k], y, gview(d.tau[par])[k]);
   }
@@ -39,13 +40,13 @@ __global__ __launch_bounds__(256) void k_meas_gL(const ChainDesc *descs, const C
   const int n = st.n, nc = d.nc, par = st.parity, ld = d.ld;
   const int rows = nc * (d.n_out + 1);
   const double dt = d.beta / d.n_out;
-  const int64_t per = static_cast<int64_t>(rows) * n;
+  const int per = rows * n;   // 32-bit indices: 2 (n_out + 1) nc n < 2^31
   const auto tau = gview(d.tau[par]);
   const auto site = gview(d.site[par]), s0 = gview(d.s0[par]);
-  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < 2 * per; e += gridDim.x * 256ll) {
-    const int sec = static_cast<int>(e / per);
-    const int64_t r = e - sec * per;
-    const int m = static_cast<int>(r / n), l = static_cast<int>(r - static_cast<int64_t>(m) * n);
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < 2 * per; e += gridDim.x * 256) {
+    const int sec = e >= per ? 1 : 0;
+    const int r = e - sec * per;
+    const int m = r / n, l = r - m * n;
     const int j = m / nc, x = m - j * nc;
     const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
     gview_w(d.gL[sec])[static_cast<size_t>(m) * ld + l] =
