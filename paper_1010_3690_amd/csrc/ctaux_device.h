@@ -58,6 +58,22 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gview_w(T *p) {
   return (__attribute__((address_space(1))) T *)(p);
 }
 
+// Chain and sub-block of a per-chain streaming kernel.  With xcd_g = G > 0 the
+// grid is one-dimensional, 8 G ceil(C / 8) workgroups, and workgroup b serves
+// chain (b % 8) + 8 (b / 8G) as sub-block (b / 8) % G: workgroups are handed to
+// the eight XCDs round-robin, so all G workgroups of a chain run on one XCD and
+// the chain's tables and operands stay in that XCD's L2.  With xcd_g = 0 the
+// grid is (G, C).  The chain index may exceed the batch (the caller checks).
+struct ChainBlock {
+  int c, sub, g;
+};
+__device__ __forceinline__ ChainBlock chain_block(int xcd_g) {
+  if (xcd_g == 0) return ChainBlock{static_cast<int>(blockIdx.y), static_cast<int>(blockIdx.x),
+                                    static_cast<int>(gridDim.x)};
+  const int b = blockIdx.x, slot = b >> 3;
+  return ChainBlock{(b & 7) + 8 * (slot / xcd_g), slot % xcd_g, xcd_g};
+}
+
 // Bare propagator G0_{xy}(dtau): linear interpolation on the uniform grid,
 // dtau in (-beta, beta); dtau < 0 uses G0(dtau) = -G0(dtau + beta); dtau = 0
 // reads the 0+ entry.

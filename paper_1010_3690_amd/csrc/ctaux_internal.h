@@ -158,4 +158,12 @@ struct Batch {
   double *r_red;             // [refine_red_doubles(n_chains)]
 };
 
+// Grid of a per-chain streaming kernel and its xcd_g argument (chain_block):
+// XCD-aware one-dimensional for batches of 8 chains or more, (G, C) otherwise.
+inline dim3 chain_grid(const Batch &b) {
+  if (b.n_chains >= 8) return dim3(8u * b.grid_per_chain * ((b.n_chains + 7) / 8));
+  return dim3(b.grid_per_chain, b.n_chains);
+}
+inline int chain_grid_arg(const Batch &b) { return b.n_chains >= 8 ? b.grid_per_chain : 0; }
+
 }  // namespace ctaux

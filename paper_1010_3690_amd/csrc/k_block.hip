@@ -96,8 +96,11 @@ void launch_block_begin(const Batch &b, hipStream_t s) {
 //   X_ji  = G0(tau_j^new - tau_i)(e^{V_i} - 1)   (so that Rt = X N)
 //   ZT_ji = G0(tau_i - tau_j^new)                 (so that YT = (N Z)^T)
 //   G0nn_jj' = G0(tau_j^new - tau_j'^new)          (0+ on the diagonal)
-__global__ __launch_bounds__(256) void k_interp(const ChainDesc *descs, const ChainState *states) {
-  const int c = blockIdx.y;
+__global__ __launch_bounds__(256) void k_interp(const ChainDesc *descs, const ChainState *states, int n_chains,
+                                                int xcd_g) {
+  const ChainBlock cb = chain_block(xcd_g);
+  const int c = cb.c;
+  if (c >= n_chains) return;
   const ChainDesc &d = descs[c];
   const ChainState &st = states[c];
   if (!st.active) return;
@@ -108,7 +111,7 @@ __global__ __launch_bounds__(256) void k_interp(const ChainDesc *descs, const Ch
   const int32_t *s0 = d.s0[par];
   // 32-bit index arithmetic: 2 (2 k n + k^2) < 2^31 for k <= 128, n <= 8192
   const int kn = k * n, per_sec = 2 * kn + k * k, total = 2 * per_sec;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+  for (int e = cb.sub * 256 + threadIdx.x; e < total; e += cb.g * 256) {
     const int sec = e >= per_sec ? 1 : 0;
     int r = e - sec * per_sec;
     if (r < 2 * kn) {
@@ -133,8 +136,8 @@ __global__ __launch_bounds__(256) void k_interp(const ChainDesc *descs, const Ch
 }
 
 void launch_interp(const Batch &b, hipStream_t s) {
-  hipLaunchKernelGGL(k_interp, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s, b.d_desc,
-                     b.d_state);
+  hipLaunchKernelGGL(k_interp, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_state, b.n_chains,
+                     chain_grid_arg(b));
 }
 
 // Ends a block and leaves a copy of the chain's state for the measurement

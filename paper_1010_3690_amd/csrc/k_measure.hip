@@ -13,15 +13,18 @@ namespace ctaux {
 
 void launch_skinny(const Batch &b, hipStream_t s, int kind);
 
-__global__ __launch_bounds__(256) void k_meas_gR(const ChainDesc *descs, const ChainState *states) {
-  const int c = blockIdx.y;
+__global__ __launch_bounds__(256) void k_meas_gR(const ChainDesc *descs, const ChainState *states, int n_chains,
+                                                 int xcd_g) {
+  const ChainBlock cb = chain_block(xcd_g);
+  const int c = cb.c;
+  if (c >= n_chains) return;
   const ChainDesc &d = descs[c];
   const ChainState &st = states[c];
   if (!st.active || !st.meas_now) return;
   const int n = st.n, nc = d.nc, par = st.parity;
   // rows y, columns k (consecutive threads write consecutive k); 32-bit indices
   const int per = n * nc;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < 2 * per; e += gridDim.x * 256) {
+  for (int e = cb.sub * 256 + threadIdx.x; e < 2 * per; e += cb.g * 256) {
     const int sec = e >= per ? 1 : 0;
     const int r = e - sec * per;
     const int y = r / n, k = r - y * n;
@@ -32,8 +35,11 @@ __global__ __launch_bounds__(256) void k_meas_gR(const ChainDesc *descs, const C
 
 // gL_{(j, x), l} = G0_{x x_l}(tau_j - tau_l) (e^{V_l} - 1) for the output times
 // tau_0 = 0+ and tau_j = (j - 1/2) beta / n_out, j >= 1 (row j*nc + x).
-__global__ __launch_bounds__(256) void k_meas_gL(const ChainDesc *descs, const ChainState *states) {
-  const int c = blockIdx.y;
+__global__ __launch_bounds__(256) void k_meas_gL(const ChainDesc *descs, const ChainState *states, int n_chains,
+                                                 int xcd_g) {
+  const ChainBlock cb = chain_block(xcd_g);
+  const int c = cb.c;
+  if (c >= n_chains) return;
   const ChainDesc &d = descs[c];
   const ChainState &st = states[c];
   if (!st.active || !st.meas_now) return;
@@ -43,7 +49,7 @@ __global__ __launch_bounds__(256) void k_meas_gL(const ChainDesc *descs, const C
   const int per = rows * n;   // 32-bit indices: 2 (n_out + 1) nc n < 2^31
   const auto tau = gview(d.tau[par]);
   const auto site = gview(d.site[par]), s0 = gview(d.s0[par]);
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < 2 * per; e += gridDim.x * 256) {
+  for (int e = cb.sub * 256 + threadIdx.x; e < 2 * per; e += cb.g * 256) {
     const int sec = e >= per ? 1 : 0;
     const int r = e - sec * per;
     const int m = r / n, l = r - m * n;
@@ -108,8 +114,8 @@ __global__ __launch_bounds__(256) void k_meas_acc(const ChainDesc *descs, const 
 }
 
 void launch_measure(const Batch &b, hipStream_t s) {
-  hipLaunchKernelGGL(k_meas_gR, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);
-  hipLaunchKernelGGL(k_meas_gL, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);
+  hipLaunchKernelGGL(k_meas_gR, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_mstate, b.n_chains, chain_grid_arg(b));
+  hipLaunchKernelGGL(k_meas_gL, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_mstate, b.n_chains, chain_grid_arg(b));
   launch_skinny(b, s, 2);   // W = N gR
   launch_skinny(b, s, 3);   // Gxy = G0 + gL W, gL_{(x,tau), l} = G0_{x x_l}(tau - tau_l)(e^{V_l} - 1)
   hipLaunchKernelGGL(k_meas_acc, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);

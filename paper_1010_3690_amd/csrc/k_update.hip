@@ -18,8 +18,11 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_assemble(const ChainDesc *descs, const ChainState *states) {
-  const int c = blockIdx.y;
+__global__ __launch_bounds__(256) void k_assemble(const ChainDesc *descs, const ChainState *states, int n_chains,
+                                                  int xcd_g) {
+  const ChainBlock cb = chain_block(xcd_g);
+  const int c = cb.c;
+  if (c >= n_chains) return;
   const ChainDesc &d = descs[c];
   const ChainState &st = states[c];
   if (!st.active) return;
@@ -32,7 +35,7 @@ __global__ __launch_bounds__(256) void k_assemble(const ChainDesc *descs, const 
   const int64_t total = 2 * per_sec;
   const int *map = d.map, *P = d.P;
   const int lda = d.lda;
-  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
+  for (int64_t e = cb.sub * 256ll + threadIdx.x; e < total; e += cb.g * 256ll) {
     const int sec = static_cast<int>(e / per_sec);
     const int64_t r = e - sec * per_sec;
     const T *N = static_cast<const T *>(d.N[par][sec]);
@@ -52,11 +55,11 @@ void launch_skinny(const Batch &b, hipStream_t s, int kind);
 // Ac = (G - I)_{map, P} here; Bc = Gamma^{-1} N_a(P, map) as a skinny MFMA product.
 void launch_assemble(const Batch &b, hipStream_t s) {
   if (b.precision == kFP64)
-    hipLaunchKernelGGL(k_assemble<double>, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s,
-                       b.d_desc, b.d_state);
+    hipLaunchKernelGGL(k_assemble<double>, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_state, b.n_chains,
+                       chain_grid_arg(b));
   else
-    hipLaunchKernelGGL(k_assemble<float>, dim3(b.grid_per_chain, b.n_chains), dim3(256), 0, s,
-                       b.d_desc, b.d_state);
+    hipLaunchKernelGGL(k_assemble<float>, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_state, b.n_chains,
+                       chain_grid_arg(b));
   launch_skinny(b, s, 4);
 }
 
