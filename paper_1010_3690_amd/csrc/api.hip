@@ -553,10 +553,14 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
     return set_err(nullptr, CTAUX_EDEVICE, "descriptor upload failed");
   }
   // measurement stream (default priority, no implicit synchronisation with the
-  // null stream) and the two events that order it against the caller's stream
+  // null stream) and the two events that order it against the caller's stream.
+  // The events only order kernels of this device (the host waits by
+  // synchronising the streams), so they release at device scope, without the
+  // system-scope fence.
+  const unsigned ev_flags = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipStreamCreateWithFlags(&h->mstream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_end, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_meas, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->ev_end, ev_flags) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_meas, ev_flags) != hipSuccess) {
     ctaux_destroy(h);
     return set_err(nullptr, CTAUX_EDEVICE, "measurement stream creation failed");
   }

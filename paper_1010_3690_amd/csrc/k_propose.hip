@@ -37,6 +37,24 @@ namespace ctaux {
 //   old column j:       G_ij = (N_a,ij e^{V_j} - delta_ij) / (e^{V_j} - 1)     (Eq. NfromG)
 //   candidate column j: G_ij = (N Z)_{i, j-n} (old row) or (X Y + G0nn)_{i-n, j-n}.
 
+// Calls f with a compile-time even count of k-steps, the smallest that covers ns
+// (ns <= 16: k_a <= 64).
+template <int V>
+struct StepCount {
+  static constexpr int value = V;
+};
+template <typename F>
+__device__ __forceinline__ void with_even_steps(int ns, F &f) {
+  if (ns <= 2) f(StepCount<2>{});
+  else if (ns <= 4) f(StepCount<4>{});
+  else if (ns <= 6) f(StepCount<6>{});
+  else if (ns <= 8) f(StepCount<8>{});
+  else if (ns <= 10) f(StepCount<10>{});
+  else if (ns <= 12) f(StepCount<12>{});
+  else if (ns <= 14) f(StepCount<14>{});
+  else f(StepCount<16>{});
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainState *states) {
   const int c = blockIdx.x;
@@ -79,6 +97,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   __shared__ int8_t sh_ptype[kMaxKmax], sh_pspin[kMaxKmax];
   __shared__ int sh_bad, sh_nnew;
   __shared__ int sh_fallback[2];
+  __shared__ unsigned sh_mx[4][3];                 // per wave: max|R|, max|Gamma|, max|X0| (high words)
   __shared__ int sh_perm[2][kMaxKcap];
   __shared__ int64_t sh_cid[kMaxKmax];
 
@@ -400,59 +419,29 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   lds_barrier();
 
   if (wave == 1) {
-    // ---- compaction map: interacting vertices in augmented order (one wave, ballot
-    // scan); loads of four chunks are in flight together ----
+    // ---- compaction map: interacting vertices in augmented order (one wave,
+    // ballot scan over the spins in LDS).  The times, sites and ids follow the
+    // map in k_assemble, whose wide grid copies them off this kernel's path;
+    // the ids given to accepted candidates go out in cid ----
     const int na = n + kins;
-    const int np = par ^ 1;
-    const double *tau_o = d.tau[par];
-    const int32_t *site_o = d.site[par];
-    const int64_t *id_o = d.id[par];
-    double *tau_n = d.tau[np];
-    int32_t *site_n = d.site[np], *s0_n = d.s0[np];
-    int64_t *id_n = d.id[np];
+    int32_t *s0_n = d.s0[par ^ 1];
     int *map = d.map;
     int running = 0;
-    for (int base = 0; base < na; base += 256) {
-      double tv[4];
-      int sv[4];
-      int64_t iv[4];
-      bool al[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = base + q * 64 + lane;
-        al[q] = (i < na) && scur[i] != 0;
-        tv[q] = 0.0;
-        sv[q] = 0;
-        iv[q] = 0;
-        if (al[q]) {
-          if (i < n) {
-            tv[q] = tau_o[i];
-            sv[q] = site_o[i];
-            iv[q] = id_o[i];
-          } else {
-            tv[q] = d.ctau[i - n];
-            sv[q] = d.csite[i - n];
-            iv[q] = sh_cid[i - n];
-          }
-        }
+    for (int base = 0; base < na; base += 64) {
+      const int i = base + lane;
+      const int sv = i < na ? static_cast<int>(scur[i]) : 0;
+      const unsigned long long m = __ballot(sv != 0);
+      if (sv != 0) {
+        const int pos = running + __popcll(m & ((1ull << lane) - 1ull));
+        map[pos] = i;
+        s0_n[pos] = sv;
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = base + q * 64 + lane;
-        const unsigned long long m = __ballot(al[q]);
-        if (al[q]) {
-          const int pos = running + __popcll(m & ((1ull << lane) - 1ull));
-          map[pos] = i;
-          tau_n[pos] = tv[q];
-          site_n[pos] = sv[q];
-          id_n[pos] = iv[q];
-          s0_n[pos] = scur[i];
-        }
-        running += __popcll(m);
-      }
+      running += __popcll(m);
     }
+    for (int j = lane; j < kins; j += 64) d.cid[j] = sh_cid[j];
     if (lane == 0) sh_nnew = running;
-  } else if (ka > 0 && (wave & 1) == 0) {
+  }
+  if (ka > 0) {
     // ---- Gamma^{-1} for the rank-k update ----
     // The ratios above came from the unpivoted growth, whose inverse X0 loses
     // accuracy when an intermediate Schur complement of Gamma is small
@@ -466,82 +455,85 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     //  * otherwise X0 is used as it is: a Newton step would add rounding of
     //    order rho |X0| (on strongly coupled models Gamma^{-1} has entries of
     //    1e6 that the update cancels, and that rounding then dominates N's error).
-    // One wave per sector (wave 0: up, wave 2: down); the products run on MFMA
-    // 16x16x4 tiles, the elimination has lane r owning row r.
+    // Two waves per sector (waves 0, 1: up; 2, 3: down; wave 1 has built the
+    // compaction map first).  The products run on MFMA 16x16x4 tiles: wave h of
+    // a sector takes the residual's row tiles and the Newton step's column tiles
+    // h and h + 2, with their global operands loaded up front; the number of
+    // k-steps is a compile-time count of at least k_a / 4 (the steps beyond k_a
+    // add exact zeros).  The elimination runs on the sector's first wave, lane r
+    // owning row r.
     typedef double v4d __attribute__((ext_vector_type(4)));
+    const int h = wave & 1;
     const int nt = (ka + 15) >> 4, lr = lane & 15, lk = lane >> 4;
     const auto Rg = gview_w(d.Rg[sec]);
     const auto gi = gview_w(d.Ginv[sec]);
     bool bad = false;
     double rmax = 0.0, gmax = 0.0, xmax = 0.0;
-    for (int ti = 0; ti < nt; ++ti) {
-      const int row = ti * 16 + lr;
-      double a[16];   // Gamma[row][4s + lk]
+    auto residual = [&](auto nsc) {
+      constexpr int NS = decltype(nsc)::value;
+      double a[2][NS];   // Gamma[16 ti + lr][4 s4 + lk], ti = h, h + 2
 #pragma unroll
-      for (int s4 = 0; s4 < 16; ++s4) {
-        const int k = 4 * s4 + lk;
-        a[s4] = (row < ka && k < ka) ? gam[row * kcap + k] : 0.0;
-        gmax = fmax(gmax, fabs(a[s4]));
-      }
-      for (int tj = 0; tj < nt; ++tj) {
-        const int col = tj * 16 + lr;
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
+      for (int u = 0; u < 2; ++u) {
+        const int row = (h + 2 * u) * 16 + lr;
 #pragma unroll
-        for (int s4 = 0; s4 < 16; ++s4) {
+        for (int s4 = 0; s4 < NS; ++s4) {
           const int k = 4 * s4 + lk;
-          const double b = (k < ka && col < ka) ? Gis[k * lg + col] : 0.0;
-          if (ti == 0) xmax = fmax(xmax, fabs(b));
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], b, acc, 0, 0, 0);
+          a[u][s4] = (row < ka && k < ka) ? gam[row * kcap + k] : 0.0;
+          gmax = fmax(gmax, fabs(a[u][s4]));
         }
+      }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int r = ti * 16 + lk + 4 * q;   // FP64 16x16x4 accumulator: row l/16 + 4q
-          if (r < ka && col < ka) {
-            const double x = (r == col ? 1.0 : 0.0) - acc[q];
-            Rg[r * kcap + col] = x;
-            const double ax = fabs(x);
-            rmax = (ax != ax) ? INFINITY : (ax > rmax ? ax : rmax);
+      for (int u = 0; u < 2; ++u) {
+        const int ti = h + 2 * u;
+        if (ti >= nt) break;
+        for (int tj = 0; tj < nt; ++tj) {
+          const int col = tj * 16 + lr;
+          v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int s4 = 0; s4 < NS; ++s4) {
+            const int k = 4 * s4 + lk;
+            const double b = (k < ka && col < ka) ? Gis[k * lg + col] : 0.0;
+            if (ti == 0) xmax = fmax(xmax, fabs(b));   // tile row 0 reads all of X0
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s4], b, acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = ti * 16 + lk + 4 * q;   // FP64 16x16x4 accumulator: row l/16 + 4q
+            if (r < ka && col < ka) {
+              const double x = (r == col ? 1.0 : 0.0) - acc[q];
+              Rg[r * kcap + col] = x;
+              const double ax = fabs(x);
+              rmax = (ax != ax) ? INFINITY : (ax > rmax ? ax : rmax);
+            }
           }
         }
       }
-    }
-    // max|R| over the wave (high words of non-negative doubles order like the values)
-    const unsigned rhi = wave_max_u32(static_cast<unsigned>(__double_as_longlong(rmax) >> 32));
-    const bool growth_ok = gtol >= 0.0 && rhi <= static_cast<unsigned>(__double_as_longlong(gtol) >> 32);
-    // rounding floor (maxima to within a factor 2 from the high words; NaN/inf in
-    // Gamma or X0 already make rmax infinite)
-    const double gm = __longlong_as_double(static_cast<long long>(
-        wave_max_u32(static_cast<unsigned>(__double_as_longlong(gmax) >> 32))) << 32);
-    const double xm = __longlong_as_double(static_cast<long long>(
-        wave_max_u32(static_cast<unsigned>(__double_as_longlong(xmax) >> 32))) << 32);
-    const double rho = 16.0 * ka * 2.220446049250313e-16 * gm * xm;
-    const bool newton = growth_ok && __longlong_as_double(static_cast<long long>(rhi) << 32) > rho;
-    // R was stored by this wave's lanes and is read back by other lanes
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    if (growth_ok && !newton) {
-      for (int e = lane; e < ka * ka; e += 64) {
-        const int r = e / ka, col = e - r * ka;
-        const double x = Gis[r * lg + col];
-        bad |= !isfinite(x);
-        gi[r * kcap + col] = x;
-      }
-    } else if (newton) {
-      for (int tj = 0; tj < nt; ++tj) {
-        const int col = tj * 16 + lr;
-        double b[16];   // R[4s + lk][col]
+    };
+    auto newton_step = [&](auto nsc) {
+      constexpr int NS = decltype(nsc)::value;
+      double b[2][NS];   // R[4 s4 + lk][16 tj + lr], tj = h, h + 2
 #pragma unroll
-        for (int s4 = 0; s4 < 16; ++s4) {
+      for (int u = 0; u < 2; ++u) {
+        const int col = (h + 2 * u) * 16 + lr;
+#pragma unroll
+        for (int s4 = 0; s4 < NS; ++s4) {
           const int k = 4 * s4 + lk;
-          b[s4] = (k < ka && col < ka) ? Rg[k * kcap + col] : 0.0;
+          b[u][s4] = (k < ka && col < ka) ? Rg[k * kcap + col] : 0.0;
         }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int tj = h + 2 * u;
+        if (tj >= nt) break;
+        const int col = tj * 16 + lr;
         for (int ti = 0; ti < nt; ++ti) {
           const int row = ti * 16 + lr;
           v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int s4 = 0; s4 < 16; ++s4) {
+          for (int s4 = 0; s4 < NS; ++s4) {
             const int k = 4 * s4 + lk;
             const double a = (row < ka && k < ka) ? Gis[row * lg + k] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[s4], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[u][s4], acc, 0, 0, 0);
           }
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
@@ -554,7 +546,41 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           }
         }
       }
-    } else {
+    };
+    const int ns = (ka + 3) >> 2;   // k-steps of four
+    with_even_steps(ns, residual);
+    // maxima of the sector's two waves (high words of non-negative doubles order
+    // like the values); the barrier also publishes R to the other wave
+    {
+      const unsigned mr = wave_max_u32(static_cast<unsigned>(__double_as_longlong(rmax) >> 32));
+      const unsigned mg = wave_max_u32(static_cast<unsigned>(__double_as_longlong(gmax) >> 32));
+      const unsigned mx = wave_max_u32(static_cast<unsigned>(__double_as_longlong(xmax) >> 32));
+      if (lane == 0) {
+        sh_mx[wave][0] = mr;
+        sh_mx[wave][1] = mg;
+        sh_mx[wave][2] = mx;
+      }
+    }
+    __syncthreads();
+    const int w0 = wave & ~1;
+    const unsigned rhi = max(sh_mx[w0][0], sh_mx[w0 + 1][0]);
+    const bool growth_ok = gtol >= 0.0 && rhi <= static_cast<unsigned>(__double_as_longlong(gtol) >> 32);
+    // rounding floor (maxima to within a factor 2 from the high words; NaN/inf in
+    // Gamma or X0 already make rmax infinite)
+    const double gm = __longlong_as_double(static_cast<long long>(max(sh_mx[w0][1], sh_mx[w0 + 1][1])) << 32);
+    const double xm = __longlong_as_double(static_cast<long long>(max(sh_mx[w0][2], sh_mx[w0 + 1][2])) << 32);
+    const double rho = 16.0 * ka * 2.220446049250313e-16 * gm * xm;
+    const bool newton = growth_ok && __longlong_as_double(static_cast<long long>(rhi) << 32) > rho;
+    if (growth_ok && !newton) {
+      for (int e = loc; e < ka * ka; e += 128) {
+        const int r = e / ka, col = e - r * ka;
+        const double x = Gis[r * lg + col];
+        bad |= !isfinite(x);
+        gi[r * kcap + col] = x;
+      }
+    } else if (newton) {
+      with_even_steps(ns, newton_step);
+    } else if (h == 0) {
       if (lane == 0) sh_fallback[sec] = 1;
       double *A = Gis;   // the growth inverse is no longer needed
       // Gamma was written by this workgroup before the full barrier after the

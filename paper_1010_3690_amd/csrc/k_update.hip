@@ -4,7 +4,8 @@
 // equivalently D^{-1}(N - G_{:,P} Gamma^{-1} N_{P,:}) when every vertex changes once),
 // and rows / columns of spin-0 vertices are deleted while storing.
 //
-// k_assemble builds the compacted operands
+// k_assemble builds the compacted operands (and copies the times, sites and
+// ids of the configuration after the block into compacted order)
 //   Ac[i'][a] = (G - I)_{map(i'), P_a}           (n' x k_a)
 //   Bc[a][j'] = sum_b Gamma^{-1}_{ab} N_a(P_b, map(j'))   (k_a x n')
 // and k_rankk computes N'[i'][j'] = N_a(map i', map j') - (Ac Bc)[i'][j'] on
@@ -27,9 +28,32 @@ __global__ __launch_bounds__(256) void k_assemble(const ChainDesc *descs, const 
   const ChainState &st = states[c];
   if (!st.active) return;
   const int n = st.n, np = st.n_new, ka = st.k_a;
+  const int par = st.parity;
+  {
+    // the configuration after the block (times, sites, ids) in compacted order;
+    // the spins and the map itself were written by the proposal kernel
+    const auto map = gview(d.map);
+    const auto tau_o = gview(d.tau[par]), ctau = gview(d.ctau);
+    const auto site_o = gview(d.site[par]), csite = gview(d.csite);
+    const auto id_o = gview(d.id[par]), cid = gview(d.cid);
+    const auto tau_n = gview_w(d.tau[par ^ 1]);
+    const auto site_n = gview_w(d.site[par ^ 1]);
+    const auto id_n = gview_w(d.id[par ^ 1]);
+    for (int pos = cb.sub * 256 + threadIdx.x; pos < np; pos += cb.g * 256) {
+      const int i = map[pos];
+      if (i < n) {
+        tau_n[pos] = tau_o[i];
+        site_n[pos] = site_o[i];
+        id_n[pos] = id_o[i];
+      } else {
+        tau_n[pos] = ctau[i - n];
+        site_n[pos] = csite[i - n];
+        id_n[pos] = cid[i - n];
+      }
+    }
+  }
   if (ka == 0 || np == 0) return;
   const int kpad = (ka + 7) & ~7;
-  const int par = st.parity;
   const int32_t *s0 = d.s0[par];
   const int64_t per_sec = static_cast<int64_t>(np) * kpad;   // Ac entries per sector
   const int64_t total = 2 * per_sec;
