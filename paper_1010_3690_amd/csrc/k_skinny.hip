@@ -380,6 +380,85 @@ __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, c
   }
 }
 
+// The operands of the rank-k update on the chain grid (a chain's workgroups on
+// one XCD when many chains run):
+//   Ac[i'][a] = (G - I)_{map(i'), P_a}, element by element from the chain's
+//   first workgroups up, after the configuration's times, sites and ids are
+//   copied into compacted order;
+//   with NRT > 0 also Bc = Gamma^{-1} N_a(P, map), one wave per 16-column item
+//   from the chain's last workgroups down.
+// Both read only what the proposal kernel left.  One launch for both saves a
+// kernel on the critical path of a few long chains; with many chains the MFMA
+// registers of Bc would cut the occupancy the Ac gathers need, so Bc then runs
+// as a persistent skinny product of its own (NRT = 0 here).
+template <typename T, int NRT>
+__global__ __launch_bounds__(256) void k_operands(const ChainDesc *descs, const ChainState *states, int n_chains,
+                                                  int xcd_g) {
+  __shared__ double red[4 * 32];   // P, 64 entries per wave, for the Bc items
+  const ChainBlock cb = chain_block(xcd_g);
+  const int c = cb.c;
+  if (c >= n_chains) return;
+  const ChainDesc &d = descs[c];
+  const ChainState &st = states[c];
+  if (!st.active) return;
+  if constexpr (NRT > 0) {
+    const int items = skinny_items(d, st, kSkAsmB);
+    for (int item = (cb.g - 1 - cb.sub) * 4 + (threadIdx.x >> 6); item < items; item += cb.g * 4)
+      skinny_dispatch<T, kModeWave, NRT, kSkAsmB>(d, st, item, red);
+  }
+  const int n = st.n, np = st.n_new, ka = st.k_a;
+  const int par = st.parity;
+  {
+    // the configuration after the block (times, sites, ids) in compacted order;
+    // the spins and the map itself were written by the proposal kernel
+    const auto map = gview(d.map);
+    const auto tau_o = gview(d.tau[par]), ctau = gview(d.ctau);
+    const auto site_o = gview(d.site[par]), csite = gview(d.csite);
+    const auto id_o = gview(d.id[par]), cid = gview(d.cid);
+    const auto tau_n = gview_w(d.tau[par ^ 1]);
+    const auto site_n = gview_w(d.site[par ^ 1]);
+    const auto id_n = gview_w(d.id[par ^ 1]);
+    for (int pos = cb.sub * 256 + threadIdx.x; pos < np; pos += cb.g * 256) {
+      const int i = map[pos];
+      if (i < n) {
+        tau_n[pos] = tau_o[i];
+        site_n[pos] = site_o[i];
+        id_n[pos] = id_o[i];
+      } else {
+        tau_n[pos] = ctau[i - n];
+        site_n[pos] = csite[i - n];
+        id_n[pos] = cid[i - n];
+      }
+    }
+  }
+  if (ka == 0 || np == 0) return;
+  const int kpad = (ka + 7) & ~7;
+  const int32_t *s0 = d.s0[par];
+  const int64_t per_sec = static_cast<int64_t>(np) * kpad;   // Ac entries per sector
+  const int64_t total = 2 * per_sec;
+  const int *map = d.map, *P = d.P;
+  const int lda = d.lda;
+  for (int64_t e = cb.sub * 256ll + threadIdx.x; e < total; e += cb.g * 256ll) {
+    const int sec = static_cast<int>(e / per_sec);
+    const int64_t r = e - sec * per_sec;
+    const T *N = static_cast<const T *>(d.N[par][sec]);
+    // consecutive threads walk the k index of one row, then rows
+    const int i = static_cast<int>(r / kpad), a = static_cast<int>(r - static_cast<int64_t>(i) * kpad);
+    double v = 0.0;
+    if (a < ka) {
+      const int mi = gview(map)[i], pa = gview(P)[a];
+      v = g_entry<T>(d, N, s0, n, sec, mi, pa) - (mi == pa ? 1.0 : 0.0);
+    }
+    gview_w(static_cast<T *>(d.Ac[sec]))[static_cast<size_t>(i) * lda + a] = static_cast<T>(v);
+  }
+}
+
+template <typename T, int NRT>
+static void launch_ops(const Batch &b, hipStream_t s) {
+  hipLaunchKernelGGL((k_operands<T, NRT>), chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_state, b.n_chains,
+                     chain_grid_arg(b));
+}
+
 template <typename T, int MODE, int NRT, int KIND>
 static void launch_kk(const Batch &b, hipStream_t s) {
   const size_t lds = sizeof(int) * (b.n_chains + 1);
@@ -445,6 +524,26 @@ void launch_skinny(const Batch &b, hipStream_t s, int kind) {
   } else {
     if (wave) launch_m<double, kModeWave>(b, s, kind, nrt);
     else launch_m<double, kModeSplitK>(b, s, kind, nrt);
+  }
+}
+
+void launch_operands(const Batch &b, hipStream_t s) {
+  if (b.n_chains >= 8) {   // Ac here, Bc as a persistent skinny product
+    if (b.precision == kFP32) launch_ops<float, 0>(b, s);
+    else launch_ops<double, 0>(b, s);
+    launch_skinny(b, s, kSkAsmB);
+    return;
+  }
+  // row tiles of Bc cover k_cap (<= 64) rounded up to 8
+  const int nrt = host_row_tiles((b.kcap + 7) & ~7);
+  if (b.precision == kFP32) {
+    if (nrt == 1) launch_ops<float, 1>(b, s);
+    else if (nrt == 2) launch_ops<float, 2>(b, s);
+    else launch_ops<float, 4>(b, s);
+  } else {
+    if (nrt == 1) launch_ops<double, 1>(b, s);
+    else if (nrt == 2) launch_ops<double, 2>(b, s);
+    else launch_ops<double, 4>(b, s);
   }
 }
 

@@ -4,8 +4,9 @@
 // equivalently D^{-1}(N - G_{:,P} Gamma^{-1} N_{P,:}) when every vertex changes once),
 // and rows / columns of spin-0 vertices are deleted while storing.
 //
-// k_assemble builds the compacted operands (and copies the times, sites and
-// ids of the configuration after the block into compacted order)
+// k_operands (with the skinny products) builds the compacted operands (and
+// copies the times, sites and ids of the configuration after the block into
+// compacted order)
 //   Ac[i'][a] = (G - I)_{map(i'), P_a}           (n' x k_a)
 //   Bc[a][j'] = sum_b Gamma^{-1}_{ab} N_a(P_b, map(j'))   (k_a x n')
 // and k_rankk computes N'[i'][j'] = N_a(map i', map j') - (Ac Bc)[i'][j'] on
@@ -18,74 +19,10 @@ namespace ctaux {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_assemble(const ChainDesc *descs, const ChainState *states, int n_chains,
-                                                  int xcd_g) {
-  const ChainBlock cb = chain_block(xcd_g);
-  const int c = cb.c;
-  if (c >= n_chains) return;
-  const ChainDesc &d = descs[c];
-  const ChainState &st = states[c];
-  if (!st.active) return;
-  const int n = st.n, np = st.n_new, ka = st.k_a;
-  const int par = st.parity;
-  {
-    // the configuration after the block (times, sites, ids) in compacted order;
-    // the spins and the map itself were written by the proposal kernel
-    const auto map = gview(d.map);
-    const auto tau_o = gview(d.tau[par]), ctau = gview(d.ctau);
-    const auto site_o = gview(d.site[par]), csite = gview(d.csite);
-    const auto id_o = gview(d.id[par]), cid = gview(d.cid);
-    const auto tau_n = gview_w(d.tau[par ^ 1]);
-    const auto site_n = gview_w(d.site[par ^ 1]);
-    const auto id_n = gview_w(d.id[par ^ 1]);
-    for (int pos = cb.sub * 256 + threadIdx.x; pos < np; pos += cb.g * 256) {
-      const int i = map[pos];
-      if (i < n) {
-        tau_n[pos] = tau_o[i];
-        site_n[pos] = site_o[i];
-        id_n[pos] = id_o[i];
-      } else {
-        tau_n[pos] = ctau[i - n];
-        site_n[pos] = csite[i - n];
-        id_n[pos] = cid[i - n];
-      }
-    }
-  }
-  if (ka == 0 || np == 0) return;
-  const int kpad = (ka + 7) & ~7;
-  const int32_t *s0 = d.s0[par];
-  const int64_t per_sec = static_cast<int64_t>(np) * kpad;   // Ac entries per sector
-  const int64_t total = 2 * per_sec;
-  const int *map = d.map, *P = d.P;
-  const int lda = d.lda;
-  for (int64_t e = cb.sub * 256ll + threadIdx.x; e < total; e += cb.g * 256ll) {
-    const int sec = static_cast<int>(e / per_sec);
-    const int64_t r = e - sec * per_sec;
-    const T *N = static_cast<const T *>(d.N[par][sec]);
-    // consecutive threads walk the k index of one row, then rows
-    const int i = static_cast<int>(r / kpad), a = static_cast<int>(r - static_cast<int64_t>(i) * kpad);
-    double v = 0.0;
-    if (a < ka) {
-      const int mi = gview(map)[i], pa = gview(P)[a];
-      v = g_entry<T>(d, N, s0, n, sec, mi, pa) - (mi == pa ? 1.0 : 0.0);
-    }
-    gview_w(static_cast<T *>(d.Ac[sec]))[static_cast<size_t>(i) * lda + a] = static_cast<T>(v);
-  }
-}
+void launch_operands(const Batch &b, hipStream_t s);
 
-void launch_skinny(const Batch &b, hipStream_t s, int kind);
-
-// Ac = (G - I)_{map, P} here; Bc = Gamma^{-1} N_a(P, map) as a skinny MFMA product.
-void launch_assemble(const Batch &b, hipStream_t s) {
-  if (b.precision == kFP64)
-    hipLaunchKernelGGL(k_assemble<double>, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_state, b.n_chains,
-                       chain_grid_arg(b));
-  else
-    hipLaunchKernelGGL(k_assemble<float>, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_state, b.n_chains,
-                       chain_grid_arg(b));
-  launch_skinny(b, s, 4);
-}
+// Ac and Bc of every chain in one launch (k_operands).
+void launch_assemble(const Batch &b, hipStream_t s) { launch_operands(b, s); }
 
 template <typename T>
 struct Mfma;

@@ -153,6 +153,29 @@ def test_batched_chains_match_their_oracles():
         _compare_obs(gb.obs(c), oc.obs())
 
 
+def test_many_chains_match_their_oracles():
+    """Nine chains: the many-chain launch shapes (chain grids with all
+    workgroups of a chain on one XCD, Bc as a persistent product of its own,
+    one wave per skinny item) against the oracle, chain by chain."""
+    ctaux = _ctaux()
+    ws = [_plaquette(beta=3.0 + 0.5 * c, U=3.0 + c, K=5.0 + 3 * c) for c in range(4)]
+    ws += [_cluster16(K=10.0 * (c + 1)) for c in range(3)]   # orders ~90: two 64-wide tiles, ragged
+    ws += [hubbard_dimer(beta=2.0, U=2.0, n_tau=2001), anderson_semicircle(n_tau=4096)]
+    n_prop = 4000
+    opts = ctaux.Options(k_max=32, k_cap=24, n_cap=1024, log_cap=n_prop, meas_every=32, n_tau_out=8,
+                         recompute_every=16, seed=5)
+    print(f"[parity] {len(ws)} chains, n_prop={n_prop}", flush=True)
+    gb = ctaux.CtauxBatch(ws, opts)
+    gb.run(n_prop)
+    for c, w in enumerate(ws):
+        oc = OracleChain(w, seed=opts.seed, chain_id=c, p_flip=opts.p_flip, meas_every=opts.meas_every,
+                         n_tau_out=opts.n_tau_out, n_cap=opts.n_cap)
+        oc.set_log(n_prop)
+        oc.run(n_prop)
+        _compare(gb, oc, n_prop, chain=c)
+        _compare_obs(gb.obs(c), oc.obs())
+
+
 def test_refinement_keeps_fp64_N():
     ctaux = _ctaux()
     w = _cluster16()
