@@ -421,7 +421,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   if (wave == 1) {
     // ---- compaction map: interacting vertices in augmented order (one wave,
     // ballot scan over the spins in LDS).  The times, sites and ids follow the
-    // map in k_assemble, whose wide grid copies them off this kernel's path;
+    // map in k_operands, whose wide grid copies them off this kernel's path;
     // the ids given to accepted candidates go out in cid ----
     const int na = n + kins;
     int32_t *s0_n = d.s0[par ^ 1];
