@@ -81,11 +81,14 @@ typedef struct {
     int32_t k_cap;            /* accepted changes per block (size of Gamma), 1..64; a block
                                  ends early once Gamma is full (does not change the chain)     */
     double p_flip;            /* P(flip); P(insert) = P(remove) = (1 - p_flip)/2              */
-    int32_t recompute_every;  /* most blocks between FP64 refinements of N (0 = never).  The
-                                 interval starts at min(8, recompute_every); after each
-                                 refinement it is quartered (down to 1) when a chain's drift
-                                 exceeded 1e-3 and doubled (up to recompute_every) when
-                                 every drift stayed below 1e-4                               */
+    int32_t recompute_every;  /* most blocks between FP64 refinements of N (0 = never).  Each
+                                 chain has its own interval, a power of two between 1 and the
+                                 largest power of two <= recompute_every, starting at
+                                 min(8, that bound) and counted in blocks of the batch (chain c
+                                 is refined after block b when b is a multiple of its
+                                 interval).  After each refinement of a chain its interval is
+                                 quartered when the drift exceeded drift_target and doubled
+                                 when the drift stayed below drift_target / 16              */
     int32_t precision;        /* CTAUX_FP64 or CTAUX_FP32                                     */
     int32_t meas_every;       /* measure after every meas_every proposals ...                 */
     int64_t n_therm;          /* ... once more than n_therm proposals are done                */
@@ -105,6 +108,13 @@ typedef struct {
                                  its definition); <= 0 disables the check                     */
     int32_t rankk_tile;       /* output tile edge of the rank-k update: 64, 32, or 0 for 64;
                                  smaller tiles waste less of the ragged edge at small orders  */
+    double drift_target;      /* N error a chain should carry at most between refinements (the
+                                 refinement drift, see ctaux_recompute); 0 selects 1e-10 for
+                                 FP64 storage and 1e-4 for FP32 storage                       */
+    int32_t recompute_mode;   /* periodic refinements: 0 = a Newton step from the current N,
+                                 recomputed from scratch when the step cannot recover it (see
+                                 ctaux_recompute); 1 = always from scratch
+                                 (ctaux_recompute_from_scratch)                               */
 } ctaux_opts;
 
 /* Per-chain counters. */
@@ -132,6 +142,8 @@ typedef struct {
                                  2 n^2 nc (W) + 2 nc^2 (n_out+1) n (G)                         */
     double meas_bytes;        /* their algorithmic bytes: N read once, gL written and read,
                                  two table reads per gL entry, gR                              */
+    int64_t scratch_recomputes; /* refinements that recomputed N from scratch                  */
+    int32_t refine_interval;  /* the chain's current refinement interval in blocks (0: none)    */
 } ctaux_stats;
 
 /* One vertex of a configuration (tau in [0, beta), site in [0, n_sites), s = +-1). */
@@ -157,13 +169,26 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
  * a chain early on CTAUX_ECAPACITY / CTAUX_ENUMERIC and returns that code. */
 int ctaux_run(ctaux_batch *b, int64_t n_proposals);
 
-/* Refine N of every chain against its definition in FP64 (one Newton step
- * N <- N + N (I - M N) with M = e^V - G0(e^V - 1) built from the tables; up to
- * two more steps for a chain whose drift exceeded 1e-9 with FP64 storage, 1e-4
- * with FP32) and return the largest relative drift of the first step,
- * ||N_before - N_after||_F / ||N_after||_F, over the chains.
- * Also runs automatically, at most every opts.recompute_every blocks. */
+/* Refine N of every chain against its definition in FP64 and return the
+ * largest relative drift of the first step, ||N_before - N_after||_F / ||N_after||_F,
+ * over the chains (the N error the chain carried, to first order).
+ * A step is one Newton iteration N <- N + N (I - M N) with M = e^V - G0(e^V - 1)
+ * built from the tables (Eq. Nmatrix); a chain whose drift exceeded 1e-9 with
+ * FP64 storage (1e-4 with FP32) gets another step, up to three in all.  N is
+ * recomputed from scratch instead (as by ctaux_recompute_from_scratch) when a
+ * step measures a drift above 1e-2 or a non-finite N, when a further step does
+ * not reduce the drift fourfold, or after the third step.  A drift above
+ * opts.drift_tol (> 0) stops the chain with CTAUX_ENUMERIC.
+ * Also runs automatically on the schedule of opts.recompute_every. */
 int ctaux_recompute(ctaux_batch *b, double *max_drift_out);
+
+/* Recompute N of every chain from scratch: M = e^V - G0(e^V - 1) from the
+ * tables, inverted in FP64 by a blocked Gauss-Jordan elimination (32 columns
+ * per step, pivot rows chosen by tournament pivoting, the trailing updates on
+ * FP64 MFMA; 2 n^3 flops per sector).  Returns the largest relative difference
+ * ||N_before - N_after||_F / ||N_after||_F over the chains.  A singular or
+ * non-finite M stops the chain with CTAUX_ENUMERIC. */
+int ctaux_recompute_from_scratch(ctaux_batch *b, double *max_drift_out);
 
 /* Observable accumulators of a chain (doubles, len >= ctaux_obs_len()):
  *   [0] measurements   [1] sum sign       [2] sum sign*order   [3] sum sign*order^2
@@ -217,6 +242,25 @@ int32_t ctaux_get_timing(ctaux_batch *b, const char **names, double *ms, int64_t
  *     rounding only.  The decision log of the target is not restored. */
 int ctaux_checkpoint(ctaux_batch *b, int32_t chain, void *buf, size_t *len);
 int ctaux_restore(ctaux_batch *b, int32_t chain, const void *buf, size_t len);
+
+/* N of one spin sector (0 up, 1 down) of a configuration, from its definition
+ * N = [e^V - G0 (e^V - 1)]^{-1} (Eq. Nmatrix) with G0 interpolated from the
+ * model's tables as the chains do, inverted in FP64 by the elimination of
+ * ctaux_recompute_from_scratch.  Stateless; independent of any batch.
+ *   model:   host, as for ctaux_create (one chain).
+ *   config:  host, n vertices (0 <= tau < beta, 0 <= site < n_sites, s = +-1;
+ *            id is ignored); row and column i of N belong to config[i].
+ *   dev_out: device, n rows of ld_out >= n doubles (row-major), written.
+ *   dev_workspace: device, >= ctaux_build_N_workspace_bytes(model, n) bytes,
+ *            256-byte aligned, used during the call only.
+ *   hip_stream: the stream every copy and kernel runs on (NULL: default).
+ * Returns after the stream has drained.  0 <= n <= 32768 (n = 0 does nothing).
+ * Errors (ctaux_last_error(NULL) describes them): CTAUX_EINVAL (arguments),
+ * CTAUX_ENOMEM (workspace too small), CTAUX_ENUMERIC (M singular or not
+ * finite; dev_out then holds NaN), CTAUX_EDEVICE. */
+size_t ctaux_build_N_workspace_bytes(const ctaux_model *model, int32_t n);
+int ctaux_build_N(const ctaux_model *model, const ctaux_vertex *config, int32_t n, int32_t sector, double *dev_out,
+                  int32_t ld_out, void *dev_workspace, size_t ws_bytes, void *hip_stream);
 
 const char *ctaux_last_error(const ctaux_batch *b);
 void ctaux_destroy(ctaux_batch *b);

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libctaux_hip.so")
 SOURCES = ["api.hip", "k_block.hip", "k_prep.hip", "k_propose.hip", "k_skinny.hip", "k_update.hip", "k_measure.hip",
-           "k_refine.hip"]
+           "k_refine.hip", "k_invert.hip", "build_n.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed FP32 instructions are kept out of every kernel (plain FP32 code only).

@@ -62,10 +62,18 @@ struct ctaux_batch {
   std::vector<int32_t> obs_len;
   int64_t blocks_launched = 0;
   int32_t recompute_every = 0;
-  // adaptive refinement schedule: refine_interval starts at min(8, recompute_every)
-  // and moves within [1, recompute_every] with the drift the refinements measure
-  int32_t refine_interval = 0;
-  int64_t since_refine = 0;
+  int32_t recompute_mode = 0;       // 0: Newton step (from scratch when it cannot recover), 1: from scratch
+  // Adaptive refinement schedule, per chain: chain c is refined after every
+  // block whose count is a multiple of interval[c], a power of two in
+  // [1, max_interval] (max_interval = the largest power of two <= recompute_every),
+  // starting at min(8, max_interval).  Powers of two keep the refinements of
+  // all chains aligned, so that a refinement (which synchronises the host with
+  // the device) happens at most every min_c interval[c] blocks.  After each
+  // refinement interval[c] is quartered when the drift of chain c exceeded the
+  // drift target and doubled when it stayed below 1/16 of it.
+  int32_t max_interval = 0;
+  std::vector<int32_t> interval;
+  double drift_target = 0.0;
   int64_t log_cap = 0;
   int32_t obs_len_max = 0;
   int32_t timing = 0;                 // bit i: time kernel i (kKernelNames)
@@ -97,6 +105,37 @@ int set_err(ctaux_batch *b, int code, const char *fmt, ...) {
     if (e_ != hipSuccess) return set_err((b), CTAUX_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+}  // namespace
+
+namespace ctaux {
+
+int create_error(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_create_error, sizeof g_create_error, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+// Model of chain c (Sec. II A): parameters, sizes and finite tables.
+int model_error(const ctaux_model &m, int c, ctaux_batch *eb) {
+  if (!(m.beta > 0) || !(m.U >= 0) || !(m.K > 0) || !isfinite(m.beta) || !isfinite(m.U) || !isfinite(m.K))
+    return set_err(eb, CTAUX_EINVAL, "chain %d: need beta > 0, U >= 0, K > 0", c);
+  if (m.n_sites < 1 || m.n_sites > 128 || m.n_tau < 2 || m.n_disp < 1 || !m.site_disp || !m.g0_up || !m.g0_dn)
+    return set_err(eb, CTAUX_EINVAL, "chain %d: invalid sizes or null tables (n_sites <= 128)", c);
+  for (int i = 0; i < m.n_sites * m.n_sites; ++i)
+    if (m.site_disp[i] < 0 || m.site_disp[i] >= m.n_disp)
+      return set_err(eb, CTAUX_EINVAL, "chain %d: site_disp out of range", c);
+  for (int64_t i = 0; i < static_cast<int64_t>(m.n_disp) * m.n_tau; ++i)
+    if (!isfinite(m.g0_up[i]) || !isfinite(m.g0_dn[i]))
+      return set_err(eb, CTAUX_EINVAL, "chain %d: non-finite G0 table entry %lld", c, (long long)i);
+  return CTAUX_OK;
+}
+
+}  // namespace ctaux
+
+namespace {
+
 int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, ctaux_batch *eb) {
   if (!models || !o || n_chains < 1 || n_chains > 8192)
     return set_err(eb, CTAUX_EINVAL, "null models/opts or n_chains not in 1..8192");
@@ -113,21 +152,23 @@ int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, c
   if (o->meas_every < 1 || o->n_tau_out < 1 || o->n_tau_out > 4096 || o->n_cap < 1 || o->n_cap > 65536 ||
       o->recompute_every < 0 || o->n_therm < 0 || o->log_cap < 0)
     return set_err(eb, CTAUX_EINVAL, "invalid meas_every/n_tau_out/n_cap/recompute_every/n_therm/log_cap");
+  if (!isfinite(o->drift_target) || o->drift_target < 0.0 || o->recompute_mode < 0 || o->recompute_mode > 1)
+    return set_err(eb, CTAUX_EINVAL, "drift_target must be finite and >= 0, recompute_mode 0 or 1");
+  // the proposal kernel holds Gamma^{-1} of both sectors and the spins of the
+  // augmented configuration in the LDS of one workgroup
+  {
+    const size_t lds = propose_lds_bytes(o->k_cap, o->k_max, o->n_cap) + kProposeStaticLds;
+    if (lds > kLdsPerWorkgroup)
+      return set_err(eb, CTAUX_EINVAL, "n_cap=%d with k_cap=%d needs %zu bytes of LDS in the proposal kernel "
+                     "(limit %zu)", o->n_cap, o->k_cap, lds, kLdsPerWorkgroup);
+  }
   for (int c = 0; c < n_chains; ++c) {
     const ctaux_model &m = models[c];
-    if (!(m.beta > 0) || !(m.U >= 0) || !(m.K > 0) || !isfinite(m.beta) || !isfinite(m.U) || !isfinite(m.K))
-      return set_err(eb, CTAUX_EINVAL, "chain %d: need beta > 0, U >= 0, K > 0", c);
-    if (m.n_sites < 1 || m.n_sites > 128 || m.n_tau < 2 || m.n_disp < 1 || !m.site_disp || !m.g0_up || !m.g0_dn)
-      return set_err(eb, CTAUX_EINVAL, "chain %d: invalid sizes or null tables (n_sites <= 128)", c);
+    int rc = model_error(m, c, eb);
+    if (rc) return rc;
     // the table kernels index a chain's elements with 32-bit integers
     if (2ll * (o->n_tau_out + 1) * m.n_sites * o->n_cap >= (1ll << 31))
       return set_err(eb, CTAUX_EINVAL, "chain %d: 2 (n_tau_out + 1) n_sites n_cap must stay below 2^31", c);
-    for (int i = 0; i < m.n_sites * m.n_sites; ++i)
-      if (m.site_disp[i] < 0 || m.site_disp[i] >= m.n_disp)
-        return set_err(eb, CTAUX_EINVAL, "chain %d: site_disp out of range", c);
-    for (int64_t i = 0; i < static_cast<int64_t>(m.n_disp) * m.n_tau; ++i)
-      if (!isfinite(m.g0_up[i]) || !isfinite(m.g0_dn[i]))
-        return set_err(eb, CTAUX_EINVAL, "chain %d: non-finite G0 table entry %lld", c, (long long)i);
   }
   return CTAUX_OK;
 }
@@ -145,16 +186,18 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
   ChainState *d_mstate = cv.take<ChainState>(n_chains);
   // refinement pool: room for one chain at n_cap, and for all chains at n_cap
   // up to 4 GiB; chains are refined in groups that fit
-  const size_t need_cap = 2ull * refine_slots(o->precision) * static_cast<size_t>(n_cap) * n_cap;
+  const size_t need_cap = refine_need_doubles(n_cap, o->precision);
   size_t pool = static_cast<size_t>(n_chains) * need_cap;
   const size_t pool_limit = (size_t{4} << 30) / sizeof(double);
   if (pool > pool_limit) pool = pool_limit > need_cap ? pool_limit : need_cap;
   double *r_pool = cv.take<double>(pool);
   RefineItem *r_items = cv.take<RefineItem>(n_chains);
   double *r_red = cv.take<double>(refine_red_doubles(n_chains));
+  InvItem *r_inv = cv.take<InvItem>(2 * static_cast<size_t>(n_chains));
   if (bt) {
     bt->d_desc = d_desc; bt->d_state = d_state; bt->d_mstate = d_mstate;
     bt->r_pool = r_pool; bt->r_pool_doubles = pool; bt->r_items = r_items; bt->r_red = r_red;
+    bt->r_inv = r_inv;
   }
   for (int c = 0; c < n_chains; ++c) {
     const ctaux_model &m = models[c];
@@ -322,64 +365,131 @@ int n_to_device(ctaux_batch *h, void *dst, const void *src, int n, size_t es) {
   return CTAUX_OK;
 }
 
-// Refines every healthy chain: reads the orders (one synchronisation), packs
-// the chains into groups whose scratch fits the pool, and launches each group.
-// One Newton step squares the error of N; a chain whose drift exceeded the
-// storage's threshold gets further steps (up to kRefinePasses in all), each
-// preceded by one more synchronisation, so that a strongly coupled chain whose
-// block updates lost several digits starts the next interval at the accuracy
-// of its storage (FP32 storage holds N only to ~1e-7 relative: its threshold
-// is set far above that floor).
+// Refinement of a set of chains.  A Newton step N <- N + N (I - M N) (k_refine.hip)
+// squares the relative error of N; a chain whose drift after a step exceeds the
+// storage's threshold `again` gets another step (up to kRefinePasses in all),
+// each preceded by one synchronisation.  N is recomputed from scratch (M built
+// from the tables and inverted by the pivoted elimination of k_invert.hip) when
+// a step leaves a drift above kScratchDrift or a non-finite N (outside the
+// region where the Newton iteration contracts), when a further step does not
+// reduce the drift at least fourfold, or when the passes run out.  With
+// scratch_only every chain is recomputed from scratch.  The first measured
+// drift of each chain is its N error before the refinement; with adapt it sets
+// the chain's next interval.
 constexpr int kRefinePasses = 3;
+constexpr double kScratchDrift = 1e-2;
 
-int refine_all(ctaux_batch *h, bool adapt) {
+// Packs the chains into groups whose scratch fits the pool, uploads the items
+// (and, for a from-scratch recompute, the elimination items carved from the
+// same scratch) and launches every group.
+int launch_refinement(ctaux_batch *h, const std::vector<int> &chains, bool scratch, int pass) {
   const Batch &b = h->b;
   const size_t slots = static_cast<size_t>(refine_slots(b.precision));
-  const double again = b.precision == kFP64 ? 1e-9 : 1e-4;
-  for (int pass = 0; pass < kRefinePasses; ++pass) {
-    int rc = sync_states(h);
-    if (rc) return rc;
-    if (pass == 1 && adapt) {
-      // the first step's drift over the chains sets the next interval: a
-      // quarter of it when a chain drifted far (well before drift_tol stops it),
-      // twice it (up to recompute_every) when every chain stayed a factor 10
-      // below that
-      double m = 0.0;
-      for (const ChainState &st : h->state)
-        if (st.status == 0 && st.last_drift > m) m = st.last_drift;
-      const double hi = 1e-3;
-      if (m > hi) h->refine_interval = h->refine_interval > 4 ? h->refine_interval / 4 : 1;
-      else if (m < 0.1 * hi)
-        h->refine_interval = 2 * h->refine_interval < h->recompute_every ? 2 * h->refine_interval : h->recompute_every;
+  std::vector<RefineItem> items;
+  std::vector<InvItem> inv;
+  std::vector<int> starts;
+  size_t used = 0;
+  for (int c : chains) {
+    const ChainState &st = h->state[c];
+    if (scratch && st.n == 0) continue;
+    const size_t need = refine_need_doubles(st.n, b.precision);
+    if (starts.empty() || used + need > b.r_pool_doubles) {
+      starts.push_back(static_cast<int>(items.size()));
+      used = 0;
     }
-    std::vector<RefineItem> items;
-    std::vector<int> starts;
-    size_t used = 0;
-    for (int c = 0; c < b.n_chains; ++c) {
-      const ChainState &st = h->state[c];
-      if (st.status != 0) continue;
-      if (pass > 0 && !(st.pass_drift > again)) continue;
-      const size_t need = 2 * slots * static_cast<size_t>(st.n) * st.n;
-      if (starts.empty() || used + need > b.r_pool_doubles) {
-        starts.push_back(static_cast<int>(items.size()));
-        used = 0;
+    items.push_back(RefineItem{c, st.n, static_cast<int64_t>(used)});
+    if (scratch) {
+      const size_t nn = static_cast<size_t>(st.n) * st.n;
+      for (int sec = 0; sec < 2; ++sec) {
+        InvItem it;
+        memset(&it, 0, sizeof it);
+        double *W = b.r_pool + used + sec * slots * nn;   // the M slot of the sector
+        double *scr = b.r_pool + used + 2 * slots * nn + sec * inv_scratch_doubles(st.n);
+        inv_item_carve(it, W, st.n, st.n, scr);
+        inv.push_back(it);
       }
-      items.push_back(RefineItem{c, st.n, static_cast<int64_t>(used)});
-      used += need;
     }
-    if (items.empty()) return CTAUX_OK;
-    // host-to-device copies go on the batch's stream and are waited for: a
-    // synchronous hipMemcpy from pageable memory may return before its DMA has
-    // landed, and is not ordered with a stream other than the null stream
-    HIPCHECK(h, hipMemcpyAsync(b.r_items, items.data(), sizeof(RefineItem) * items.size(), hipMemcpyHostToDevice,
-                               h->stream));
-    HIPCHECK(h, hipStreamSynchronize(h->stream));
-    starts.push_back(static_cast<int>(items.size()));
-    Timer t(h, 8);
-    for (size_t g = 0; g + 1 < starts.size(); ++g)
-      launch_refine_group(b, h->stream, b.r_items + starts[g], starts[g + 1] - starts[g], pass);
+    used += need;
+  }
+  if (items.empty()) return CTAUX_OK;
+  // host-to-device copies go on the batch's stream and are waited for: a
+  // synchronous hipMemcpy from pageable memory may return before its DMA has
+  // landed, and is not ordered with a stream other than the null stream
+  HIPCHECK(h, hipMemcpyAsync(b.r_items, items.data(), sizeof(RefineItem) * items.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  if (scratch)
+    HIPCHECK(h, hipMemcpyAsync(b.r_inv, inv.data(), sizeof(InvItem) * inv.size(), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  starts.push_back(static_cast<int>(items.size()));
+  Timer t(h, 8);
+  for (size_t g = 0; g + 1 < starts.size(); ++g) {
+    const int i0 = starts[g], cnt = starts[g + 1] - starts[g];
+    if (scratch) {
+      int n_max = 0;
+      for (int i = i0; i < i0 + cnt; ++i) n_max = items[i].n > n_max ? items[i].n : n_max;
+      launch_scratch_group(b, h->stream, b.r_items + i0, b.r_inv + 2 * i0, cnt, n_max, pass);
+    } else {
+      launch_refine_group(b, h->stream, b.r_items + i0, cnt, pass);
+    }
   }
   return CTAUX_OK;
+}
+
+int refine_chains(ctaux_batch *h, const std::vector<int> &which, bool adapt, bool scratch_only) {
+  const Batch &b = h->b;
+  const double again = b.precision == kFP64 ? 1e-9 : 1e-4;
+  int rc = sync_states(h);
+  if (rc) return rc;
+  std::vector<int> newton, scratch;
+  for (int c : which)
+    if (h->state[c].status == 0) (scratch_only ? scratch : newton).push_back(c);
+  std::vector<double> prev(b.n_chains, INFINITY);
+  int pass = 0;
+  auto adapt_intervals = [&](const std::vector<int> &cs) {
+    for (int c : cs) {
+      const ChainState &st = h->state[c];
+      if (st.status != 0) continue;
+      const double d = st.last_drift;
+      int32_t &iv = h->interval[c];
+      if (!(d <= h->drift_target)) iv = iv > 4 ? iv / 4 : 1;
+      else if (d < h->drift_target / 16.0) iv = 2 * iv < h->max_interval ? 2 * iv : h->max_interval;
+    }
+  };
+  for (; pass < kRefinePasses && !newton.empty(); ++pass) {
+    rc = launch_refinement(h, newton, false, pass);
+    if (rc) return rc;
+    rc = sync_states(h);
+    if (rc) return rc;
+    if (pass == 0 && adapt) adapt_intervals(newton);
+    std::vector<int> next;
+    for (int c : newton) {
+      const ChainState &st = h->state[c];
+      if (st.status != 0) continue;   // drift_tol stopped it
+      const double d = st.pass_drift;
+      if (!(d <= kScratchDrift)) scratch.push_back(c);
+      else if (d > again) {
+        if ((pass > 0 && d > 0.25 * prev[c]) || pass + 1 == kRefinePasses) scratch.push_back(c);
+        else next.push_back(c);
+      }
+      prev[c] = d;
+    }
+    newton.swap(next);
+  }
+  if (!scratch.empty()) {
+    // scratch_only: the recompute's drift is the chain's N error before it (pass 0)
+    rc = launch_refinement(h, scratch, true, scratch_only ? 0 : pass);
+    if (rc) return rc;
+    rc = sync_states(h);
+    if (rc) return rc;
+    if (scratch_only && adapt) adapt_intervals(scratch);
+  }
+  return CTAUX_OK;
+}
+
+int refine_all(ctaux_batch *h, bool scratch_only) {
+  std::vector<int> all(h->b.n_chains);
+  for (int c = 0; c < h->b.n_chains; ++c) all[c] = c;
+  return refine_chains(h, all, false, scratch_only);
 }
 
 // next_follows: another block is enqueued right after this one, so its start
@@ -417,10 +527,14 @@ int enqueue_block(ctaux_batch *h, bool next_follows) {
     if (rc2) return rc2;
   }
   h->blocks_launched += 1;
-  if (h->recompute_every > 0 && ++h->since_refine >= h->refine_interval) {
-    h->since_refine = 0;
-    int rc = refine_all(h, true);
-    if (rc) return rc;
+  if (h->recompute_every > 0) {
+    std::vector<int> due;
+    for (int c = 0; c < b.n_chains; ++c)
+      if (h->blocks_launched % h->interval[c] == 0) due.push_back(c);
+    if (!due.empty()) {
+      int rc2 = refine_chains(h, due, true, h->recompute_mode == 1);
+      if (rc2) return rc2;
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(h, CTAUX_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -438,6 +552,9 @@ int chain_error(ctaux_batch *h) {
     if (st.status == CTAUX_ECAPACITY)
       return set_err(h, CTAUX_ECAPACITY, "chain %d: an insertion at proposal %lld would exceed n_cap=%d", c,
                      (long long)st.err_index, h->b.n_cap);
+    if (st.status != 0 && st.err_index == -6)
+      return set_err(h, st.status, "chain %d: N^{-1} of the configuration is singular or not finite "
+                     "(from-scratch recompute failed)", c);
     if (st.status != 0 && st.err_index == -5)
       return set_err(h, st.status, "chain %d: refinement drift %.3g exceeds drift_tol (N is no longer the "
                      "inverse of its definition: refine more often, or use FP64 storage)", c, st.last_drift);
@@ -496,7 +613,11 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
   b.grid_per_chain = n_chains >= 2048 ? 1 : 2048 / n_chains;
   if (b.grid_per_chain > 1024) b.grid_per_chain = 1024;
   h->recompute_every = opts->recompute_every;
-  h->refine_interval = opts->recompute_every < 8 ? opts->recompute_every : 8;
+  h->recompute_mode = opts->recompute_mode;
+  h->max_interval = 1;
+  while (2 * h->max_interval <= opts->recompute_every) h->max_interval *= 2;
+  h->interval.assign(n_chains, h->max_interval < 8 ? h->max_interval : 8);
+  h->drift_target = opts->drift_target > 0.0 ? opts->drift_target : (opts->precision == CTAUX_FP64 ? 1e-10 : 1e-4);
   h->log_cap = opts->log_cap;
   layout(models, n_chains, opts, static_cast<char *>(dev_workspace), &b, &h->desc);
   // upload tables, maps and descriptors
@@ -540,8 +661,11 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
     st[c].sign = 1.0;
   }
   h->state = st;
-  setup_propose(b);
-  setup_refine(b);
+  if (setup_propose(b) != 0 || setup_refine(b) != 0) {
+    delete h;
+    return set_err(nullptr, CTAUX_EDEVICE, "setting the dynamic LDS limits of the kernels failed (LDS of the "
+                   "proposal kernel: %zu bytes)", propose_lds_bytes(b.kcap, b.kmax, b.n_cap));
+  }
   if (hipMemcpyAsync(b.d_desc, h->desc.data(), sizeof(ChainDesc) * n_chains, hipMemcpyHostToDevice, h->stream) !=
           hipSuccess ||
       hipMemcpyAsync(b.d_state, st.data(), sizeof(ChainState) * n_chains, hipMemcpyHostToDevice, h->stream) !=
@@ -599,9 +723,9 @@ int ctaux_run(ctaux_batch *h, int64_t n_proposals) {
   return CTAUX_OK;
 }
 
-int ctaux_recompute(ctaux_batch *h, double *max_drift_out) {
+static int recompute_impl(ctaux_batch *h, double *max_drift_out, bool scratch_only) {
   if (!h) return CTAUX_EINVAL;
-  int rc0 = refine_all(h, false);
+  int rc0 = refine_all(h, scratch_only);
   if (rc0) return rc0;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(h, CTAUX_EDEVICE, "refine launch failed: %s", hipGetErrorString(e));
@@ -611,6 +735,12 @@ int ctaux_recompute(ctaux_batch *h, double *max_drift_out) {
   for (const ChainState &st : h->state) m = st.last_drift > m ? st.last_drift : m;
   if (max_drift_out) *max_drift_out = m;
   return chain_error(h);
+}
+
+int ctaux_recompute(ctaux_batch *h, double *max_drift_out) { return recompute_impl(h, max_drift_out, false); }
+
+int ctaux_recompute_from_scratch(ctaux_batch *h, double *max_drift_out) {
+  return recompute_impl(h, max_drift_out, true);
 }
 
 int32_t ctaux_obs_len(const ctaux_batch *h) { return h ? h->obs_len_max : 0; }
@@ -666,6 +796,8 @@ int ctaux_get_stats(ctaux_batch *h, int32_t chain, ctaux_stats *out) {
   out->prep_bytes = st.prep_bytes;
   out->meas_flops = st.meas_flops;
   out->meas_bytes = st.meas_bytes;
+  out->scratch_recomputes = st.scratch_recomputes;
+  out->refine_interval = h->recompute_every > 0 ? h->interval[chain] : 0;
   return CTAUX_OK;
 }
 
@@ -766,7 +898,7 @@ struct CkptHeader {
   double beta, K, gamma;
   int64_t next_id, done, accepted, blocks, sum_ka;
   int64_t launches;   // blocks enqueued on the batch
-  int64_t refine_interval, since_refine;   // state of the adaptive refinement schedule
+  int64_t refine_interval, since_refine;   // the chain's refinement interval (since_refine unused)
   double sign, max_drift, last_drift, rk_flops, rk_bytes, sum_order;
 };
 constexpr char kCkptMagic[8] = {'C', 'T', 'A', 'U', 'X', 'C', 'K', '1'};
@@ -794,7 +926,7 @@ int ctaux_checkpoint(ctaux_batch *h, int32_t chain, void *buf, size_t *len) {
   CkptHeader hd;
   memset(&hd, 0, sizeof hd);
   memcpy(hd.magic, kCkptMagic, 8);
-  hd.version = 1;
+  hd.version = 2;
   hd.precision = h->b.precision;
   hd.nc = d.nc;
   hd.n_tau = d.n_tau;
@@ -809,8 +941,8 @@ int ctaux_checkpoint(ctaux_batch *h, int32_t chain, void *buf, size_t *len) {
   hd.blocks = st.blocks;
   hd.sum_ka = st.sum_ka;
   hd.launches = h->blocks_launched;
-  hd.refine_interval = h->refine_interval;
-  hd.since_refine = h->since_refine;
+  hd.refine_interval = h->recompute_every > 0 ? h->interval[chain] : 0;
+  hd.since_refine = 0;
   hd.sign = st.sign;
   hd.max_drift = st.max_drift;
   hd.last_drift = st.last_drift;
@@ -847,8 +979,8 @@ int ctaux_restore(ctaux_batch *h, int32_t chain, const void *buf, size_t len) {
   if (len < sizeof hd) return set_err(h, CTAUX_EINVAL, "checkpoint truncated");
   memcpy(&hd, buf, sizeof hd);
   const ChainDesc &d = h->desc[chain];
-  if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1)
-    return set_err(h, CTAUX_EINVAL, "not a version-1 checkpoint");
+  if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 2)
+    return set_err(h, CTAUX_EINVAL, "not a version-2 checkpoint");
   if (hd.precision != h->b.precision || hd.nc != d.nc || hd.n_tau != d.n_tau || hd.beta != d.beta ||
       hd.K != d.K || hd.gamma != d.gamma || hd.obs_len != h->obs_len[chain])
     return set_err(h, CTAUX_EINVAL, "checkpoint of another model or precision");
@@ -899,13 +1031,10 @@ int ctaux_restore(ctaux_batch *h, int32_t chain, const void *buf, size_t len) {
   h->state[chain] = st;
   // The refinement schedule belongs to the batch; a one-chain batch takes over
   // the schedule of the checkpointed one (when both use the same recompute_every).
-  if (h->b.n_chains == 1) {
-    h->blocks_launched = hd.launches;
-    if (h->recompute_every > 0 && hd.refine_interval >= 1 && hd.refine_interval <= h->recompute_every) {
-      h->refine_interval = static_cast<int32_t>(hd.refine_interval);
-      h->since_refine = hd.since_refine;
-    }
-  }
+  if (h->b.n_chains == 1) h->blocks_launched = hd.launches;
+  if (h->recompute_every > 0 && hd.refine_interval >= 1 && hd.refine_interval <= h->max_interval &&
+      (hd.refine_interval & (hd.refine_interval - 1)) == 0)
+    h->interval[chain] = static_cast<int32_t>(hd.refine_interval);
   return CTAUX_OK;
 }
 

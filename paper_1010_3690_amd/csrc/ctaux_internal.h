@@ -61,13 +61,13 @@ struct ChainDesc {
   // Gamma bookkeeping of the block
   int32_t *P;              // [kcap] augmented index of each accepted change
   double *ghat[2];         // [kcap]
-  double *Gam[2];          // [kcap][kcap] Gamma entries of the accepted changes
-  double *Ginv[2];         // [kcap][kcap] Gamma^{-1} for the rank-k update
-  double *Rg[2];           // [kcap][kcap] residual I - Gamma X0 of the growth inverse
+  double *Gam[2];          // [kcap][kcap] entries of the column-scaled Gamma~ of the accepted changes
+  double *Ginv[2];         // [kcap][kcap] Gamma~^{-1} for the rank-k update
+  double *Rg[2];           // [kcap][kcap] residual I - Gamma~ X0 of the growth inverse
   int32_t *map;            // [n_cap] new canonical index -> augmented index
   // rank-k operands (storage type of N)
-  void *Ac[2];             // [ld rows][lda]  (G - I)_{map, P}
-  void *Bc[2];             // [lda][ld]       Gamma^{-1} N_a(P, map)
+  void *Ac[2];             // [ld rows][lda]  ((G - I) D^{-1})_{map, P}
+  void *Bc[2];             // [lda][ld]       Gamma~^{-1} N_a(P, map)
   // measurement
   double *W[2];            // [n_cap][nc]  N gR
   double *gR[2];           // [nc][n_cap]  G0_{x_k y}(tau_k), transposed
@@ -111,6 +111,7 @@ struct ChainState {
   int64_t gj_fallbacks;  // sector-blocks whose Gamma^{-1} needed the pivoted elimination
   double prep_flops, prep_bytes;   // algorithmic work of the preparation products
   double meas_flops, meas_bytes;   // algorithmic work of the measurements
+  int64_t scratch_recomputes;      // refinements that recomputed N from scratch (pivoted elimination)
 };
 
 // Kernel launchers (each .hip file owns its kernels).
@@ -133,11 +134,46 @@ struct RefineItem {
 };
 int refine_slots(int precision);           // n x n scratch blocks per sector
 size_t refine_red_doubles(int n_items);    // partial sums for the drift of n_items chains
+// pool doubles one chain of order n needs for a refinement (Newton slots of both
+// sectors, then the from-scratch elimination's scratch of both sectors)
+size_t refine_need_doubles(int n, int precision);
 void launch_refine_group(const Batch &b, hipStream_t s, const RefineItem *items, int n_items, int pass);
+// From-scratch recompute of the chains of a group: M from the tables, inverted
+// by the blocked Gauss-Jordan elimination (k_invert.hip); inv = 2 items per
+// chain (sector 0, 1) whose pointers the host has carved from the pool.
+struct InvItem;
+void launch_scratch_group(const Batch &b, hipStream_t s, const RefineItem *items, const InvItem *inv, int n_items,
+                          int n_max, int pass);
+
+// ---- blocked Gauss-Jordan inversion (k_invert.hip) ----
+constexpr int kInvNB = 32;   // columns eliminated per step
+constexpr int kBuildMaxOrder = 32768;   // largest configuration of the stateless N builder
+struct InvItem {
+  double *W;        // [n][ldw] the matrix, eliminated in place
+  double *T;        // [kInvNB][n]   A11^{-1} W[p, :] of the current step
+  double *Lp;       // [n][kInvNB]   W[:, J] of the current step
+  double *Ainv;     // [kInvNB][kInvNB]
+  int32_t *cand;    // [ceil(n/256) * kInvNB] tournament candidate lists
+  int32_t *blk;     // [n] step at which a row became a pivot (-1: not yet)
+  int32_t *slot;    // [n] its place within that step
+  int32_t *perm;    // [n] pivot row of each position
+  int32_t *flag;    // [1] set when a pivot block is singular or not finite
+  int32_t n, ldw;
+};
+size_t inv_scratch_doubles(int n);   // T, Lp, Ainv and the index arrays of one n x n elimination
+void inv_item_carve(InvItem &it, double *W, int n, int ldw, double *scratch);
+int setup_invert(int max_items);     // 0 or -1 (attribute call failed)
+void launch_invert(hipStream_t s, const InvItem *items, int n_items, int n_max, int n_cu);
+void launch_inv_gather(hipStream_t s, const InvItem *items, double *out, int ldo, int n);
 void launch_set_target(const Batch &b, hipStream_t s, int64_t n_proposals);
-// per-batch kernel attributes (dynamic LDS limits), once at creation
-void setup_propose(const Batch &b);
-void setup_refine(const Batch &b);
+// per-batch kernel attributes (dynamic LDS limits), once at creation; 0 or -1
+int setup_propose(const Batch &b);
+int setup_refine(const Batch &b);
+// LDS of the proposal kernel: dynamic bytes for these options, and the bound
+// on its static LDS that validation adds to them
+size_t propose_lds_bytes(int kcap, int kmax, int n_cap);
+constexpr size_t kProposeStaticLds = 8192;
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;   // gfx950
 
 // Host-side view of a batch used by the launchers.
 struct Batch {
@@ -156,6 +192,7 @@ struct Batch {
   size_t r_pool_doubles;
   RefineItem *r_items;       // [n_chains]
   double *r_red;             // [refine_red_doubles(n_chains)]
+  InvItem *r_inv;            // [2 n_chains] from-scratch elimination items
 };
 
 // Grid of a per-chain streaming kernel and its xcd_g argument (chain_block):

@@ -3,12 +3,37 @@
 //
 // For a change of vertex p from spin s_old to s_new (block-start spin s0),
 //   gh = exp(V(s_new) - V(s0)) - exp(V(s_old) - V(s0))        (per sector)
-// the new row/column of Gamma are s_a = G_{P_a p} - delta, w_b = G_{p P_b} - delta,
-// d = G_pp - 1 - 1/gh, with G the block-start Green's function (Eq. Gamma with
-// repeated changes allowed).  Inversion by partitioning (Sec. III B 2):
-//   beta = d - w^T Gamma^{-1} s,   det ratio of the sector = -gh * beta  (Eq. ratS),
-// and on acceptance Gamma^{-1} grows by one row and column.
+// Gamma (Eq. Gamma, repeated changes allowed) has the entries
+// Gamma_ab = (G - I)_{P_a P_b} - delta_ab / gh_b with G the block-start Green's
+// function.  The loop works with the column-scaled Gamma~ = Gamma D^{-1},
+// D_b = e^{V_b} / (e^{V_b} - 1) for an old vertex P_b (block-start V) and 1 for
+// a candidate: by Eq. (NfromG) the scaled old columns are plain entries of the
+// augmented N, (G - I)_{i b} / D_b = (N_a - I)_{i b}, so Gamma~ has O(1) entries
+// where Gamma's columns span factors e^{+-gamma} (whose cancellation in the
+// update cost FP64 digits).  The new column and row are
+//   s_a = Gamma_{P_a p} / D_p,  w_b = Gamma_{p P_b} / D_b,  d = Gamma_pp / D_p,
+// and inversion by partitioning (Sec. III B 2) gives
+//   beta~ = d - w^T Gamma~^{-1} s = beta / D_p,
+//   det ratio of the sector = -gh * beta = -gh * D_p * beta~   (Eq. ratS);
+// on acceptance Gamma~^{-1} grows by one row and column.  The N update uses
+// (G - I)_{:,P} Gamma^{-1} = [(G - I)_{:,P} D^{-1}] Gamma~^{-1}.
+//
+// Repeated changes of one vertex within a block (the modification the paper
+// asks for, Sec. III B): P holds every changed vertex once, with its net
+// change gh = exp(V(s) - V(s0)) - 1 from the block-start spin.  A further
+// change of a vertex in P (slot a) only replaces gh_a, i.e. the diagonal entry
+// Gamma~_aa = (.)_pp - 1/(gh_a D_p), so the sector's determinant ratio is
+//   (gh_new / gh_old) (1 + delta X_aa),  delta = (1/gh_old - 1/gh_new) / D_p,
+// with X = Gamma~^{-1} (matrix determinant lemma), and on acceptance
+// X <- X - delta/(1 + delta X_aa) X_{:,a} X_{a,:} (Sherman-Morrison).  A change
+// back to the block-start spin (gh_new = 0) removes slot a: the ratio is
+// X_aa / (-gh_old D_p) (the cofactor) and X loses row and column a by the
+// Schur complement X_{-a,-a} - X_{-a,a} X_{a,-a} / X_aa.  Without this, a vertex
+// changed twice contributes two almost equal columns to Gamma (condition
+// numbers of 1e6 - 1e8), and the update loses FP64 digits.
 // R = {K/(n+1), n/K, 1} * r_up * r_dn (Eq. insprob and Sec. II B); accept iff u < |R|.
+//
+// Below, Gamma stands for the column-scaled Gamma~.
 //
 // One workgroup (4 waves) per chain; Gamma^{-1} of both sectors lives in LDS.
 // Threads 0..127 serve the up sector, 128..255 the down sector.
@@ -32,10 +57,10 @@
 
 namespace ctaux {
 
-// Entry G_ij of the block-start Green's function of the augmented configuration
+// Entry (i, j) of the column-scaled (G - I) D^{-1} of the augmented configuration
 // (old vertices 0..n-1, candidates n..):
-//   old column j:       G_ij = (N_a,ij e^{V_j} - delta_ij) / (e^{V_j} - 1)     (Eq. NfromG)
-//   candidate column j: G_ij = (N Z)_{i, j-n} (old row) or (X Y + G0nn)_{i-n, j-n}.
+//   old column j:       (N_a - I)_ij, N_a,ij = N_ij (old row) or Rt_{i-n, j}
+//   candidate column j: (G - I)_ij, G_ij = (N Z)_{i, j-n} (old row) or (X Y + G0nn)_{i-n, j-n}.
 
 // Calls f with a compile-time even count of k-steps, the smallest that covers ns
 // (ns <= 16: k_a <= 64).
@@ -88,9 +113,10 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   int *P = reinterpret_cast<int *>(vu + 2 * kp);   // [kcap]
   int8_t *scur = reinterpret_cast<int8_t *>(P + kcap);  // [n + kmax] current spins
   int8_t *s0l = scur + (n_cap + kmax);                      // [n + kmax] block-start spins
+  int8_t *slot_of = s0l + (n_cap + kmax);                   // [n + kmax] slot of a vertex in P (-1: none)
   double *Gis = Gi + sec * kp * lg;
   __shared__ double sh_ev[2][5];                   // exp(gamma*sigma*d), d = -2..2
-  __shared__ double sh_rm[2][5];                   // 1 / (exp(gamma*sigma*d) - 1), d = +-1
+  __shared__ double sh_dsc[2][5];                  // D = e^V / (e^V - 1) for block-start spin d = +-1
   __shared__ double sh_gpp[2][2], sh_beta[2][2];   // [proposal parity][sector]
   __shared__ double sh_gh[2][kMaxKcap];
   __shared__ double sh_pacc[kMaxKmax], sh_ppick[kMaxKmax];
@@ -111,6 +137,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   bool pend = false;
   int pk = 0;
   double pbeta = 1.0;
+  bool had_repeat = false;   // an accepted repeated change rewrote Gamma~ (rebuilt at block end)
 
   // Gamma^{-1} of both sectors (with the padding rows) and the s, w vectors start
   // at zero: entries beyond k_a stay zero for the whole block, so the
@@ -120,6 +147,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     const int8_t v = (i < n) ? static_cast<int8_t>(d.s0[par][i]) : 0;
     scur[i] = v;
     s0l[i] = v;
+    slot_of[i] = -1;
   }
   if (tid == 0) {
     sh_bad = 0;
@@ -129,7 +157,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   if (tid < 10) {
     const double e = d.evd[tid / 5][tid % 5];
     sh_ev[tid / 5][tid % 5] = e;
-    sh_rm[tid / 5][tid % 5] = (tid % 5 == 2) ? 0.0 : 1.0 / (e - 1.0);
+    sh_dsc[tid / 5][tid % 5] = (tid % 5 == 2) ? 1.0 : e / (e - 1.0);
   }
   for (int t = tid; t < L; t += 256) {
     sh_ptype[t] = static_cast<int8_t>(d.ptype[t]);
@@ -138,7 +166,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     sh_ppick[t] = d.ppick[t];
   }
   __syncthreads();
-  const double *ev = sh_ev[sec], *rm = sh_rm[sec];
+
   // The proposals' draws live in registers (proposal t in lane t % 64 of slot
   // t / 64) and are read with readlane; lane b of each wave holds P_b and the
   // b-th removed old vertex.  The loop then reads them without LDS round trips.
@@ -187,6 +215,56 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         }
       }
     }
+  };
+
+  // Accepted repeated change of slot a (k = k_a slots): snapshots of X's column
+  // and row a (and of its last row and column) in the vector buffers, then every
+  // thread rewrites the entries it owns in grow's layout.  remove: slot a is
+  // deleted by the Schur complement and the last slot takes its place (its row
+  // and column then zero, keeping the zero padding beyond k_a); otherwise the
+  // Sherman-Morrison update of the diagonal change.
+  auto repeat_update = [&](int a, bool remove, double gn, double dp) {
+    const int k = ka, last = ka - 1;
+    double *cv = vv + sec * kp, *rv = vu + sec * kp, *lrw = vs + sec * kp, *lcl = vw + sec * kp;
+    for (int i = loc; i < k; i += 128) {
+      cv[i] = Gis[i * lg + a];
+      rv[i] = Gis[a * lg + i];
+      lrw[i] = Gis[last * lg + i];
+      lcl[i] = Gis[i * lg + last];
+    }
+    const double xaa = Gis[a * lg + a], go = sh_gh[sec][a];
+    lds_barrier();
+    const int cp = loc & 31, rg = loc >> 5;
+    if (!remove) {
+      const double del = (1.0 / go - 1.0 / gn) / dp;
+      const double coef = del / (1.0 + del * xaa);
+      for (int r = rg; r < k; r += 4)
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+          const int c = 2 * cp + h2;
+          if (c < k) Gis[r * lg + c] -= coef * cv[r] * rv[c];
+        }
+    } else {
+      const double ixa = 1.0 / xaa;
+      for (int r = rg; r < k; r += 4)
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+          const int c = 2 * cp + h2;
+          if (c >= k) continue;
+          double x = 0.0;
+          if (r != last && c != last) {
+            const int sr = (r == a) ? last : r, sc = (c == a) ? last : c;
+            double base;
+            if (sr == last && sc == last) base = lrw[last];
+            else if (sr == last) base = lrw[sc];
+            else if (sc == last) base = lcl[sr];
+            else base = Gis[r * lg + c];
+            x = base - cv[sr] * rv[sc] * ixa;
+          }
+          Gis[r * lg + c] = x;
+        }
+    }
+    lds_barrier();
   };
 
   for (int t = 0; t < L; ++t) {
@@ -250,8 +328,28 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     // gathers below are in flight
     const double fpre = (type == 0) ? Kc / static_cast<double>(ncur + 1)
                                     : (type == 1 ? static_cast<double>(ncur) / Kc : 1.0);
-    double gh0 = 0.0, gh1 = 0.0;
-    if (!skip && !gz) {
+    double gh0 = 0.0, gh1 = 0.0, dp0 = 1.0, dp1 = 1.0;
+    const int rp = (!skip && !gz) ? static_cast<int>(slot_of[p]) : -1;   // slot of a repeated change
+    if (rp >= 0) {
+      // ---- repeated change: ratio from X_aa (the owed growth first) ----
+      const int s0p = s0l[p];
+      gh0 = sh_ev[0][s_new - s0p + 2] - 1.0;   // net change from the block-start spin
+      gh1 = sh_ev[1][s_new - s0p + 2] - 1.0;
+      dp0 = sh_dsc[0][s0p + 2];
+      dp1 = sh_dsc[1][s0p + 2];
+      if (pend) {
+        grow(pk, pbeta);
+        pend = false;
+      }
+      lds_barrier();
+      if (loc == 0) {
+        const double xaa = Gis[rp * lg + rp], go = sh_gh[sec][rp];
+        const double gn = sec == 0 ? gh0 : gh1, dp = sec == 0 ? dp0 : dp1;
+        sh_beta[tp][sec] = (s_new == s0p) ? xaa / (-go * dp)
+                                          : (gn / go) * (1.0 + (1.0 / go - 1.0 / gn) / dp * xaa);
+      }
+      lds_barrier();
+    } else if (!skip && !gz) {
       // ---- issue the gathers: thread loc < 64 takes s_loc = G(P_loc, p) (loc == 63: G_pp),
       // thread 64 + b takes w_b = G(p, P_b) ----
       int gi = -1, gj = -1;
@@ -273,31 +371,29 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         const int s0p = s0l[p];
         gh0 = sh_ev[0][s_new - s0p + 2] - sh_ev[0][s_old - s0p + 2];
         gh1 = sh_ev[1][s_new - s0p + 2] - sh_ev[1][s_old - s0p + 2];
+        dp0 = sh_dsc[0][s0p + 2];   // 1 for a candidate (s0 = 0)
+        dp1 = sh_dsc[1][s0p + 2];
       }
       // ---- owed growth of Gamma^{-1} by partitioning (Sec. III B 2), LDS only ----
       if (pend) {
         grow(pk, pbeta);
         pend = false;
       }
-      // ---- finish the gathers; each thread also records its entry as row / column ka
-      // of Gamma for the pivoted inversion at block end (a rejected proposal's
-      // entries are overwritten by the next one) ----
-      const double gh = sec == 0 ? gh0 : gh1;
+      // ---- finish the gathers (entries of Gamma~: the raw entry minus the identity);
+      // each thread also records its entry as row / column ka of Gamma~ for the
+      // pivoted inversion at block end (a rejected proposal's entries are
+      // overwritten by the next one) ----
+      const double gh = sec == 0 ? gh0 : gh1, dp = sec == 0 ? dp0 : dp1;
       if (gi >= 0) {
-        double g = raw;
-        if (gj < n) {
-          const int sj = s0l[gj] + 2;
-          g = (raw * ev[sj] - (gi == gj ? 1.0 : 0.0)) * rm[sj];   // Eq. NfromG
-        }
+        const double v = raw - (gi == gj ? 1.0 : 0.0);
         if (loc == 63 && gi == gj && loc >= ka) {
-          sh_gpp[tp][sec] = g;
-          gam[ka * kcap + ka] = g - 1.0 - 1.0 / gh;
+          const double dd = v - 1.0 / (gh * dp);
+          sh_gpp[tp][sec] = dd;
+          gam[ka * kcap + ka] = dd;
         } else if (loc < 64) {
-          const double v = g - (gi == gj ? 1.0 : 0.0);
           vs[sec * kp + loc] = v;
           gam[loc * kcap + ka] = v;
         } else {
-          const double v = g - (gi == gj ? 1.0 : 0.0);
           vw[sec * kp + loc - 64] = v;
           gam[ka * kcap + loc - 64] = v;
         }
@@ -326,7 +422,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         }
         const double x = (loc < ka) ? vw[sec * kp + loc] * acc : 0.0;
         const double s = wave_sum_dpp(x);
-        if (lane == 0) sh_beta[tp][sec] = (sh_gpp[tp][sec] - 1.0 - 1.0 / gh) - s;
+        if (lane == 0) sh_beta[tp][sec] = sh_gpp[tp][sec] - s;
       } else {
         const int b = loc - 64;
         if (b < ka) {
@@ -354,9 +450,12 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       R = 0.0;
     } else {
       double r0 = 1.0, r1 = 1.0;
-      if (!gz) {
-        r0 = -gh0 * sh_beta[tp][0];
-        r1 = -gh1 * sh_beta[tp][1];
+      if (rp >= 0) {   // the sector ratios themselves
+        r0 = sh_beta[tp][0];
+        r1 = sh_beta[tp][1];
+      } else if (!gz) {
+        r0 = -gh0 * dp0 * sh_beta[tp][0];
+        r1 = -gh1 * dp1 * sh_beta[tp][1];
       }
       R = fpre * r0 * r1;
     }
@@ -378,11 +477,35 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       accepted += 1;
       nchg += 1;
       if (R < 0.0) sign = -sign;
-      if (!gz) {
+      if (rp >= 0) {
+        had_repeat = true;
+        repeat_update(rp, s_new == s0l[p], sec == 0 ? gh0 : gh1, sec == 0 ? dp0 : dp1);
+        if (s_new != s0l[p]) {
+          if (tid == 0) {
+            sh_gh[0][rp] = gh0;
+            sh_gh[1][rp] = gh1;
+          }
+        } else {
+          // slot rp is removed: the last slot moves into it (every thread writes the same values)
+          const int last = ka - 1, pl = P[last];
+          if (rp != last) {
+            P[rp] = pl;
+            slot_of[pl] = static_cast<int8_t>(rp);
+            if (lane == rp) myP = pl;
+            if (tid == 0) {
+              sh_gh[0][rp] = sh_gh[0][last];
+              sh_gh[1][rp] = sh_gh[1][last];
+            }
+          }
+          slot_of[p] = -1;
+          ka -= 1;
+        }
+      } else if (!gz) {
         pend = true;
         pk = ka;
         pbeta = sh_beta[tp][sec];
         P[ka] = p;           // every thread writes the same value
+        slot_of[p] = static_cast<int8_t>(ka);
         if (lane == ka) myP = p;
         if (tid == 0) {
           sh_gh[0][ka] = gh0;
@@ -407,7 +530,9 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     // with U = 0 there are no gather barriers; without one here a wave could run
     // ahead and overwrite spins another wave still has to read
     if (gz) lds_barrier();
-    if (nchg == kcap) {   // Gamma (and the removed-vertex list) is full: the block ends here
+    // Gamma full: the block ends here (with U = 0 the removed-vertex list, whose
+    // length never exceeds that of P otherwise, bounds the block)
+    if ((gz ? nchg : ka) == kcap) {
       L_eff = t + 1;
       break;
     }
@@ -417,6 +542,23 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   // starting point of the refinement below
   if (pend) grow(pk, pbeta);
   lds_barrier();
+  // Gamma~ as recorded while proposing is stale once a repeated change rewrote
+  // a slot: gather it again for the final P and net changes
+  if (had_repeat && ka > 0) {
+    for (int e = loc; e < ka * ka; e += 128) {
+      const int a = e / ka, b = e - a * ka;
+      const int pa = P[a], pb = P[b];
+      double raw;
+      if (pb < n) raw = (pa < n) ? static_cast<double>(Nsec[static_cast<size_t>(pa) * ld + pb])
+                                 : Rts[static_cast<size_t>(pa - n) * ld + pb];
+      else raw = (pa < n) ? YTs[static_cast<size_t>(pb - n) * ld + pa]
+                          : Gnns[static_cast<size_t>(pa - n) * kmax + (pb - n)];
+      double v = raw - (a == b ? 1.0 : 0.0);
+      if (a == b) v -= 1.0 / (sh_gh[sec][b] * sh_dsc[sec][s0l[pb] + 2]);
+      gam[a * kcap + b] = v;
+    }
+  }
+  __syncthreads();
 
   if (wave == 1) {
     // ---- compaction map: interacting vertices in augmented order (one wave,
@@ -696,21 +838,31 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
 
 // LDS: Gamma^{-1} of both sectors as k_cap rounded up to 8 rows (the
 // matrix-vector products read whole batches of 8) of that many plus one
-// entries, the four vectors, P and the spins.
-size_t propose_lds_bytes(const Batch &b) {
-  const size_t kp = (static_cast<size_t>(b.kcap) + 7) & ~size_t{7};
-  return sizeof(double) * (2 * kp * (kp + 1) + 8 * kp) + sizeof(int) * static_cast<size_t>(b.kcap) +
-         2ull * static_cast<size_t>(b.n_cap + b.kmax) + 16;
+// entries, the four vectors, P, the spins and the slots.
+size_t propose_lds_bytes(int kcap, int kmax, int n_cap) {
+  const size_t kp = (static_cast<size_t>(kcap) + 7) & ~size_t{7};
+  return sizeof(double) * (2 * kp * (kp + 1) + 8 * kp) + sizeof(int) * static_cast<size_t>(kcap) +
+         3ull * static_cast<size_t>(n_cap + kmax) + 16;
 }
 
+static size_t propose_lds_bytes(const Batch &b) { return propose_lds_bytes(b.kcap, b.kmax, b.n_cap); }
+
 // Dynamic LDS limits are set once per batch: the call costs host time that would
-// otherwise sit between the launches of every block.
-void setup_propose(const Batch &b) {
+// otherwise sit between the launches of every block.  Returns -1 if the runtime
+// refuses the size (the options were validated against the LDS of a workgroup,
+// so this signals a device that has less).
+int setup_propose(const Batch &b) {
   const int lds = static_cast<int>(propose_lds_bytes(b));
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_propose<double>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_propose<float>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_propose<double>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
+      hipFuncSetAttribute(reinterpret_cast<const void *>(k_propose<float>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+    return -1;
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_propose<double>)) != hipSuccess ||
+      fa.sharedSizeBytes > kProposeStaticLds)
+    return -1;
+  return 0;
 }
 
 void launch_propose(const Batch &b, hipStream_t s) {

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_ref_apply(const ChainDesc *descs, const
 // (last_drift, max_drift, the drift_tol check); every pass leaves its drift in
 // pass_drift for the host's decision on one more step.
 __global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const RefineItem *items, int n_items,
-                             const double *red, int pass) {
+                             const double *red, int pass, int scratch) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_items) return;
   const int c = items[q].chain;
@@ -246,11 +246,15 @@ __global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const R
     else if (dr > drift) drift = dr;
   }
   st.pass_drift = drift;
-  // A failing chain is also deactivated: the next block may already have been
-  // started (its start is fused into the previous block's end), and its kernels
-  // then skip the chain.
-  if (!isfinite(drift) && st.status == 0) {
+  if (scratch) st.scratch_recomputes += 1;
+  // A Newton step that left a non-finite N is repaired by a from-scratch
+  // recompute (the host reads pass_drift); a from-scratch recompute that fails
+  // (singular or non-finite M) stops the chain.  A failing chain is also
+  // deactivated: the next block may already have been started (its start is
+  // fused into the previous block's end), and its kernels then skip the chain.
+  if (scratch && !isfinite(drift) && st.status == 0) {
     st.status = -4;
+    st.err_index = -6;
     st.active = 0;
   }
   if (pass > 0) return;
@@ -265,6 +269,10 @@ __global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const R
 
 int refine_slots(int precision) { return precision == kFP64 ? 2 : 3; }
 
+size_t refine_need_doubles(int n, int precision) {
+  return 2 * (static_cast<size_t>(refine_slots(precision)) * n * n + inv_scratch_doubles(n));
+}
+
 size_t refine_red_doubles(int n_items) { return static_cast<size_t>(n_items) * 2 * kRefBlocks * 2; }
 
 template <typename T>
@@ -278,15 +286,77 @@ static void launch_group_t(const Batch &b, hipStream_t s, const RefineItem *item
   hipLaunchKernelGGL(k_ref_apply<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
                      b.r_pool, b.r_red);
   hipLaunchKernelGGL(k_ref_reduce, dim3((n_items + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items,
-                     b.r_red, pass);
+                     b.r_red, pass, 0);
 }
 
-void setup_refine(const Batch &b) {
+// After the elimination: N <- M^{-1} in canonical order, N[i][j] = W[perm[i]][pos(j)]
+// (k_invert.hip), with per-workgroup partial sums of |N_before - N_after|^2 and
+// N_after^2 for the drift.  A singular M leaves NaN in the sums.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ref_scratch_store(const ChainDesc *descs, const ChainState *states,
+                                                           const RefineItem *items, const InvItem *inv, double *red) {
+  const RefineItem it = items[blockIdx.y];
+  const ChainDesc &d = descs[it.chain];
+  const ChainState &st = states[it.chain];
+  const int n = it.n;
+  __shared__ double sh[2][4];
+  for (int sec = 0; sec < 2; ++sec) {
+    const InvItem &iv = inv[2 * blockIdx.y + sec];
+    T *N = static_cast<T *>(d.N[st.parity][sec]);
+    const bool bad = iv.flag[0] != 0;
+    const int64_t total = static_cast<int64_t>(n) * n;
+    double s_t = 0.0, s_n = 0.0;
+    for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
+      const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<int64_t>(i) * n);
+      const int bj = iv.blk[j];   // every row is a pivot once the elimination is complete
+      const double nv = bj >= 0 ? iv.W[static_cast<size_t>(iv.perm[i]) * iv.ldw + bj * kInvNB + iv.slot[j]] : NAN;
+      const size_t o = static_cast<size_t>(i) * d.ld + j;
+      const double dv = static_cast<double>(N[o]) - nv;
+      N[o] = static_cast<T>(nv);
+      s_t += dv * dv;
+      s_n += nv * nv;
+    }
+    if (bad) s_t = NAN;
+    s_t = wave_sum(s_t);
+    s_n = wave_sum(s_n);
+    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = s_t; sh[1][threadIdx.x >> 6] = s_n; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double *r = red + ((static_cast<size_t>(blockIdx.y) * 2 + sec) * gridDim.x + blockIdx.x) * 2;
+      r[0] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+      r[1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+static void launch_scratch_t(const Batch &b, hipStream_t s, const RefineItem *items, const InvItem *inv, int n_items,
+                             int n_max, int pass) {
+  hipLaunchKernelGGL(k_ref_build<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
+                     b.r_pool);
+  launch_invert(s, inv, 2 * n_items, n_max, b.n_cu);
+  hipLaunchKernelGGL(k_ref_scratch_store<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
+                     inv, b.r_red);
+  hipLaunchKernelGGL(k_ref_reduce, dim3((n_items + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items,
+                     b.r_red, pass, 1);
+}
+
+void launch_scratch_group(const Batch &b, hipStream_t s, const RefineItem *items, const InvItem *inv, int n_items,
+                          int n_max, int pass) {
+  if (n_items <= 0) return;
+  if (b.precision == kFP64) launch_scratch_t<double>(b, s, items, inv, n_items, n_max, pass);
+  else launch_scratch_t<float>(b, s, items, inv, n_items, n_max, pass);
+}
+
+int setup_refine(const Batch &b) {
   const int lds = static_cast<int>(sizeof(int) * (b.n_chains + 1));
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ref_gemm<double>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ref_gemm<float>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_ref_gemm<double>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
+      hipFuncSetAttribute(reinterpret_cast<const void *>(k_ref_gemm<float>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+    return -1;
+  return setup_invert(2 * b.n_chains);
 }
 
 // One group of chains (items in device memory, scratch offsets within the pool).

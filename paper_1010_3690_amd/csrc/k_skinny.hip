@@ -4,7 +4,7 @@
 // handed to an output functor.  They are
 //   - the preparation products of a block (Sec. IV A): YT = ZT N^T, Rt = X N
 //     (each reads N once) and Gnn = X YT^T + G0nn;
-//   - the operand B_c = Gamma^{-1} N_a(P, map) of the rank-k update (Sec. IV C),
+//   - the operand B_c = Gamma~^{-1} N_a(P, map) of the rank-k update (Sec. IV C),
 //     with N_a gathered on the fly;
 //   - the measurement (Sec. IV D): W = N gR, then G(x tau_j; y 0) = G0 + gL W.
 // A work item is a tile of 16*NRT rows and 16 columns of one product of one
@@ -271,7 +271,7 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
     };
     skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, ki, c0, red);
   } else if constexpr (KIND == kSkAsmB) {
-    // Bc[sec] = Gamma^{-1} N_a(P, map): rows a < kpad (zero beyond k_a), K = k_a
+    // Bc[sec] = Gamma~^{-1} N_a(P, map): rows a < kpad (zero beyond k_a), K = k_a
     const int np = st.n_new, ka = st.k_a, kpad = (ka + 7) & ~7, nt = (np + 15) >> 4;
     const int sec = local / nt, c0 = (local - sec * nt) * 16, ld = d.ld, kcap = d.kcap;
     const auto Gi = gview(d.Ginv[sec]), Rt = gview(d.Rt[sec]);
@@ -382,10 +382,11 @@ __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, c
 
 // The operands of the rank-k update on the chain grid (a chain's workgroups on
 // one XCD when many chains run):
-//   Ac[i'][a] = (G - I)_{map(i'), P_a}, element by element from the chain's
+//   Ac[i'][a] = ((G - I) D^{-1})_{map(i'), P_a} (the column scaling of the proposal
+//   kernel's Gamma~, so that Ac Gamma~^{-1} = (G - I)_{:,P} Gamma^{-1}), element by element from the chain's
 //   first workgroups up, after the configuration's times, sites and ids are
 //   copied into compacted order;
-//   with NRT > 0 also Bc = Gamma^{-1} N_a(P, map), one wave per 16-column item
+//   with NRT > 0 also Bc = Gamma~^{-1} N_a(P, map), one wave per 16-column item
 //   from the chain's last workgroups down.
 // Both read only what the proposal kernel left.  One launch for both saves a
 // kernel on the critical path of a few long chains; with many chains the MFMA
@@ -446,8 +447,9 @@ __global__ __launch_bounds__(256) void k_operands(const ChainDesc *descs, const 
     const int i = static_cast<int>(r / kpad), a = static_cast<int>(r - static_cast<int64_t>(i) * kpad);
     double v = 0.0;
     if (a < ka) {
+      // (G - I)_{map, P} D^{-1}: (N_a - I) for an old column, (G - I) for a candidate
       const int mi = gview(map)[i], pa = gview(P)[a];
-      v = g_entry<T>(d, N, s0, n, sec, mi, pa) - (mi == pa ? 1.0 : 0.0);
+      v = (pa < n ? na_entry<T>(d, N, n, sec, mi, pa) : g_entry<T>(d, N, s0, n, sec, mi, pa)) - (mi == pa ? 1.0 : 0.0);
     }
     gview_w(static_cast<T *>(d.Ac[sec]))[static_cast<size_t>(i) * lda + a] = static_cast<T>(v);
   }

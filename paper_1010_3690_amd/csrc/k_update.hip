@@ -6,9 +6,11 @@
 //
 // k_operands (with the skinny products) builds the compacted operands (and
 // copies the times, sites and ids of the configuration after the block into
-// compacted order)
-//   Ac[i'][a] = (G - I)_{map(i'), P_a}           (n' x k_a)
-//   Bc[a][j'] = sum_b Gamma^{-1}_{ab} N_a(P_b, map(j'))   (k_a x n')
+// compacted order), with Gamma~ = Gamma D^{-1} the column-scaled Gamma of the
+// proposal loop (D_b = e^{V_b}/(e^{V_b} - 1) for an old vertex, 1 for a candidate)
+//   Ac[i'][a] = ((G - I) D^{-1})_{map(i'), P_a}            (n' x k_a)
+//   Bc[a][j'] = sum_b Gamma~^{-1}_{ab} N_a(P_b, map(j'))   (k_a x n')
+// so that Ac Bc = (G - I)_{:,P} Gamma^{-1} N_a(P,:).
 // and k_rankk computes N'[i'][j'] = N_a(map i', map j') - (Ac Bc)[i'][j'] on
 // MFMA 16x16x4 tiles (FP64, or FP32 for FP32 storage), 64x64 or 32x32 outputs
 // per workgroup, tiles of every chain scheduled from one persistent grid.

@@ -28,7 +28,8 @@ EXPORTED = [
     "ctaux_workspace_bytes", "ctaux_create", "ctaux_run", "ctaux_recompute", "ctaux_obs_len",
     "ctaux_get_obs", "ctaux_reset_obs", "ctaux_get_stats", "ctaux_get_config", "ctaux_get_N",
     "ctaux_get_decisions", "ctaux_set_timing", "ctaux_set_timing_every", "ctaux_get_timing",
-    "ctaux_checkpoint", "ctaux_restore",
+    "ctaux_checkpoint", "ctaux_restore", "ctaux_recompute_from_scratch",
+    "ctaux_build_N_workspace_bytes", "ctaux_build_N",
     "ctaux_last_error", "ctaux_destroy",
 ]
 
@@ -44,7 +45,8 @@ class _Opts(C.Structure):
                 ("recompute_every", C.c_int32), ("precision", C.c_int32), ("meas_every", C.c_int32),
                 ("n_therm", C.c_int64), ("n_tau_out", C.c_int32), ("n_cap", C.c_int32),
                 ("seed", C.c_uint64), ("log_cap", C.c_int64), ("gamma_tol", C.c_double),
-                ("drift_tol", C.c_double), ("rankk_tile", C.c_int32)]
+                ("drift_tol", C.c_double), ("rankk_tile", C.c_int32), ("drift_target", C.c_double),
+                ("recompute_mode", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -53,7 +55,8 @@ class _Stats(C.Structure):
                 ("status", C.c_int32), ("sign", C.c_double), ("max_drift", C.c_double),
                 ("rankk_flops", C.c_double), ("rankk_bytes", C.c_double), ("sum_order", C.c_double),
                 ("gj_fallbacks", C.c_int64), ("prep_flops", C.c_double), ("prep_bytes", C.c_double),
-                ("meas_flops", C.c_double), ("meas_bytes", C.c_double)]
+                ("meas_flops", C.c_double), ("meas_bytes", C.c_double), ("scratch_recomputes", C.c_int64),
+                ("refine_interval", C.c_int32)]
 
 
 class _Vertex(C.Structure):
@@ -86,6 +89,10 @@ def load_library(path: str = LIB_PATH):
     lib.ctaux_create.argtypes = [vp, i32, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.ctaux_run.argtypes = [vp, i64]
     lib.ctaux_recompute.argtypes = [vp, C.POINTER(d)]
+    lib.ctaux_recompute_from_scratch.argtypes = [vp, C.POINTER(d)]
+    lib.ctaux_build_N_workspace_bytes.restype = C.c_size_t
+    lib.ctaux_build_N_workspace_bytes.argtypes = [vp, i32]
+    lib.ctaux_build_N.argtypes = [vp, vp, i32, i32, vp, i32, vp, C.c_size_t, vp]
     lib.ctaux_obs_len.restype = i32
     lib.ctaux_obs_len.argtypes = [vp]
     lib.ctaux_get_obs.argtypes = [vp, i32, vp, i32]
@@ -123,11 +130,13 @@ class Options:
     gamma_tol: float = 1e-8
     drift_tol: float = 1e-2
     rankk_tile: int = 64
+    drift_target: float = 0.0
+    recompute_mode: int = 0
 
     def _c(self) -> _Opts:
         return _Opts(self.k_max, self.k_cap, self.p_flip, self.recompute_every, self.precision,
                      self.meas_every, self.n_therm, self.n_tau_out, self.n_cap, self.seed, self.log_cap,
-                     self.gamma_tol, self.drift_tol, self.rankk_tile)
+                     self.gamma_tol, self.drift_tol, self.rankk_tile, self.drift_target, self.recompute_mode)
 
 
 def _ptr(a: np.ndarray):
@@ -193,6 +202,11 @@ class CtauxBatch:
     def recompute(self) -> float:
         d = C.c_double()
         self._check(self.lib.ctaux_recompute(self.h, C.byref(d)))
+        return d.value
+
+    def recompute_from_scratch(self) -> float:
+        d = C.c_double()
+        self._check(self.lib.ctaux_recompute_from_scratch(self.h, C.byref(d)))
         return d.value
 
     def obs(self, chain: int = 0) -> np.ndarray:
@@ -265,3 +279,43 @@ class CtauxBatch:
         cnt = np.zeros(cap, np.int64)
         k = self.lib.ctaux_get_timing(self.h, names, _ptr(ms), _ptr(cnt), cap)
         return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
+
+
+def _model_of(w):
+    sd = np.ascontiguousarray(w.site_disp, np.int32)
+    gu = np.ascontiguousarray(w.g0_up, np.float64)
+    gd = np.ascontiguousarray(w.g0_dn, np.float64)
+    return _Model(w.beta, w.U, w.K, w.n_sites, w.n_tau, w.n_disp, _ptr(sd), _ptr(gu), _ptr(gd)), (sd, gu, gd)
+
+
+def _vertices(tau, site, s):
+    n = len(tau)
+    buf = (_Vertex * max(n, 1))()
+    for i in range(n):
+        buf[i] = _Vertex(i, float(tau[i]), int(site[i]), int(s[i]))
+    return buf
+
+
+def build_N(w, tau, site, s, sector: int, device: str = "cuda:0") -> np.ndarray:
+    """N of one sector of a configuration from its definition, computed on the
+    GPU by ctaux_build_N (M from the tables, pivoted elimination)."""
+    import torch
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("build_N needs a GPU; there is no CPU path")
+    model, keep = _model_of(w)
+    n = len(tau)
+    verts = _vertices(tau, site, s)
+    nbytes = lib.ctaux_build_N_workspace_bytes(C.byref(model), n)
+    if nbytes == 0:
+        raise CtauxError(CTAUX_EINVAL, lib.ctaux_last_error(None).decode())
+    dev = torch.device(device)
+    with torch.cuda.device(dev):
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        out = torch.empty((max(n, 1), max(n, 1)), dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream(dev)
+        rc = lib.ctaux_build_N(C.byref(model), verts, n, sector, C.c_void_p(out.data_ptr()), max(n, 1),
+                               C.c_void_p(ws.data_ptr()), nbytes, C.c_void_p(stream.cuda_stream))
+    if rc != 0:
+        raise CtauxError(rc, lib.ctaux_last_error(None).decode())
+    return out[:n, :n].cpu().numpy()

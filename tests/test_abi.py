@@ -62,7 +62,10 @@ def test_workspace_bytes_and_validation(lib):
                 dict(precision=7), dict(n_cap=0), dict(meas_every=0), dict(rankk_tile=16),
                 dict(gamma_tol=float("nan")),
                 # 2 (n_tau_out + 1) n_sites n_cap >= 2^31 (32-bit table indices): 2 * 4097 * 4 * 65536
-                dict(n_tau_out=4096, n_cap=65536)):
+                dict(n_tau_out=4096, n_cap=65536),
+                # the proposal kernel's LDS (Gamma^-1 of both sectors plus three bytes per
+                # vertex of the augmented configuration) exceeds 160 KB
+                dict(n_cap=40000), dict(drift_target=-1.0), dict(recompute_mode=2)):
         mb, ob, kb = _model_and_opts(ctaux, **bad)
         assert lib.ctaux_workspace_bytes(C.byref(mb), 1, C.byref(ob)) == 0, bad
     # a non-finite table entry is rejected
@@ -81,3 +84,33 @@ def test_create_rejects_small_workspace(lib):
     assert rc == ctaux.CTAUX_ENOMEM
     assert not h.value
     assert b"workspace" in lib.ctaux_last_error(None)
+
+
+def test_lds_bound_is_the_boundary(lib):
+    """The largest n_cap accepted at k_cap = 64 leaves the proposal kernel within
+    the 160 KB of LDS of a workgroup; one more vertex of capacity does not."""
+    from paper_1010_3690_amd import ctaux
+    ok, bad = [], []
+    # 8 (2 * 64 * 65 + 8 * 64) + 4 * 64 + 3 (n_cap + 64) + 16 + 8192 <= 163840  <=>  n_cap <= 28176
+    for n_cap in (16384, 28176, 28177, 32768):
+        m, o, keep = _model_and_opts(ctaux, n_cap=n_cap)
+        (ok if lib.ctaux_workspace_bytes(C.byref(m), 1, C.byref(o)) > 0 else bad).append(n_cap)
+    assert ok == [16384, 28176] and bad == [28177, 32768], (ok, bad)
+    assert b"LDS" in lib.ctaux_last_error(None)
+
+
+def test_build_N_validation_without_gpu(lib):
+    from paper_1010_3690_amd import ctaux
+    m, o, keep = _model_and_opts(ctaux)
+    assert lib.ctaux_build_N_workspace_bytes(C.byref(m), -1) == 0
+    assert lib.ctaux_build_N_workspace_bytes(C.byref(m), 40000) == 0
+    nb = lib.ctaux_build_N_workspace_bytes(C.byref(m), 100)
+    assert nb > 100 * 100 * 8
+    verts = (ctaux._Vertex * 2)(ctaux._Vertex(0, 0.5, 0, 1), ctaux._Vertex(1, 0.7, 9, 1))   # site 9 >= n_sites
+    rc = lib.ctaux_build_N(C.byref(m), verts, 2, 0, None, 2, None, 0, None)
+    assert rc == ctaux.CTAUX_EINVAL and b"vertex 1" in lib.ctaux_last_error(None)
+    verts[1] = ctaux._Vertex(1, 0.7, 1, 1)
+    out = C.c_void_p(256)   # never dereferenced: the workspace check fails first
+    rc = lib.ctaux_build_N(C.byref(m), verts, 2, 0, out, 2, None, 0, None)
+    assert rc == ctaux.CTAUX_ENOMEM
+    assert lib.ctaux_build_N(C.byref(m), verts, 0, 0, None, 0, None, 0, None) == 0   # n = 0: nothing to do

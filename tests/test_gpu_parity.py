@@ -18,10 +18,10 @@ from oracle import OracleChain
 pytestmark = pytest.mark.gpu
 
 N_TOL = 1e-10          # ||N_gpu - N_oracle||_F / ||N_oracle||_F, FP64
-# Per-proposal ratios: the GPU takes them from Gamma^{-1} grown by partitioning
-# (unpivoted), whose relative error reaches cond(Gamma) * eps ~ 1e-8 when a
-# vertex changes repeatedly within a block (cond 1e6..1e8 observed); the oracle
-# takes them from rank-1 updated N.  Decisions are compared exactly.
+# Per-proposal ratios: the GPU takes them from Gamma~^{-1} grown by partitioning
+# (unpivoted), the oracle from rank-1 updated N; a ratio that is small because
+# its Schur complement cancels carries a relative error of eps times that
+# cancellation on both sides.  Decisions are compared exactly.
 R_TOL = 1e-6
 
 
@@ -138,8 +138,7 @@ def test_batched_chains_match_their_oracles():
     ws = [_plaquette(), hubbard_dimer(beta=2.0, U=2.0, n_tau=2001), _plaquette(beta=2.0, U=6.0),
           _cluster16(K=5.0), anderson_semicircle(n_tau=4096)]
     n_prop = 3000
-    # ~94 blocks per chain: the FP64 refinement every 16 blocks bounds the
-    # ~1e-12 per-block rounding of the rank-k updates, as in production runs
+    # ~94 blocks per chain with the FP64 refinement schedule of production runs
     opts = ctaux.Options(k_max=32, k_cap=24, n_cap=1024, log_cap=n_prop, meas_every=32, n_tau_out=8,
                          recompute_every=16, seed=11)
     gb = ctaux.CtauxBatch(ws, opts)
@@ -400,29 +399,37 @@ def test_config5_cubic_nc100_eight_chains():
     print(f"[config5] chain 3 N error after recompute {max(errs):.3e}", flush=True)
 
 
-def test_refinement_restores_a_strongly_coupled_chain():
-    """Nc = 32, beta = 7.08, U = 7.13, K = 1 (gamma ~ 7.4): the FP64 block
-    updates lose digits (Gamma^{-1} has entries of ~1e6 that the update
-    cancels), so 60 blocks without refinement leave a drift well above FP64
-    rounding.  One refinement call takes as many Newton steps as needed: a
-    second call right after it measures a drift at the rounding level, and N
-    then matches the inverse of its definition."""
+def test_strongly_coupled_chain_holds_fp64_without_refinement():
+    """Nc = 32, beta = 7.08, U = 7.13, K = 1 (gamma ~ 7.4, N^{-1} conditioned
+    ~1e5): 60 blocks of 64 proposals without any refinement keep N within 1e-9
+    of the inverse of its definition (repeated changes of a vertex update its
+    slot of Gamma instead of adding a nearly equal column), and one
+    refinement brings it to FP64 rounding."""
     from ctaux_inputs.workloads import _MIX_LATTICES
     ctaux = _ctaux()
     w = dca_square(beta=7.0812185938101795, U=7.13460658748971, K=1.0, n_tau=2048, n_fine=16,
                    superlattice=_MIX_LATTICES[32])
     opts = ctaux.Options(k_max=64, k_cap=64, n_cap=2048, recompute_every=0, seed=0, drift_tol=0.0,
-                         meas_every=64, n_tau_out=8)
+                         meas_every=64, n_tau_out=8, log_cap=4000)
     print(f"[strong] nc={w.n_sites} K={w.K}", flush=True)
     gb = ctaux.CtauxBatch([w], opts)
     gb.run(64 * 60)
+    oc = OracleChain(w, n_cap=2048)
+    errs = _n_vs_definition(ctaux, gb, oc, 0, 1e-9)
     d1 = gb.recompute()
     d2 = gb.recompute()
-    print(f"[strong] order {gb.stats(0)['order']} drift {d1:.3e} then {d2:.3e}", flush=True)
-    assert d1 > 1e-9          # the interval drifted past the extra-step threshold
-    assert d2 < 1e-10
-    oc = OracleChain(w, n_cap=2048)
-    _n_vs_definition(ctaux, gb, oc, 0, 1e-8)
+    print(f"[strong] order {gb.stats(0)['order']} N error {max(errs):.3e} drift {d1:.3e} then {d2:.3e}",
+          flush=True)
+    assert d1 < 1e-9 and d2 < 1e-12
+    # the LAPACK inverse that serves as reference carries cond(M) eps ~ 1e-11 itself
+    _n_vs_definition(ctaux, gb, oc, 0, 1e-10)
+    oc2 = OracleChain(w, seed=0, n_cap=2048)
+    oc2.set_log(4000)
+    oc2.run(4000)
+    acc_g, R_g = gb.decisions(0, 0, 4000)
+    acc_o, R_o = oc2.get_log(0, 4000)
+    assert np.array_equal(acc_g, acc_o)
+    np.testing.assert_allclose(R_g, R_o, rtol=R_TOL)
 
 
 def test_autotune_keeps_the_chain():
