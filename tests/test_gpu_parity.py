@@ -424,10 +424,10 @@ def test_strongly_coupled_chain_holds_fp64_without_refinement():
     # the LAPACK inverse that serves as reference carries cond(M) eps ~ 1e-11 itself
     _n_vs_definition(ctaux, gb, oc, 0, 1e-10)
     oc2 = OracleChain(w, seed=0, n_cap=2048)
-    oc2.set_log(4000)
-    oc2.run(4000)
-    acc_g, R_g = gb.decisions(0, 0, 4000)
-    acc_o, R_o = oc2.get_log(0, 4000)
+    oc2.set_log(64 * 60)
+    oc2.run(64 * 60)
+    acc_g, R_g = gb.decisions(0, 0, 64 * 60)
+    acc_o, R_o = oc2.get_log(0, 64 * 60)
     assert np.array_equal(acc_g, acc_o)
     np.testing.assert_allclose(R_g, R_o, rtol=R_TOL)
 
