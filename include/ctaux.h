@@ -262,6 +262,18 @@ size_t ctaux_build_N_workspace_bytes(const ctaux_model *model, int32_t n);
 int ctaux_build_N(const ctaux_model *model, const ctaux_vertex *config, int32_t n, int32_t sector, double *dev_out,
                   int32_t ld_out, void *dev_workspace, size_t ws_bytes, void *hip_stream);
 
+/* ctaux_build_N without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * ctaux_build_N; allocates nothing.  Its scratch is a fixed 24 MiB array in
+ * device memory that each GPU the library runs on holds until the process
+ * ends; n is limited to 1024 and the model's tables of one sector plus
+ * 8 n^2 bytes must fit in it (CTAUX_EINVAL otherwise).  Every call on a GPU
+ * uses that GPU's one array: calls that overlap on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller. */
+int ctaux_build_N_noalloc(const ctaux_model *model, const ctaux_vertex *config, int32_t n, int32_t sector,
+                          double *dev_out, int32_t ld_out, void *hip_stream);
+
 const char *ctaux_last_error(const ctaux_batch *b);
 void ctaux_destroy(ctaux_batch *b);
 

@@ -6,7 +6,7 @@
 // workspace for the duration of the call.
 #include <string.h>
 
-#include <vector>
+#include <mutex>
 
 #include "../../include/ctaux.h"
 #include "ctaux_device.h"
@@ -17,17 +17,17 @@ int model_error(const ctaux_model &m, int c, ctaux_batch *eb);
 int create_error(int code, const char *fmt, ...);
 
 // M[i][j] = delta_ij e^{V_i} - G0_{x_i x_j}(tau_i - tau_j) (e^{V_j} - 1) (Eq. Nmatrix),
-// row-major with leading dimension n.
-__global__ __launch_bounds__(256) void k_build_M(const ChainDesc *dp, int sec, int n, double *W) {
+// row-major with leading dimension n, from the caller's vertices as given.
+__global__ __launch_bounds__(256) void k_build_M(const ChainDesc *dp, const ctaux_vertex *vx, int sec, int n,
+                                                 double *W) {
   const ChainDesc &d = *dp;
-  const auto tau = gview(d.tau[0]);
-  const auto site = gview(d.site[0]), s0 = gview(d.s0[0]);
   const int64_t total = static_cast<int64_t>(n) * n;
   for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += gridDim.x * 256ll) {
     const int i = static_cast<int>(e / n), j = static_cast<int>(e - static_cast<int64_t>(i) * n);
-    const double evj = d.evd[sec][s0[j] + 2];
-    double v = -g0_interp(d, sec, site[i], site[j], tau[i] - tau[j]) * (evj - 1.0);
-    if (i == j) v += d.evd[sec][s0[i] + 2];
+    const ctaux_vertex vi = vx[i], vj = vx[j];
+    const double evj = d.evd[sec][vj.s + 2];
+    double v = -g0_interp(d, sec, vi.site, vj.site, vi.tau - vj.tau) * (evj - 1.0);
+    if (i == j) v += d.evd[sec][vi.s + 2];
     W[e] = v;
   }
 }
@@ -39,7 +39,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // Workspace of one call: descriptor, the sector's tables, the site map, the
 // configuration, the elimination item, M (n x n) and the elimination scratch.
 struct BuildLayout {
-  size_t desc, table, site_disp, tau, site, s0, item, W, scratch, total;
+  size_t desc, table, site_disp, verts, item, W, scratch, total;
 };
 
 BuildLayout build_layout(const ctaux_model &m, int n) {
@@ -53,9 +53,7 @@ BuildLayout build_layout(const ctaux_model &m, int n) {
   L.desc = take(sizeof(ChainDesc));
   L.table = take(sizeof(double) * static_cast<size_t>(m.n_disp) * m.n_tau);
   L.site_disp = take(sizeof(int32_t) * static_cast<size_t>(m.n_sites) * m.n_sites);
-  L.tau = take(sizeof(double) * n);
-  L.site = take(sizeof(int32_t) * n);
-  L.s0 = take(sizeof(int32_t) * n);
+  L.verts = take(sizeof(ctaux_vertex) * n);
   L.item = take(sizeof(InvItem));
   L.W = take(sizeof(double) * static_cast<size_t>(n) * n);
   L.scratch = take(sizeof(double) * inv_scratch_doubles(n));
@@ -81,7 +79,10 @@ int build_args_error(const ctaux_model *model, const ctaux_vertex *config, int32
 
 size_t build_workspace_bytes(const ctaux_model &m, int n) { return build_layout(m, n).total; }
 
-// The computation itself on a workspace of build_workspace_bytes(model, n) bytes.
+// The computation itself on a workspace of build_workspace_bytes(model, n) bytes
+// (device memory; every byte the kernels read is written first).  Allocates
+// nothing: the host values go to the device straight from the caller's arrays
+// and from this frame.
 int build_N_on(const ctaux_model *model, const ctaux_vertex *config, int32_t n, int32_t sector, double *dev_out,
                int32_t ld_out, char *ws, hipStream_t s) {
   const ctaux_model &m = *model;
@@ -101,16 +102,6 @@ int build_N_on(const ctaux_model *model, const ctaux_vertex *config, int32_t n, 
   d.n_disp = m.n_disp;
   d.g0[0] = d.g0[1] = reinterpret_cast<const double *>(ws + L.table);
   d.site_disp = reinterpret_cast<const int32_t *>(ws + L.site_disp);
-  d.tau[0] = reinterpret_cast<double *>(ws + L.tau);
-  d.site[0] = reinterpret_cast<int32_t *>(ws + L.site);
-  d.s0[0] = reinterpret_cast<int32_t *>(ws + L.s0);
-  std::vector<double> tau(n);
-  std::vector<int32_t> site(n), sp(n);
-  for (int i = 0; i < n; ++i) {
-    tau[i] = config[i].tau;
-    site[i] = config[i].site;
-    sp[i] = config[i].s;
-  }
   InvItem it;
   memset(&it, 0, sizeof it);
   double *W = reinterpret_cast<double *>(ws + L.W);
@@ -127,18 +118,16 @@ int build_N_on(const ctaux_model *model, const ctaux_vertex *config, int32_t n, 
                         hipMemcpyHostToDevice, s));
   BCHECK(hipMemcpyAsync(ws + L.site_disp, m.site_disp, sizeof(int32_t) * m.n_sites * m.n_sites,
                         hipMemcpyHostToDevice, s));
-  BCHECK(hipMemcpyAsync(ws + L.tau, tau.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-  BCHECK(hipMemcpyAsync(ws + L.site, site.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-  BCHECK(hipMemcpyAsync(ws + L.s0, sp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  BCHECK(hipMemcpyAsync(ws + L.verts, config, sizeof(ctaux_vertex) * n, hipMemcpyHostToDevice, s));
   BCHECK(hipMemcpyAsync(ws + L.item, &it, sizeof it, hipMemcpyHostToDevice, s));
-  BCHECK(hipStreamSynchronize(s));   // the host temporaries above are released on return
+  BCHECK(hipStreamSynchronize(s));   // d and it live in this frame
   int dev = 0, n_cu = 0;
   BCHECK(hipGetDevice(&dev));
   BCHECK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   const int64_t nn = static_cast<int64_t>(n) * n;
   const int g = static_cast<int>((nn + 255) / 256 < 2048 ? (nn + 255) / 256 : 2048);
-  hipLaunchKernelGGL(k_build_M, dim3(g), dim3(256), 0, s, reinterpret_cast<const ChainDesc *>(ws + L.desc), sector,
-                     n, W);
+  hipLaunchKernelGGL(k_build_M, dim3(g), dim3(256), 0, s, reinterpret_cast<const ChainDesc *>(ws + L.desc),
+                     reinterpret_cast<const ctaux_vertex *>(ws + L.verts), sector, n, W);
   launch_invert(s, d_item, 1, n, n_cu);
   launch_inv_gather(s, d_item, dev_out, ld_out, n);
   BCHECK(hipGetLastError());
@@ -149,6 +138,40 @@ int build_N_on(const ctaux_model *model, const ctaux_vertex *config, int32_t n, 
   if (flag) return create_error(CTAUX_ENUMERIC, "N^{-1} of the configuration is singular or not finite");
   return CTAUX_OK;
 }
+
+// ---- the allocation-free variant ----
+// Device scratch of ctaux_build_N_noalloc: a file-scope array that every device
+// the library runs on holds until the process ends.  Its host-side name is only
+// a stand-in; kernels get the device address that hipGetSymbolAddress returns.
+constexpr size_t kNoallocBytes = size_t{24} << 20;
+constexpr int kNoallocMaxOrder = 1024;
+static __device__ __align__(256) char scratch[kNoallocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device
+// with that device current.
+int scratch_ptr(char **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return create_error(CTAUX_EDEVICE, "no HIP device");
+  if (dev < 0 || dev >= kMaxDevices) return create_error(CTAUX_EDEVICE, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return create_error(CTAUX_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<char *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return CTAUX_OK;
+}
+
+}  // namespace
 
 }  // namespace ctaux
 
@@ -177,3 +200,22 @@ int ctaux_build_N(const ctaux_model *model, const ctaux_vertex *config, int32_t 
 }
 
 }  // extern "C"
+
+extern "C" int ctaux_build_N_noalloc(const ctaux_model *model, const ctaux_vertex *config, int32_t n,
+                                     int32_t sector, double *dev_out, int32_t ld_out, void *hip_stream) {
+  int rc = build_args_error(model, config, n, sector);
+  if (rc) return rc;
+  if (n == 0) return CTAUX_OK;
+  if (!dev_out || ld_out < n) return create_error(CTAUX_EINVAL, "need an output and ld_out >= n");
+  if (n > kNoallocMaxOrder)
+    return create_error(CTAUX_EINVAL, "n = %d exceeds %d, the largest order of the allocation-free variant", n,
+                        kNoallocMaxOrder);
+  const size_t need = build_workspace_bytes(*model, n);
+  if (need > kNoallocBytes)
+    return create_error(CTAUX_EINVAL, "this model and order need %zu bytes of scratch; the allocation-free "
+                        "variant has %zu (tables too large)", need, kNoallocBytes);
+  char *ws = nullptr;
+  rc = scratch_ptr(&ws);
+  if (rc) return rc;
+  return build_N_on(model, config, n, sector, dev_out, ld_out, ws, static_cast<hipStream_t>(hip_stream));
+}

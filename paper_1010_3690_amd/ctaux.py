@@ -29,7 +29,7 @@ EXPORTED = [
     "ctaux_get_obs", "ctaux_reset_obs", "ctaux_get_stats", "ctaux_get_config", "ctaux_get_N",
     "ctaux_get_decisions", "ctaux_set_timing", "ctaux_set_timing_every", "ctaux_get_timing",
     "ctaux_checkpoint", "ctaux_restore", "ctaux_recompute_from_scratch",
-    "ctaux_build_N_workspace_bytes", "ctaux_build_N",
+    "ctaux_build_N_workspace_bytes", "ctaux_build_N", "ctaux_build_N_noalloc",
     "ctaux_last_error", "ctaux_destroy",
 ]
 
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
     lib.ctaux_build_N_workspace_bytes.restype = C.c_size_t
     lib.ctaux_build_N_workspace_bytes.argtypes = [vp, i32]
     lib.ctaux_build_N.argtypes = [vp, vp, i32, i32, vp, i32, vp, C.c_size_t, vp]
+    lib.ctaux_build_N_noalloc.argtypes = [vp, vp, i32, i32, vp, i32, vp]
     lib.ctaux_obs_len.restype = i32
     lib.ctaux_obs_len.argtypes = [vp]
     lib.ctaux_get_obs.argtypes = [vp, i32, vp, i32]
@@ -316,6 +317,30 @@ def build_N(w, tau, site, s, sector: int, device: str = "cuda:0") -> np.ndarray:
         stream = torch.cuda.current_stream(dev)
         rc = lib.ctaux_build_N(C.byref(model), verts, n, sector, C.c_void_p(out.data_ptr()), max(n, 1),
                                C.c_void_p(ws.data_ptr()), nbytes, C.c_void_p(stream.cuda_stream))
+    if rc != 0:
+        raise CtauxError(rc, lib.ctaux_last_error(None).decode())
+    return out[:n, :n].cpu().numpy()
+
+
+def build_N_noalloc(w, tau, site, s, sector: int, out=None, device: str = "cuda:0"):
+    """As build_N, through the allocation-free entry point ctaux_build_N_noalloc.
+    out: an optional float64 device tensor of at least n x n (row-major); the
+    result is written there and returned as a numpy copy."""
+    import torch
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("build_N_noalloc needs a GPU; there is no CPU path")
+    model, keep = _model_of(w)
+    n = len(tau)
+    verts = _vertices(tau, site, s)
+    dev = torch.device(device)
+    with torch.cuda.device(dev):
+        if out is None:
+            out = torch.empty((max(n, 1), max(n, 1)), dtype=torch.float64, device=dev)
+        ld = out.shape[1]
+        stream = torch.cuda.current_stream(dev)
+        rc = lib.ctaux_build_N_noalloc(C.byref(model), verts, n, sector, C.c_void_p(out.data_ptr()), ld,
+                                       C.c_void_p(stream.cuda_stream))
     if rc != 0:
         raise CtauxError(rc, lib.ctaux_last_error(None).decode())
     return out[:n, :n].cpu().numpy()
