@@ -1,24 +1,33 @@
 #!/usr/bin/env python
 """Throughput of the CT-AUX submatrix path on one MI355X.
 
-Workload (step = one block: k_max = 64 proposals, the Gamma inner loop, the
-rank-k update of N in both spin sectors, the measurement, and every 64 blocks
-the FP64 refinement of N): 2D Hubbard DCA cluster 4x4 (Nc = 16), t = 1, U = 8,
-beta = 8, <n> = 0.9, cluster G0(tau) from the coarse-grained square-lattice
-dispersion on 8192 points, one chain, FP64 plain submatrix, K = 600 so that
-the mean order is ~1000.  Inputs are synthetic and resident in HBM before the
-timed region.
+Headline workload (step = one block: k_max = 64 proposals, the Gamma inner
+loop, the rank-k update of N in both spin sectors, the measurement, and the
+FP64 refinement of N on its schedule): 2D Hubbard DCA cluster 4x4 (Nc = 16),
+t = 1, U = 8, beta = 8, <n> = 0.9, cluster G0(tau) from the coarse-grained
+square-lattice dispersion on 8192 points, one chain, FP64 plain submatrix,
+K = 600 so that the mean order is ~1000.  The chain is thermalised until its
+mean order is stable (whatever --warmup asks for beyond that), then exactly
+--steps blocks are timed.  Inputs are synthetic and resident in HBM before
+the timed region.
 
 Prints one JSON line: vertex updates/s (proposals processed, accepted or not),
 the rank-k TFLOP/s, the roofline of the dominant kernel (per-launch device
-time from HIP events on the library's stream over the timed region), and the
-CPU oracle timed on a bounded sample of the same workload.
-
-Extra legs (--legs): "mixed" runs the same chain with FP32 storage and the FP32
-MFMA rank-k update; "batched" runs 512 independent chains of mixed clusters
-(Nc in {4, 8, 16, 32}, beta in [4, 12], U in [4, 8]) in FP64; "batched32" the
-same with FP32 storage, which stops with an error when a chain's refinement
-drift shows that FP32 cannot hold its N.
+time from HIP events on the library's stream over the timed region), the CPU
+oracle timed on a bounded sample of the same workload, and further forms:
+  mixed       the same chain with N in FP32 (FP32 MFMA rank-k update), at the
+              default drift target and at an N error target of 1e-6;
+  cfg2x128    128 independent chains of the headline workload, FP64 and FP32
+              storage (mixed/batched vs plain on one workload);
+  batched     512 chains of mixed clusters (Nc in {4, 8, 16, 32}, beta in
+              [4, 12], U in [4, 8], K = 1), FP64, k and tile autotuned;
+  config3     6x6 cluster, beta = 10, order ~3000, FP32 storage with FP64
+              refresh every <= 64 blocks, and the same in FP64;
+  config5     3D Nc = 100 cluster, beta = 6, order ~5000, 8 chains, FP32
+              storage with FP64 refresh every <= 32 blocks.
+Each form reports its N error: the largest refinement drift of the run
+(||N - N_refined|| / ||N_refined|| before each refinement) and the drift of a
+refinement taken at the end of the timed region.
 """
 
 from __future__ import annotations
@@ -26,6 +35,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -35,8 +45,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
+N_CU = 256
 
 METRIC = "vertex updates/s + rank-k TFLOP/s, mixed/batched vs plain FP64, same GPU"
+ALL_LEGS = "plain,mixed,cfg2x128,batched,config3,config5"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cfg2_workload():
@@ -44,19 +60,42 @@ def cfg2_workload():
     return dca_square(L=4, beta=8.0, U=8.0, K=600.0, density=0.9, n_tau=8192, t=1.0, n_fine=64)
 
 
-def _opts(ctaux, precision, n_cap=2048, k=64):
-    return ctaux.Options(k_max=k, k_cap=k, p_flip=0.2, recompute_every=64, precision=precision,
-                         meas_every=k, n_therm=0, n_tau_out=16, n_cap=n_cap, seed=0)
+def _opts(ctaux, precision, n_cap=2048, k=64, **kw):
+    o = dict(k_max=k, k_cap=min(k, 64), p_flip=0.2, recompute_every=64, precision=precision,
+             meas_every=k, n_therm=0, n_tau_out=16, n_cap=n_cap, seed=0)
+    o.update(kw)
+    return ctaux.Options(**o)
 
 
 STAT_KEYS = ("proposals", "accepted", "blocks", "sum_ka", "rankk_flops", "rankk_bytes", "sum_order",
              "prep_flops", "prep_bytes", "meas_flops", "meas_bytes")
 
 
+def _stats(gb, n_chains):
+    return [gb.stats(c) for c in range(n_chains)]
+
+
 def _delta(gb, s0, n_chains):
-    s1 = [gb.stats(c) for c in range(n_chains)]
+    s1 = _stats(gb, n_chains)
     d = {key: sum(s1[c][key] - s0[c][key] for c in range(n_chains)) for key in STAT_KEYS}
     return d, s1
+
+
+def thermalise(gb, k, n_chains, min_blocks, chunk, tol=0.02, max_chunks=40):
+    """Runs min_blocks blocks, then chunks of `chunk` blocks until the mean order
+    over a chunk differs from the previous chunk's by less than tol (relative)."""
+    gb.run(min_blocks * k)
+    prev, total, mean = None, min_blocks, 0.0
+    for _ in range(max_chunks):
+        s0 = _stats(gb, n_chains)
+        gb.run(chunk * k)
+        total += chunk
+        d, _ = _delta(gb, s0, n_chains)
+        mean = d["sum_order"] / max(d["blocks"], 1)
+        if prev is not None and abs(mean - prev) <= tol * prev:
+            break
+        prev = mean
+    return {"blocks": total, "mean_order": mean}
 
 
 def timed_run(gb, steps, k, n_chains=1, profile_blocks=40):
@@ -64,7 +103,7 @@ def timed_run(gb, steps, k, n_chains=1, profile_blocks=40):
     then `steps` blocks with events around the dominant kernel only (each event
     pair adds device time), timed on the host between synchronisations."""
     import torch
-    s0 = [gb.stats(c) for c in range(n_chains)]
+    s0 = _stats(gb, n_chains)
     gb.set_timing(True)
     gb.run(profile_blocks * k)
     prof = gb.timing()
@@ -74,7 +113,7 @@ def timed_run(gb, steps, k, n_chains=1, profile_blocks=40):
     dominant = max((n for n in prof if n != "refine"), key=lambda name: prof[name][0])
     # one launch in four carries the events: their device time stays out of the rest
     gb.set_timing(False, kernels=[dominant], every=4)
-    s0 = [gb.stats(c) for c in range(n_chains)]
+    s0 = _stats(gb, n_chains)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gb.run(steps * k)
@@ -89,17 +128,18 @@ def timed_run(gb, steps, k, n_chains=1, profile_blocks=40):
     d["profile"] = {"blocks": dprof["blocks"], "timing": prof, "stats": dprof}
     d["order_now"] = [s1[c]["order"] for c in range(n_chains)]
     d["max_drift"] = max(s1[c]["max_drift"] for c in range(n_chains))
+    d["n_chains"] = n_chains
     return d
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel's source has changed since the counters
-    were taken (the summary records the source's SHA-256)."""
+def measured_traffic(kernel, n_chains):
+    """HBM bytes per launch of `kernel` on the headline chain from the committed
+    rocprofv3 counter summary, or None when the kernel's source has changed since
+    the counters were taken (the summary records the source's SHA-256)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_bytes_per_launch.txt")
     src = {"propose": "k_propose.hip", "rankk": "k_update.hip"}.get(kernel)
-    if src is None or not os.path.exists(path):
+    if n_chains != 1 or src is None or not os.path.exists(path):
         return None
     with open(os.path.join(ROOT, "paper_1010_3690_amd", "csrc", src), "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
@@ -110,17 +150,17 @@ def measured_traffic(kernel):
     return None
 
 
-def roofline(d, precision):
+def roofline(d):
     """Roofline of the dominant kernel of the timed region: its algorithmic work
     per launch over its average launch duration (HIP events on the library's
-    stream around each launch of that kernel)."""
+    stream around each launch of that kernel), against the chip's published peak."""
     name = d["dominant"]
     ms, timed = d["timing"][name]
     if timed == 0 or ms <= 0.0:
         return {"kernel": name, "error": "no timed launch"}
     avg_s = ms / 1e3 / timed
-    # one launch of each per-block kernel per block of the batch
-    launches = d["blocks"] / d.get("n_chains", 1)
+    n_chains = d.get("n_chains", 1)
+    launches = d["blocks"] / n_chains   # one launch of each per-block kernel serves every chain
     prof = d["profile"]["timing"]
     out = {"kernel": name, "share": prof[name][0] / sum(v[0] for v in prof.values()),
            "launches": launches, "timed_launches": timed, "avg_launch_us": avg_s * 1e6}
@@ -133,25 +173,43 @@ def roofline(d, precision):
         # The proposal loop is one workgroup per chain running k dependent
         # proposals; its work per launch is the O(k_a^2) Gamma^{-1} arithmetic
         # (per proposal and sector two matrix-vector products with Gamma^{-1},
-        # 4 k_a^2 flops, and for an accepted proposal the growth, 2 k_a^2),
-        # reported against the FP64 vector peak of the compute units it
-        # occupies (one per chain).
+        # 4 k_a^2 flops, and for an accepted proposal the growth, 2 k_a^2).  It is
+        # latency-bound: the figure that matters is the time per proposal.
         ka = d["sum_ka"] / max(d["blocks"], 1)
         k = d["proposals"] / max(d["blocks"], 1)
         acc_frac = ka / max(k, 1)
         flops_launch = d["proposals"] / max(launches, 1) * 2 * (4 * ka * ka / 4 + acc_frac * 2 * ka * ka / 4)
         achieved = flops_launch / avg_s / 1e12
-        n_chains = d.get("n_chains", 1)
-        peak = FP64_PEAK_TFS * min(n_chains, 256) / 256.0
-        out.update({"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                    "frac": achieved / peak, "traffic": measured_traffic(name) if n_chains == 1 else None})
+        per_chain_props = d["proposals"] / max(launches, 1) / n_chains
+        cu_peak = FP64_PEAK_TFS * min(n_chains, N_CU) / N_CU
+        out.update({"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                    "frac": achieved / FP64_PEAK_TFS, "traffic": measured_traffic(name, n_chains),
+                    "frac_of_occupied_cus": achieved / cu_peak,
+                    "us_per_proposal": avg_s * 1e6 / max(per_chain_props, 1e-9),
+                    "proposals_per_s_per_chain": per_chain_props / avg_s})
     return out
 
 
-def cpu_baseline(w, config, budget_s=15.0):
+def host_info():
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu": model, "nproc": avail, "cpu_count": os.cpu_count()}
+
+
+def cpu_baseline(w, config, therm_blocks, budget_s=15.0):
     """The oracle (rank-1 CT-AUX, one core) on a bounded sample of the workload:
-    it starts from the GPU chain's thermalised configuration and runs
-    proposals until about budget_s seconds have elapsed."""
+    it starts from the configuration the GPU chain reached after thermalisation
+    and runs proposals until about budget_s seconds have elapsed."""
     from oracle import OracleChain
     ids, tau, site, s = config
     oc = OracleChain(w, seed=12345, meas_every=64, n_tau_out=16, n_cap=4096)
@@ -163,46 +221,12 @@ def cpu_baseline(w, config, budget_s=15.0):
         oc.run(16)
         done += 16
     el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "vertex updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} proposals of the same chain from a thermalised order-{len(ids)} "
-                      f"configuration, {el:.1f} s on one host core"}
-
-
-def leg_plain(args, precision):
-    import torch
-    from paper_1010_3690_amd import ctaux
-    w = cfg2_workload()
-    gb = ctaux.CtauxBatch([w], _opts(ctaux, precision))
-    gb.run(args.warmup * 64)
-    torch.cuda.synchronize()
-    d = timed_run(gb, args.steps, 64)
-    return w, gb, d
-
-
-def leg_batched(args, precision):
-    """512 chains; with --autotune the block length and rank-k tile come from
-    paper_1010_3690_amd.autotune (trials continue the same thermalised chains)."""
-    import torch
-    from ctaux_inputs import batched_mix
-    from paper_1010_3690_amd import ctaux
-    ws = batched_mix(n_chains=args.batch_chains, seed=0, n_tau=2048, n_fine=16)
-    opts = ctaux.Options(k_max=64, k_cap=64, recompute_every=64, precision=precision, meas_every=64,
-                         n_tau_out=8, n_cap=2048, seed=0)
-    tuning = None
-    if args.autotune:
-        from paper_1010_3690_amd.autotune import autotune
-        print("[bench] autotuning the batched form", file=sys.stderr, flush=True)
-        opts, tuning = autotune(ws, opts, warmup_proposals=args.batch_warmup * 64, trial_proposals=32 * 64)
-        print(f"[bench] autotuned: k_max={opts.k_max} k_cap={opts.k_cap} rankk_tile={opts.rankk_tile}",
-              file=sys.stderr, flush=True)
-    gb = ctaux.CtauxBatch(ws, opts)
-    gb.run(args.batch_warmup * 64)
-    torch.cuda.synchronize()
-    d = timed_run(gb, args.batch_steps, 64, n_chains=len(ws), profile_blocks=4)
-    d["n_chains"] = len(ws)
-    d["options"] = {"k_max": opts.k_max, "k_cap": opts.k_cap, "rankk_tile": opts.rankk_tile}
-    d["tuning"] = tuning
-    return d
+    out = {"value": done / el, "unit": "vertex updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"{done} proposals of the headline chain from the order-{len(ids)} configuration the GPU "
+                     f"chain reached after {therm_blocks} blocks of thermalisation, {el:.1f} s on one host core "
+                     f"(the oracle is single-threaded)"}
+    out.update({"host_" + k: v for k, v in host_info().items()})
+    return out
 
 
 def summary(d):
@@ -216,26 +240,77 @@ def summary(d):
         "rankk_tflops": (prof["stats"]["rankk_flops"] / (rk[0] / 1e3) / 1e12) if rk and rk[0] > 0 else None,
         "mean_order": d["sum_order"] / max(d["blocks"], 1),
         "mean_ka": d["sum_ka"] / max(d["blocks"], 1),
-        "ms_per_block": d["seconds"] * 1e3 / max(d["blocks"], 1),
-        "kernel_us_per_block": {k: round(v[0] * 1e3 / pb, 2) for k, v in prof["timing"].items()},
+        "ms_per_block": d["seconds"] * 1e3 / max(d["blocks"] / d.get("n_chains", 1), 1),
+        "kernel_us_per_block": {k: round(v[0] * 1e3 / max(pb / d.get("n_chains", 1), 1), 2)
+                                for k, v in prof["timing"].items()},
     }
+
+
+def form(gb, d, therm, extra=None):
+    """Summary of a timed form plus its N error: the largest refinement drift of
+    the run and the drift of one refinement at the end."""
+    s = summary(d)
+    out = {k: s[k] for k in ("updates_per_s", "accepted_per_s", "rankk_tflops", "mean_order", "mean_ka",
+                             "ms_per_block", "kernel_us_per_block")}
+    out["n_chains"] = d.get("n_chains", 1)
+    out["thermalisation_blocks"] = therm["blocks"]
+    out["max_refinement_drift"] = d["max_drift"]
+    out["n_error_at_end"] = gb.recompute()
+    out["roofline"] = roofline(d)
+    if extra:
+        out.update(extra)
+    return out
+
+
+def single_chain(ctaux, w, precision, steps, warmup, k=64, n_cap=2048, chunk=50, **kw):
+    gb = ctaux.CtauxBatch([w], _opts(ctaux, precision, n_cap=n_cap, k=k, **kw))
+    therm = thermalise(gb, k, 1, max(warmup, 100), chunk)
+    d = timed_run(gb, steps, k)
+    return gb, d, therm
+
+
+def many_chains(ctaux, ws, opts, steps, min_blocks, chunk, profile_blocks=4):
+    gb = ctaux.CtauxBatch(ws, opts)
+    therm = thermalise(gb, opts.k_max, len(ws), min_blocks, chunk)
+    d = timed_run(gb, steps, opts.k_max, n_chains=len(ws), profile_blocks=profile_blocks)
+    return gb, d, therm
+
+
+def leg_batched(ctaux, args):
+    """512 chains of the config-4 mix in FP64; k and the rank-k tile from the
+    autotuner (its trials continue the same thermalised chains)."""
+    from ctaux_inputs import batched_mix
+    ws = batched_mix(n_chains=args.batch_chains, seed=0, n_tau=2048, n_fine=16)
+    opts = ctaux.Options(k_max=64, k_cap=64, recompute_every=64, precision=ctaux.CTAUX_FP64, meas_every=64,
+                         n_tau_out=8, n_cap=2048, seed=0)
+    tuning = None
+    if args.autotune:
+        from paper_1010_3690_amd.autotune import autotune
+        log("autotuning the batched form")
+        opts, tuning = autotune(ws, opts, warmup_proposals=60 * 64, trial_proposals=32 * 64)
+        log(f"autotuned: k_max={opts.k_max} k_cap={opts.k_cap} rankk_tile={opts.rankk_tile}")
+    gb, d, therm = many_chains(ctaux, ws, opts, args.batch_steps, 60, 20)
+    extra = {"options": {"k_max": opts.k_max, "k_cap": opts.k_cap, "rankk_tile": opts.rankk_tile}}
+    if tuning:
+        extra["autotune"] = [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in tuning]
+    out = form(gb, d, therm, extra)
+    gb.close()
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--legs", default="plain,mixed,batched",
-                    help="comma list of plain (FP64, one chain), mixed (FP32 storage, one chain), "
-                         "batched (FP64, many chains), batched32 (FP32 storage, many chains)")
+    ap.add_argument("--steps", type=int, default=400, help="timed blocks of the headline chain")
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="least blocks before timing; thermalisation continues until the mean order is stable")
+    ap.add_argument("--legs", default=ALL_LEGS, help=f"comma list of extra forms: {ALL_LEGS}")
     ap.add_argument("--batch-chains", type=int, default=512)
-    ap.add_argument("--batch-steps", type=int, default=64)
-    ap.add_argument("--batch-warmup", type=int, default=60)
+    ap.add_argument("--batch-steps", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=True,
-                    help="choose k and the rank-k tile of the batched legs with the autotuner")
+                    help="choose k and the rank-k tile of the batched leg with the autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 10 device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -258,11 +333,12 @@ def main():
     from paper_1010_3690_amd import ctaux
 
     legs = [x.strip() for x in args.legs.split(",") if x.strip()]
-    print(f"[bench] plain FP64 leg: warmup {args.warmup} blocks, timed {args.steps} blocks", file=sys.stderr,
-          flush=True)
-    w, gb, d = leg_plain(args, ctaux.CTAUX_FP64)
+    log(f"plain FP64 leg: thermalise (>= {max(args.warmup, 100)} blocks), time {args.steps} blocks")
+    w = cfg2_workload()
+    gb, d, therm = single_chain(ctaux, w, ctaux.CTAUX_FP64, args.steps, args.warmup)
     s = summary(d)
-    roof = roofline(d, ctaux.CTAUX_FP64)
+    roof = roofline(d)
+    plain = form(gb, d, therm)
     out = {
         "metric": METRIC,
         "value": s["updates_per_s"],
@@ -279,46 +355,55 @@ def main():
         "config": {"workload": "2D Hubbard DCA 4x4 cluster (Nc=16), t=1, U=8, beta=8, <n>=0.9, "
                                "coarse-grained G0 on 8192 tau points, K=600, one chain, FP64 plain "
                                "submatrix, k=64, step = one block of 64 proposals",
-                   "k": 64, "mean_order": s["mean_order"], "mean_accepted_per_block": s["mean_ka"]},
+                   "k": 64, "mean_order": s["mean_order"], "mean_accepted_per_block": s["mean_ka"],
+                   "thermalisation_blocks": therm["blocks"]},
         "rankk_tflops": s["rankk_tflops"],
         "accepted_per_s": s["accepted_per_s"],
         "kernel_us_per_block": s["kernel_us_per_block"],
         "roofline": roof,
     }
-    forms = {"plain_fp64": {k: s[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}}
-    forms["plain_fp64"]["max_refinement_drift"] = d["max_drift"]
+    forms = {"plain_fp64": plain}
+    config0 = gb.config(0)
+    gb.close()
     if "mixed" in legs:
-        print("[bench] mixed leg: FP32 storage, same chain", file=sys.stderr, flush=True)
-        _, gbm, dm = leg_plain(args, ctaux.CTAUX_FP32)
-        sm = summary(dm)
-        forms["mixed_fp32"] = {k: sm[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}
-        forms["mixed_fp32"]["max_refinement_drift"] = dm["max_drift"]
-        forms["mixed_fp32"]["kernel_us_per_block"] = sm["kernel_us_per_block"]
-        gbm.close()
-    for leg, name, prec in (("batched", "batched_fp64", ctaux.CTAUX_FP64),
-                            ("batched32", "batched_fp32", ctaux.CTAUX_FP32)):
-        if leg not in legs:
-            continue
-        print(f"[bench] {name} leg: {args.batch_chains} chains", file=sys.stderr, flush=True)
-        try:
-            db = leg_batched(args, prec)
-        except ctaux.CtauxError as e:   # FP32 storage cannot hold every chain of the mix
-            forms[name] = {"error": str(e)}
-            continue
-        sb = summary(db)
-        forms[name] = {k: sb[k] for k in ("updates_per_s", "rankk_tflops", "mean_order", "mean_ka")}
-        forms[name]["n_chains"] = args.batch_chains
-        forms[name]["max_refinement_drift"] = db["max_drift"]
-        forms[name]["roofline"] = roofline(db, prec)
-        forms[name]["kernel_us_per_block"] = sb["kernel_us_per_block"]
-        forms[name]["options"] = db["options"]
-        if db["tuning"]:
-            forms[name]["autotune"] = [{k: (round(v, 1) if isinstance(v, float) else v) for k, v in r.items()}
-                                       for r in db["tuning"]]
+        log("mixed leg: FP32 storage, same chain (default drift target, then 1e-6)")
+        g2, d2, t2 = single_chain(ctaux, w, ctaux.CTAUX_FP32, args.steps, args.warmup)
+        forms["mixed_fp32"] = form(g2, d2, t2)
+        g2.close()
+        g2, d2, t2 = single_chain(ctaux, w, ctaux.CTAUX_FP32, args.steps, args.warmup, drift_target=1e-6)
+        forms["mixed_fp32_target_1e-6"] = form(g2, d2, t2, {"drift_target": 1e-6})
+        g2.close()
+    if "cfg2x128" in legs:
+        for name, prec in (("cfg2x128_fp64", ctaux.CTAUX_FP64), ("cfg2x128_fp32", ctaux.CTAUX_FP32)):
+            log(f"{name}: 128 chains of the headline workload")
+            opts = _opts(ctaux, prec)
+            g2, d2, t2 = many_chains(ctaux, [w] * 128, opts, 32, 150, 20)
+            forms[name] = form(g2, d2, t2)
+            g2.close()
+    if "batched" in legs:
+        log(f"batched_fp64 leg: {args.batch_chains} chains")
+        forms["batched_fp64"] = leg_batched(ctaux, args)
+    if "config3" in legs:
+        from ctaux_inputs import dca_square
+        w3 = dca_square(L=6, beta=10.0, U=8.0, K=1800.0, density=0.9, n_tau=8192)
+        for name, prec in (("config3_fp32", ctaux.CTAUX_FP32), ("config3_fp64", ctaux.CTAUX_FP64)):
+            log(f"{name}: 6x6 cluster, order ~3000")
+            g3, d3, t3 = single_chain(ctaux, w3, prec, 100, 200, k=128, n_cap=4096, chunk=40,
+                                      n_tau_out=8)
+            forms[name] = form(g3, d3, t3)
+            g3.close()
+    if "config5" in legs:
+        from ctaux_inputs import dca_cubic
+        w5 = dca_cubic(beta=6.0, U=8.0, K=3500.0, n_tau=8192)
+        log("config5_fp32: 3D Nc = 100, 8 chains, order ~5000")
+        opts = _opts(ctaux, ctaux.CTAUX_FP32, n_cap=8192, k=128, recompute_every=32, n_tau_out=8)
+        g5, d5, t5 = many_chains(ctaux, [w5] * 8, opts, 16, 200, 20)
+        forms["config5_fp32"] = form(g5, d5, t5)
+        g5.close()
     out["forms"] = forms
     if not args.no_cpu_baseline:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, gb.config(0), args.cpu_budget)
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(w, config0, therm["blocks"], args.cpu_budget)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))

@@ -83,8 +83,8 @@ typedef struct {
     double p_flip;            /* P(flip); P(insert) = P(remove) = (1 - p_flip)/2              */
     int32_t recompute_every;  /* most blocks between FP64 refinements of N (0 = never).  Each
                                  chain has its own interval, a power of two between 1 and the
-                                 largest power of two <= recompute_every, starting at
-                                 min(8, that bound) and counted in blocks of the batch (chain c
+                                 largest power of two <= recompute_every, starting at 1
+                                 and counted in blocks of the batch (chain c
                                  is refined after block b when b is a multiple of its
                                  interval).  After each refinement of a chain its interval is
                                  quartered when the drift exceeded drift_target and doubled

@@ -66,7 +66,7 @@ struct ctaux_batch {
   // Adaptive refinement schedule, per chain: chain c is refined after every
   // block whose count is a multiple of interval[c], a power of two in
   // [1, max_interval] (max_interval = the largest power of two <= recompute_every),
-  // starting at min(8, max_interval).  Powers of two keep the refinements of
+  // starting at 1.  Powers of two keep the refinements of
   // all chains aligned, so that a refinement (which synchronises the host with
   // the device) happens at most every min_c interval[c] blocks.  After each
   // refinement interval[c] is quartered when the drift of chain c exceeded the
@@ -616,7 +616,7 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
   h->recompute_mode = opts->recompute_mode;
   h->max_interval = 1;
   while (2 * h->max_interval <= opts->recompute_every) h->max_interval *= 2;
-  h->interval.assign(n_chains, h->max_interval < 8 ? h->max_interval : 8);
+  h->interval.assign(n_chains, 1);
   h->drift_target = opts->drift_target > 0.0 ? opts->drift_target : (opts->precision == CTAUX_FP64 ? 1e-10 : 1e-4);
   h->log_cap = opts->log_cap;
   layout(models, n_chains, opts, static_cast<char *>(dev_workspace), &b, &h->desc);
