@@ -30,6 +30,7 @@ from .workloads import (  # noqa: F401
     anderson_semicircle,
     hubbard_atom,
     hubbard_dimer,
+    hubbard_plaquette,
     anderson_bath,
     dca_square,
     dca_cubic,

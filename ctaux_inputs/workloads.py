@@ -77,6 +77,22 @@ def hubbard_dimer(beta=2.0, U=2.0, K=1.0, t=1.0, mu_tilde=0.0, n_tau=2048) -> Wo
                     {"h1": h1, "t": t, "mu_tilde": mu_tilde})
 
 
+def hubbard_plaquette(beta=8.0, U=6.0, K=1.0, t=1.0, tp=0.4, mu_tilde=-1.2, n_tau=2048) -> Workload:
+    """Isolated 2x2 Hubbard plaquette with nearest (t) and diagonal (tp)
+    hopping; every site pair has its own table.  Away from half filling with
+    tp != 0 the auxiliary-field weights take both signs."""
+    h1 = np.zeros((4, 4))
+    for a, b in ((0, 1), (1, 3), (3, 2), (2, 0)):
+        h1[a, b] = h1[b, a] = -t
+    for a, b in ((0, 3), (1, 2)):
+        h1[a, b] = h1[b, a] = -tp
+    h1 -= mu_tilde * np.eye(4)
+    g = finite_system_g0(h1, beta, n_tau)
+    tables, disp = _finite_tables(g)
+    return Workload("hubbard_plaquette", beta, U, K, 4, disp, tables, tables.copy(),
+                    {"h1": h1, "t": t, "tp": tp, "mu_tilde": mu_tilde})
+
+
 def anderson_bath(beta=4.0, U=3.0, K=1.0, v=0.7, eps_bath=(-1.0, 1.0), mu_tilde=0.0,
                   n_tau=2048) -> Workload:
     """Impurity (orbital 0) hybridised with a few bath levels; Nc = 1."""
@@ -149,6 +165,7 @@ def named_workload(name: str, **kw) -> Workload:
         "anderson_semicircle": anderson_semicircle,
         "hubbard_atom": hubbard_atom,
         "hubbard_dimer": hubbard_dimer,
+        "hubbard_plaquette": hubbard_plaquette,
         "anderson_bath": anderson_bath,
         "dca_square": dca_square,
         "dca_cubic": dca_cubic,

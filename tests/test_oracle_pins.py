@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from ctaux_inputs import (anderson_bath, anderson_semicircle, dca_square, fermi_weight,
-                          hubbard_atom, hubbard_dimer)
+                          hubbard_atom, hubbard_dimer, hubbard_plaquette)
 from ctaux_inputs.workloads import Workload
 from ed import ED, Fock, greens_with_vertices, trace_ratio
 from oracle import OracleChain, draws, gamma_of, philox4x32_10
@@ -267,6 +267,71 @@ def test_walk_against_exact_diagonalisation(make):
                     exact.append(ed.greens(x, y, sec, tj))
     ok, z = _family_ok(means, errs, exact)
     assert ok, z
+
+
+def test_sign_weighted_walk_against_exact_diagonalisation():
+    """A doped 2x2 plaquette with diagonal hopping (beta = 8, U = 6, mu~ = -1.2,
+    t' = 0.4) has <sign> ~ 0.5: the sign flips on accepted negative ratios and
+    the sign-weighted estimators <sign X> / <sign> must give the exact D, n,
+    <k> = K - beta <V> and G(tau) (the bookkeeping behind them is pinned
+    exactly by the next test)."""
+    w = hubbard_plaquette()
+    nto = 4
+    ed = ED(w.meta["h1"], w.U, w.beta, range(4))
+    B = _bins(lambda sd: OracleChain(w, seed=sd, meas_every=4, n_tau_out=nto), w, 4, 8, 15000, 4000, nto)
+    m, e = _mean_err([b["sign"] for b in B])
+    assert m < 0.8
+    kex = w.K - w.beta * ed.potential()
+    m, e = _mean_err([b["order"] for b in B])
+    assert _within(m, e, kex), (m, e, kex)
+    m, e = _mean_err([b["D"] for b in B])
+    assert _within(m, e, np.mean([ed.double_occ(x) for x in range(4)]))
+    m, e = _mean_err([0.5 * (b["n_up"] + b["n_dn"]) for b in B])
+    assert _within(m, e, np.mean([ed.density(x, 0) for x in range(4)]))
+    G, Ge = _mean_err([b["G"] for b in B])
+    means, errs, exact = [], [], []
+    for x in range(4):
+        for y in range(4):
+            d = w.site_disp[x * 4 + y]
+            for j in range(nto):
+                tj = (j + 0.5) * w.beta / nto
+                means.append(G[0, d, j])
+                errs.append(Ge[0, d, j])
+                exact.append(ed.greens(x, y, 0, tj))
+    ok, z = _family_ok(means, errs, exact)
+    assert ok, z
+
+
+def test_sign_bookkeeping_exact():
+    """On the sign-problem plaquette: at every measurement the chain's running
+    sign (flipped on each accepted negative ratio) equals
+    sign(det N_up^{-1} det N_dn^{-1}) of its configuration, from numpy
+    determinants of the definition; and the accumulators equal sums of the
+    order, the density and the double occupancy (from the estimator pinned by the
+    Fock trace) weighted by that independent sign."""
+    w = hubbard_plaquette()
+    M = 8
+    c = OracleChain(w, seed=3, meas_every=M, n_tau_out=2)
+    c.run(3000)
+    c.reset_obs()
+    acc = np.zeros(8)
+    seen = set()
+    for _ in range(250):
+        c.run(M)
+        ids, tau, site, s = c.config()
+        sg = 1.0
+        for sec in (0, 1):
+            if len(tau):
+                sg *= np.linalg.slogdet(c.M_of(sec, tau, site, s))[0]
+        assert sg == c.sign
+        seen.add(sg)
+        n = len(tau)
+        dens = np.array([[1.0 - c.estimate_G(sec, x, x, 0.0) for x in range(4)] for sec in (0, 1)])
+        acc += sg * np.array([1.0 / sg, 1.0, n, n * n, n == 0, np.mean(dens[0] * dens[1]),
+                              dens[0].mean(), dens[1].mean()])
+    assert seen == {1.0, -1.0}
+    o = c.obs()[:8]
+    np.testing.assert_allclose(o, acc, rtol=1e-10, atol=1e-12)
 
 
 def test_hubbard_atom_closed_forms():
