@@ -27,6 +27,8 @@ class Workload:
     g0_up: np.ndarray              # float64 [n_disp, n_tau]
     g0_dn: np.ndarray              # float64 [n_disp, n_tau]
     meta: dict = field(default_factory=dict)
+    site_pos: np.ndarray | None = None   # [n_sites, 3] positions r_x (momentum measurement)
+    kvecs: np.ndarray | None = None      # [n_k, 3] cluster momenta K
 
     @property
     def n_tau(self) -> int:
@@ -46,6 +48,20 @@ class Workload:
         assert self.site_disp.size == self.n_sites * self.n_sites
         assert self.g0_up.shape == self.g0_dn.shape
         assert int(self.site_disp.max()) < self.n_disp
+        if self.site_pos is not None:
+            self.site_pos = _pad3(self.site_pos)
+            self.kvecs = _pad3(self.kvecs)
+            assert self.site_pos.shape[0] == self.n_sites
+
+
+def _pad3(a) -> np.ndarray:
+    """Rows of 1-3 coordinates as rows of 3 (missing dimensions zero)."""
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a[:, None]
+    out = np.zeros((a.shape[0], 3))
+    out[:, :a.shape[1]] = a
+    return np.ascontiguousarray(out)
 
 
 def anderson_semicircle(beta=10.0, U=4.0, K=1.0, n_tau=4096, mu_tilde=0.0) -> Workload:
@@ -74,7 +90,8 @@ def hubbard_dimer(beta=2.0, U=2.0, K=1.0, t=1.0, mu_tilde=0.0, n_tau=2048) -> Wo
     g = finite_system_g0(h1, beta, n_tau)
     tables, disp = _finite_tables(g)
     return Workload("hubbard_dimer", beta, U, K, 2, disp, tables, tables.copy(),
-                    {"h1": h1, "t": t, "mu_tilde": mu_tilde})
+                    {"h1": h1, "t": t, "mu_tilde": mu_tilde},
+                    site_pos=[[0.0], [1.0]], kvecs=[[0.0], [np.pi]])
 
 
 def hubbard_plaquette(beta=8.0, U=6.0, K=1.0, t=1.0, tp=0.4, mu_tilde=-1.2, n_tau=2048) -> Workload:
@@ -90,7 +107,9 @@ def hubbard_plaquette(beta=8.0, U=6.0, K=1.0, t=1.0, tp=0.4, mu_tilde=-1.2, n_ta
     g = finite_system_g0(h1, beta, n_tau)
     tables, disp = _finite_tables(g)
     return Workload("hubbard_plaquette", beta, U, K, 4, disp, tables, tables.copy(),
-                    {"h1": h1, "t": t, "tp": tp, "mu_tilde": mu_tilde})
+                    {"h1": h1, "t": t, "tp": tp, "mu_tilde": mu_tilde},
+                    site_pos=[[0, 0], [1, 0], [0, 1], [1, 1]],
+                    kvecs=[[0, 0], [np.pi, 0], [0, np.pi], [np.pi, np.pi]])
 
 
 def anderson_bath(beta=4.0, U=3.0, K=1.0, v=0.7, eps_bath=(-1.0, 1.0), mu_tilde=0.0,
@@ -120,7 +139,8 @@ def dca_square(L=4, beta=8.0, U=8.0, K=1.0, density=None, n_tau=8192, t=1.0,
     g = dca_cluster_g0(cl, beta, n_tau, mu, t, n_fine)
     return Workload(f"dca_square_{cl.n_sites}", beta, U, K, cl.n_sites, cl.site_disp, g,
                     g.copy(), {"mu_tilde": mu, "superlattice": np.asarray(sl).tolist(),
-                               "density": density, "t": t, "n_fine": n_fine})
+                               "density": density, "t": t, "n_fine": n_fine},
+                    site_pos=cl.sites, kvecs=cl.momenta)
 
 
 def dca_cubic(beta=6.0, U=8.0, K=1.0, n_tau=8192, t=1.0, n_fine=20,
@@ -130,7 +150,8 @@ def dca_cubic(beta=6.0, U=8.0, K=1.0, n_tau=8192, t=1.0, n_fine=20,
     g = dca_cluster_g0(cl, beta, n_tau, 0.0, t, n_fine)
     return Workload(f"dca_cubic_{cl.n_sites}", beta, U, K, cl.n_sites, cl.site_disp, g,
                     g.copy(), {"mu_tilde": 0.0, "superlattice": np.asarray(superlattice).tolist(),
-                               "t": t, "n_fine": n_fine})
+                               "t": t, "n_fine": n_fine},
+                    site_pos=cl.sites, kvecs=cl.momenta)
 
 
 _MIX_LATTICES = {

@@ -73,6 +73,10 @@ typedef struct {
     const int32_t *site_disp; /* host, [n_sites*n_sites], values in [0, n_disp) */
     const double *g0_up;      /* host, [n_disp*n_tau], finite                  */
     const double *g0_dn;      /* host, [n_disp*n_tau], finite                  */
+    const double *site_pos;   /* host, [n_sites*3] site positions r_x (lattice units), or NULL;
+                                 needed when opts.n_matsubara > 0                          */
+    const double *kvecs;      /* host, [n_k*3] cluster momenta K                             */
+    int32_t n_k;              /* number of momenta, 1..512 when site_pos is given           */
 } ctaux_model;
 
 /* Run options shared by all chains of a batch. */
@@ -92,7 +96,8 @@ typedef struct {
     int32_t precision;        /* CTAUX_FP64 or CTAUX_FP32                                     */
     int32_t meas_every;       /* measure after every meas_every proposals ...                 */
     int64_t n_therm;          /* ... once more than n_therm proposals are done                */
-    int32_t n_tau_out;        /* G(tau) output points tau_j = (j+1/2) beta / n_tau_out        */
+    int32_t n_tau_out;        /* G(tau) output points tau_j = (j+1/2) beta / n_tau_out (0: none;
+                                 densities and double occupancy are measured regardless)     */
     int32_t n_cap;            /* maximum order per chain                                      */
     uint64_t seed;
     int64_t log_cap;          /* decisions of proposals with index < log_cap are recorded     */
@@ -111,6 +116,9 @@ typedef struct {
     double drift_target;      /* N error a chain should carry at most between refinements (the
                                  refinement drift, see ctaux_recompute); 0 selects 1e-10 for
                                  FP64 storage and 1e-4 for FP32 storage                       */
+    int32_t n_matsubara;      /* 0..32: also measure in cluster momenta and the first
+                                 n_matsubara fermionic frequencies (ctaux_get_obs_kw);
+                                 n_sites * n_matsubara <= 2048                               */
     int32_t recompute_mode;   /* periodic refinements: 0 = a Newton step from the current N,
                                  recomputed from scratch when the step cannot recover it (see
                                  ctaux_recompute); 1 = always from scratch
@@ -197,6 +205,17 @@ int ctaux_recompute_from_scratch(ctaux_batch *b, double *max_drift_out);
  *   [8 ...] sum sign*G_up[d][j]; then sum sign*G_dn[d][j]  (d < n_disp, j < n_tau_out),
  * G_sigma[d][j] = average of G_sigma(x, tau_j; y, 0) over pairs with table d. */
 int32_t ctaux_obs_len(const ctaux_batch *b);
+/* Measurement in cluster momenta and Matsubara frequencies (Sec. IV D), with
+ * n_matsubara > 0.  With M = (e^V - 1) N, every measurement adds sign * S(K, w_n),
+ *   S(K, w) = sum_{l,k} exp(i w tau_l - i K.r_{x_l}) M_lk exp(-i w tau_k + i K.r_{x_k}),
+ * w_n = (2n + 1) pi / beta, so that the estimate of the Green's function is
+ *   G(K, i w_n) = G0(K, i w_n) + G0(K, i w_n)^2 (sum sign S / sum sign) / (beta n_sites)
+ * (sum sign is entry [1] of ctaux_get_obs), with
+ *   G0(K, i w_n) = (1/n_sites) sum_{x,y} exp(-i K.(r_x - r_y)) int_0^beta exp(i w_n s) G0_xy(s) ds
+ * for the linear interpolant of the tables (computed at ctaux_create).
+ * s_out receives the accumulated sign * S and g0_out (may be NULL) G0, both as
+ * [sector][k][n][re, im] doubles; len >= 4 n_k n_matsubara. */
+int ctaux_get_obs_kw(ctaux_batch *b, int32_t chain, double *s_out, double *g0_out, int32_t len);
 int ctaux_get_obs(ctaux_batch *b, int32_t chain, double *out, int32_t len);
 int ctaux_reset_obs(ctaux_batch *b);
 

@@ -46,6 +46,10 @@ struct oc_chain {
     /* observables */
     double *obs;
     int32_t obs_len;
+    /* momentum / Matsubara measurement */
+    int32_t n_k, n_mats;
+    double *kvecs, *site_pos;   /* [n_k*3], [nc*3] */
+    double *obs_kw;             /* [2][n_k][n_mats][2] */
     char err[256];
 };
 
@@ -182,6 +186,7 @@ void oc_destroy(oc_chain *c) {
     free(c->N[0]); free(c->N[1]);
     free(c->v1); free(c->v2); free(c->v3);
     free(c->log_acc); free(c->log_R); free(c->obs);
+    free(c->kvecs); free(c->site_pos); free(c->obs_kw);
     free(c);
 }
 
@@ -326,6 +331,103 @@ int oc_estimate_G(const oc_chain *c, int32_t sector, int32_t x, int32_t y, doubl
     return OC_OK;
 }
 
+/* Sec. IV D in cluster momenta and Matsubara frequencies: the estimator
+ * G(x tau; y tau') = G0_xy(tau - tau') + sum_lk G0_{x x_l}(tau - tau_l) M_lk G0_{x_k y}(tau_k - tau')
+ * transformed in both arguments,
+ *   G(K, iw) = (1 / (beta Nc)) sum_xy int int exp(iw(tau - tau') - iK.(r_x - r_y)) G(x tau; y tau'),
+ * gives G0(K, iw) + G0(K, iw)^2 S(K, w) / (beta Nc) with S as declared in the
+ * header (fermionic antiperiodicity makes each factor a full-period transform).
+ * S is summed here directly over all vertex pairs. */
+static void measure_kw(oc_chain *c, double w) {
+    int n = c->n;
+    const double pi = 3.14159265358979323846;
+    for (int sec = 0; sec < 2; ++sec)
+        for (int q = 0; q < c->n_k; ++q) {
+            const double *K = c->kvecs + 3 * q;
+            for (int m = 0; m < c->n_mats; ++m) {
+                double om = (2.0 * m + 1.0) * pi / c->beta;
+                double sre = 0.0, sim = 0.0;
+                for (int l = 0; l < n; ++l) {
+                    const double *rl = c->site_pos + 3 * c->site[l];
+                    double fl = expV(c, sec, c->s[l]) - 1.0;
+                    double al = om * c->tau[l] - (K[0] * rl[0] + K[1] * rl[1] + K[2] * rl[2]);
+                    for (int k = 0; k < n; ++k) {
+                        const double *rk = c->site_pos + 3 * c->site[k];
+                        double ak = -om * c->tau[k] + (K[0] * rk[0] + K[1] * rk[1] + K[2] * rk[2]);
+                        double mlk = fl * NE(c, sec, l, k);
+                        sre += mlk * cos(al + ak);
+                        sim += mlk * sin(al + ak);
+                    }
+                }
+                double *o = c->obs_kw + (((size_t)sec * c->n_k + q) * c->n_mats + m) * 2;
+                o[0] += w * sre;
+                o[1] += w * sim;
+            }
+        }
+}
+
+int oc_set_momentum(oc_chain *c, int32_t n_k, const double *kvecs, const double *site_pos,
+                    int32_t n_matsubara) {
+    if (n_k < 1 || n_matsubara < 1 || !kvecs || !site_pos) return fail(c, OC_EINVAL, "bad momentum set-up");
+    free(c->kvecs); free(c->site_pos); free(c->obs_kw);
+    c->kvecs = (double *)malloc(sizeof(double) * 3 * n_k);
+    c->site_pos = (double *)malloc(sizeof(double) * 3 * c->nc);
+    c->obs_kw = (double *)calloc((size_t)2 * n_k * n_matsubara * 2, sizeof(double));
+    if (!c->kvecs || !c->site_pos || !c->obs_kw) return fail(c, OC_ENOMEM, "allocation failed");
+    memcpy(c->kvecs, kvecs, sizeof(double) * 3 * n_k);
+    memcpy(c->site_pos, site_pos, sizeof(double) * 3 * c->nc);
+    c->n_k = n_k;
+    c->n_mats = n_matsubara;
+    return OC_OK;
+}
+
+int oc_get_obs_kw(const oc_chain *c, double *out) {
+    if (!c->obs_kw) return OC_EINVAL;
+    memcpy(out, c->obs_kw, sizeof(double) * 2 * (size_t)c->n_k * c->n_mats * 2);
+    return OC_OK;
+}
+
+/* int_0^beta exp(i w s) g(s) ds for the linear interpolant g of a table: on
+ * each segment [s0, s0 + h], with E = exp(i w s),
+ *   int E (f0 + (f1 - f0)(s - s0)/h) ds = f0 (E1 - E0)/(i w) + (f1 - f0)/h (h E1/(i w) + (E1 - E0)/w^2). */
+static void table_matsubara(const oc_chain *c, const double *tab, double om, double *re, double *im) {
+    double h = c->beta / (double)(c->n_tau - 1);
+    double sr = 0.0, si = 0.0;
+    for (int m = 0; m + 1 < c->n_tau; ++m) {
+        double s0 = m * h, s1 = (m + 1) * h;
+        double e0r = cos(om * s0), e0i = sin(om * s0), e1r = cos(om * s1), e1i = sin(om * s1);
+        double dr = e1r - e0r, di = e1i - e0i;
+        double f0 = tab[m], sl = (tab[m + 1] - tab[m]) / h;
+        /* (E1 - E0)/(i w) = (di - i dr)/w ;  h E1/(i w) = h (e1i - i e1r)/w ;  (E1 - E0)/w^2 */
+        double ar = di / om, ai = -dr / om;
+        double br = h * e1i / om + dr / (om * om), bi = -h * e1r / om + di / (om * om);
+        sr += f0 * ar + sl * br;
+        si += f0 * ai + sl * bi;
+    }
+    *re = sr;
+    *im = si;
+}
+
+int oc_g0_matsubara(const oc_chain *c, int32_t sector, int32_t k, int32_t n, double *out) {
+    if (!c->kvecs || sector < 0 || sector > 1 || k < 0 || k >= c->n_k || n < 0) return OC_EINVAL;
+    const double pi = 3.14159265358979323846;
+    double om = (2.0 * n + 1.0) * pi / c->beta;
+    const double *K = c->kvecs + 3 * k;
+    double gr = 0.0, gi = 0.0;
+    for (int x = 0; x < c->nc; ++x)
+        for (int y = 0; y < c->nc; ++y) {
+            const double *rx = c->site_pos + 3 * x, *ry = c->site_pos + 3 * y;
+            double ph = -(K[0] * (rx[0] - ry[0]) + K[1] * (rx[1] - ry[1]) + K[2] * (rx[2] - ry[2]));
+            double tr, ti;
+            table_matsubara(c, c->g0[sector] + (int64_t)c->site_disp[x * c->nc + y] * c->n_tau, om, &tr, &ti);
+            gr += cos(ph) * tr - sin(ph) * ti;
+            gi += cos(ph) * ti + sin(ph) * tr;
+        }
+    out[0] = gr / c->nc;
+    out[1] = gi / c->nc;
+    return OC_OK;
+}
+
 static void measure(oc_chain *c) {
     int n = c->n, nc = c->nc, no = c->n_out, nd = c->n_disp;
     double w = c->sign;
@@ -363,6 +465,7 @@ static void measure(oc_chain *c) {
     for (int x = 0; x < nc; ++x) D += dens[x] * dens[nc + x];
     o[5] += w * D / nc;
     free(W); free(dens); free(cnt);
+    if (c->obs_kw) measure_kw(c, w);
 }
 
 /* ---------------- the walk (Sec. II B) ------------------------------------- */
@@ -573,5 +676,6 @@ int oc_get_obs(const oc_chain *c, double *out) {
 
 int oc_reset_obs(oc_chain *c) {
     memset(c->obs, 0, sizeof(double) * (size_t)c->obs_len);
+    if (c->obs_kw) memset(c->obs_kw, 0, sizeof(double) * 2 * (size_t)c->n_k * c->n_mats * 2);
     return OC_OK;
 }

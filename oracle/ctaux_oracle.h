@@ -110,6 +110,21 @@ int oc_reset_obs(oc_chain *c);
 int oc_estimate_G(const oc_chain *c, int32_t sector, int32_t x, int32_t y, double tau,
                   double *out);
 
+/* Measurement in cluster momenta and Matsubara frequencies (Sec. IV D).  With
+ * M = (e^V - 1) N, site positions r_x and momenta K, every measurement adds
+ * sign * S_sigma(K, w_n) with
+ *   S(K, w) = sum_{l,k} exp(i w tau_l - i K.r_{x_l}) M_lk exp(-i w tau_k + i K.r_{x_k}),
+ * w_n = (2n + 1) pi / beta, so that
+ *   G(K, i w_n) = G0(K, i w_n) + G0(K, i w_n)^2 <S(K, w_n)> / (beta Nc).
+ * site_pos [n_sites*3], kvecs [n_k*3]; n_matsubara frequencies.  Layout of the
+ * accumulator (oc_get_obs_kw): [sector][k][n][re, im]. */
+int oc_set_momentum(oc_chain *c, int32_t n_k, const double *kvecs, const double *site_pos,
+                    int32_t n_matsubara);
+int oc_get_obs_kw(const oc_chain *c, double *out);
+/* G0(K, i w_n) = (1/Nc) sum_{x,y} exp(-i K.(r_x - r_y)) int_0^beta exp(i w_n s) G0_xy(s) ds
+ * with G0_xy the linear interpolant of the tables; out = [re, im]. */
+int oc_g0_matsubara(const oc_chain *c, int32_t sector, int32_t k, int32_t n, double *out);
+
 /* Building blocks exposed for the pins. */
 double oc_g0_lookup(const oc_chain *c, int32_t sector, int32_t x, int32_t y, double dtau);
 void oc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

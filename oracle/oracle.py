@@ -69,6 +69,9 @@ def _load():
     lib.oc_estimate_G.argtypes = [vp, i32, i32, i32, d, P(d)]
     lib.oc_g0_lookup.restype = d
     lib.oc_g0_lookup.argtypes = [vp, i32, i32, i32, d]
+    lib.oc_set_momentum.argtypes = [vp, i32, vp, vp, i32]
+    lib.oc_get_obs_kw.argtypes = [vp, vp]
+    lib.oc_g0_matsubara.argtypes = [vp, i32, i32, i32, vp]
     lib.oc_philox4x32_10.argtypes = [vp, vp, vp]
     lib.oc_draws.argtypes = [u64, u32, u64, vp]
     lib.oc_gamma_of.restype = d
@@ -227,6 +230,25 @@ class OracleChain:
 
     def reset_obs(self):
         self._check(self.lib.oc_reset_obs(self.h))
+
+    def set_momentum(self, kvecs, site_pos, n_matsubara):
+        k = np.ascontiguousarray(np.asarray(kvecs, np.float64).reshape(-1, 3))
+        r = np.ascontiguousarray(np.asarray(site_pos, np.float64).reshape(-1, 3))
+        self._kw = (k, r, int(n_matsubara))
+        self._check(self.lib.oc_set_momentum(self.h, len(k), _ptr(k), _ptr(r), int(n_matsubara)))
+
+    def obs_kw(self) -> np.ndarray:
+        """Accumulated sign * S_sigma(K, w_n) as complex [2, n_k, n_matsubara]."""
+        k, r, nm = self._kw
+        out = np.zeros(2 * len(k) * nm * 2)
+        self._check(self.lib.oc_get_obs_kw(self.h, _ptr(out)))
+        out = out.reshape(2, len(k), nm, 2)
+        return out[..., 0] + 1j * out[..., 1]
+
+    def g0_matsubara(self, sector, k, n) -> complex:
+        out = np.zeros(2)
+        self._check(self.lib.oc_g0_matsubara(self.h, sector, k, n, _ptr(out)))
+        return complex(out[0], out[1])
 
     def estimate_G(self, sector, x, y, tau) -> float:
         out = C.c_double()

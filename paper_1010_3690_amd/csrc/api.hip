@@ -149,11 +149,13 @@ int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, c
     return set_err(eb, CTAUX_EINVAL, "rankk_tile must be 0, 32 or 64");
   if (o->precision != CTAUX_FP64 && o->precision != CTAUX_FP32)
     return set_err(eb, CTAUX_EINVAL, "precision must be CTAUX_FP64 or CTAUX_FP32");
-  if (o->meas_every < 1 || o->n_tau_out < 1 || o->n_tau_out > 4096 || o->n_cap < 1 || o->n_cap > 65536 ||
+  if (o->meas_every < 1 || o->n_tau_out < 0 || o->n_tau_out > 4096 || o->n_cap < 1 || o->n_cap > 65536 ||
       o->recompute_every < 0 || o->n_therm < 0 || o->log_cap < 0)
     return set_err(eb, CTAUX_EINVAL, "invalid meas_every/n_tau_out/n_cap/recompute_every/n_therm/log_cap");
   if (!isfinite(o->drift_target) || o->drift_target < 0.0 || o->recompute_mode < 0 || o->recompute_mode > 1)
     return set_err(eb, CTAUX_EINVAL, "drift_target must be finite and >= 0, recompute_mode 0 or 1");
+  if (o->n_matsubara < 0 || o->n_matsubara > 32)
+    return set_err(eb, CTAUX_EINVAL, "n_matsubara must be in 0..32");
   // the proposal kernel holds Gamma^{-1} of both sectors and the spins of the
   // augmented configuration in the LDS of one workgroup
   {
@@ -166,6 +168,16 @@ int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, c
     const ctaux_model &m = models[c];
     int rc = model_error(m, c, eb);
     if (rc) return rc;
+    if (o->n_matsubara > 0) {
+      if (m.n_sites * o->n_matsubara > 2048)
+        return set_err(eb, CTAUX_EINVAL, "chain %d: n_sites * n_matsubara must not exceed 2048", c);
+      if (!m.site_pos || !m.kvecs || m.n_k < 1 || m.n_k > 512)
+        return set_err(eb, CTAUX_EINVAL, "chain %d: the momentum measurement needs site_pos and 1..512 kvecs", c);
+      for (int i = 0; i < 3 * m.n_sites; ++i)
+        if (!isfinite(m.site_pos[i])) return set_err(eb, CTAUX_EINVAL, "chain %d: non-finite site_pos", c);
+      for (int i = 0; i < 3 * m.n_k; ++i)
+        if (!isfinite(m.kvecs[i])) return set_err(eb, CTAUX_EINVAL, "chain %d: non-finite kvecs", c);
+    }
     // the table kernels index a chain's elements with 32-bit integers
     if (2ll * (o->n_tau_out + 1) * m.n_sites * o->n_cap >= (1ll << 31))
       return set_err(eb, CTAUX_EINVAL, "chain %d: 2 (n_tau_out + 1) n_sites n_cap must stay below 2^31", c);
@@ -248,6 +260,22 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
     d.log_cap = o->log_cap;
     d.log_acc = cv.take<uint8_t>(o->log_cap > 0 ? o->log_cap : 1);
     d.log_R = cv.take<double>(o->log_cap > 0 ? o->log_cap : 1);
+    {
+      const int nm = o->n_matsubara, nk = nm > 0 ? m.n_k : 0;
+      d.n_mats = nm;
+      d.n_k = nk;
+      const size_t one = 1;
+      d.kw_pos = cv.take<double>(nm > 0 ? 3 * static_cast<size_t>(nc) : one);
+      d.kw_k = cv.take<double>(nm > 0 ? 3 * static_cast<size_t>(nk) : one);
+      d.kw_g0 = cv.take<double>(nm > 0 ? 4 * static_cast<size_t>(nk) * nm : one);
+      d.kw_off = cv.take<int32_t>(nm > 0 ? nc + 1 : 1);
+      d.kw_list = cv.take<int32_t>(nm > 0 ? n_cap : 1);
+      d.kw_ph = cv.take<double>(nm > 0 ? 2 * static_cast<size_t>(n_cap) * nm : one);
+      // the C blocks also hold the transforms of the tables while G0(K, i w) is set up
+      const size_t cblk = 4 * static_cast<size_t>(nc) * nc * nm, tblk = 4 * static_cast<size_t>(m.n_disp) * nm;
+      d.kw_C = cv.take<double>(nm > 0 ? (cblk > tblk ? cblk : tblk) : one);
+      d.obs_kw = cv.take<double>(nm > 0 ? 4 * static_cast<size_t>(nk) * nm : one);
+    }
     if (descs) {
       d.beta = m.beta; d.K = m.K;
       d.gamma = acosh(1.0 + m.beta * m.U * nc / (2.0 * m.K));
@@ -598,9 +626,12 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
   b.nc_max = 1;
   b.n_out_max = opts->n_tau_out;
   b.n_tau_max = 2;
+  b.n_mats = opts->n_matsubara;
+  b.n_k_max = 0;
   for (int c = 0; c < n_chains; ++c) {
     b.nc_max = models[c].n_sites > b.nc_max ? models[c].n_sites : b.nc_max;
     b.n_tau_max = models[c].n_tau > b.n_tau_max ? models[c].n_tau : b.n_tau_max;
+    if (opts->n_matsubara > 0 && models[c].n_k > b.n_k_max) b.n_k_max = models[c].n_k;
   }
   int dev = 0;
   hipDeviceProp_t prop;
@@ -643,6 +674,12 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
         hipMemcpyAsync(const_cast<int32_t *>(d.cls_pairs), pairs.data(), sizeof(int32_t) * pairs.size(),
                        hipMemcpyHostToDevice, h->stream) != hipSuccess ||
         hipMemsetAsync(d.obs, 0, sizeof(double) * d.obs_len, h->stream) != hipSuccess ||
+        (d.n_mats > 0 &&
+         (hipMemcpyAsync(d.kw_pos, m.site_pos, sizeof(double) * 3 * nc, hipMemcpyHostToDevice, h->stream) !=
+              hipSuccess ||
+          hipMemcpyAsync(d.kw_k, m.kvecs, sizeof(double) * 3 * d.n_k, hipMemcpyHostToDevice, h->stream) !=
+              hipSuccess ||
+          hipMemsetAsync(d.obs_kw, 0, sizeof(double) * 4 * d.n_k * d.n_mats, h->stream) != hipSuccess)) ||
         (opts->log_cap > 0 &&
          (hipMemsetAsync(d.log_acc, 0, opts->log_cap, h->stream) != hipSuccess ||
           hipMemsetAsync(d.log_R, 0, sizeof(double) * opts->log_cap, h->stream) != hipSuccess))) {
@@ -675,6 +712,13 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
       hipStreamSynchronize(h->stream) != hipSuccess) {
     delete h;
     return set_err(nullptr, CTAUX_EDEVICE, "descriptor upload failed");
+  }
+  if (b.n_mats > 0) {
+    launch_kw_g0(b, h->stream);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
+      delete h;
+      return set_err(nullptr, CTAUX_EDEVICE, "G0(K, i w_n) set-up failed");
+    }
   }
   // measurement stream (default priority, no implicit synchronisation with the
   // null stream) and the two events that order it against the caller's stream.
@@ -759,14 +803,34 @@ int ctaux_get_obs(ctaux_batch *h, int32_t chain, double *out, int32_t len) {
   return CTAUX_OK;
 }
 
+int ctaux_get_obs_kw(ctaux_batch *h, int32_t chain, double *s_out, double *g0_out, int32_t len) {
+  if (!h || !s_out || chain < 0 || chain >= h->b.n_chains) return CTAUX_EINVAL;
+  const ChainDesc &d = h->desc[chain];
+  if (d.n_mats == 0) return set_err(h, CTAUX_EINVAL, "the batch was created with n_matsubara = 0");
+  const int32_t L = 4 * d.n_k * d.n_mats;
+  if (len < L) return set_err(h, CTAUX_EINVAL, "kw buffer of %d doubles needed", L);
+  {
+    int rc_ = sync_all(h);
+    if (rc_) return rc_;
+  }
+  HIPCHECK(h, hipMemcpyAsync(s_out, d.obs_kw, sizeof(double) * L, hipMemcpyDeviceToHost, h->stream));
+  if (g0_out) HIPCHECK(h, hipMemcpyAsync(g0_out, d.kw_g0, sizeof(double) * L, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  return CTAUX_OK;
+}
+
 int ctaux_reset_obs(ctaux_batch *h) {
   if (!h) return CTAUX_EINVAL;
   {
     int rc_ = sync_all(h);   // a measurement in flight writes obs
     if (rc_) return rc_;
   }
-  for (int c = 0; c < h->b.n_chains; ++c)
+  for (int c = 0; c < h->b.n_chains; ++c) {
     HIPCHECK(h, hipMemsetAsync(h->desc[c].obs, 0, sizeof(double) * h->obs_len[c], h->stream));
+    if (h->desc[c].n_mats > 0)
+      HIPCHECK(h, hipMemsetAsync(h->desc[c].obs_kw, 0, sizeof(double) * 4 * h->desc[c].n_k * h->desc[c].n_mats,
+                                 h->stream));
+  }
   {
     int rc_ = sync_all(h);
     if (rc_) return rc_;
@@ -900,13 +964,18 @@ struct CkptHeader {
   int64_t launches;   // blocks enqueued on the batch
   int64_t refine_interval, since_refine;   // the chain's refinement interval (since_refine unused)
   double sign, max_drift, last_drift, rk_flops, rk_bytes, sum_order;
+  int64_t kw_len;   // doubles of the momentum / Matsubara accumulators
 };
 constexpr char kCkptMagic[8] = {'C', 'T', 'A', 'U', 'X', 'C', 'K', '1'};
+
+size_t kw_len(const ctaux_batch *h, int chain) {
+  return 4 * static_cast<size_t>(h->desc[chain].n_k) * h->desc[chain].n_mats;
+}
 
 size_t ckpt_bytes(const ctaux_batch *h, int chain, int n) {
   const size_t es = h->b.precision == CTAUX_FP64 ? sizeof(double) : sizeof(float);
   return sizeof(CkptHeader) + static_cast<size_t>(n) * (8 + 8 + 4 + 4) + 2 * es * n * n +
-         sizeof(double) * h->obs_len[chain];
+         sizeof(double) * (h->obs_len[chain] + kw_len(h, chain));
 }
 
 int ctaux_checkpoint(ctaux_batch *h, int32_t chain, void *buf, size_t *len) {
@@ -949,6 +1018,7 @@ int ctaux_checkpoint(ctaux_batch *h, int32_t chain, void *buf, size_t *len) {
   hd.rk_flops = st.rk_flops;
   hd.rk_bytes = st.rk_bytes;
   hd.sum_order = st.sum_order;
+  hd.kw_len = static_cast<int64_t>(kw_len(h, chain));
   char *p = static_cast<char *>(buf);
   memcpy(p, &hd, sizeof hd);
   p += sizeof hd;
@@ -969,6 +1039,9 @@ int ctaux_checkpoint(ctaux_batch *h, int32_t chain, void *buf, size_t *len) {
     }
   }
   HIPCHECK(h, hipMemcpyAsync(p, d.obs, sizeof(double) * h->obs_len[chain], hipMemcpyDeviceToHost, h->stream));
+  p += sizeof(double) * h->obs_len[chain];
+  if (kw_len(h, chain) > 0)
+    HIPCHECK(h, hipMemcpyAsync(p, d.obs_kw, sizeof(double) * kw_len(h, chain), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   return CTAUX_OK;
 }
@@ -982,7 +1055,8 @@ int ctaux_restore(ctaux_batch *h, int32_t chain, const void *buf, size_t len) {
   if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 2)
     return set_err(h, CTAUX_EINVAL, "not a version-2 checkpoint");
   if (hd.precision != h->b.precision || hd.nc != d.nc || hd.n_tau != d.n_tau || hd.beta != d.beta ||
-      hd.K != d.K || hd.gamma != d.gamma || hd.obs_len != h->obs_len[chain])
+      hd.K != d.K || hd.gamma != d.gamma || hd.obs_len != h->obs_len[chain] ||
+      hd.kw_len != static_cast<int64_t>(kw_len(h, chain)))
     return set_err(h, CTAUX_EINVAL, "checkpoint of another model or precision");
   if (hd.n < 0 || hd.n > h->b.n_cap) return set_err(h, CTAUX_EINVAL, "checkpoint order %d exceeds n_cap", hd.n);
   if (len < ckpt_bytes(h, chain, hd.n)) return set_err(h, CTAUX_EINVAL, "checkpoint truncated");
@@ -1007,6 +1081,9 @@ int ctaux_restore(ctaux_batch *h, int32_t chain, const void *buf, size_t len) {
     }
   }
   HIPCHECK(h, hipMemcpyAsync(d.obs, p, sizeof(double) * hd.obs_len, hipMemcpyHostToDevice, h->stream));
+  p += sizeof(double) * hd.obs_len;
+  if (kw_len(h, chain) > 0)
+    HIPCHECK(h, hipMemcpyAsync(d.obs_kw, p, sizeof(double) * kw_len(h, chain), hipMemcpyHostToDevice, h->stream));
   ChainState st;
   memset(&st, 0, sizeof st);
   st.n = n;

@@ -78,6 +78,16 @@ struct ChainDesc {
   double *obs;             // accumulators
   int32_t obs_len;
   int32_t pad1;
+  // measurement in cluster momenta and Matsubara frequencies (n_mats = 0: off)
+  int32_t n_k, n_mats;
+  double *kw_pos;          // [nc*3] site positions
+  double *kw_k;            // [n_k*3] cluster momenta
+  double *kw_g0;           // [2][n_k][n_mats][2] G0(K, i w_n), set at creation
+  int32_t *kw_off;         // [nc+1] vertices of each site (CSR offsets into kw_list)
+  int32_t *kw_list;        // [n_cap] vertex indices sorted by site (ascending within a site)
+  double *kw_ph;           // [n_cap][n_mats][2] exp(-i w_n tau_k)
+  double *kw_C;            // [2][nc][nc][n_mats][2] sum_{l in x, k in x'} e^{i w tau_l} M_lk e^{-i w tau_k}
+  double *obs_kw;          // [2][n_k][n_mats][2] sum of sign * S(K, w_n)
   // decision log
   uint8_t *log_acc;        // [log_cap]
   double *log_R;           // [log_cap]
@@ -125,6 +135,7 @@ void launch_rankk(const Batch &b, hipStream_t s);
 void launch_block_end(const Batch &b, hipStream_t s);
 void launch_block_turn(const Batch &b, hipStream_t s);   // block end + next block begin
 void launch_measure(const Batch &b, hipStream_t s);
+void launch_kw_g0(const Batch &b, hipStream_t s);   // G0(K, i w_n) of every chain, once at creation
 // Refinement of a group of chains: each item names a chain, its order and the
 // offset (in doubles) of its scratch in the refinement pool.
 struct RefineItem {
@@ -179,6 +190,7 @@ constexpr size_t kLdsPerWorkgroup = 160 * 1024;   // gfx950
 struct Batch {
   int32_t n_chains;
   int32_t kmax, kcap, n_cap, ld, nc_max, n_out_max, n_tau_max;
+  int32_t n_mats, n_k_max;   // momentum / Matsubara measurement (n_mats = 0: off)
   int32_t precision;
   int32_t grid_per_chain;    // workgroups per chain for per-chain streaming kernels
   int32_t rankk_tile;        // rank-k output tile edge, 64 or 32

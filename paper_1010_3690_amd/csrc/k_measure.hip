@@ -113,12 +113,275 @@ __global__ __launch_bounds__(256) void k_meas_acc(const ChainDesc *descs, const 
   }
 }
 
+// ---- measurement in cluster momenta and Matsubara frequencies (Sec. IV D) ----
+// The real-space estimator, transformed in both of its arguments (time and
+// site), gives G(K, i w) = G0(K, i w) + G0(K, i w)^2 S(K, w) / (beta Nc) with
+//   S(K, w) = sum_{l,k} e^{i w tau_l - i K.r_l} M_lk e^{-i w tau_k + i K.r_k},  M = (e^V - 1) N.
+// With the vertices grouped by site, S(K, w) = sum_{x,x'} e^{-i K.r_x} e^{i K.r_x'} C_xx'(w),
+//   C_xx'(w) = sum_{l at x} e^{i w tau_l} (e^{V_l} - 1) sum_{k at x'} N_lk e^{-i w tau_k},
+// which reads N once and costs 4 n^2 N_w flops per sector (not n^2 N_K N_w).
+
+__device__ __forceinline__ double matsubara(const ChainDesc &d, int m) {
+  return (2.0 * m + 1.0) * 3.14159265358979323846 / d.beta;
+}
+
+// Vertices sorted by site (stable: ascending index within a site) and the
+// phases e^{-i w_n tau_k}; one workgroup per chain.
+__global__ __launch_bounds__(256) void k_meas_kw_sort(const ChainDesc *descs, const ChainState *states) {
+  __shared__ int cnt[128], run[128], chunk_site[256];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const ChainDesc &d = descs[c];
+  const ChainState &st = states[c];
+  if (!st.active || !st.meas_now || d.n_mats == 0) return;
+  const int n = st.n, nc = d.nc, nm = d.n_mats, par = st.parity;
+  const auto site = gview(d.site[par]);
+  const auto tau = gview(d.tau[par]);
+  for (int x = tid; x < nc; x += 256) cnt[x] = 0;
+  __syncthreads();
+  for (int i = tid; i < n; i += 256) atomicAdd(&cnt[site[i]], 1);   // integer counts: any order
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int x = 0; x < nc; ++x) {
+      gview_w(d.kw_off)[x] = acc;
+      run[x] = acc;
+      acc += cnt[x];
+    }
+    gview_w(d.kw_off)[nc] = acc;
+  }
+  __syncthreads();
+  for (int base = 0; base < n; base += 256) {
+    const int i = base + tid;
+    const int sx = i < n ? site[i] : -1;
+    chunk_site[tid] = sx;
+    __syncthreads();
+    if (i < n) {
+      int r = 0;
+      for (int j = 0; j < tid; ++j) r += chunk_site[j] == sx;
+      gview_w(d.kw_list)[run[sx] + r] = i;
+    }
+    __syncthreads();
+    if (tid < nc) {
+      int add = 0;
+      for (int j = 0; j < 256; ++j) add += chunk_site[j] == tid;
+      run[tid] += add;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * nm; e += 256) {
+    const int k = e / nm, m = e - k * nm;
+    double sn, cs;
+    sincos(matsubara(d, m) * tau[k], &sn, &cs);
+    gview_w(d.kw_ph)[2 * e] = cs;
+    gview_w(d.kw_ph)[2 * e + 1] = -sn;
+  }
+}
+
+// C_xx'(w) for one (chain, sector, site x) per workgroup.  Thread (g, b) owns
+// bin b = (x', m) (m fastest, so the lanes of one x' read the same N entries)
+// for the rows of site x in row group g; the row groups are summed in a fixed
+// order.  Deterministic: no atomics, every sum in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_meas_kw_C(const ChainDesc *descs, const ChainState *states, int nc_max) {
+  __shared__ double red[256][2];
+  const int c = blockIdx.y, tid = threadIdx.x;
+  const ChainDesc &d = descs[c];
+  const ChainState &st = states[c];
+  if (!st.active || !st.meas_now || d.n_mats == 0) return;
+  const int sec = blockIdx.x >= nc_max ? 1 : 0, x = blockIdx.x - sec * nc_max;
+  const int nc = d.nc, nm = d.n_mats, par = st.parity, ld = d.ld;
+  if (x >= nc) return;
+  const auto N = gview(static_cast<const T *>(d.N[par][sec]));
+  const auto s0 = gview(d.s0[par]);
+  const auto off = gview(d.kw_off);
+  const auto list = gview(d.kw_list);
+  const auto ph = gview(d.kw_ph);
+  const int nb = nc * nm, nbe = nb < 256 ? nb : 256, G = 256 / nbe;
+  const int g = tid / nbe, b = tid - g * nbe;
+  const int l0 = off[x], l1 = off[x + 1];
+  for (int bb = 0; bb < nb; bb += nbe) {
+    const int bin = bb + b;
+    double are = 0.0, aim = 0.0;
+    if (g < G && bin < nb) {
+      const int xp = bin / nm, m = bin - xp * nm;
+      const int k0 = off[xp], k1 = off[xp + 1];
+      for (int li = l0 + g; li < l1; li += G) {
+        const int l = list[li];
+        const double evl = gview(d.evd[sec])[s0[l] + 2] - 1.0;
+        double yre = 0.0, yim = 0.0;
+        for (int ki = k0; ki < k1; ++ki) {
+          const int k = list[ki];
+          const double nlk = static_cast<double>(N[static_cast<size_t>(l) * ld + k]);
+          yre = fma(nlk, ph[2 * (k * nm + m)], yre);
+          yim = fma(nlk, ph[2 * (k * nm + m) + 1], yim);
+        }
+        // e^{+i w tau_l} = conj(ph_l)
+        const double pr = ph[2 * (l * nm + m)], pi = -ph[2 * (l * nm + m) + 1];
+        are += evl * (pr * yre - pi * yim);
+        aim += evl * (pr * yim + pi * yre);
+      }
+    }
+    red[tid][0] = are;
+    red[tid][1] = aim;
+    __syncthreads();
+    if (g == 0 && bin < nb) {
+      for (int q = 1; q < G; ++q) {
+        are += red[q * nbe + b][0];
+        aim += red[q * nbe + b][1];
+      }
+      double *C = d.kw_C + 2 * ((static_cast<size_t>(sec) * nc + x) * nb + bin);
+      gview_w(C)[0] = are;
+      gview_w(C)[1] = aim;
+    }
+    __syncthreads();
+  }
+}
+
+// S(K, w) = sum_x e^{-i K.r_x} sum_x' e^{i K.r_x'} C_xx'(w), accumulated with the
+// configuration's sign; one workgroup per (chain, K).
+__global__ __launch_bounds__(256) void k_meas_kw_S(const ChainDesc *descs, const ChainState *states) {
+  __shared__ double P[128][2];
+  __shared__ double Tsh[2048][2];   // n_sites * n_matsubara <= 2048
+  const int c = blockIdx.y, q = blockIdx.x, tid = threadIdx.x;
+  const ChainDesc &d = descs[c];
+  const ChainState &st = states[c];
+  if (!st.active || !st.meas_now || d.n_mats == 0 || q >= d.n_k) return;
+  const int nc = d.nc, nm = d.n_mats;
+  const double *K = d.kw_k + 3 * q;
+  for (int x = tid; x < nc; x += 256) {
+    const double *r = d.kw_pos + 3 * x;
+    double sn, cs;
+    sincos(K[0] * r[0] + K[1] * r[1] + K[2] * r[2], &sn, &cs);
+    P[x][0] = cs;   // e^{i K.r_x}
+    P[x][1] = sn;
+  }
+  __syncthreads();
+  const double w = st.sign;
+  for (int sec = 0; sec < 2; ++sec) {
+    const double *C = d.kw_C + 2 * static_cast<size_t>(sec) * nc * nc * nm;
+    for (int e = tid; e < nc * nm; e += 256) {
+      const int x = e / nm, m = e - x * nm;
+      double tr = 0.0, ti = 0.0;
+      for (int xp = 0; xp < nc; ++xp) {
+        const double *cv = C + 2 * ((static_cast<size_t>(x) * nc + xp) * nm + m);
+        tr += P[xp][0] * cv[0] - P[xp][1] * cv[1];
+        ti += P[xp][0] * cv[1] + P[xp][1] * cv[0];
+      }
+      Tsh[e][0] = tr;
+      Tsh[e][1] = ti;
+    }
+    __syncthreads();
+    for (int m = tid; m < nm; m += 256) {
+      double sr = 0.0, si = 0.0;
+      for (int x = 0; x < nc; ++x) {   // e^{-i K.r_x} = conj(P_x)
+        const double *tv = Tsh[x * nm + m];
+        sr += P[x][0] * tv[0] + P[x][1] * tv[1];
+        si += P[x][0] * tv[1] - P[x][1] * tv[0];
+      }
+      double *o = d.obs_kw + 2 * ((static_cast<size_t>(sec) * d.n_k + q) * nm + m);
+      o[0] += w * sr;
+      o[1] += w * si;
+    }
+    __syncthreads();
+  }
+}
+
+// G0(K, i w_n) = (1/Nc) sum_{x,y} e^{-i K.(r_x - r_y)} g_{d(x,y)}(i w_n), where
+// g_d(i w) = int_0^beta e^{i w s} g_d(s) ds for the linear interpolant of table d
+// on the grid s_m = m h:  sum_m e^{i w s_m} (g_m A + g_{m+1} B) with
+//   A = int_0^h e^{i w u} (1 - u/h) du,  B = int_0^h e^{i w u} (u/h) du
+// (power series in i w h below w h = 1, closed forms above).  One workgroup
+// per chain; the table transforms are staged in kw_C.
+__device__ void seg_weights(double theta, double h, double *A, double *B) {
+  if (theta < 1.0) {
+    // A = h sum_j (i theta)^j / (j! (j+1)(j+2)),  B = h sum_j (i theta)^j / (j! (j+2))
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    double pr = 1.0, pi = 0.0;   // (i theta)^j / j!
+    for (int j = 0; j < 24; ++j) {
+      const double fa = 1.0 / ((j + 1.0) * (j + 2.0)), fb = 1.0 / (j + 2.0);
+      ar += pr * fa; ai += pi * fa;
+      br += pr * fb; bi += pi * fb;
+      const double nr = -pi * theta / (j + 1.0), ni = pr * theta / (j + 1.0);
+      pr = nr;
+      pi = ni;
+    }
+    A[0] = h * ar; A[1] = h * ai; B[0] = h * br; B[1] = h * bi;
+  } else {
+    double sn, cs;
+    sincos(theta, &sn, &cs);
+    // E - 1 with E = e^{i theta};  int_0^1 e^{i theta t} dt = (E - 1)/(i theta)
+    const double er = cs - 1.0, ei = sn;
+    const double ir = ei / theta, ii = -er / theta;                 // (E - 1)/(i theta)
+    // int_0^1 t e^{i theta t} dt = E/(i theta) + (E - 1)/theta^2
+    const double tr = sn / theta + er / (theta * theta), ti = -cs / theta + ei / (theta * theta);
+    B[0] = h * tr; B[1] = h * ti;
+    A[0] = h * (ir - tr); A[1] = h * (ii - ti);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_kw_g0(const ChainDesc *descs) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const ChainDesc &d = descs[c];
+  if (d.n_mats == 0) return;
+  const int nm = d.n_mats, nd = d.n_disp, nt = d.n_tau, nc = d.nc;
+  const double h = d.beta / (nt - 1);
+  double *gt = d.kw_C;   // [2][nd][nm][2]
+  for (int e = tid; e < 2 * nd * nm; e += 256) {
+    const int sec = e / (nd * nm), r = e - sec * nd * nm, dd = r / nm, m = r - dd * nm;
+    const double om = matsubara(d, m);
+    double A[2], B[2];
+    seg_weights(om * h, h, A, B);
+    const double *tab = d.g0[sec] + static_cast<size_t>(dd) * nt;
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j + 1 < nt; ++j) {
+      double sn, cs;
+      sincos(om * (j * h), &sn, &cs);
+      const double vr = tab[j] * A[0] + tab[j + 1] * B[0], vi = tab[j] * A[1] + tab[j + 1] * B[1];
+      sr += cs * vr - sn * vi;
+      si += cs * vi + sn * vr;
+    }
+    gt[2 * e] = sr;
+    gt[2 * e + 1] = si;
+  }
+  __syncthreads();
+  for (int e = tid; e < 2 * d.n_k * nm; e += 256) {
+    const int sec = e / (d.n_k * nm), r = e - sec * d.n_k * nm, q = r / nm, m = r - q * nm;
+    const double *K = d.kw_k + 3 * q;
+    double sr = 0.0, si = 0.0;
+    for (int x = 0; x < nc; ++x)
+      for (int y = 0; y < nc; ++y) {
+        const double *rx = d.kw_pos + 3 * x, *ry = d.kw_pos + 3 * y;
+        double sn, cs;
+        sincos(-(K[0] * (rx[0] - ry[0]) + K[1] * (rx[1] - ry[1]) + K[2] * (rx[2] - ry[2])), &sn, &cs);
+        const double *g = gt + 2 * ((static_cast<size_t>(sec) * nd + d.site_disp[x * nc + y]) * nm + m);
+        sr += cs * g[0] - sn * g[1];
+        si += cs * g[1] + sn * g[0];
+      }
+    d.kw_g0[2 * e] = sr / nc;
+    d.kw_g0[2 * e + 1] = si / nc;
+  }
+}
+
+void launch_kw_g0(const Batch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_kw_g0, dim3(b.n_chains), dim3(256), 0, s, b.d_desc);
+}
+
 void launch_measure(const Batch &b, hipStream_t s) {
   hipLaunchKernelGGL(k_meas_gR, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_mstate, b.n_chains, chain_grid_arg(b));
   hipLaunchKernelGGL(k_meas_gL, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_mstate, b.n_chains, chain_grid_arg(b));
   launch_skinny(b, s, 2);   // W = N gR
   launch_skinny(b, s, 3);   // Gxy = G0 + gL W, gL_{(x,tau), l} = G0_{x x_l}(tau - tau_l)(e^{V_l} - 1)
   hipLaunchKernelGGL(k_meas_acc, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);
+  if (b.n_mats > 0) {
+    hipLaunchKernelGGL(k_meas_kw_sort, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);
+    if (b.precision == kFP64)
+      hipLaunchKernelGGL(k_meas_kw_C<double>, dim3(2 * b.nc_max, b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate,
+                         b.nc_max);
+    else
+      hipLaunchKernelGGL(k_meas_kw_C<float>, dim3(2 * b.nc_max, b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate,
+                         b.nc_max);
+    hipLaunchKernelGGL(k_meas_kw_S, dim3(b.n_k_max, b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);
+  }
 }
 
 }  // namespace ctaux

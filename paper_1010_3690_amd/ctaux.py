@@ -25,7 +25,7 @@ TIMED_KERNELS = ["block_begin", "interp", "prep", "propose", "assemble", "rankk"
                  "refine"]
 
 EXPORTED = [
-    "ctaux_workspace_bytes", "ctaux_create", "ctaux_run", "ctaux_recompute", "ctaux_obs_len",
+    "ctaux_workspace_bytes", "ctaux_create", "ctaux_run", "ctaux_recompute", "ctaux_obs_len", "ctaux_get_obs_kw",
     "ctaux_get_obs", "ctaux_reset_obs", "ctaux_get_stats", "ctaux_get_config", "ctaux_get_N",
     "ctaux_get_decisions", "ctaux_set_timing", "ctaux_set_timing_every", "ctaux_get_timing",
     "ctaux_checkpoint", "ctaux_restore", "ctaux_recompute_from_scratch",
@@ -37,7 +37,8 @@ EXPORTED = [
 class _Model(C.Structure):
     _fields_ = [("beta", C.c_double), ("U", C.c_double), ("K", C.c_double), ("n_sites", C.c_int32),
                 ("n_tau", C.c_int32), ("n_disp", C.c_int32), ("site_disp", C.c_void_p),
-                ("g0_up", C.c_void_p), ("g0_dn", C.c_void_p)]
+                ("g0_up", C.c_void_p), ("g0_dn", C.c_void_p), ("site_pos", C.c_void_p), ("kvecs", C.c_void_p),
+                ("n_k", C.c_int32)]
 
 
 class _Opts(C.Structure):
@@ -46,7 +47,7 @@ class _Opts(C.Structure):
                 ("n_therm", C.c_int64), ("n_tau_out", C.c_int32), ("n_cap", C.c_int32),
                 ("seed", C.c_uint64), ("log_cap", C.c_int64), ("gamma_tol", C.c_double),
                 ("drift_tol", C.c_double), ("rankk_tile", C.c_int32), ("drift_target", C.c_double),
-                ("recompute_mode", C.c_int32)]
+                ("n_matsubara", C.c_int32), ("recompute_mode", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -97,6 +98,7 @@ def load_library(path: str = LIB_PATH):
     lib.ctaux_obs_len.restype = i32
     lib.ctaux_obs_len.argtypes = [vp]
     lib.ctaux_get_obs.argtypes = [vp, i32, vp, i32]
+    lib.ctaux_get_obs_kw.argtypes = [vp, i32, vp, vp, i32]
     lib.ctaux_reset_obs.argtypes = [vp]
     lib.ctaux_get_stats.argtypes = [vp, i32, C.POINTER(_Stats)]
     lib.ctaux_get_config.argtypes = [vp, i32, i32, vp, C.POINTER(i32)]
@@ -132,12 +134,14 @@ class Options:
     drift_tol: float = 1e-2
     rankk_tile: int = 64
     drift_target: float = 0.0
+    n_matsubara: int = 0
     recompute_mode: int = 0
 
     def _c(self) -> _Opts:
         return _Opts(self.k_max, self.k_cap, self.p_flip, self.recompute_every, self.precision,
                      self.meas_every, self.n_therm, self.n_tau_out, self.n_cap, self.seed, self.log_cap,
-                     self.gamma_tol, self.drift_tol, self.rankk_tile, self.drift_target, self.recompute_mode)
+                     self.gamma_tol, self.drift_tol, self.rankk_tile, self.drift_target, self.n_matsubara,
+                     self.recompute_mode)
 
 
 def _ptr(a: np.ndarray):
@@ -161,12 +165,8 @@ class CtauxBatch:
         self._arrays = []
         models = (_Model * len(workloads))()
         for i, w in enumerate(workloads):
-            sd = np.ascontiguousarray(w.site_disp, np.int32)
-            gu = np.ascontiguousarray(w.g0_up, np.float64)
-            gd = np.ascontiguousarray(w.g0_dn, np.float64)
-            self._arrays += [sd, gu, gd]
-            models[i] = _Model(w.beta, w.U, w.K, w.n_sites, w.n_tau, w.n_disp, _ptr(sd), _ptr(gu),
-                               _ptr(gd))
+            models[i], keep = _model_of(w)
+            self._arrays += list(keep)
         self._models = models
         self._copts = opts._c()
         nbytes = self.lib.ctaux_workspace_bytes(C.byref(models), len(workloads), C.byref(self._copts))
@@ -216,6 +216,17 @@ class CtauxBatch:
         self._check(self.lib.ctaux_get_obs(self.h, chain, _ptr(out), n))
         w = self.workloads[chain]
         return out[: OBS_HEADER + 2 * w.n_disp * self.opts.n_tau_out]
+
+    def obs_kw(self, chain: int = 0):
+        """(accumulated sign * S(K, w_n), G0(K, i w_n)), complex [2, n_k, n_matsubara] each."""
+        w = self.workloads[chain]
+        nk, nm = w.kvecs.shape[0], self.opts.n_matsubara
+        s = np.zeros(4 * nk * nm)
+        g = np.zeros(4 * nk * nm)
+        self._check(self.lib.ctaux_get_obs_kw(self.h, chain, _ptr(s), _ptr(g), len(s)))
+        s = s.reshape(2, nk, nm, 2)
+        g = g.reshape(2, nk, nm, 2)
+        return s[..., 0] + 1j * s[..., 1], g[..., 0] + 1j * g[..., 1]
 
     def reset_obs(self):
         self._check(self.lib.ctaux_reset_obs(self.h))
@@ -283,10 +294,21 @@ class CtauxBatch:
 
 
 def _model_of(w):
+    """ctaux_model of a workload and the arrays it points to (kept alive by the caller)."""
     sd = np.ascontiguousarray(w.site_disp, np.int32)
     gu = np.ascontiguousarray(w.g0_up, np.float64)
     gd = np.ascontiguousarray(w.g0_dn, np.float64)
-    return _Model(w.beta, w.U, w.K, w.n_sites, w.n_tau, w.n_disp, _ptr(sd), _ptr(gu), _ptr(gd)), (sd, gu, gd)
+    keep = [sd, gu, gd]
+    pos = kv = None
+    n_k = 0
+    if getattr(w, "site_pos", None) is not None:
+        pos = np.ascontiguousarray(w.site_pos, np.float64)
+        kv = np.ascontiguousarray(w.kvecs, np.float64)
+        n_k = kv.shape[0]
+        keep += [pos, kv]
+    m = _Model(w.beta, w.U, w.K, w.n_sites, w.n_tau, w.n_disp, _ptr(sd), _ptr(gu), _ptr(gd),
+               _ptr(pos) if pos is not None else None, _ptr(kv) if kv is not None else None, n_k)
+    return m, keep
 
 
 def _vertices(tau, site, s):

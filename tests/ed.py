@@ -100,6 +100,20 @@ class ED:
         return float(np.einsum("a,ab,b,ba->", left, cx, right, cy) / self.Z)
 
 
+    def greens_matsubara(self, x: int, y: int, spin: int, omega: float) -> complex:
+        """int_0^beta e^{i omega tau} <T c_x(tau) c_y^dagger(0)> d tau for a fermionic
+        omega (Lehmann):  -(1/Z) sum_mn (e^{-beta E_n} + e^{-beta E_m}) <m|c_x|n><n|c_y^+|m>
+        / (i omega + E_m - E_n)."""
+        f = self.f
+        cx = self.v.T @ f.c[f.mode(x, spin)] @ self.v
+        cy = self.v.T @ f.c[f.mode(y, spin)].T @ self.v
+        e = self.e - self.e.min()
+        w = np.exp(-self.beta * e)
+        num = (w[None, :] + w[:, None]) * cx * cy.T          # [m, n]
+        den = 1j * omega + e[:, None] - e[None, :]
+        return complex(-(num / den).sum() / self.Z)
+
+
 def vertex_product(f: Fock, H0: np.ndarray, beta: float, gamma: float, verts,
                    extra=None) -> float:
     """Tr of the time-ordered product of Eq. (Zn).

@@ -162,6 +162,42 @@ def test_thermalisation_and_meas_cadence_match_oracle():
     _compare_obs(og, oo)
 
 
+def test_momentum_matsubara_measurement_matches_oracle():
+    """Measurement in cluster momenta and Matsubara frequencies: three chains of
+    different Nc (4x4 DCA cluster, the sign-problem plaquette, the dimer) in one
+    batch, with no G(tau) bins (n_tau_out = 0).  The sign-weighted S(K, w_n)
+    accumulators equal the oracle's (element by element; the same
+    configurations are measured) and G0(K, i w_n) equals the oracle's transform
+    of the interpolated tables."""
+    ctaux = _ctaux()
+    ws = [_cluster16(), hubbard_plaquette(), hubbard_dimer(beta=2.0, U=2.0, n_tau=2001)]
+    n_prop, nm = 3000, 6
+    opts = ctaux.Options(k_max=64, k_cap=48, n_cap=1024, log_cap=n_prop, meas_every=64, n_tau_out=0,
+                         n_matsubara=nm, recompute_every=16, seed=4)
+    gb = ctaux.CtauxBatch(ws, opts)
+    gb.run(n_prop)
+    for c, w in enumerate(ws):
+        oc = OracleChain(w, seed=4, chain_id=c, meas_every=64, n_tau_out=2, n_cap=1024)
+        oc.set_momentum(w.kvecs, w.site_pos, nm)
+        oc.set_log(n_prop)
+        oc.run(n_prop)
+        _compare(gb, oc, n_prop, chain=c)
+        og, oo = gb.obs(c), oc.obs()
+        assert og[0] == oo[0] > 0
+        np.testing.assert_allclose(og[:8] / og[0], oo[:8] / oo[0], rtol=1e-7, atol=1e-9)
+        S_g, G0_g = gb.obs_kw(c)
+        S_o = oc.obs_kw()
+        scale = np.abs(S_o).max()
+        print(f"[kw] chain {c} nc={w.n_sites}: max |S| {scale:.3e}, max diff {np.abs(S_g - S_o).max():.3e}",
+              flush=True)
+        np.testing.assert_allclose(S_g, S_o, rtol=1e-8, atol=1e-10 * scale)
+        for sec in (0, 1):
+            for q in range(len(w.kvecs)):
+                for n in range(nm):
+                    go = oc.g0_matsubara(sec, q, n)
+                    assert abs(G0_g[sec, q, n] - go) <= 1e-10 * abs(go) + 1e-13, (sec, q, n)
+
+
 def test_batched_chains_match_their_oracles():
     ctaux = _ctaux()
     ws = [_plaquette(), hubbard_dimer(beta=2.0, U=2.0, n_tau=2001), _plaquette(beta=2.0, U=6.0),

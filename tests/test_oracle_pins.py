@@ -334,6 +334,83 @@ def test_sign_bookkeeping_exact():
     np.testing.assert_allclose(o, acc, rtol=1e-10, atol=1e-12)
 
 
+_DIMER_R = [[0, 0, 0], [1, 0, 0]]
+_DIMER_K = [[0, 0, 0], [math.pi, 0, 0]]
+_PLAQ_R = [[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]]
+_PLAQ_K = [[0, 0, 0], [math.pi, 0, 0], [0, math.pi, 0], [math.pi, math.pi, 0]]
+
+
+def _ed_gk(ed, r, K, spin, omega):
+    """(1/Nc) sum_xy exp(-i K.(r_x - r_y)) G_xy(i omega) from exact diagonalisation."""
+    nc = len(r)
+    g = 0.0j
+    for x in range(nc):
+        for y in range(nc):
+            ph = -np.dot(K, np.subtract(r[x], r[y]))
+            g += np.exp(1j * ph) * ed.greens_matsubara(x, y, spin, omega)
+    return g / nc
+
+
+@pytest.mark.parametrize("make,r,K", [
+    (lambda: hubbard_dimer(beta=2.0, U=2.0, n_tau=4001), _DIMER_R, _DIMER_K),
+    (lambda: hubbard_plaquette(beta=4.0, U=4.0, tp=0.0, mu_tilde=0.0, n_tau=4001), _PLAQ_R, _PLAQ_K),
+])
+def test_g0_matsubara_against_noninteracting_lehmann(make, r, K):
+    """The oracle's G0(K, i w_n) (exact transform of the interpolated tables)
+    equals the non-interacting Lehmann sum to the interpolation error."""
+    w = make()
+    c = OracleChain(w)
+    c.set_momentum(K, r, 6)
+    ed0 = ED(w.meta["h1"], 0.0, w.beta, [])
+    for q in range(len(K)):
+        for n in range(6):
+            om = (2 * n + 1) * math.pi / w.beta
+            ex = _ed_gk(ed0, r, K[q], 0, om)
+            got = c.g0_matsubara(0, q, n)
+            assert abs(got - ex) <= 2e-6 * abs(ex) + 1e-9, (q, n, got, ex)
+
+
+@pytest.mark.parametrize("make,r,K,n_prop", [
+    (lambda: hubbard_dimer(beta=2.0, U=2.0, n_tau=4001), _DIMER_R, _DIMER_K, 15000),
+    (lambda: hubbard_plaquette(beta=4.0, U=4.0, tp=0.0, mu_tilde=0.0, n_tau=4001), _PLAQ_R, _PLAQ_K, 8000),
+])
+def test_momentum_matsubara_estimator_against_lehmann(make, r, K, n_prop):
+    """G(K, i w_n) = G0 + G0^2 <S> / (beta Nc) from the walk's momentum /
+    Matsubara accumulators against the interacting Lehmann G(K, i w_n) of
+    exact diagonalisation (real and imaginary parts, every K and w_n)."""
+    w = make()
+    nm = 4
+    ed = ED(w.meta["h1"], w.U, w.beta, range(w.n_sites))
+    vals = []
+    for seed in range(4):
+        c = OracleChain(w, seed=seed, meas_every=4, n_tau_out=2)
+        c.set_momentum(K, r, nm)
+        c.run(3000)
+        for _ in range(6):
+            c.reset_obs()
+            c.run(n_prop)
+            o = c.obs()
+            vals.append(c.obs_kw() / o[1])   # sign-weighted mean of S
+    S, Se = _mean_err(np.array(vals).real), _mean_err(np.array(vals).imag)
+    means, errs, exact = [], [], []
+    for q in range(len(K)):
+        for n in range(nm):
+            om = (2 * n + 1) * math.pi / w.beta
+            g0 = c.g0_matsubara(0, q, n)
+            fac = g0 * g0 / (w.beta * w.n_sites)
+            ex = _ed_gk(ed, r, K[q], 0, om)
+            # G = g0 + fac S: propagate the error of S through the complex factor
+            s_mean = S[0][0, q, n] + 1j * Se[0][0, q, n]
+            g = g0 + fac * s_mean
+            err_re = math.hypot(fac.real * S[1][0, q, n], fac.imag * Se[1][0, q, n])
+            err_im = math.hypot(fac.imag * S[1][0, q, n], fac.real * Se[1][0, q, n])
+            means += [g.real, g.imag]
+            errs += [err_re, err_im]
+            exact += [ex.real, ex.imag]
+    ok, z = _family_ok(means, errs, exact)
+    assert ok, z
+
+
 def test_hubbard_atom_closed_forms():
     """Isolated atom at half filling: D = 1/(2(1+e^{beta U/2})),
     G(tau) = (e^{tau U/2} + e^{(beta - tau) U/2}) / (2 + 2 e^{beta U/2})."""
