@@ -16,13 +16,17 @@ the rank-k TFLOP/s, the roofline of the dominant kernel (per-launch device
 time from HIP events on the library's stream over the timed region), the CPU
 oracle timed on a bounded sample of the same workload, and further forms:
   mixed       the same chain with N in FP32 (FP32 MFMA rank-k update), at the
-              default drift target and at an N error target of 1e-6;
+              default drift target and at an N error target of 1e-6, and with
+              the split-BF16x3 rank-k update;
   cfg2x128    128 independent chains of the headline workload, FP64 and FP32
               storage (mixed/batched vs plain on one workload);
   batched     512 chains of mixed clusters (Nc in {4, 8, 16, 32}, beta in
-              [4, 12], U in [4, 8], K = 1), FP64, k and tile autotuned;
-  config3     6x6 cluster, beta = 10, order ~3000, FP32 storage with FP64
-              refresh every <= 64 blocks, and the same in FP64;
+              [4, 12], U in [4, 8], K = 1), FP64, k and tile autotuned, with the
+              real-space G(tau) measurement and again measuring in cluster
+              momenta and Matsubara frequencies;
+  config3     6x6 cluster, beta = 10, order ~3000, FP32 storage (FP32 MFMA and
+              split-BF16x3 rank-k) with FP64 refresh every <= 64 blocks, and the
+              same in FP64;
   config5     3D Nc = 100 cluster, beta = 6, order ~5000, 8 chains, FP32
               storage with FP64 refresh every <= 32 blocks.
 Each form reports its N error: the largest refinement drift of the run
@@ -298,6 +302,21 @@ def leg_batched(ctaux, args):
     return out
 
 
+def leg_batched_kw(ctaux, args, opts_like):
+    """The same 512 chains measuring G in cluster momenta and 8 Matsubara
+    frequencies instead of the real-space G(tau) bins (densities and double
+    occupancy still from the equal-time G)."""
+    from dataclasses import replace
+    from ctaux_inputs import batched_mix
+    ws = batched_mix(n_chains=args.batch_chains, seed=0, n_tau=2048, n_fine=16)
+    opts = replace(opts_like, n_tau_out=0, n_matsubara=8)
+    gb, d, therm = many_chains(ctaux, ws, opts, args.batch_steps, 60, 20)
+    out = form(gb, d, therm, {"options": {"k_max": opts.k_max, "k_cap": opts.k_cap, "rankk_tile": opts.rankk_tile,
+                                          "n_tau_out": 0, "n_matsubara": 8}})
+    gb.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,6 +392,9 @@ def main():
         g2, d2, t2 = single_chain(ctaux, w, ctaux.CTAUX_FP32, args.steps, args.warmup, drift_target=1e-6)
         forms["mixed_fp32_target_1e-6"] = form(g2, d2, t2, {"drift_target": 1e-6})
         g2.close()
+        g2, d2, t2 = single_chain(ctaux, w, ctaux.CTAUX_BF16X3, args.steps, args.warmup)
+        forms["mixed_bf16x3"] = form(g2, d2, t2)
+        g2.close()
     if "cfg2x128" in legs:
         for name, prec in (("cfg2x128_fp64", ctaux.CTAUX_FP64), ("cfg2x128_fp32", ctaux.CTAUX_FP32)):
             log(f"{name}: 128 chains of the headline workload")
@@ -383,10 +405,16 @@ def main():
     if "batched" in legs:
         log(f"batched_fp64 leg: {args.batch_chains} chains")
         forms["batched_fp64"] = leg_batched(ctaux, args)
+        o = forms["batched_fp64"]["options"]
+        log("batched_fp64_kw: the same chains measuring in cluster momenta / Matsubara frequencies")
+        forms["batched_fp64_kw"] = leg_batched_kw(
+            ctaux, args, ctaux.Options(k_max=o["k_max"], k_cap=o["k_cap"], rankk_tile=o["rankk_tile"],
+                                       recompute_every=64, meas_every=64, n_tau_out=8, n_cap=2048, seed=0))
     if "config3" in legs:
         from ctaux_inputs import dca_square
         w3 = dca_square(L=6, beta=10.0, U=8.0, K=1800.0, density=0.9, n_tau=8192)
-        for name, prec in (("config3_fp32", ctaux.CTAUX_FP32), ("config3_fp64", ctaux.CTAUX_FP64)):
+        for name, prec in (("config3_fp32", ctaux.CTAUX_FP32), ("config3_bf16x3", ctaux.CTAUX_BF16X3),
+                           ("config3_fp64", ctaux.CTAUX_FP64)):
             log(f"{name}: 6x6 cluster, order ~3000")
             g3, d3, t3 = single_chain(ctaux, w3, prec, 100, 200, k=128, n_cap=4096, chunk=40,
                                       n_tau_out=8)

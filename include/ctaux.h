@@ -57,6 +57,10 @@ extern "C" {
 
 #define CTAUX_FP64 0          /* N stored and updated in FP64 (FP64 MFMA)               */
 #define CTAUX_FP32 1          /* N stored in FP32, rank-k update on FP32 MFMA, FP64 Gamma */
+#define CTAUX_BF16X3 2        /* N stored in FP32, rank-k update as split-BF16x3: each FP32
+                                 operand split into two BF16 terms (hi + lo), the product taken
+                                 as hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32 accumulation
+                                 (~2^-16 relative per product); FP64 Gamma                    */
 
 /* Model of one chain (Sec. II A).  U >= 0, K > 0, beta > 0.
  * gamma is fixed by cosh(gamma) = 1 + beta*U*n_sites/(2K)  (Eq. gamma; the
@@ -93,7 +97,7 @@ typedef struct {
                                  interval).  After each refinement of a chain its interval is
                                  quartered when the drift exceeded drift_target and doubled
                                  when the drift stayed below drift_target / 16              */
-    int32_t precision;        /* CTAUX_FP64 or CTAUX_FP32                                     */
+    int32_t precision;        /* CTAUX_FP64, CTAUX_FP32 or CTAUX_BF16X3                       */
     int32_t meas_every;       /* measure after every meas_every proposals ...                 */
     int64_t n_therm;          /* ... once more than n_therm proposals are done                */
     int32_t n_tau_out;        /* G(tau) output points tau_j = (j+1/2) beta / n_tau_out (0: none;

@@ -147,8 +147,8 @@ int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, c
     return set_err(eb, CTAUX_EINVAL, "gamma_tol and drift_tol must be finite");
   if (o->rankk_tile != 0 && o->rankk_tile != 32 && o->rankk_tile != 64)
     return set_err(eb, CTAUX_EINVAL, "rankk_tile must be 0, 32 or 64");
-  if (o->precision != CTAUX_FP64 && o->precision != CTAUX_FP32)
-    return set_err(eb, CTAUX_EINVAL, "precision must be CTAUX_FP64 or CTAUX_FP32");
+  if (o->precision != CTAUX_FP64 && o->precision != CTAUX_FP32 && o->precision != CTAUX_BF16X3)
+    return set_err(eb, CTAUX_EINVAL, "precision must be CTAUX_FP64, CTAUX_FP32 or CTAUX_BF16X3");
   if (o->meas_every < 1 || o->n_tau_out < 0 || o->n_tau_out > 4096 || o->n_cap < 1 || o->n_cap > 65536 ||
       o->recompute_every < 0 || o->n_therm < 0 || o->log_cap < 0)
     return set_err(eb, CTAUX_EINVAL, "invalid meas_every/n_tau_out/n_cap/recompute_every/n_therm/log_cap");

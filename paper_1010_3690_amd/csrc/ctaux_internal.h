@@ -16,7 +16,7 @@ constexpr int kMaxKcap = 64;    // Gamma capacity per block (Gamma^{-1} of both 
 constexpr int kMaxKmax = 128;   // proposals per block
 
 
-enum Precision : int32_t { kFP64 = 0, kFP32 = 1 };
+enum Precision : int32_t { kFP64 = 0, kFP32 = 1, kBF16X3 = 2 };   // storage of N: FP64, FP32, FP32
 
 struct ChainDesc {
   // ---- model (Sec. II A) ----

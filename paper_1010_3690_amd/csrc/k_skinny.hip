@@ -520,7 +520,7 @@ void launch_skinny(const Batch &b, hipStream_t s, int kind) {
   // Products with K = k_a (B_c) are short: one wave per item.  Otherwise split K
   // across the waves of a workgroup when few chains run (long K, few items).
   const bool wave = (kind == kSkAsmB || b.n_chains >= 8);
-  if (b.precision == kFP32) {
+  if (b.precision != kFP64) {
     if (wave) launch_m<float, kModeWave>(b, s, kind, nrt);
     else launch_m<float, kModeSplitK>(b, s, kind, nrt);
   } else {
@@ -531,14 +531,14 @@ void launch_skinny(const Batch &b, hipStream_t s, int kind) {
 
 void launch_operands(const Batch &b, hipStream_t s) {
   if (b.n_chains >= 8) {   // Ac here, Bc as a persistent skinny product
-    if (b.precision == kFP32) launch_ops<float, 0>(b, s);
+    if (b.precision != kFP64) launch_ops<float, 0>(b, s);
     else launch_ops<double, 0>(b, s);
     launch_skinny(b, s, kSkAsmB);
     return;
   }
   // row tiles of Bc cover k_cap (<= 64) rounded up to 8
   const int nrt = host_row_tiles((b.kcap + 7) & ~7);
-  if (b.precision == kFP32) {
+  if (b.precision != kFP64) {
     if (nrt == 1) launch_ops<float, 1>(b, s);
     else if (nrt == 2) launch_ops<float, 2>(b, s);
     else launch_ops<float, 4>(b, s);

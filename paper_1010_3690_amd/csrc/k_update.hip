@@ -50,6 +50,24 @@ struct Mfma<float> {
   }
 };
 
+// Split-BF16x3 products: an FP32 value x is split into bf16 terms hi = rne(x) and
+// lo = rne(x - hi); a b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b (the lo lo term,
+// ~2^-16 of the product, is dropped).  mfma_f32_16x16x16bf16_1k: lane l supplies
+// A[l%16][4(l/16) + i] and B[4(l/16) + i][l%16], i < 4, and receives D in the
+// layout of the FP32 16x16x4 instruction (row 4(l/16) + q).
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned bf16_rne_bits(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;   // finite x
+}
+
+__device__ __forceinline__ void split_bf16(float x, short &hi, short &lo) {
+  const unsigned h = bf16_rne_bits(x);
+  hi = static_cast<short>(h);
+  lo = static_cast<short>(bf16_rne_bits(x - __uint_as_float(h << 16)));
+}
+
 // Base value N_a(map i', map j') in the storage type.
 template <typename T>
 __device__ __forceinline__ T base_entry(const ChainDesc &d, const T *N, const double *Rt, int n, int mi, int mj) {
@@ -64,7 +82,7 @@ __device__ __forceinline__ T base_entry(const ChainDesc &d, const T *N, const do
 // TILE/2 square of NB x NB MFMA blocks.  Persistent over the tiles of all
 // chains: chain c owns tiles [prefix[c], prefix[c+1]), 2 sectors x
 // ceil(n'/TILE)^2 each; every workgroup builds the prefix in LDS first.
-template <typename T, int TILE>
+template <typename T, int TILE, bool BF3 = false>
 __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const ChainState *states, int n_chains) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int SUB = TILE / 2, NB = SUB / 16;
@@ -142,7 +160,50 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
     for (int i = 0; i < NB; ++i)
 #pragma unroll
       for (int j = 0; j < NB; ++j) acc[i][j] = Mfma<T>::zero();
-    if (ka > 0) {
+    if constexpr (BF3) {
+     if (ka > 0) {
+      // split-BF16x3, k in steps of 16; entries beyond k_a are masked to zero
+      for (int k0 = 0; k0 < ka; k0 += 16) {
+        v4s ahi[NB], alo[NB], bhi[NB], blo[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int r = row0 + i * 16 + lr;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int k = k0 + 4 * lk + e;
+            const float a = (r < np && k < ka) ? static_cast<float>(Ac[static_cast<size_t>(r) * lda + k]) : 0.f;
+            short h, l;
+            split_bf16(a, h, l);
+            ahi[i][e] = h;
+            alo[i][e] = l;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int cc = col0 + j * 16 + lr;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int k = k0 + 4 * lk + e;
+            const float b = (cc < np && k < ka) ? static_cast<float>(Bc[static_cast<size_t>(k) * ldn + cc]) : 0.f;
+            short h, l;
+            split_bf16(b, h, l);
+            bhi[j][e] = h;
+            blo[j][e] = l;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            v4f c = acc[i][j];
+            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], bhi[j], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[i], blo[j], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[i], bhi[j], c, 0, 0, 0);
+            acc[i][j] = c;
+          }
+      }
+     }
+    } else if (ka > 0) {
       // k in batches of KS k-steps; the next batch's operands are loaded before
       // the current batch's products (two batches in flight).  Ac and Bc are zero
       // between k_a and kpad; steps past kpad load nothing.
@@ -216,8 +277,18 @@ static void launch_rankk_t(const Batch &b, hipStream_t s) {
 }
 
 void launch_rankk(const Batch &b, hipStream_t s) {
-  if (b.precision == kFP64) launch_rankk_t<double>(b, s);
-  else launch_rankk_t<float>(b, s);
+  if (b.precision == kFP64) {
+    launch_rankk_t<double>(b, s);
+  } else if (b.precision == kFP32) {
+    launch_rankk_t<float>(b, s);
+  } else {
+    const int grid = b.n_cu * 8;
+    const size_t lds = sizeof(int) * (b.n_chains + 1);
+    if (b.rankk_tile == 32)
+      hipLaunchKernelGGL((k_rankk<float, 32, true>), dim3(grid), dim3(256), lds, s, b.d_desc, b.d_state, b.n_chains);
+    else
+      hipLaunchKernelGGL((k_rankk<float, 64, true>), dim3(grid), dim3(256), lds, s, b.d_desc, b.d_state, b.n_chains);
+  }
 }
 
 }  // namespace ctaux

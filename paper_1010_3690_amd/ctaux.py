@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libctaux_hip.so")
 
 CTAUX_OK, CTAUX_EINVAL, CTAUX_ENOMEM, CTAUX_EDEVICE, CTAUX_ENUMERIC, CTAUX_ECAPACITY = 0, -1, -2, -3, -4, -5
-CTAUX_FP64, CTAUX_FP32 = 0, 1
+CTAUX_FP64, CTAUX_FP32, CTAUX_BF16X3 = 0, 1, 2
 OBS_HEADER = 8
 # order of the per-kernel timing entries (ctaux_get_timing)
 TIMED_KERNELS = ["block_begin", "interp", "prep", "propose", "assemble", "rankk", "block_end", "measure",

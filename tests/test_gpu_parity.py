@@ -309,6 +309,40 @@ def test_fp32_storage_error_and_refinement():
         assert np.linalg.norm(gb.N(0, sec) - ref) / np.linalg.norm(ref) < 1e-6
 
 
+def test_bf16x3_storage_error_and_refinement():
+    """Split-BF16x3 rank-k update (FP32 storage): N against the FP64 inverse of
+    the same configuration, beside FP32 MFMA on the same chain; a refinement
+    restores the FP32 rounding of the FP64 inverse."""
+    ctaux = _ctaux()
+    w = _cluster16()
+    errs = {}
+    for prec in (ctaux.CTAUX_FP32, ctaux.CTAUX_BF16X3):
+        opts = ctaux.Options(k_max=64, k_cap=48, n_cap=1024, recompute_every=0, precision=prec, seed=5,
+                             log_cap=4000)
+        gb = ctaux.CtauxBatch([w], opts)
+        gb.run(4000)
+        ids, tau, site, s = gb.config(0)
+        oc = OracleChain(w, n_cap=1024)
+        e = []
+        for sec in (0, 1):
+            ref = np.linalg.inv(oc.M_of(sec, tau, site, s))
+            e.append(np.linalg.norm(gb.N(0, sec) - ref) / np.linalg.norm(ref))
+        errs[prec] = max(e)
+        gb.recompute()
+        for sec in (0, 1):
+            ref = np.linalg.inv(oc.M_of(sec, tau, site, s))
+            assert np.linalg.norm(gb.N(0, sec) - ref) / np.linalg.norm(ref) < 1e-6
+        if prec == ctaux.CTAUX_BF16X3:
+            # the first decisions (before N carries enough error to flip one) are the oracle's
+            oc2 = OracleChain(w, seed=5, n_cap=1024)
+            oc2.set_log(1000)
+            oc2.run(1000)
+            assert np.array_equal(gb.decisions(0, 0, 1000)[0], oc2.get_log(0, 1000)[0])
+    print(f"[bf16x3] N error after 4000 proposals: FP32 {errs[ctaux.CTAUX_FP32]:.2e}, "
+          f"BF16x3 {errs[ctaux.CTAUX_BF16X3]:.2e}", flush=True)
+    assert errs[ctaux.CTAUX_BF16X3] < 1e-2
+
+
 def test_u_zero_walk():
     ctaux = _ctaux()
     w = hubbard_atom(beta=2.0, U=0.0, K=3.0)
