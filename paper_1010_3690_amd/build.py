@@ -39,6 +39,21 @@ def _compile(src: str) -> str:
     return obj
 
 
+CPU_LIB = os.path.join(LIBDIR, "libctaux_cpu.so")
+CXX = os.environ.get("CXX", "g++")
+# the host library runs on other x86-64 hosts than the build's: AVX2 + FMA, no -march=native
+CPU_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "-mavx2", "-mfma", "-Wall", "-I", os.path.join(ROOT, "include")]
+
+
+def build_cpu() -> str:
+    """The host (CPU) submatrix library, libctaux_cpu.so."""
+    os.makedirs(LIBDIR, exist_ok=True)
+    tmp = CPU_LIB + ".tmp"
+    subprocess.check_call([CXX, *CPU_FLAGS, "-o", tmp, os.path.join(CSRC, "cpu_submatrix.cpp")])
+    os.replace(tmp, CPU_LIB)
+    return CPU_LIB
+
+
 def build(jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
@@ -48,6 +63,7 @@ def build(jobs: int = 8) -> str:
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_cpu()
     return LIB
 
 
