@@ -28,7 +28,9 @@ oracle timed on a bounded sample of the same workload, and further forms:
               split-BF16x3 rank-k) with FP64 refresh every <= 64 blocks, and the
               same in FP64;
   config5     3D Nc = 100 cluster, beta = 6, order ~5000, 8 chains, FP32
-              storage with FP64 refresh every <= 32 blocks.
+              storage with FP64 refresh every <= 32 blocks;
+  cpu         the host FP64 submatrix form on one core, on the oracle's
+              sample, with and without the measurement, beside the oracle.
 Each form reports its N error: the largest refinement drift of the run
 (||N - N_refined|| / ||N_refined|| before each refinement) and the drift of a
 refinement taken at the end of the timed region.
@@ -52,7 +54,7 @@ FP32_PEAK_TFS = 157.3
 N_CU = 256
 
 METRIC = "vertex updates/s + rank-k TFLOP/s, mixed/batched vs plain FP64, same GPU"
-ALL_LEGS = "plain,mixed,cfg2x128,batched,config3,config5"
+ALL_LEGS = "plain,mixed,cfg2x128,batched,config3,config5,cpu"
 
 
 def log(msg):
@@ -213,23 +215,60 @@ def host_info():
 def cpu_baseline(w, config, therm_blocks, budget_s=15.0):
     """The oracle (rank-1 CT-AUX, one core) on a bounded sample of the workload:
     it starts from the configuration the GPU chain reached after thermalisation
-    and runs proposals until about budget_s seconds have elapsed."""
+    and runs proposals until about budget_s seconds have elapsed, measuring
+    every 64 proposals like the GPU chain; then a third as long with the
+    measurement off (the update rate alone, compared with the host submatrix
+    form)."""
     from oracle import OracleChain
     ids, tau, site, s = config
-    oc = OracleChain(w, seed=12345, meas_every=64, n_tau_out=16, n_cap=4096)
-    oc.set_config(ids, tau, site, s)
-    oc.set_state(0, int(ids.max()) + 1 if len(ids) else 0, 1.0)
-    done = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        oc.run(16)
-        done += 16
-    el = time.perf_counter() - t0
+
+    def sample(meas_every, seconds):
+        oc = OracleChain(w, seed=12345, meas_every=meas_every, n_tau_out=16, n_cap=4096)
+        oc.set_config(ids, tau, site, s)
+        oc.set_state(0, int(ids.max()) + 1 if len(ids) else 0, 1.0)
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            oc.run(16)
+            done += 16
+        return done, time.perf_counter() - t0
+
+    done, el = sample(64, budget_s)
+    done_nm, el_nm = sample(1 << 30, budget_s / 3)
     out = {"value": done / el, "unit": "vertex updates/s", "cores": 1, "kind": "oracle",
            "sample": f"{done} proposals of the headline chain from the order-{len(ids)} configuration the GPU "
-                     f"chain reached after {therm_blocks} blocks of thermalisation, {el:.1f} s on one host core "
-                     f"(the oracle is single-threaded)"}
+                     f"chain reached after {therm_blocks} blocks of thermalisation, measuring every 64 proposals, "
+                     f"{el:.1f} s on one host core (the oracle is single-threaded)",
+           "no_measurement": {"value": done_nm / el_nm, "proposals": done_nm, "seconds": el_nm}}
     out.update({"host_" + k: v for k, v in host_info().items()})
+    return out
+
+
+def leg_cpu_submatrix(w, config, oracle, budget_s=10.0):
+    """The host FP64 submatrix form (one core, k = 64, AVX2 register tiles) on the
+    oracle's sample: the same starting configuration, measuring every 64
+    proposals, then with the measurement off; each rate beside the oracle's
+    under the same settings (the paper compares the two update rates on one
+    core)."""
+    from paper_1010_3690_amd import ctaux
+    from paper_1010_3690_amd.cpu import CpuChain
+    ids, tau, site, s = config
+    out = {"cores": 1, "k": 64, "host_cpu": host_info()["cpu"]}
+    for name, meas in (("measuring", 64), ("no_measurement", 1 << 30)):
+        ch = CpuChain(w, ctaux.Options(k_max=64, k_cap=64, p_flip=0.2, meas_every=meas, n_tau_out=16,
+                                       n_cap=4096, seed=12345))
+        ch.set_config(ids, tau, site, s)
+        ch.run(64 * 4)   # first blocks: buffers sized
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s / 2:
+            ch.run(64 * 4)
+            done += 64 * 4
+        el = time.perf_counter() - t0
+        rate = done / el
+        ref = oracle["value"] if name == "measuring" else oracle["no_measurement"]["value"]
+        out[name] = {"updates_per_s": rate, "proposals": done, "seconds": el, "mean_order_end": ch.state()["order"],
+                     "oracle_updates_per_s": ref, "vs_oracle": rate / ref}
     return out
 
 
@@ -432,6 +471,9 @@ def main():
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(w, config0, therm["blocks"], args.cpu_budget)
+        if "cpu" in legs:
+            log("cpu_submatrix_fp64: host submatrix form on the oracle's sample")
+            forms["cpu_submatrix_fp64"] = leg_cpu_submatrix(w, config0, out["cpu_baseline"])
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))

@@ -8,7 +8,7 @@
 //  * candidates j (the block's insertion proposals, in order) are pre-inserted
 //    with spin 0; the augmented N_a = [[N, 0], [Rt, 1]] with Rt = X N,
 //    X_ji = G0(tau_j - tau_i)(e^{V_i} - 1), and G of the candidate columns,
-//    YT = (N Z)^T with Z_ij = G0(tau_i - tau_j), Gnn = X Y + G0nn (Sec. IV A);
+//    Y = N Z with Z_ij = G0(tau_i - tau_j), Gnn = X Y + G0nn (Sec. IV A);
 //  * Gamma is kept column-scaled, Gamma~ = Gamma D^{-1} with D_b = e^{V_b}/(e^{V_b} - 1)
 //    for an old vertex and 1 for a candidate, so its entries are those of
 //    (N_a - I) (old columns) or (G - I) (candidate columns) minus 1/(gh_b D_b) on
@@ -27,12 +27,115 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <immintrin.h>
+
+#include <algorithm>
 #include <string>
 #include <vector>
 
 #include "../../include/ctaux_cpu.h"
 
 namespace {
+
+// ---- C += alpha A B on row-major FP64 arrays, read in place ----
+// A kMr x kNr tile of C accumulates in twelve AVX2 registers (named
+// variables, so that they are not kept in memory): per k step, kMr broadcasts
+// of A and two loads of a row of B feed twelve FMAs.  The caller chooses
+// leading dimensions that are not multiples of 512 doubles (N's is 64 m + 8),
+// so that the rows of a tile fall in different cache sets.
+constexpr int kMr = 6, kNr = 8, kKc = 256;
+
+// full-width tile; rows of A beyond mr repeat row 0 and are not stored
+void tile(int mr, int k, const double *a, int lda, const double *b, int ldb, double *c, int ldc, double alpha) {
+  const double *a0 = a, *a1 = mr > 1 ? a + lda : a, *a2 = mr > 2 ? a + 2 * static_cast<size_t>(lda) : a;
+  const double *a3 = mr > 3 ? a + 3 * static_cast<size_t>(lda) : a, *a4 = mr > 4 ? a + 4 * static_cast<size_t>(lda) : a;
+  const double *a5 = mr > 5 ? a + 5 * static_cast<size_t>(lda) : a;
+  __m256d c00 = _mm256_setzero_pd(), c01 = c00, c10 = c00, c11 = c00, c20 = c00, c21 = c00;
+  __m256d c30 = c00, c31 = c00, c40 = c00, c41 = c00, c50 = c00, c51 = c00;
+  for (int p = 0; p < k; ++p) {
+    const double *bp = b + static_cast<size_t>(p) * ldb;
+    const __m256d b0 = _mm256_loadu_pd(bp), b1 = _mm256_loadu_pd(bp + 4);
+    __m256d ar = _mm256_broadcast_sd(a0 + p);
+    c00 = _mm256_fmadd_pd(ar, b0, c00); c01 = _mm256_fmadd_pd(ar, b1, c01);
+    ar = _mm256_broadcast_sd(a1 + p);
+    c10 = _mm256_fmadd_pd(ar, b0, c10); c11 = _mm256_fmadd_pd(ar, b1, c11);
+    ar = _mm256_broadcast_sd(a2 + p);
+    c20 = _mm256_fmadd_pd(ar, b0, c20); c21 = _mm256_fmadd_pd(ar, b1, c21);
+    ar = _mm256_broadcast_sd(a3 + p);
+    c30 = _mm256_fmadd_pd(ar, b0, c30); c31 = _mm256_fmadd_pd(ar, b1, c31);
+    ar = _mm256_broadcast_sd(a4 + p);
+    c40 = _mm256_fmadd_pd(ar, b0, c40); c41 = _mm256_fmadd_pd(ar, b1, c41);
+    ar = _mm256_broadcast_sd(a5 + p);
+    c50 = _mm256_fmadd_pd(ar, b0, c50); c51 = _mm256_fmadd_pd(ar, b1, c51);
+  }
+  const __m256d al = _mm256_set1_pd(alpha);
+  auto put = [&](int r, __m256d v0, __m256d v1) {
+    double *cr = c + static_cast<size_t>(r) * ldc;
+    _mm256_storeu_pd(cr, _mm256_fmadd_pd(al, v0, _mm256_loadu_pd(cr)));
+    _mm256_storeu_pd(cr + 4, _mm256_fmadd_pd(al, v1, _mm256_loadu_pd(cr + 4)));
+  };
+  put(0, c00, c01);
+  if (mr > 1) put(1, c10, c11);
+  if (mr > 2) put(2, c20, c21);
+  if (mr > 3) put(3, c30, c31);
+  if (mr > 4) put(4, c40, c41);
+  if (mr > 5) put(5, c50, c51);
+}
+
+// tile narrower than kNr (the last columns of C)
+void tile_edge(int mr, int nr, int k, const double *a, int lda, const double *b, int ldb, double *c, int ldc,
+               double alpha) {
+  double acc[kMr][kNr] = {};
+  for (int p = 0; p < k; ++p)
+    for (int r = 0; r < mr; ++r) {
+      const double ar = a[static_cast<size_t>(r) * lda + p];
+      for (int q = 0; q < nr; ++q) acc[r][q] += ar * b[static_cast<size_t>(p) * ldb + q];
+    }
+  for (int r = 0; r < mr; ++r)
+    for (int q = 0; q < nr; ++q) c[static_cast<size_t>(r) * ldc + q] += alpha * acc[r][q];
+}
+
+// C (m x n) += alpha A (m x k) B (k x n), alpha = +-1.  For each panel of kNr
+// columns of B (kKc rows, held in L1) every strip of kMr rows of A passes.
+void gemm(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+          double alpha) {
+  for (int pc = 0; pc < k; pc += kKc) {
+    const int kb = std::min(kKc, k - pc);
+    for (int j0 = 0; j0 < n; j0 += kNr) {
+      const int nr = std::min(kNr, n - j0);
+      const double *b = B + static_cast<size_t>(pc) * ldb + j0;
+      for (int i0 = 0; i0 < m; i0 += kMr) {
+        const int mr = std::min(kMr, m - i0);
+        const double *a = A + static_cast<size_t>(i0) * lda + pc;
+        double *c = C + static_cast<size_t>(i0) * ldc + j0;
+        if (nr == kNr)
+          tile(mr, kb, a, lda, b, ldb, c, ldc, alpha);
+        else
+          tile_edge(mr, nr, kb, a, lda, b, ldb, c, ldc, alpha);
+      }
+    }
+  }
+}
+
+// Y += N Z and Rt += X N in one pass over N (n0 x n0, leading dimension ldn):
+// each block of kBr rows x kBw columns of N serves both products while it is
+// in L1/L2 (Z, Y: n0 x kp; X, Rt: ki x n0)
+void prep_products(int n0, int ki, int kp, const double *Nm, int ldn, const double *X, const double *Z, double *Y,
+                   double *Rt) {
+  constexpr int kBr = 24, kBw = 256;
+  for (int c0 = 0; c0 < n0; c0 += kBw) {
+    const int w = std::min(kBw, n0 - c0);
+    for (int i0 = 0; i0 < n0; i0 += kBr) {
+      const int r = std::min(kBr, n0 - i0);
+      const double *blk = Nm + static_cast<size_t>(i0) * ldn + c0;
+      gemm(r, kp, w, blk, ldn, Z + static_cast<size_t>(c0) * kp, kp, Y + static_cast<size_t>(i0) * kp, kp, 1.0);
+      gemm(ki, w, r, X + i0, n0, blk, ldn, Rt + c0, n0, 1.0);
+    }
+  }
+}
+
+// leading dimension of an array of rows of length n: 64 m + 8 doubles
+int pad_ld(int n) { return (n + 63) / 64 * 64 + 8; }
 
 // ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ----
 void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
@@ -113,7 +216,7 @@ struct ctaux_cpu_chain {
   std::vector<double> g0[2];
   double ev[2][5];   // exp(gamma sigma d), d = -2..2
   // options
-  int kmax, meas_every, n_out, n_cap;
+  int kmax, meas_every, n_out, n_cap, ldn;   // ldn: leading dimension of N
   int64_t n_therm, log_cap;
   uint64_t seed;
   uint32_t chain_id;
@@ -124,9 +227,9 @@ struct ctaux_cpu_chain {
   std::vector<int64_t> id;
   std::vector<double> tau;
   std::vector<int32_t> site, spin;
-  std::vector<double> N[2][2];   // [parity][sector], n_cap x n_cap
+  std::vector<double> N[2][2];   // [parity][sector], n_cap rows of ldn
   // block buffers
-  std::vector<double> X[2], ZT[2], Rt[2], YT[2], Gnn[2];
+  std::vector<double> X[2], Z[2], Rt[2], Y[2], Gnn[2];   // X, Rt: ki x n0; Z, Y: n0 x kp; Gnn: ki x kp
   std::vector<double> Xi[2];     // Gamma~^{-1} (kmax x kmax, leading dimension kmax)
   std::vector<double> obs;
   std::vector<uint8_t> log_acc;
@@ -156,7 +259,7 @@ struct ctaux_cpu_chain {
     return sg * ((1.0 - w) * t[m] + w * t[m + 1]);
   }
   double e(int sec, int d) const { return ev[sec][d + 2]; }
-  double *Nrow(int p, int sec, int i) { return N[p][sec].data() + static_cast<size_t>(i) * n_cap; }
+  double *Nrow(int p, int sec, int i) { return N[p][sec].data() + static_cast<size_t>(i) * ldn; }
 
   int block(int64_t L);
   void measure();
@@ -183,85 +286,35 @@ int ctaux_cpu_chain::block(int64_t L) {
     }
   }
   const int ki = static_cast<int>(ctau.size()), na = n0 + ki;
+  const int kp = (ki + kNr - 1) / kNr * kNr;   // candidate columns padded to whole register tiles
   // ---- preparation products, per sector ----
   for (int sec = 0; sec < 2; ++sec) {
     X[sec].assign(static_cast<size_t>(ki) * n0, 0.0);
-    ZT[sec].assign(static_cast<size_t>(ki) * n0, 0.0);
+    Z[sec].assign(static_cast<size_t>(n0) * kp, 0.0);
     Rt[sec].assign(static_cast<size_t>(ki) * n0, 0.0);
-    YT[sec].assign(static_cast<size_t>(ki) * n0, 0.0);
-    Gnn[sec].assign(static_cast<size_t>(ki) * ki, 0.0);
-    for (int j = 0; j < ki; ++j)
-      for (int i = 0; i < n0; ++i) {
-        X[sec][static_cast<size_t>(j) * n0 + i] = g0v(sec, csite[j], site[i], ctau[j] - tau[i]) * (e(sec, spin[i]) - 1.0);
-        ZT[sec][static_cast<size_t>(j) * n0 + i] = g0v(sec, site[i], csite[j], tau[i] - ctau[j]);
-      }
-    // Rt = X N: four rows of N at a time are read once and used by every
-    // candidate (four FMAs per load and store of a row of Rt)
-    {
-      int i = 0;
-      for (; i + 4 <= n0; i += 4) {
-        const double *n0r = Nrow(par, sec, i), *n1r = Nrow(par, sec, i + 1);
-        const double *n2r = Nrow(par, sec, i + 2), *n3r = Nrow(par, sec, i + 3);
-        for (int j = 0; j < ki; ++j) {
-          const double *xj = X[sec].data() + static_cast<size_t>(j) * n0 + i;
-          const double x0 = xj[0], x1 = xj[1], x2 = xj[2], x3 = xj[3];
-          double *rt = Rt[sec].data() + static_cast<size_t>(j) * n0;
-          for (int c = 0; c < n0; ++c) rt[c] += x0 * n0r[c] + x1 * n1r[c] + x2 * n2r[c] + x3 * n3r[c];
-        }
-      }
-      for (; i < n0; ++i) {
-        const double *nr = Nrow(par, sec, i);
-        for (int j = 0; j < ki; ++j) {
-          const double xji = X[sec][static_cast<size_t>(j) * n0 + i];
-          double *rt = Rt[sec].data() + static_cast<size_t>(j) * n0;
-          for (int c = 0; c < n0; ++c) rt[c] += xji * nr[c];
-        }
+    Y[sec].assign(static_cast<size_t>(n0) * kp, 0.0);
+    Gnn[sec].assign(static_cast<size_t>(ki) * kp, 0.0);
+    for (int i = 0; i < n0; ++i) {
+      const double f = e(sec, spin[i]) - 1.0;
+      for (int j = 0; j < ki; ++j) {
+        X[sec][static_cast<size_t>(j) * n0 + i] = g0v(sec, csite[j], site[i], ctau[j] - tau[i]) * f;
+        Z[sec][static_cast<size_t>(i) * kp + j] = g0v(sec, site[i], csite[j], tau[i] - ctau[j]);
       }
     }
-    // YT = (N Z)^T: dot products of four rows of N with each candidate's Z column
-    {
-      int r = 0;
-      for (; r + 4 <= n0; r += 4) {
-        const double *n0r = Nrow(par, sec, r), *n1r = Nrow(par, sec, r + 1);
-        const double *n2r = Nrow(par, sec, r + 2), *n3r = Nrow(par, sec, r + 3);
-        for (int j = 0; j < ki; ++j) {
-          const double *z = ZT[sec].data() + static_cast<size_t>(j) * n0;
-          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-          for (int c = 0; c < n0; ++c) {
-            s0 += n0r[c] * z[c];
-            s1 += n1r[c] * z[c];
-            s2 += n2r[c] * z[c];
-            s3 += n3r[c] * z[c];
-          }
-          double *yt = YT[sec].data() + static_cast<size_t>(j) * n0 + r;
-          yt[0] = s0; yt[1] = s1; yt[2] = s2; yt[3] = s3;
-        }
-      }
-      for (; r < n0; ++r) {
-        const double *nr = Nrow(par, sec, r);
-        for (int j = 0; j < ki; ++j) {
-          const double *z = ZT[sec].data() + static_cast<size_t>(j) * n0;
-          double s = 0.0;
-          for (int c = 0; c < n0; ++c) s += nr[c] * z[c];
-          YT[sec][static_cast<size_t>(j) * n0 + r] = s;
-        }
-      }
+    if (n0 > 0 && ki > 0) {
+      prep_products(n0, ki, kp, Nrow(par, sec, 0), ldn, X[sec].data(), Z[sec].data(), Y[sec].data(), Rt[sec].data());
+      gemm(ki, kp, n0, X[sec].data(), n0, Y[sec].data(), kp, Gnn[sec].data(), kp, 1.0);   // X Y
     }
     for (int j = 0; j < ki; ++j)
-      for (int jj = 0; jj < ki; ++jj) {
-        const double *x = X[sec].data() + static_cast<size_t>(j) * n0;
-        const double *y = YT[sec].data() + static_cast<size_t>(jj) * n0;
-        double s = 0.0;
-        for (int i = 0; i < n0; ++i) s += x[i] * y[i];
-        Gnn[sec][static_cast<size_t>(j) * ki + jj] = s + g0v(sec, csite[j], csite[jj], ctau[j] - ctau[jj]);
-      }
+      for (int jj = 0; jj < ki; ++jj)
+        Gnn[sec][static_cast<size_t>(j) * kp + jj] += g0v(sec, csite[j], csite[jj], ctau[j] - ctau[jj]);
   }
   // entries of the augmented N_a and of G for candidate columns
   auto na_at = [&](int sec, int i, int j) -> double {   // j < n0
-    return i < n0 ? N[par][sec][static_cast<size_t>(i) * n_cap + j] : Rt[sec][static_cast<size_t>(i - n0) * n0 + j];
+    return i < n0 ? N[par][sec][static_cast<size_t>(i) * ldn + j] : Rt[sec][static_cast<size_t>(i - n0) * n0 + j];
   };
   auto g_cand = [&](int sec, int i, int j) -> double {   // j >= n0
-    return i < n0 ? YT[sec][static_cast<size_t>(j - n0) * n0 + i] : Gnn[sec][static_cast<size_t>(i - n0) * ki + (j - n0)];
+    return i < n0 ? Y[sec][static_cast<size_t>(i) * kp + (j - n0)] : Gnn[sec][static_cast<size_t>(i - n0) * kp + (j - n0)];
   };
   // (Gamma~ entry before the diagonal term): (N_a - I) for an old column, (G - I) for a candidate
   auto gt = [&](int sec, int i, int j) -> double {
@@ -436,7 +489,8 @@ int ctaux_cpu_chain::block(int64_t L) {
       break;
     }
     // Bc = Gamma~^{-1} N_a(P, map), Ac = ((G - I) D^{-1})(map, P)
-    std::vector<double> Bc(static_cast<size_t>(ka) * np, 0.0), Ac(static_cast<size_t>(np) * (ka > 0 ? ka : 1));
+    const int ldbc = pad_ld(np);
+    std::vector<double> Bc(static_cast<size_t>(ka) * ldbc, 0.0), Ac(static_cast<size_t>(np) * (ka > 0 ? ka : 1));
     for (int b = 0; b < ka; ++b) {
       const int pb = P[b];
       std::vector<double> row(np);
@@ -446,35 +500,44 @@ int ctaux_cpu_chain::block(int64_t L) {
       }
       for (int a2 = 0; a2 < ka; ++a2) {
         const double g = Gi[static_cast<size_t>(a2) * ka + b];
-        double *bc = Bc.data() + static_cast<size_t>(a2) * np;
+        double *bc = Bc.data() + static_cast<size_t>(a2) * ldbc;
         for (int j = 0; j < np; ++j) bc[j] += g * row[j];
       }
     }
     for (int i = 0; i < np; ++i)
       for (int b = 0; b < ka; ++b) Ac[static_cast<size_t>(i) * ka + b] = gt(sec, map[i], P[b]);
-    // N'[i][:] = N_a(map i, map) - Ac[i][:] Bc, row by row (Bc stays in cache)
-    for (int i = 0; i < np; ++i) {
-      const int mi = map[i];
-      double *out = Nrow(par ^ 1, sec, i);
-      for (int j = 0; j < np; ++j) {
-        const int mj = map[j];
-        out[j] = mj < n0 ? (mi < n0 ? N[par][sec][static_cast<size_t>(mi) * n_cap + mj] : Rt[sec][static_cast<size_t>(mi - n0) * n0 + mj])
-                         : (mi == mj ? 1.0 : 0.0);
+    // N' = N_a(map, map) - Ac Bc, a strip of rows at a time: the rows are
+    // gathered and then updated while they are still in cache (Bc in L2)
+    constexpr int kStrip = 12 * kMr;
+    for (int i0 = 0; i0 < np; i0 += kStrip) {
+      const int ie = std::min(np, i0 + kStrip);
+      for (int i = i0; i < ie; ++i) {
+        const int mi = map[i];
+        double *out = Nrow(par ^ 1, sec, i);
+        if (mi < n0) {   // old row: runs of consecutive surviving columns, zeros under candidates
+          const double *src = Nrow(par, sec, mi);
+          int j = 0;
+          while (j < np && map[j] < n0) {
+            int e2 = j + 1;
+            while (e2 < np && map[e2] == map[e2 - 1] + 1 && map[e2] < n0) ++e2;
+            memcpy(out + j, src + map[j], sizeof(double) * (e2 - j));
+            j = e2;
+          }
+          for (; j < np; ++j) out[j] = 0.0;
+        } else {
+          const double *src = Rt[sec].data() + static_cast<size_t>(mi - n0) * n0;
+          for (int j = 0; j < np; ++j) {
+            const int mj = map[j];
+            out[j] = mj < n0 ? src[mj] : (mi == mj ? 1.0 : 0.0);
+          }
+        }
       }
-      const double *ai = Ac.data() + static_cast<size_t>(i) * ka;
-      int b = 0;
-      for (; b + 4 <= ka; b += 4) {   // four rows of Bc per pass over the output row
-        const double a0 = ai[b], a1 = ai[b + 1], a2 = ai[b + 2], a3 = ai[b + 3];
-        const double *b0 = Bc.data() + static_cast<size_t>(b) * np, *b1 = b0 + np, *b2 = b1 + np, *b3 = b2 + np;
-        for (int j = 0; j < np; ++j) out[j] -= a0 * b0[j] + a1 * b1[j] + a2 * b2[j] + a3 * b3[j];
-      }
-      for (; b < ka; ++b) {
-        const double ac = ai[b];
-        const double *bc = Bc.data() + static_cast<size_t>(b) * np;
-        for (int j = 0; j < np; ++j) out[j] -= ac * bc[j];
-      }
+      if (ka > 0)
+        gemm(ie - i0, np, ka, Ac.data() + static_cast<size_t>(i0) * ka, ka, Bc.data(), ldbc, Nrow(par ^ 1, sec, i0), ldn,
+             -1.0);
     }
   }
+
   if (rc == CTAUX_OK || rc == CTAUX_ECAPACITY) {
     std::vector<int64_t> nid(np);
     std::vector<double> ntau(np);
@@ -515,14 +578,11 @@ void ctaux_cpu_chain::measure() {
   for (int sec = 0; sec < 2; ++sec) {
     for (int k = 0; k < n; ++k)
       for (int y = 0; y < nc; ++y) gr[static_cast<size_t>(k) * nc + y] = g0v(sec, site[k], y, tau[k]);
+    std::fill(Wm.begin(), Wm.end(), 0.0);
+    if (n > 0) gemm(n, nc, n, Nrow(par, sec, 0), ldn, gr.data(), nc, Wm.data(), nc, 1.0);   // N g
     for (int l = 0; l < n; ++l) {
-      const double *nr = Nrow(par, sec, l);
       const double f = e(sec, spin[l]) - 1.0;
-      for (int y = 0; y < nc; ++y) {
-        double s = 0.0;
-        for (int k = 0; k < n; ++k) s += nr[k] * gr[static_cast<size_t>(k) * nc + y];
-        Wm[static_cast<size_t>(l) * nc + y] = f * s;
-      }
+      for (int y = 0; y < nc; ++y) Wm[static_cast<size_t>(l) * nc + y] *= f;
     }
     // G(x t_j; y) = G0_xy(t_j) + sum_l gl_{(j,x) l} W_ly with gl tabulated once
     // per output time and site (t_0 = 0+, t_j = (j - 1/2) beta / n_out)
@@ -579,10 +639,11 @@ int ctaux_cpu_create(const ctaux_model *m, const ctaux_opts *o, int32_t chain_id
   for (int sec = 0; sec < 2; ++sec)
     for (int d = -2; d <= 2; ++d) c->ev[sec][d + 2] = exp(c->gamma * (sec == 0 ? 1.0 : -1.0) * d);
   c->kmax = o->k_max; c->meas_every = o->meas_every; c->n_out = o->n_tau_out; c->n_cap = o->n_cap;
+  c->ldn = pad_ld(o->n_cap);
   c->n_therm = o->n_therm; c->log_cap = o->log_cap; c->seed = o->seed; c->chain_id = static_cast<uint32_t>(chain_id);
   c->id.resize(o->n_cap); c->tau.resize(o->n_cap); c->site.resize(o->n_cap); c->spin.resize(o->n_cap);
   for (int p = 0; p < 2; ++p)
-    for (int s = 0; s < 2; ++s) c->N[p][s].assign(static_cast<size_t>(o->n_cap) * o->n_cap, 0.0);
+    for (int s = 0; s < 2; ++s) c->N[p][s].assign(static_cast<size_t>(o->n_cap) * c->ldn, 0.0);
   c->obs.assign(8 + 2 * static_cast<size_t>(m->n_disp) * o->n_tau_out, 0.0);
   c->log_acc.assign(static_cast<size_t>(o->log_cap), 0);
   c->log_R.assign(static_cast<size_t>(o->log_cap), 0.0);
@@ -627,7 +688,7 @@ int ctaux_cpu_get_config(const ctaux_cpu_chain *c, int32_t cap, ctaux_vertex *ou
 int ctaux_cpu_get_N(const ctaux_cpu_chain *c, int32_t sector, double *out, int32_t ld) {
   if (!c || sector < 0 || sector > 1 || !out || ld < c->n) return CTAUX_EINVAL;
   for (int i = 0; i < c->n; ++i)
-    memcpy(out + static_cast<size_t>(i) * ld, c->N[c->par][sector].data() + static_cast<size_t>(i) * c->n_cap,
+    memcpy(out + static_cast<size_t>(i) * ld, c->N[c->par][sector].data() + static_cast<size_t>(i) * c->ldn,
            sizeof(double) * c->n);
   return CTAUX_OK;
 }
@@ -662,10 +723,10 @@ int ctaux_cpu_set_config(ctaux_cpu_chain *c, int32_t n, const ctaux_vertex *v, i
     double *a = c->N[0][sec].data();
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j)   // N^{-1} of Eq. (Nmatrix)
-        a[static_cast<size_t>(i) * c->n_cap + j] =
+        a[static_cast<size_t>(i) * c->ldn + j] =
             (i == j ? c->e(sec, c->spin[i]) : 0.0) -
             c->g0v(sec, c->site[i], c->site[j], c->tau[i] - c->tau[j]) * (c->e(sec, c->spin[j]) - 1.0);
-    if (n > 0 && !invert_gj(a, n, c->n_cap)) return c->fail(CTAUX_ENUMERIC, "singular configuration");
+    if (n > 0 && !invert_gj(a, n, c->ldn)) return c->fail(CTAUX_ENUMERIC, "singular configuration");
   }
   c->done = proposals_done;
   c->next_id = next_id;
