@@ -35,20 +35,27 @@
 //
 // Below, Gamma stands for the column-scaled Gamma~.
 //
-// One workgroup (4 waves) per chain; Gamma^{-1} of both sectors lives in LDS.
-// Threads 0..127 serve the up sector, 128..255 the down sector.
-//
-// Synchronisation: two barriers per proposal (after the gathers, after
-// Gamma^{-1} s and w^T Gamma^{-1}); they also keep the waves within one
-// proposal of each other.  They order LDS only: the global stores of the loop
-// (the recorded Gamma entries, the decision log) are read only after the
-// full barrier that ends the loop, so they stay in flight.  Bookkeeping that the next proposal reads
-// (P, the spins, the removed list) is written by every thread with the same
-// value and each thread reads back only what it wrote itself or what precedes
-// a barrier, so every wave selects the vertex of a removal or flip on its own;
-// the per-proposal scalars are double-buffered by proposal parity.  The
-// growth of Gamma^{-1} after an acceptance is deferred to the next proposal and
-// runs while that proposal's gathers are in flight.
+// One workgroup (4 waves) per chain.  X = Gamma~^{-1} lives in registers:
+// waves 0 and 2 hold the rows of the up and down sector's X (lane a: row a),
+// waves 1 and 3 its columns (lane b: column b), zero beyond k_a.  Every wave
+// gathers both s and w of its sector (one load each per lane, in flight
+// together); a row wave forms v = X s and beta~ = d - w.v, a column wave
+// u = X^T w, each from registers and an LDS broadcast of its own vector.  One
+// barrier per proposal publishes the two sectors' beta~ (and v, u for the
+// growth); it orders LDS only, so the global stores of the loop (the recorded
+// Gamma entries, the decision log) stay in flight until the full barrier
+// after the loop.  The growth after an acceptance is deferred to the next
+// proposal with gathers, where it runs while those loads are in flight:
+//   X' = [[X + v u^T / beta~, -v / beta~], [-u^T / beta~, 1 / beta~]]
+//      = [[X, 0], [0, 0]] + (vt / beta~) ut^T,  vt = [v; -1], ut = [u; -1],
+// a rank-1 update of the zero-padded X; both copies form each term as
+// fma(vt_a / beta~, ut_b, X_ab), so rows and columns stay equal bit for bit.
+// v, u and the beta~ are double-buffered by the parity of the proposals with
+// gathers.  A repeated change (rare) and the end of the loop write the rows to
+// LDS, where the code that follows works as before.  Bookkeeping that the next
+// proposal reads (P, the spins) is written by every thread with the same value
+// and each thread reads back only what it wrote itself or what precedes a
+// barrier, so every wave selects the vertex of a removal or flip on its own.
 //
 // Everything the loop reads from the chain descriptor is copied to registers
 // or LDS first: the loop stores to global memory, so reads through the
@@ -93,8 +100,9 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   const int64_t done0 = st.done;
   // descriptor fields used in the loop
   const int kcap = d.kcap, n_cap = d.n_cap, kmax = d.kmax, ld = d.ld;
-  // LDS layout per sector: k_cap rounded up to 8 (kp) rows of lg = kp + 1 entries
-  const int kp = (kcap + 7) & ~7, lg = kp + 1;
+  // LDS layout per sector: kp = 64 rows of lg = 65 entries whatever k_cap is, so
+  // that every offset into the written-out X is a compile-time constant
+  constexpr int kp = kMaxKcap, lg = kMaxKcap + 1;
   const double Kc = d.K, gtol = d.gamma_tol;
   const bool gz = (d.gamma == 0.0);
   const auto Nsec = gview(static_cast<const T *>(d.N[par][sec]));
@@ -105,19 +113,18 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   const int64_t log_cap = d.log_cap;
 
   extern __shared__ double smem[];
-  double *Gi = smem;                         // [2][kp][lg]
-  double *vs = Gi + 2 * kp * lg;             // [2][kp]   s vectors
-  double *vw = vs + 2 * kp;                  // [2][kp]   w vectors
-  double *vv = vw + 2 * kp;                  // [2][kp]   Gamma^{-1} s
-  double *vu = vv + 2 * kp;                  // [2][kp]   w^T Gamma^{-1}
-  int *P = reinterpret_cast<int *>(vu + 2 * kp);   // [kcap]
+  double *Gi = smem;                         // [2][kp][lg]  X written out (repeated changes, block end)
+  double *vs = Gi + 2 * kp * lg;             // [2][kp]   s vectors (row waves)
+  double *vw = vs + 2 * kp;                  // [2][kp]   w vectors (column waves)
+  double *vv = vw + 2 * kp;                  // [2][2][kp] v = X s, [parity][sector]
+  double *vu = vv + 4 * kp;                  // [2][2][kp] u = X^T w
+  int *P = reinterpret_cast<int *>(vu + 4 * kp);   // [kcap]
   int8_t *scur = reinterpret_cast<int8_t *>(P + kcap);  // [n + kmax] current spins
   int8_t *s0l = scur + (n_cap + kmax);                      // [n + kmax] block-start spins
-  int8_t *slot_of = s0l + (n_cap + kmax);                   // [n + kmax] slot of a vertex in P (-1: none)
   double *Gis = Gi + sec * kp * lg;
   __shared__ double sh_ev[2][5];                   // exp(gamma*sigma*d), d = -2..2
   __shared__ double sh_dsc[2][5];                  // D = e^V / (e^V - 1) for block-start spin d = +-1
-  __shared__ double sh_gpp[2][2], sh_beta[2][2];   // [proposal parity][sector]
+  __shared__ double sh_beta[2][2];                 // [parity][sector]
   __shared__ double sh_gh[2][kMaxKcap];
   __shared__ double sh_pacc[kMaxKmax], sh_ppick[kMaxKmax];
   __shared__ int8_t sh_ptype[kMaxKmax], sh_pspin[kMaxKmax];
@@ -139,15 +146,12 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   double pbeta = 1.0;
   bool had_repeat = false;   // an accepted repeated change rewrote Gamma~ (rebuilt at block end)
 
-  // Gamma^{-1} of both sectors (with the padding rows) and the s, w vectors start
-  // at zero: entries beyond k_a stay zero for the whole block, so the
-  // matrix-vector products below can read whole batches of 8 without masks.
-  for (int i = tid; i < static_cast<int>(vv - Gi); i += 256) Gi[i] = 0.0;
+  // the written-out X (with the padding rows) and the vectors start at zero
+  for (int i = tid; i < static_cast<int>(reinterpret_cast<double *>(P) - Gi); i += 256) Gi[i] = 0.0;
   for (int i = tid; i < n + kins; i += 256) {
     const int8_t v = (i < n) ? static_cast<int8_t>(d.s0[par][i]) : 0;
     scur[i] = v;
     s0l[i] = v;
-    slot_of[i] = -1;
   }
   if (tid == 0) {
     sh_bad = 0;
@@ -169,7 +173,8 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
 
   // The proposals' draws live in registers (proposal t in lane t % 64 of slot
   // t / 64) and are read with readlane; lane b of each wave holds P_b and the
-  // b-th removed old vertex.  The loop then reads them without LDS round trips.
+  // b-th removed old vertex, and two 64-bit masks the live candidates.  The
+  // loop then reads them without LDS round trips.
   double r_pacc[2], r_ppick[2];
   int r_tspin[2];   // type | (spin + 1) << 8
 #pragma unroll
@@ -181,48 +186,91 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   }
   int myP = 0, myDead = 0x7fffffff;
 
-  // Gamma^{-1} of size k grows to k + 1 after an acceptance with Schur
-  // complement beta, from v = Gamma^{-1} s and u = w^T Gamma^{-1}:
-  //   [[X + v u^T / beta, -v / beta], [-u^T / beta, 1 / beta]].
-  // Thread (cp = loc % 32, rg = loc / 32) of the sector owns columns 2cp, 2cp+1
-  // (adjacent doubles: paired LDS accesses) of rows rg + 4i; batches of four
-  // rows are loaded before they are stored.  Load addresses are clamped into the
-  // matrix and values beyond k never used, so the loads need no branch.
-  auto grow = [&](int k, double beta) {
-    const double ib = 1.0 / beta;
-    const double *v = vv + sec * kp, *u = vu + sec * kp;
-    const int cp = loc & 31, rg = loc >> 5, b0 = 2 * cp, b1 = b0 + 1;
-    if (b0 <= k) {
-      const double ub0 = (b0 < k) ? u[b0] * ib : 0.0;
-      const double ub1 = (b1 < k) ? u[b1] * ib : 0.0;
-      for (int a1 = rg; a1 <= k; a1 += 16) {
-        double va[4], g0[4], g1[4];
+  // ---- X = Gamma~^{-1} in registers (row or column copy, see the top) ----
+  const int role = wave & 1;   // 0: rows, 1: columns
+  double xr[kMaxKcap];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int ac = min(a1 + 4 * i, kcap - 1);
-          va[i] = v[ac];
-          g0[i] = Gis[ac * lg + b0];
-          g1[i] = Gis[ac * lg + b1];
-        }
+  for (int i = 0; i < kMaxKcap; ++i) xr[i] = 0.0;
+  double *bcast = (role == 0 ? vs : vw) + sec * kp;   // this wave's s (rows) or w (columns)
+  double myv = 0.0;   // v_a (rows) or u_b (columns) of the last proposal with gathers
+  int q = 0;          // parity of the proposals with gathers
+  int pq = 0;         // parity of the proposal whose growth is owed
+
+  auto chunks = [&](const double *src, int nent, auto &&body) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int a = a1 + 4 * i;
-          if (a <= k) {
-            Gis[a * lg + b0] = (a < k) ? ((b0 < k) ? g0[i] + va[i] * ub0 : -va[i] * ib) : ((b0 < k) ? -ub0 : ib);
-            if (b1 <= k)
-              Gis[a * lg + b1] = (a < k) ? ((b1 < k) ? g1[i] + va[i] * ub1 : -va[i] * ib) : ((b1 < k) ? -ub1 : ib);
-          }
-        }
+    for (int c = 0; c < kMaxKcap; c += 8) {
+      if (c < nent) {
+        double o[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = src[c + i];
+        body(c, o);
       }
     }
   };
+  // owed growth of X from k to k + 1 slots with Schur complement beta~ (the
+  // vectors of the proposal of parity bq)
+  auto growth = [&](int k, double beta, int bq) {
+    const double ib = 1.0 / beta;
+    const double mine = (lane < k) ? myv : (lane == k ? -1.0 : 0.0);
+    const double *other = (role == 0 ? vu : vv) + (bq * 2 + sec) * kp;
+    const double f = mine * ib;
+    if (role == 0) {
+      chunks(other, k + 1, [&](int c, const double *o) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xr[c + i] = fma(f, o[i], xr[c + i]);
+      });
+    } else {
+      chunks(other, k + 1, [&](int c, const double *o) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xr[c + i] = fma(o[i] * ib, mine, xr[c + i]);
+      });
+    }
+  };
+  // row a . s (rows) or column b . w (columns) over k entries: four
+  // accumulators, the broadcast vector read from LDS
+  auto matvec = [&](int k) -> double {
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    chunks(bcast, k, [&](int c, const double *o) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a4[i & 3] = fma(xr[c + i], o[i], a4[i & 3]);
+    });
+    return (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  };
+  // X to LDS (the rows; the LDS code of repeated changes and of the block end
+  // reads it there) and back
+  auto write_out = [&]() {
+    if (role == 0) {
+#pragma unroll
+      for (int b = 0; b < kMaxKcap; ++b) Gis[lane * lg + b] = xr[b];
+    }
+  };
+  auto read_back = [&]() {
+    if (role == 0) {
+      const double *row = Gis + lane * lg;
+#pragma unroll
+      for (int i = 0; i < kMaxKcap; ++i) xr[i] = row[i];
+    } else {
+      const double *col = Gis + lane;
+#pragma unroll
+      for (int i = 0; i < kMaxKcap; ++i) xr[i] = col[i * lg];
+    }
+  };
+  // entry (i, j) of the block-start G - I, column-scaled (see the top)
+  auto gat = [&](int gi, int gj) -> double {
+    if (gj < n) return (gi < n) ? static_cast<double>(Nsec[static_cast<size_t>(gi) * ld + gj])
+                                : Rts[static_cast<size_t>(gi - n) * ld + gj];
+    return (gi < n) ? YTs[static_cast<size_t>(gj - n) * ld + gi]
+                    : Gnns[static_cast<size_t>(gi - n) * kmax + (gj - n)];
+  };
 
-  // Accepted repeated change of slot a (k = k_a slots): snapshots of X's column
-  // and row a (and of its last row and column) in the vector buffers, then every
-  // thread rewrites the entries it owns in grow's layout.  remove: slot a is
-  // deleted by the Schur complement and the last slot takes its place (its row
-  // and column then zero, keeping the zero padding beyond k_a); otherwise the
-  // Sherman-Morrison update of the diagonal change.
+  // Accepted repeated change of slot a (k = k_a slots), on the X written out to
+  // LDS: snapshots of X's column and row a (and of its last row and column) in
+  // the vector buffers, then every thread rewrites the entries it owns (thread
+  // (cp = loc % 32, rg = loc / 32) of the sector: columns 2cp, 2cp + 1 of rows
+  // rg + 4i).  remove: slot a is deleted by the Schur complement and the last
+  // slot takes its place (its row and column then zero, keeping the zero
+  // padding beyond k_a); otherwise the Sherman-Morrison update of the diagonal
+  // change.
   auto repeat_update = [&](int a, bool remove, double gn, double dp) {
     const int k = ka, last = ka - 1;
     double *cv = vv + sec * kp, *rv = vu + sec * kp, *lrw = vs + sec * kp, *lcl = vw + sec * kp;
@@ -267,220 +315,246 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     lds_barrier();
   };
 
-  for (int t = 0; t < L; ++t) {
-    const int tp = t & 1, tj = t >> 6, tl = t & 63;
-    const int tspin = __builtin_amdgcn_readlane(tj ? r_tspin[1] : r_tspin[0], tl);
-    const int type = tspin & 0xff;
-    const double u_acc = readlane_f64(tj ? r_pacc[1] : r_pacc[0], tl);
-    int p = -1, s_old = 0, s_new = 0, skip = 0;
-    if (type == 0) {
-      if (ncur + 1 > n_cap) {
-        status = -5;  // CTAUX_ECAPACITY
-        L_eff = t;
-        err_index = done0 + t;
-        break;
-      }
-      p = n + next_cand;
-      s_new = (tspin >> 8) - 1;
-    } else if (ncur == 0) {
-      skip = 1;
-    } else {
-      // rank r among interacting vertices in canonical (augmented-index) order;
-      // every wave computes it from the bookkeeping all threads wrote identically
-      int r = static_cast<int>(floor(static_cast<double>(ncur) * readlane_f64(tj ? r_ppick[1] : r_ppick[0], tl)));
-      if (r > ncur - 1) r = ncur - 1;
-      if (r < n - ndead) {
-        // old vertex: least idx with idx = r + #{dead <= idx}
-        int idx = r;
-        while (true) {
-          const bool le = myDead <= idx;   // lanes past the list hold INT_MAX
-          const int nw = r + __popcll(__ballot(le));
-          if (nw == idx) break;
-          idx = nw;
+  unsigned long long alive[2] = {0ull, 0ull};   // live candidates (bit j: candidate j)
+  // The proposals run in an inner loop that handles insertions, removals and
+  // flips of vertices outside P; a repeated change of a vertex in P leaves it
+  // and is handled once below (X written out, updated in LDS, read back), so
+  // that the inner loop keeps X in registers without that path's demands.
+  int t = 0;
+  bool stop = false;
+  while (!stop && t < L) {
+    int rp = -1, p = -1, s_old = 0, s_new = 0, type = 0;
+    double u_acc = 0.0, fpre = 0.0;
+    for (; t < L; ++t) {
+      const int tj = t >> 6, tl = t & 63;
+      const int tspin = __builtin_amdgcn_readlane(tj ? r_tspin[1] : r_tspin[0], tl);
+      type = tspin & 0xff;
+      u_acc = readlane_f64(tj ? r_pacc[1] : r_pacc[0], tl);
+      p = -1;
+      s_old = 0;
+      s_new = 0;
+      int skip = 0;
+      if (type == 0) {
+        if (ncur + 1 > n_cap) {
+          status = -5;  // CTAUX_ECAPACITY
+          L_eff = t;
+          err_index = done0 + t;
+          stop = true;
+          break;
         }
-        p = idx;
+        p = n + next_cand;
+        s_new = (tspin >> 8) - 1;
+      } else if (ncur == 0) {
+        skip = 1;
       } else {
-        int r2 = r - (n - ndead);
-        for (int base = 0; base < next_cand; base += 64) {
-          const int j = base + lane;
-          const bool alive = (j < next_cand) && scur[n + j] != 0;
-          const unsigned long long m = __ballot(alive);
-          const int cnt = __popcll(m);
-          if (r2 < cnt) {
-            const unsigned long long hit = __ballot(alive && __popcll(m & ((1ull << lane) - 1ull)) == r2);
-            p = n + base + __ffsll(static_cast<long long>(hit)) - 1;
-            break;
+        // rank r among interacting vertices in canonical (augmented-index) order;
+        // every wave computes it from the bookkeeping all threads wrote identically
+        int r = static_cast<int>(floor(static_cast<double>(ncur) * readlane_f64(tj ? r_ppick[1] : r_ppick[0], tl)));
+        if (r > ncur - 1) r = ncur - 1;
+        if (r < n - ndead) {
+          // old vertex: least idx with idx = r + #{dead <= idx}
+          int idx = r;
+          while (true) {
+            const bool le = myDead <= idx;   // lanes past the list hold INT_MAX
+            const int nw = r + __popcll(__ballot(le));
+            if (nw == idx) break;
+            idx = nw;
           }
-          r2 -= cnt;
+          p = idx;
+        } else {
+          // the r2-th live candidate in index order
+          int r2 = r - (n - ndead);
+          const int c0 = __popcll(alive[0]);
+          const int wsel = (r2 < c0) ? 0 : 1;
+          const unsigned long long m = alive[wsel];
+          if (wsel == 1) r2 -= c0;
+          const bool hitl = ((m >> lane) & 1ull) && __popcll(m & ((1ull << lane) - 1ull)) == r2;
+          const unsigned long long hit = __ballot(hitl);
+          if (hit) p = n + 64 * wsel + __ffsll(static_cast<long long>(hit)) - 1;
         }
+        if (p < 0 || p >= n + next_cand || scur[p] == 0) {   // cannot happen unless bookkeeping is broken
+          status = -4;
+          L_eff = t;
+          err_index = -3;
+          stop = true;
+          break;
+        }
+        s_old = scur[p];
+        s_new = (type == 1) ? 0 : -s_old;
       }
-      if (p < 0 || p >= n + next_cand || scur[p] == 0) {   // cannot happen unless bookkeeping is broken
-        status = -4;
-        L_eff = t;
-        err_index = -3;
-        break;
-      }
-      s_old = scur[p];
-      s_new = (type == 1) ? 0 : -s_old;
-    }
 
-    // prefactor of the acceptance ratio (Eq. insprob), computed while the
-    // gathers below are in flight
-    const double fpre = (type == 0) ? Kc / static_cast<double>(ncur + 1)
-                                    : (type == 1 ? static_cast<double>(ncur) / Kc : 1.0);
-    double gh0 = 0.0, gh1 = 0.0, dp0 = 1.0, dp1 = 1.0;
-    const int rp = (!skip && !gz) ? static_cast<int>(slot_of[p]) : -1;   // slot of a repeated change
-    if (rp >= 0) {
-      // ---- repeated change: ratio from X_aa (the owed growth first) ----
-      const int s0p = s0l[p];
-      gh0 = sh_ev[0][s_new - s0p + 2] - 1.0;   // net change from the block-start spin
-      gh1 = sh_ev[1][s_new - s0p + 2] - 1.0;
-      dp0 = sh_dsc[0][s0p + 2];
-      dp1 = sh_dsc[1][s0p + 2];
-      if (pend) {
-        grow(pk, pbeta);
-        pend = false;
-      }
-      lds_barrier();
-      if (loc == 0) {
-        const double xaa = Gis[rp * lg + rp], go = sh_gh[sec][rp];
-        const double gn = sec == 0 ? gh0 : gh1, dp = sec == 0 ? dp0 : dp1;
-        sh_beta[tp][sec] = (s_new == s0p) ? xaa / (-go * dp)
-                                          : (gn / go) * (1.0 + (1.0 / go - 1.0 / gn) / dp * xaa);
-      }
-      lds_barrier();
-    } else if (!skip && !gz) {
-      // ---- issue the gathers: thread loc < 64 takes s_loc = G(P_loc, p) (loc == 63: G_pp),
-      // thread 64 + b takes w_b = G(p, P_b) ----
-      int gi = -1, gj = -1;
-      if (loc < 64) {
-        if (loc < ka) { gi = myP; gj = p; }
-        else if (loc == 63) { gi = p; gj = p; }
-      } else if (loc - 64 < ka) {
-        gi = p;
-        gj = myP;
-      }
-      double raw = 0.0;
-      if (gi >= 0) {
-        if (gj < n) raw = (gi < n) ? static_cast<double>(Nsec[static_cast<size_t>(gi) * ld + gj])
-                                   : Rts[static_cast<size_t>(gi - n) * ld + gj];
-        else raw = (gi < n) ? YTs[static_cast<size_t>(gj - n) * ld + gi]
-                            : Gnns[static_cast<size_t>(gi - n) * kmax + (gj - n)];
-      }
-      {
+      // prefactor of the acceptance ratio (Eq. insprob), computed while the
+      // gathers below are in flight
+      fpre = (type == 0) ? Kc / static_cast<double>(ncur + 1)
+                         : (type == 1 ? static_cast<double>(ncur) / Kc : 1.0);
+      double gh0 = 0.0, gh1 = 0.0, dp0 = 1.0, dp1 = 1.0;
+      if (!skip && !gz) {
+        if (type != 0) {
+          const unsigned long long hit = __ballot(lane < ka && myP == p);
+          if (hit) {
+            rp = __ffsll(static_cast<long long>(hit)) - 1;
+            break;   // a repeated change: handled after this loop
+          }
+        }
+        // ---- issue the gathers: lane b < k_a takes s_b = G(P_b, p) and
+        // w_b = G(p, P_b), lane 63 (never a slot while proposing) takes G_pp ----
+        int si = -1, sj = -1, wi = -1, wj = -1;
+        if (lane < ka) {
+          si = myP; sj = p; wi = p; wj = myP;
+        } else if (lane == 63) {
+          si = p; sj = p;
+        }
+        const double raw_s = (si >= 0) ? gat(si, sj) : 0.0;
+        const double raw_w = (wi >= 0) ? gat(wi, wj) : 0.0;
         const int s0p = s0l[p];
         gh0 = sh_ev[0][s_new - s0p + 2] - sh_ev[0][s_old - s0p + 2];
         gh1 = sh_ev[1][s_new - s0p + 2] - sh_ev[1][s_old - s0p + 2];
         dp0 = sh_dsc[0][s0p + 2];   // 1 for a candidate (s0 = 0)
         dp1 = sh_dsc[1][s0p + 2];
+        // ---- owed growth of X (registers only) ----
+        if (pend) {
+          growth(pk, pbeta, pq);
+          pend = false;
+        }
+        // ---- entries of Gamma~ (the raw entry minus the identity; P_b != p) ----
+        const double gh = sec == 0 ? gh0 : gh1, dp = sec == 0 ? dp0 : dp1;
+        const double dd = raw_s - 1.0 - 1.0 / (gh * dp);   // d, in lane 63
+        const double sv = (lane < ka) ? raw_s : 0.0, wv = (lane < ka) ? raw_w : 0.0;
+        bcast[lane] = (role == 0) ? sv : wv;
+        // record row / column ka of Gamma~ for the inversion at block end (a
+        // rejected proposal's entries are overwritten by the next one)
+        if (role == 0) {
+          if (lane < ka) gam[lane * kcap + ka] = sv;
+          else if (lane == 63) gam[ka * kcap + ka] = dd;
+        } else if (lane < ka) {
+          gam[ka * kcap + lane] = wv;
+        }
+        __builtin_amdgcn_wave_barrier();   // the wave's LDS stores before its loads
+        myv = matvec(ka);
+        if (role == 0) {
+          const double beta = readlane_f64(dd, 63) - wave_sum_dpp(wv * myv);
+          if (lane == 0) sh_beta[q][sec] = beta;
+        }
+        double *mv = (role == 0 ? vv : vu) + (q * 2 + sec) * kp;
+        mv[lane] = (lane == ka) ? -1.0 : myv;
+        lds_barrier();
       }
-      // ---- owed growth of Gamma^{-1} by partitioning (Sec. III B 2), LDS only ----
+
+      double R = 0.0;
+      if (!skip) {
+        double r0 = 1.0, r1 = 1.0;
+        if (!gz) {
+          r0 = -gh0 * dp0 * sh_beta[q][0];
+          r1 = -gh1 * dp1 * sh_beta[q][1];
+        }
+        R = fpre * r0 * r1;
+      }
+      if (!isfinite(R)) {
+        status = -4;  // CTAUX_ENUMERIC
+        L_eff = t;
+        err_index = done0 + t;
+        stop = true;
+        break;
+      }
+      const int acc = (!skip && u_acc < fabs(R)) ? 1 : 0;
+      if (tid == 0) {
+        const int64_t idx = done0 + t;
+        if (idx < log_cap) {
+          log_acc[idx] = static_cast<uint8_t>(acc);
+          log_R[idx] = R;
+        }
+      }
+      if (acc) {
+        accepted += 1;
+        nchg += 1;
+        if (R < 0.0) sign = -sign;
+        if (!gz) {
+          pend = true;
+          pk = ka;
+          pbeta = sh_beta[q][sec];
+          pq = q;
+          P[ka] = p;           // every thread writes the same value
+          if (lane == ka) myP = p;
+          if (tid == 0) {
+            sh_gh[0][ka] = gh0;
+            sh_gh[1][ka] = gh1;
+          }
+          ka += 1;
+        }
+        scur[p] = static_cast<int8_t>(s_new);   // every thread writes the same value
+        if (type == 0) {
+          const int j = p - n;
+          alive[j >> 6] |= 1ull << (j & 63);
+          if (tid == 0) sh_cid[next_cand] = next_id;
+          next_id += 1;
+          ncur += 1;
+        } else if (type == 1) {
+          ncur -= 1;
+          if (p < n) {
+            if (lane == ndead) myDead = p;
+            ndead += 1;
+          } else {
+            const int j = p - n;
+            alive[j >> 6] &= ~(1ull << (j & 63));
+          }
+        }
+      }
+      if (!skip && !gz) q ^= 1;
+      if (type == 0) next_cand += 1;
+      // with U = 0 there are no gather barriers; without one here a wave could run
+      // ahead and overwrite spins another wave still has to read
+      if (gz) lds_barrier();
+      // Gamma full: the block ends here (with U = 0 the removed-vertex list, whose
+      // length never exceeds that of P otherwise, bounds the block)
+      if ((gz ? nchg : ka) == kcap) {
+        L_eff = t + 1;
+        stop = true;
+        break;
+      }
+    }
+    if (stop || rp < 0) break;
+
+    // ---- a repeated change of slot rp at proposal t (a removal or a flip) ----
+    {
+      const int s0p = s0l[p];
+      // net change from the block-start spin
+      const double gh0 = sh_ev[0][s_new - s0p + 2] - 1.0, gh1 = sh_ev[1][s_new - s0p + 2] - 1.0;
+      const double dp0 = sh_dsc[0][s0p + 2], dp1 = sh_dsc[1][s0p + 2];
       if (pend) {
-        grow(pk, pbeta);
+        growth(pk, pbeta, pq);
         pend = false;
       }
-      // ---- finish the gathers (entries of Gamma~: the raw entry minus the identity);
-      // each thread also records its entry as row / column ka of Gamma~ for the
-      // pivoted inversion at block end (a rejected proposal's entries are
-      // overwritten by the next one) ----
-      const double gh = sec == 0 ? gh0 : gh1, dp = sec == 0 ? dp0 : dp1;
-      if (gi >= 0) {
-        const double v = raw - (gi == gj ? 1.0 : 0.0);
-        if (loc == 63 && gi == gj && loc >= ka) {
-          const double dd = v - 1.0 / (gh * dp);
-          sh_gpp[tp][sec] = dd;
-          gam[ka * kcap + ka] = dd;
-        } else if (loc < 64) {
-          vs[sec * kp + loc] = v;
-          gam[loc * kcap + ka] = v;
-        } else {
-          vw[sec * kp + loc - 64] = v;
-          gam[ka * kcap + loc - 64] = v;
-        }
+      write_out();
+      lds_barrier();
+      if (loc == 0) {   // the sector ratio from X_aa
+        const double xaa = Gis[rp * lg + rp], go = sh_gh[sec][rp];
+        const double gn = sec == 0 ? gh0 : gh1, dp = sec == 0 ? dp0 : dp1;
+        sh_beta[q][sec] = (s_new == s0p) ? xaa / (-go * dp)
+                                         : (gn / go) * (1.0 + (1.0 / go - 1.0 / gn) / dp * xaa);
       }
       lds_barrier();
-      // v = Gamma^{-1} s and beta = d - w.v (waves 0 and 2), u = w^T Gamma^{-1} (waves 1 and 3);
-      // four accumulators, loads of eight terms in flight together
-      if (loc < 64) {
-        double acc = 0.0;
-        if (loc < ka) {
-          const double *row = Gis + loc * lg;
-          const double *sv = vs + sec * kp;
-          double a4[4] = {0.0, 0.0, 0.0, 0.0};
-          for (int b0 = 0; b0 < ka; b0 += 8) {   // whole batches of 8: entries beyond k_a are zero
-            double x[8], y[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              x[i] = row[b0 + i];
-              y[i] = sv[b0 + i];
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) a4[i & 3] = fma(x[i], y[i], a4[i & 3]);
-          }
-          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-          vv[sec * kp + loc] = acc;
-        }
-        const double x = (loc < ka) ? vw[sec * kp + loc] * acc : 0.0;
-        const double s = wave_sum_dpp(x);
-        if (lane == 0) sh_beta[tp][sec] = sh_gpp[tp][sec] - s;
-      } else {
-        const int b = loc - 64;
-        if (b < ka) {
-          const double *wv = vw + sec * kp;
-          double a4[4] = {0.0, 0.0, 0.0, 0.0};
-          for (int a0 = 0; a0 < ka; a0 += 8) {   // whole batches of 8: entries beyond k_a are zero
-            double x[8], y[8];
-            const double *col = Gis + a0 * lg + b;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              x[i] = wv[a0 + i];
-              y[i] = col[i * lg];
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) a4[i & 3] = fma(x[i], y[i], a4[i & 3]);
-          }
-          vu[sec * kp + b] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+      const double R = fpre * sh_beta[q][0] * sh_beta[q][1];
+      if (!isfinite(R)) {
+        status = -4;  // CTAUX_ENUMERIC
+        L_eff = t;
+        err_index = done0 + t;
+        break;
+      }
+      const int acc = (u_acc < fabs(R)) ? 1 : 0;
+      if (tid == 0) {
+        const int64_t idx = done0 + t;
+        if (idx < log_cap) {
+          log_acc[idx] = static_cast<uint8_t>(acc);
+          log_R[idx] = R;
         }
       }
-      lds_barrier();
-    }
-
-    double R;
-    if (skip) {
-      R = 0.0;
-    } else {
-      double r0 = 1.0, r1 = 1.0;
-      if (rp >= 0) {   // the sector ratios themselves
-        r0 = sh_beta[tp][0];
-        r1 = sh_beta[tp][1];
-      } else if (!gz) {
-        r0 = -gh0 * dp0 * sh_beta[tp][0];
-        r1 = -gh1 * dp1 * sh_beta[tp][1];
-      }
-      R = fpre * r0 * r1;
-    }
-    if (!isfinite(R)) {
-      status = -4;  // CTAUX_ENUMERIC
-      L_eff = t;
-      err_index = done0 + t;
-      break;
-    }
-    const int acc = (!skip && u_acc < fabs(R)) ? 1 : 0;
-    if (tid == 0) {
-      const int64_t idx = done0 + t;
-      if (idx < log_cap) {
-        log_acc[idx] = static_cast<uint8_t>(acc);
-        log_R[idx] = R;
-      }
-    }
-    if (acc) {
-      accepted += 1;
-      nchg += 1;
-      if (R < 0.0) sign = -sign;
-      if (rp >= 0) {
+      if (acc) {
+        accepted += 1;
+        nchg += 1;
+        if (R < 0.0) sign = -sign;
         had_repeat = true;
-        repeat_update(rp, s_new == s0l[p], sec == 0 ? gh0 : gh1, sec == 0 ? dp0 : dp1);
-        if (s_new != s0l[p]) {
+        repeat_update(rp, s_new == s0p, sec == 0 ? gh0 : gh1, sec == 0 ? dp0 : dp1);
+        if (s_new != s0p) {
           if (tid == 0) {
             sh_gh[0][rp] = gh0;
             sh_gh[1][rp] = gh1;
@@ -490,57 +564,36 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           const int last = ka - 1, pl = P[last];
           if (rp != last) {
             P[rp] = pl;
-            slot_of[pl] = static_cast<int8_t>(rp);
             if (lane == rp) myP = pl;
             if (tid == 0) {
               sh_gh[0][rp] = sh_gh[0][last];
               sh_gh[1][rp] = sh_gh[1][last];
             }
           }
-          slot_of[p] = -1;
           ka -= 1;
         }
-      } else if (!gz) {
-        pend = true;
-        pk = ka;
-        pbeta = sh_beta[tp][sec];
-        P[ka] = p;           // every thread writes the same value
-        slot_of[p] = static_cast<int8_t>(ka);
-        if (lane == ka) myP = p;
-        if (tid == 0) {
-          sh_gh[0][ka] = gh0;
-          sh_gh[1][ka] = gh1;
-        }
-        ka += 1;
-      }
-      scur[p] = static_cast<int8_t>(s_new);   // every thread writes the same value
-      if (type == 0) {
-        if (tid == 0) sh_cid[next_cand] = next_id;
-        next_id += 1;
-        ncur += 1;
-      } else if (type == 1) {
-        ncur -= 1;
-        if (p < n) {
-          if (lane == ndead) myDead = p;
-          ndead += 1;
+        scur[p] = static_cast<int8_t>(s_new);   // every thread writes the same value
+        if (type == 1) {
+          ncur -= 1;
+          if (p < n) {
+            if (lane == ndead) myDead = p;
+            ndead += 1;
+          } else {
+            const int j = p - n;
+            alive[j >> 6] &= ~(1ull << (j & 63));
+          }
         }
       }
-    }
-    if (type == 0) next_cand += 1;
-    // with U = 0 there are no gather barriers; without one here a wave could run
-    // ahead and overwrite spins another wave still has to read
-    if (gz) lds_barrier();
-    // Gamma full: the block ends here (with U = 0 the removed-vertex list, whose
-    // length never exceeds that of P otherwise, bounds the block)
-    if ((gz ? nchg : ka) == kcap) {
-      L_eff = t + 1;
-      break;
+      read_back();   // X as written out and, on acceptance, updated
+      q ^= 1;
+      ++t;
     }
   }
   __syncthreads();
-  // the growth owed by the last acceptance: Gamma^{-1} of the growth is the
-  // starting point of the refinement below
-  if (pend) grow(pk, pbeta);
+  // the growth owed by the last acceptance; X then goes to LDS, the starting
+  // point of the refinement below
+  if (pend) growth(pk, pbeta, pq);
+  write_out();
   lds_barrier();
   // Gamma~ as recorded while proposing is stale once a repeated change rewrote
   // a slot: gather it again for the final P and net changes
@@ -836,13 +889,12 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   }
 }
 
-// LDS: Gamma^{-1} of both sectors as k_cap rounded up to 8 rows (the
-// matrix-vector products read whole batches of 8) of that many plus one
-// entries, the four vectors, P, the spins and the slots.
+// LDS: X of both sectors written out as 64 rows of 65 entries, the s and w
+// vectors, v and u by parity, P and the current and block-start spins.
 size_t propose_lds_bytes(int kcap, int kmax, int n_cap) {
-  const size_t kp = (static_cast<size_t>(kcap) + 7) & ~size_t{7};
-  return sizeof(double) * (2 * kp * (kp + 1) + 8 * kp) + sizeof(int) * static_cast<size_t>(kcap) +
-         3ull * static_cast<size_t>(n_cap + kmax) + 16;
+  const size_t kp = kMaxKcap;
+  return sizeof(double) * (2 * kp * (kp + 1) + 12 * kp) + sizeof(int) * static_cast<size_t>(kcap) +
+         2ull * static_cast<size_t>(n_cap + kmax) + 16;
 }
 
 static size_t propose_lds_bytes(const Batch &b) { return propose_lds_bytes(b.kcap, b.kmax, b.n_cap); }

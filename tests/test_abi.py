@@ -63,9 +63,9 @@ def test_workspace_bytes_and_validation(lib):
                 dict(gamma_tol=float("nan")),
                 # 2 (n_tau_out + 1) n_sites n_cap >= 2^31 (32-bit table indices): 2 * 4097 * 4 * 65536
                 dict(n_tau_out=4096, n_cap=65536),
-                # the proposal kernel's LDS (Gamma^-1 of both sectors plus three bytes per
+                # the proposal kernel's LDS (Gamma^-1 of both sectors plus two bytes per
                 # vertex of the augmented configuration) exceeds 160 KB
-                dict(n_cap=40000), dict(drift_target=-1.0), dict(recompute_mode=2)):
+                dict(n_cap=45000), dict(drift_target=-1.0), dict(recompute_mode=2)):
         mb, ob, kb = _model_and_opts(ctaux, **bad)
         assert lib.ctaux_workspace_bytes(C.byref(mb), 1, C.byref(ob)) == 0, bad
     # a non-finite table entry is rejected
@@ -91,11 +91,11 @@ def test_lds_bound_is_the_boundary(lib):
     the 160 KB of LDS of a workgroup; one more vertex of capacity does not."""
     from paper_1010_3690_amd import ctaux
     ok, bad = [], []
-    # 8 (2 * 64 * 65 + 8 * 64) + 4 * 64 + 3 (n_cap + 64) + 16 + 8192 <= 163840  <=>  n_cap <= 28176
-    for n_cap in (16384, 28176, 28177, 32768):
+    # 8 (2 * 64 * 65 + 12 * 64) + 4 * 64 + 2 (n_cap + 64) + 16 + 8192 <= 163840  <=>  n_cap <= 41272
+    for n_cap in (16384, 41272, 41273, 49152):
         m, o, keep = _model_and_opts(ctaux, n_cap=n_cap)
         (ok if lib.ctaux_workspace_bytes(C.byref(m), 1, C.byref(o)) > 0 else bad).append(n_cap)
-    assert ok == [16384, 28176] and bad == [28177, 32768], (ok, bad)
+    assert ok == [16384, 41272] and bad == [41273, 49152], (ok, bad)
     assert b"LDS" in lib.ctaux_last_error(None)
 
 

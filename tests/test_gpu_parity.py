@@ -374,9 +374,10 @@ def test_capacity_error_matches_oracle():
 def test_drift_tol_stops_the_chains():
     """A refinement whose drift exceeds drift_tol stops the chain with
     CTAUX_ENUMERIC.  A tolerance below any FP64 drift forces it at the first
-    refinement (after block 4): both chains of the batch stop there, although
-    the next block's start has already been launched, their decisions up to
-    there equal the oracle's, and a further run reports the same error."""
+    refinement (after block 1: a chain's refinement interval starts at one
+    block): both chains of the batch stop there, although the next block's
+    start has already been launched, their decisions up to there equal the
+    oracle's, and a further run reports the same error."""
     ctaux = _ctaux()
     w = _plaquette()
     n_prop = 64 * 12
@@ -389,8 +390,8 @@ def test_drift_tol_stops_the_chains():
     for c in range(2):
         st = gb.stats(c)
         assert st["status"] == ctaux.CTAUX_ENUMERIC
-        # the first refinement follows block 4 (interval min(8, 4)); nothing runs after it
-        assert st["proposals"] == 4 * 64, st["proposals"]
+        # the first refinement follows block 1; nothing runs after it
+        assert st["proposals"] == 64, st["proposals"]
         oc = OracleChain(w, seed=3, chain_id=c, n_cap=512)
         oc.set_log(st["proposals"])
         oc.run(st["proposals"])
