@@ -48,8 +48,9 @@
 // proposal with gathers, where it runs while those loads are in flight:
 //   X' = [[X + v u^T / beta~, -v / beta~], [-u^T / beta~, 1 / beta~]]
 //      = [[X, 0], [0, 0]] + (vt / beta~) ut^T,  vt = [v; -1], ut = [u; -1],
-// a rank-1 update of the zero-padded X; both copies form each term as
-// fma(vt_a / beta~, ut_b, X_ab), so rows and columns stay equal bit for bit.
+// a rank-1 update of the zero-padded X (the two copies round its terms in a
+// different order; the row copy is the one written out, and a column copy
+// that is read back from it takes its values).
 // v, u and the beta~ are double-buffered by the parity of the proposals with
 // gathers.  A repeated change (rare) and the end of the loop write the rows to
 // LDS, where the code that follows works as before.  Bookkeeping that the next
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   double *Gis = Gi + sec * kp * lg;
   __shared__ double sh_ev[2][5];                   // exp(gamma*sigma*d), d = -2..2
   __shared__ double sh_dsc[2][5];                  // D = e^V / (e^V - 1) for block-start spin d = +-1
+  __shared__ double sh_igd[2][27];                 // 1 / (gh D) by (s0 + 1, s_old + 1, s_new + 1)
   __shared__ double sh_beta[2][2];                 // [parity][sector]
   __shared__ double sh_gh[2][kMaxKcap];
   __shared__ double sh_pacc[kMaxKmax], sh_ppick[kMaxKmax];
@@ -162,6 +164,13 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     const double e = d.evd[tid / 5][tid % 5];
     sh_ev[tid / 5][tid % 5] = e;
     sh_dsc[tid / 5][tid % 5] = (tid % 5 == 2) ? 1.0 : e / (e - 1.0);
+  }
+  if (tid >= 64 && tid < 64 + 54) {   // entries whose s_new equals s_old never occur in the loop
+    const int sc = (tid - 64) / 27, e = (tid - 64) % 27;
+    const int s0 = e / 9 - 1, so = (e / 3) % 3 - 1, sn = e % 3 - 1;
+    const double ev_new = d.evd[sc][sn - s0 + 2], ev_old = d.evd[sc][so - s0 + 2];
+    const double dv = (s0 == 0) ? 1.0 : d.evd[sc][s0 + 2] / (d.evd[sc][s0 + 2] - 1.0);
+    sh_igd[sc][e] = (sn != so) ? 1.0 / ((ev_new - ev_old) * dv) : 0.0;
   }
   for (int t = tid; t < L; t += 256) {
     sh_ptype[t] = static_cast<int8_t>(d.ptype[t]);
@@ -213,18 +222,12 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     const double ib = 1.0 / beta;
     const double mine = (lane < k) ? myv : (lane == k ? -1.0 : 0.0);
     const double *other = (role == 0 ? vu : vv) + (bq * 2 + sec) * kp;
+    // rows: X_ab += (vt_a / beta~) ut_b; columns: X_ab += (ut_b / beta~) vt_a
     const double f = mine * ib;
-    if (role == 0) {
-      chunks(other, k + 1, [&](int c, const double *o) {
+    chunks(other, k + 1, [&](int c, const double *o) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) xr[c + i] = fma(f, o[i], xr[c + i]);
-      });
-    } else {
-      chunks(other, k + 1, [&](int c, const double *o) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) xr[c + i] = fma(o[i] * ib, mine, xr[c + i]);
-      });
-    }
+      for (int i = 0; i < 8; ++i) xr[c + i] = fma(f, o[i], xr[c + i]);
+    });
   };
   // row a . s (rows) or column b . w (columns) over k entries: four
   // accumulators, the broadcast vector read from LDS
@@ -417,8 +420,8 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           pend = false;
         }
         // ---- entries of Gamma~ (the raw entry minus the identity; P_b != p) ----
-        const double gh = sec == 0 ? gh0 : gh1, dp = sec == 0 ? dp0 : dp1;
-        const double dd = raw_s - 1.0 - 1.0 / (gh * dp);   // d, in lane 63
+        const double igd = sh_igd[sec][(s0p + 1) * 9 + (s_old + 1) * 3 + (s_new + 1)];   // 1 / (gh D_p)
+        const double dd = raw_s - 1.0 - igd;   // d, in lane 63
         const double sv = (lane < ka) ? raw_s : 0.0, wv = (lane < ka) ? raw_w : 0.0;
         bcast[lane] = (role == 0) ? sv : wv;
         // record row / column ka of Gamma~ for the inversion at block end (a
