@@ -318,14 +318,14 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     lds_barrier();
   };
 
-  unsigned long long alive[2] = {0ull, 0ull};   // live candidates (bit j: candidate j)
+  unsigned long long alive_lo = 0ull, alive_hi = 0ull;   // live candidates (bit j of candidates 0-63, 64-127)
+  int why = 0;   // why the inner loop stopped: 1 capacity, 2 bookkeeping, 3 non-finite ratio, 4 Gamma full
   // The proposals run in an inner loop that handles insertions, removals and
   // flips of vertices outside P; a repeated change of a vertex in P leaves it
   // and is handled once below (X written out, updated in LDS, read back), so
   // that the inner loop keeps X in registers without that path's demands.
   int t = 0;
-  bool stop = false;
-  while (!stop && t < L) {
+  while (t < L) {
     int rp = -1, p = -1, s_old = 0, s_new = 0, type = 0;
     double u_acc = 0.0, fpre = 0.0;
     for (; t < L; ++t) {
@@ -339,10 +339,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       int skip = 0;
       if (type == 0) {
         if (ncur + 1 > n_cap) {
-          status = -5;  // CTAUX_ECAPACITY
-          L_eff = t;
-          err_index = done0 + t;
-          stop = true;
+          why = 1;
           break;
         }
         p = n + next_cand;
@@ -367,19 +364,16 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         } else {
           // the r2-th live candidate in index order
           int r2 = r - (n - ndead);
-          const int c0 = __popcll(alive[0]);
+          const int c0 = __popcll(alive_lo);
           const int wsel = (r2 < c0) ? 0 : 1;
-          const unsigned long long m = alive[wsel];
+          const unsigned long long m = wsel ? alive_hi : alive_lo;
           if (wsel == 1) r2 -= c0;
           const bool hitl = ((m >> lane) & 1ull) && __popcll(m & ((1ull << lane) - 1ull)) == r2;
           const unsigned long long hit = __ballot(hitl);
           if (hit) p = n + 64 * wsel + __ffsll(static_cast<long long>(hit)) - 1;
         }
         if (p < 0 || p >= n + next_cand || scur[p] == 0) {   // cannot happen unless bookkeeping is broken
-          status = -4;
-          L_eff = t;
-          err_index = -3;
-          stop = true;
+          why = 2;
           break;
         }
         s_old = scur[p];
@@ -453,10 +447,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         R = fpre * r0 * r1;
       }
       if (!isfinite(R)) {
-        status = -4;  // CTAUX_ENUMERIC
-        L_eff = t;
-        err_index = done0 + t;
-        stop = true;
+        why = 3;
         break;
       }
       const int acc = (!skip && u_acc < fabs(R)) ? 1 : 0;
@@ -487,7 +478,8 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         scur[p] = static_cast<int8_t>(s_new);   // every thread writes the same value
         if (type == 0) {
           const int j = p - n;
-          alive[j >> 6] |= 1ull << (j & 63);
+          if (j < 64) alive_lo |= 1ull << j;
+          else alive_hi |= 1ull << (j - 64);
           if (tid == 0) sh_cid[next_cand] = next_id;
           next_id += 1;
           ncur += 1;
@@ -498,7 +490,8 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
             ndead += 1;
           } else {
             const int j = p - n;
-            alive[j >> 6] &= ~(1ull << (j & 63));
+            if (j < 64) alive_lo &= ~(1ull << j);
+            else alive_hi &= ~(1ull << (j - 64));
           }
         }
       }
@@ -510,12 +503,19 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       // Gamma full: the block ends here (with U = 0 the removed-vertex list, whose
       // length never exceeds that of P otherwise, bounds the block)
       if ((gz ? nchg : ka) == kcap) {
-        L_eff = t + 1;
-        stop = true;
+        why = 4;
         break;
       }
     }
-    if (stop || rp < 0) break;
+    if (why != 0) {
+      L_eff = (why == 4) ? t + 1 : t;
+      if (why != 4) {
+        status = (why == 1) ? -5 : -4;   // CTAUX_ECAPACITY, CTAUX_ENUMERIC
+        err_index = (why == 2) ? -3 : done0 + t;
+      }
+      break;
+    }
+    if (rp < 0) break;
 
     // ---- a repeated change of slot rp at proposal t (a removal or a flip) ----
     {
@@ -583,7 +583,8 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
             ndead += 1;
           } else {
             const int j = p - n;
-            alive[j >> 6] &= ~(1ull << (j & 63));
+            if (j < 64) alive_lo &= ~(1ull << j);
+            else alive_hi &= ~(1ull << (j - 64));
           }
         }
       }
