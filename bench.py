@@ -29,6 +29,8 @@ oracle timed on a bounded sample of the same workload, and further forms:
               same in FP64;
   config5     3D Nc = 100 cluster, beta = 6, order ~5000, 8 chains, FP32
               storage with FP64 refresh every <= 32 blocks;
+  graph       windows of 16 blocks replayed from a captured HIP graph against
+              blocks launched one by one (headline chain; one-site chain);
   cpu         the host FP64 submatrix form on one core, on the oracle's
               sample, with and without the measurement, beside the oracle.
 Each form reports its N error: the largest refinement drift of the run
@@ -54,7 +56,7 @@ FP32_PEAK_TFS = 157.3
 N_CU = 256
 
 METRIC = "vertex updates/s + rank-k TFLOP/s, mixed/batched vs plain FP64, same GPU"
-ALL_LEGS = "plain,mixed,cfg2x128,batched,config3,config5,cpu"
+ALL_LEGS = "plain,mixed,cfg2x128,batched,config3,config5,graph,cpu"
 
 
 def log(msg):
@@ -241,6 +243,41 @@ def cpu_baseline(w, config, therm_blocks, budget_s=15.0):
                      f"{el:.1f} s on one host core (the oracle is single-threaded)",
            "no_measurement": {"value": done_nm / el_nm, "proposals": done_nm, "seconds": el_nm}}
     out.update({"host_" + k: v for k, v in host_info().items()})
+    return out
+
+
+def leg_graph(ctaux):
+    """Blocks launched one by one against windows of 16 blocks replayed from a
+    captured HIP graph: the headline chain (k = 64, order ~1000) and the
+    one-site chain of a semicircular bath (beta = 10, U = 4, K = 1, order ~20,
+    k = 16), whose kernels are short enough for launch costs to show."""
+    import torch
+    from ctaux_inputs import anderson_semicircle
+    out = {}
+    cases = (("headline_4x4", cfg2_workload(), 64, 300, 200),
+             ("semicircle_nc1", anderson_semicircle(beta=10.0, U=4.0, K=1.0, n_tau=4096), 16, 4000, 2000))
+    for name, w, k, steps, warm in cases:
+        res = {}
+        for g in (0, 16):
+            gb = ctaux.CtauxBatch([w], _opts(ctaux, ctaux.CTAUX_FP64, k=k))
+            gb.set_graph(g)
+            gb.run(warm * k)
+            torch.cuda.synchronize()
+            best = None
+            for _ in range(3):
+                s0 = gb.stats(0)
+                t0 = time.perf_counter()
+                gb.run(steps * k)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                s1 = gb.stats(0)
+                rate = (s1["proposals"] - s0["proposals"]) / el
+                best = rate if best is None else max(best, rate)
+            res[f"graph_{g}"] = {"updates_per_s": best, "us_per_block": k / best * 1e6,
+                                 "mean_order_end": gb.stats(0)["order"], "graph_launches": gb.graph_launches}
+            gb.close()
+        res["speedup"] = res["graph_16"]["updates_per_s"] / res["graph_0"]["updates_per_s"]
+        out[name] = res
     return out
 
 
@@ -459,6 +496,9 @@ def main():
                                       n_tau_out=8)
             forms[name] = form(g3, d3, t3)
             g3.close()
+    if "graph" in legs:
+        log("graph: block windows replayed from a HIP graph vs launched one by one")
+        forms["graph_windows"] = leg_graph(ctaux)
     if "config5" in legs:
         from ctaux_inputs import dca_cubic
         w5 = dca_cubic(beta=6.0, U=8.0, K=3500.0, n_tau=8192)

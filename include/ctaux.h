@@ -244,6 +244,19 @@ int ctaux_set_timing(ctaux_batch *b, int32_t mask);
 /* Time only one launch in `every` of each selected kernel (default 1), which
  * keeps the events' own device time out of most launches. */
 int ctaux_set_timing_every(ctaux_batch *b, int32_t every);
+/* Replay windows of `blocks` blocks (0: off, or a power of two <= 64) from a
+ * HIP graph captured at the first window: ctaux_run then launches one graph
+ * per window instead of the window's kernels one by one (the same kernels in
+ * the same order, so the chains' results are unchanged).  A window is used
+ * where at least one more block of the run follows it, it starts at a
+ * multiple of `blocks` blocks, and every chain's refinement interval is at
+ * least `blocks` (refinements, which synchronise with the host, then fall
+ * between windows); elsewhere blocks are launched one by one.  No event
+ * timing runs inside a window.  Waits for the batch's streams; CTAUX_EINVAL
+ * for an invalid size. */
+int ctaux_set_graph(ctaux_batch *b, int32_t blocks);
+/* Number of graph windows launched so far (-1 for b == NULL). */
+int64_t ctaux_graph_launches(const ctaux_batch *b);
 int32_t ctaux_get_timing(ctaux_batch *b, const char **names, double *ms, int64_t *launches,
                          int32_t cap);
 

@@ -83,6 +83,14 @@ struct ctaux_batch {
   size_t pool_used = 0;
   double ms[kNumNames] = {0};
   int64_t launches[kNumNames] = {0};
+  // Block sequences replayed from a HIP graph (ctaux_set_graph): graph_blocks
+  // blocks (each ending in k_block_turn) and the last one's measurement,
+  // captured once and replayed where no refinement falls inside the window.
+  int32_t graph_blocks = 0;
+  bool capturing = false;
+  hipStream_t cstream = nullptr;   // capture stream (the batch's stream may be the null stream)
+  hipGraphExec_t gexec = nullptr;
+  int64_t graph_launches = 0;
   std::string err;
 };
 
@@ -301,6 +309,7 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
 }
 
 int enqueue_block(ctaux_batch *h, bool next_follows);
+int schedule_refinements(ctaux_batch *h);
 
 struct Timer {
   ctaux_batch *h;
@@ -554,15 +563,11 @@ int enqueue_block(ctaux_batch *h, bool next_follows) {
     int rc2 = launch_owed_measure(h);
     if (rc2) return rc2;
   }
+  if (h->capturing) return CTAUX_OK;   // counted and scheduled by the graph replay
   h->blocks_launched += 1;
-  if (h->recompute_every > 0) {
-    std::vector<int> due;
-    for (int c = 0; c < b.n_chains; ++c)
-      if (h->blocks_launched % h->interval[c] == 0) due.push_back(c);
-    if (!due.empty()) {
-      int rc2 = refine_chains(h, due, true, h->recompute_mode == 1);
-      if (rc2) return rc2;
-    }
+  {
+    int rc2 = schedule_refinements(h);
+    if (rc2) return rc2;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(h, CTAUX_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -572,6 +577,99 @@ int enqueue_block(ctaux_batch *h, bool next_follows) {
     flush_timing(h);
   }
   return CTAUX_OK;
+}
+
+// The refinements due after block blocks_launched (intervals are powers of two,
+// so with every interval a multiple of a graph window they fall at its ends).
+int schedule_refinements(ctaux_batch *h) {
+  if (h->recompute_every <= 0) return CTAUX_OK;
+  std::vector<int> due;
+  for (int c = 0; c < h->b.n_chains; ++c)
+    if (h->blocks_launched % h->interval[c] == 0) due.push_back(c);
+  if (due.empty()) return CTAUX_OK;
+  return refine_chains(h, due, true, h->recompute_mode == 1);
+}
+
+// Brings the streams to the state a graph window starts from: the next
+// block's start launched, no measurement owed or in flight.
+int graph_entry(ctaux_batch *h) {
+  if (!h->begun) {
+    Timer t(h, 0);
+    launch_block_begin(h->b, h->stream);
+    h->begun = true;
+  }
+  int rc = launch_owed_measure(h);
+  if (rc) return rc;
+  if (h->meas_pending) {
+    HIPCHECK(h, hipStreamWaitEvent(h->stream, h->ev_meas, 0));
+    h->meas_pending = false;
+  }
+  return CTAUX_OK;
+}
+
+// Captures graph_blocks blocks and the last one's measurement (joined back to
+// the capture stream) and instantiates them; nothing runs during the capture.
+// The capture runs on a stream of the library's own, since the batch's stream
+// may be the null stream; the graph is then launched on the batch's stream.
+int capture_window(ctaux_batch *h) {
+  if (!h->cstream && hipStreamCreate(&h->cstream) != hipSuccess) {
+    h->cstream = nullptr;
+    return set_err(h, CTAUX_EDEVICE, "hipStreamCreate failed");
+  }
+  const hipStream_t orig = h->stream;
+  const int32_t timing = h->timing;
+  h->timing = 0;   // no event pairs inside the graph
+  h->capturing = true;
+  h->stream = h->cstream;
+  int rc = CTAUX_OK;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = set_err(h, CTAUX_EDEVICE, "hipStreamBeginCapture failed");
+  } else {
+    for (int i = 0; i < h->graph_blocks && rc == CTAUX_OK; ++i) rc = enqueue_block(h, true);
+    if (rc == CTAUX_OK) rc = launch_owed_measure(h);
+    if (rc == CTAUX_OK && hipStreamWaitEvent(h->stream, h->ev_meas, 0) != hipSuccess)
+      rc = set_err(h, CTAUX_EDEVICE, "graph capture: joining the measurement stream failed");
+    const hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc == CTAUX_OK && e != hipSuccess) rc = set_err(h, CTAUX_EDEVICE, "hipStreamEndCapture failed");
+  }
+  h->capturing = false;
+  h->stream = orig;
+  h->timing = timing;
+  h->meas_owed = false;
+  h->meas_pending = false;
+  h->begun = true;
+  if (rc == CTAUX_OK && hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+    h->gexec = nullptr;
+    rc = set_err(h, CTAUX_EDEVICE, "hipGraphInstantiate failed");
+  }
+  if (g) (void)hipGraphDestroy(g);
+  return rc;
+}
+
+// A graph window may start here: graph_blocks blocks remain before the last
+// block of the run, the window is aligned to graph_blocks, and no chain's
+// refinement interval is shorter than the window.
+bool graph_window_ok(const ctaux_batch *h, int64_t blocks_left) {
+  const int g = h->graph_blocks;
+  if (g <= 0 || blocks_left <= g || h->blocks_launched % g != 0) return false;
+  if (h->recompute_every > 0)
+    for (int32_t iv : h->interval)
+      if (iv < g) return false;
+  return true;
+}
+
+int run_graph_window(ctaux_batch *h) {
+  int rc = graph_entry(h);
+  if (rc) return rc;
+  if (!h->gexec) {
+    rc = capture_window(h);
+    if (rc) return rc;
+  }
+  HIPCHECK(h, hipGraphLaunch(h->gexec, h->stream));
+  h->graph_launches += 1;
+  h->blocks_launched += h->graph_blocks;
+  return schedule_refinements(h);
 }
 
 int chain_error(ctaux_batch *h) {
@@ -746,8 +844,14 @@ int ctaux_run(ctaux_batch *h, int64_t n_proposals) {
   int64_t iters = (n_proposals + h->b.kmax - 1) / h->b.kmax;
   int64_t prev_done = -1;
   while (true) {
-    for (int64_t i = 0; i < iters; ++i) {
-      rc = enqueue_block(h, i + 1 < iters);
+    for (int64_t i = 0; i < iters;) {
+      if (graph_window_ok(h, iters - i)) {
+        rc = run_graph_window(h);
+        i += h->graph_blocks;
+      } else {
+        rc = enqueue_block(h, i + 1 < iters);
+        i += 1;
+      }
       if (rc) return rc;
     }
     rc = sync_states(h);
@@ -1115,6 +1219,22 @@ int ctaux_restore(ctaux_batch *h, int32_t chain, const void *buf, size_t len) {
   return CTAUX_OK;
 }
 
+int ctaux_set_graph(ctaux_batch *h, int32_t blocks) {
+  if (!h) return CTAUX_EINVAL;
+  if (blocks < 0 || blocks > 64 || (blocks & (blocks - 1)) != 0)
+    return set_err(h, CTAUX_EINVAL, "graph window must be 0 or a power of two up to 64 blocks");
+  int rc = sync_all(h);
+  if (rc) return rc;
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  h->graph_blocks = blocks;
+  return CTAUX_OK;
+}
+
+int64_t ctaux_graph_launches(const ctaux_batch *h) { return h ? h->graph_launches : -1; }
+
 int ctaux_set_timing_every(ctaux_batch *h, int32_t every) {
   if (!h || every < 1) return CTAUX_EINVAL;
   h->timing_every = every;
@@ -1130,6 +1250,8 @@ void ctaux_destroy(ctaux_batch *h) {
     (void)hipStreamSynchronize(h->mstream);
     (void)hipStreamDestroy(h->mstream);
   }
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->cstream) (void)hipStreamDestroy(h->cstream);
   if (h->ev_end) (void)hipEventDestroy(h->ev_end);
   if (h->ev_meas) (void)hipEventDestroy(h->ev_meas);
   for (TimedEvent &e : h->pool) {

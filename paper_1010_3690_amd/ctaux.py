@@ -28,6 +28,7 @@ EXPORTED = [
     "ctaux_workspace_bytes", "ctaux_create", "ctaux_run", "ctaux_recompute", "ctaux_obs_len", "ctaux_get_obs_kw",
     "ctaux_get_obs", "ctaux_reset_obs", "ctaux_get_stats", "ctaux_get_config", "ctaux_get_N",
     "ctaux_get_decisions", "ctaux_set_timing", "ctaux_set_timing_every", "ctaux_get_timing",
+    "ctaux_set_graph", "ctaux_graph_launches",
     "ctaux_checkpoint", "ctaux_restore", "ctaux_recompute_from_scratch",
     "ctaux_build_N_workspace_bytes", "ctaux_build_N", "ctaux_build_N_noalloc",
     "ctaux_last_error", "ctaux_destroy",
@@ -106,6 +107,9 @@ def load_library(path: str = LIB_PATH):
     lib.ctaux_get_decisions.argtypes = [vp, i32, i64, i64, vp, vp]
     lib.ctaux_set_timing.argtypes = [vp, i32]
     lib.ctaux_set_timing_every.argtypes = [vp, i32]
+    lib.ctaux_set_graph.argtypes = [vp, i32]
+    lib.ctaux_graph_launches.restype = i64
+    lib.ctaux_graph_launches.argtypes = [vp]
     lib.ctaux_get_timing.restype = i32
     lib.ctaux_get_timing.argtypes = [vp, vp, vp, vp, i32]
     lib.ctaux_checkpoint.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
@@ -270,6 +274,14 @@ class CtauxBatch:
 
     def restore(self, blob: bytes, chain: int = 0):
         self._check(self.lib.ctaux_restore(self.h, chain, C.c_char_p(blob), len(blob)))
+
+    def set_graph(self, blocks: int):
+        """Replay windows of `blocks` blocks from a captured HIP graph (0: off)."""
+        self._check(self.lib.ctaux_set_graph(self.h, int(blocks)))
+
+    @property
+    def graph_launches(self) -> int:
+        return int(self.lib.ctaux_graph_launches(self.h))
 
     def set_timing(self, enable, kernels=None, every=1):
         """Time every kernel (enable True), none (False), or only the named ones,
