@@ -592,12 +592,18 @@ def test_strongly_coupled_chain_holds_fp64_without_refinement():
 
 def test_autotune_keeps_the_chain():
     """The autotuner's candidates continue the same thermalised chains; the
-    chosen options are one of the candidates and the trial rates are positive."""
+    chosen options are one of the timed candidates, each timed three times
+    (median and spread reported), and a candidate with k_max > meas_every is
+    skipped."""
     ctaux = _ctaux()
     from paper_1010_3690_amd.autotune import autotune
     ws = [_plaquette(beta=3.0 + 0.25 * i) for i in range(6)]
     opts = ctaux.Options(k_max=64, k_cap=64, n_cap=512, recompute_every=16, seed=2, meas_every=64)
-    best, results = autotune(ws, opts, candidates=((32, 64), (64, 32)), warmup_proposals=64 * 20,
-                             trial_proposals=64 * 8)
-    assert len(results) == 2 and all(r["updates_per_s"] > 0 for r in results)
-    assert (best.k_max, best.rankk_tile) in ((32, 64), (64, 32))
+    best, results = autotune(ws, opts, candidates=((16, 32), (32, 64), (64, 32), (128, 64)),
+                             warmup_proposals=64 * 20, trial_proposals=64 * 8)
+    timed = [r for r in results if "updates_per_s" in r]
+    assert len(results) == 4 and len(timed) == 3
+    assert results[3].get("skipped") and results[3]["k_max"] == 128
+    for r in timed:
+        assert r["trials"] == 3 and 0 < r["min_updates_per_s"] <= r["updates_per_s"] <= r["max_updates_per_s"]
+    assert (best.k_max, best.rankk_tile) in ((16, 32), (32, 64), (64, 32))
