@@ -177,14 +177,17 @@ __global__ __launch_bounds__(256) void k_meas_kw_sort(const ChainDesc *descs, co
   }
 }
 
-// C_xx'(w) for one (chain, sector, site x) per workgroup.  Thread (g, b) owns
-// bin b = (x', m) (m fastest, so the lanes of one x' read the same N entries)
-// for the rows of site x in row group g; the row groups are summed in a fixed
-// order.  Deterministic: no atomics, every sum in a fixed order.
+// C_xx'(w) for one (chain, sector, site x) per workgroup:
+//   C_xx'(w) = sum_{l in x} e^{i w tau_l} (e^{V_l} - 1) sum_{k in x'} N_lk e^{-i w tau_k}.
+// Wave w takes the sites x' = w, w + 4, ...; lane (r, m) takes frequency m and
+// row r of a pass over up to 16 rows of site x, so the lanes of one row read
+// the same N entry (one transaction for all frequencies) and each N entry of
+// the pass is loaded once.  The rows' partial sums are added in a fixed order
+// through LDS: deterministic, no atomics.
 template <typename T>
 __global__ __launch_bounds__(256) void k_meas_kw_C(const ChainDesc *descs, const ChainState *states, int nc_max) {
-  __shared__ double red[256][2];
-  const int c = blockIdx.y, tid = threadIdx.x;
+  __shared__ double red[4][64][2];
+  const int c = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const ChainDesc &d = descs[c];
   const ChainState &st = states[c];
   if (!st.active || !st.meas_now || d.n_mats == 0) return;
@@ -196,44 +199,71 @@ __global__ __launch_bounds__(256) void k_meas_kw_C(const ChainDesc *descs, const
   const auto off = gview(d.kw_off);
   const auto list = gview(d.kw_list);
   const auto ph = gview(d.kw_ph);
-  const int nb = nc * nm, nbe = nb < 256 ? nb : 256, G = 256 / nbe;
-  const int g = tid / nbe, b = tid - g * nbe;
-  const int l0 = off[x], l1 = off[x + 1];
-  for (int bb = 0; bb < nb; bb += nbe) {
-    const int bin = bb + b;
-    double are = 0.0, aim = 0.0;
-    if (g < G && bin < nb) {
-      const int xp = bin / nm, m = bin - xp * nm;
-      const int k0 = off[xp], k1 = off[xp + 1];
-      for (int li = l0 + g; li < l1; li += G) {
-        const int l = list[li];
-        const double evl = gview(d.evd[sec])[s0[l] + 2] - 1.0;
-        double yre = 0.0, yim = 0.0;
-        for (int ki = k0; ki < k1; ++ki) {
-          const int k = list[ki];
-          const double nlk = static_cast<double>(N[static_cast<size_t>(l) * ld + k]);
-          yre = fma(nlk, ph[2 * (k * nm + m)], yre);
-          yim = fma(nlk, ph[2 * (k * nm + m) + 1], yim);
-        }
+  const auto evd = gview(d.evd[sec]);
+  int mp = 1;   // frequencies padded to a power of two (n_matsubara <= 32)
+  while (mp < nm) mp <<= 1;
+  const int rows = min(16, 64 / mp);           // rows of site x per pass
+  const int r = lane / mp, m = lane - r * mp;  // lane's row in the pass, frequency
+  const bool mine = m < nm && r < rows;
+  const int l0 = off[x], l1 = off[x + 1], nb = nc * nm;
+  double *C = d.kw_C + 2 * (static_cast<size_t>(sec) * nc + x) * nb;
+  for (int xp = wave; xp < nc; xp += 4) {
+    const int k0 = off[xp], k1 = off[xp + 1];
+    double cre = 0.0, cim = 0.0;
+    for (int lb = l0; lb < l1; lb += rows) {
+      const bool on = mine && lb + r < l1;
+      const int l = on ? list[lb + r] : list[l0];   // an in-range row for idle lanes (value unused)
+      const auto nrow = N + static_cast<size_t>(l) * ld;
+      const int mm = m < nm ? m : 0;
+      double yre = 0.0, yim = 0.0;
+      int ki = k0;
+      for (; ki + 4 <= k1; ki += 4) {   // four independent loads in flight
+        const int ka = list[ki], kb = list[ki + 1], kc = list[ki + 2], kd = list[ki + 3];
+        const double na = static_cast<double>(nrow[ka]), nb2 = static_cast<double>(nrow[kb]);
+        const double nc2 = static_cast<double>(nrow[kc]), nd = static_cast<double>(nrow[kd]);
+        const auto pa = ph + 2 * (ka * nm + mm), pb = ph + 2 * (kb * nm + mm);
+        const auto pc = ph + 2 * (kc * nm + mm), pd = ph + 2 * (kd * nm + mm);
+        yre = fma(na, pa[0], yre);
+        yim = fma(na, pa[1], yim);
+        yre = fma(nb2, pb[0], yre);
+        yim = fma(nb2, pb[1], yim);
+        yre = fma(nc2, pc[0], yre);
+        yim = fma(nc2, pc[1], yim);
+        yre = fma(nd, pd[0], yre);
+        yim = fma(nd, pd[1], yim);
+      }
+      for (; ki < k1; ++ki) {
+        const int k = list[ki];
+        const double nlk = static_cast<double>(nrow[k]);
+        yre = fma(nlk, ph[2 * (k * nm + mm)], yre);
+        yim = fma(nlk, ph[2 * (k * nm + mm) + 1], yim);
+      }
+      if (on) {
+        const double evl = evd[s0[l] + 2] - 1.0;
         // e^{+i w tau_l} = conj(ph_l)
         const double pr = ph[2 * (l * nm + m)], pi = -ph[2 * (l * nm + m) + 1];
-        are += evl * (pr * yre - pi * yim);
-        aim += evl * (pr * yim + pi * yre);
+        cre += evl * (pr * yre - pi * yim);
+        cim += evl * (pr * yim + pi * yre);
       }
     }
-    red[tid][0] = are;
-    red[tid][1] = aim;
-    __syncthreads();
-    if (g == 0 && bin < nb) {
-      for (int q = 1; q < G; ++q) {
-        are += red[q * nbe + b][0];
-        aim += red[q * nbe + b][1];
+    // rows of the pass in a fixed order: lane m collects lanes m, m + mp, ...
+    red[wave][lane][0] = cre;
+    red[wave][lane][1] = cim;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    if (lane < nm) {
+      double sre = 0.0, sim = 0.0;
+      for (int q = 0; q < rows; ++q) {
+        sre += red[wave][q * mp + lane][0];
+        sim += red[wave][q * mp + lane][1];
       }
-      double *C = d.kw_C + 2 * ((static_cast<size_t>(sec) * nc + x) * nb + bin);
-      gview_w(C)[0] = are;
-      gview_w(C)[1] = aim;
+      gview_w(C)[2 * (xp * nm + lane)] = sre;
+      gview_w(C)[2 * (xp * nm + lane) + 1] = sim;
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();   // red is reused for the next site
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
   }
 }
 
