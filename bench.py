@@ -284,16 +284,18 @@ def leg_graph(ctaux):
 def leg_cpu_submatrix(w, config, oracle, budget_s=10.0):
     """The host FP64 submatrix form (one core, k = 64, AVX2 register tiles) on the
     oracle's sample: the same starting configuration, measuring every 64
-    proposals, then with the measurement off; each rate beside the oracle's
-    under the same settings (the paper compares the two update rates on one
-    core)."""
+    proposals, then with the measurement off, Gamma grown by partitioning and
+    then as LU factors; each rate beside the oracle's under the same settings
+    (the paper compares the two update rates on one core)."""
     from paper_1010_3690_amd import ctaux
     from paper_1010_3690_amd.cpu import CpuChain
     ids, tau, site, s = config
     out = {"cores": 1, "k": 64, "host_cpu": host_info()["cpu"]}
-    for name, meas in (("measuring", 64), ("no_measurement", 1 << 30)):
+    for name, meas, growth in (("measuring", 64, 0), ("no_measurement", 1 << 30, 0),
+                               ("no_measurement_lu_growth", 1 << 30, 1)):
         ch = CpuChain(w, ctaux.Options(k_max=64, k_cap=64, p_flip=0.2, meas_every=meas, n_tau_out=16,
                                        n_cap=4096, seed=12345))
+        ch.set_growth(growth)
         ch.set_config(ids, tau, site, s)
         ch.run(64 * 4)   # first blocks: buffers sized
         done = 0

@@ -50,6 +50,14 @@ int ctaux_cpu_get_obs(const ctaux_cpu_chain *c, double *out, int32_t len);
  * definition by Gauss-Jordan elimination with partial pivoting. */
 int ctaux_cpu_set_config(ctaux_cpu_chain *c, int32_t n, const ctaux_vertex *config, int64_t proposals_done,
                          int64_t next_id, double sign);
+/* How Gamma grows inside a block (Sec. III B): mode 0 keeps its inverse by
+ * partitioning (Eq. ratS; the default), mode 1 an LU factorisation grown by two
+ * triangular solves per proposal (Eqs. lineq1, lineq2, detrat, betagammak),
+ * re-factorised after an accepted repeated change of a vertex.  Both give the
+ * same ratios up to rounding and the same N (Gamma's inverse for the update is
+ * taken from Gamma itself at the end of the block either way).  Applies from
+ * the next block; CTAUX_EINVAL for another mode. */
+int ctaux_cpu_set_growth(ctaux_cpu_chain *c, int32_t mode);
 const char *ctaux_cpu_last_error(const ctaux_cpu_chain *c);
 void ctaux_cpu_destroy(ctaux_cpu_chain *c);
 

@@ -13,8 +13,8 @@ from .ctaux import CtauxError, Options, _Vertex, _model_of, _ptr
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libctaux_cpu.so")
 EXPORTED = ["ctaux_cpu_create", "ctaux_cpu_run", "ctaux_cpu_get_state", "ctaux_cpu_get_config", "ctaux_cpu_get_N",
-            "ctaux_cpu_get_decisions", "ctaux_cpu_get_obs", "ctaux_cpu_set_config", "ctaux_cpu_last_error",
-            "ctaux_cpu_destroy"]
+            "ctaux_cpu_get_decisions", "ctaux_cpu_get_obs", "ctaux_cpu_set_config", "ctaux_cpu_set_growth",
+            "ctaux_cpu_last_error", "ctaux_cpu_destroy"]
 
 _lib = None
 
@@ -37,6 +37,7 @@ def load_cpu_library(path: str = LIB_PATH):
     lib.ctaux_cpu_set_config.argtypes = [vp, i32, vp, i64, i64, C.c_double]
     lib.ctaux_cpu_last_error.restype = C.c_char_p
     lib.ctaux_cpu_last_error.argtypes = [vp]
+    lib.ctaux_cpu_set_growth.argtypes = [vp, i32]
     lib.ctaux_cpu_destroy.argtypes = [vp]
     _lib = lib
     return lib
@@ -65,6 +66,10 @@ class CpuChain:
     def _check(self, rc):
         if rc != 0:
             raise CtauxError(rc, self.lib.ctaux_cpu_last_error(self.h).decode())
+
+    def set_growth(self, mode: int):
+        """0: Gamma's inverse grown by partitioning; 1: Gamma's LU factors grown."""
+        self._check(self.lib.ctaux_cpu_set_growth(self.h, int(mode)))
 
     def run(self, n_proposals: int):
         self._check(self.lib.ctaux_cpu_run(self.h, int(n_proposals)))

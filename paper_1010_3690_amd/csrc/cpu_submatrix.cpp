@@ -14,7 +14,12 @@
 //    (N_a - I) (old columns) or (G - I) (candidate columns) minus 1/(gh_b D_b) on
 //    the diagonal, gh_b = e^{V(s_b) - V(s0_b)} - 1 the net change of vertex b;
 //  * a new change grows X = Gamma~^{-1} by partitioning (Sec. III B 2):
-//    beta~ = d - w^T X s, sector ratio -gh D_p beta~ (Eq. ratS);
+//    beta~ = d - w^T X s, sector ratio -gh D_p beta~ (Eq. ratS); or (growth
+//    mode 1) an LU factorisation Gamma~ = L U grows by the solutions of
+//    L y = s and U^T x = w, with beta~ = d - x^T y (Sec. III B 1, Eqs. lineq1,
+//    lineq2, detrat): L gains the row [x^T 1], U the column [y; beta~], and a
+//    repeated change takes X_aa from two triangular solves and factorises
+//    Gamma~ again once accepted (in place of Bennett's rank-1 update);
 //  * a further change of a vertex already in P replaces its gh (ratio by the
 //    matrix determinant lemma, X by Sherman-Morrison), and a change back to the
 //    block-start spin removes its slot (ratio X_aa / (-gh D_p), X by the Schur
@@ -206,6 +211,31 @@ bool invert_gj(double *a, int n, int lda) {
   return true;
 }
 
+// Doolittle LU of the k x k matrix A (leading dimension ld) without pivoting,
+// the factorisation the growth builds row by row; false on a zero pivot.
+bool lu_nopiv(const double *A, int k, int ld, double *L, double *U) {
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      L[static_cast<size_t>(i) * ld + j] = (i == j) ? 1.0 : 0.0;
+      U[static_cast<size_t>(i) * ld + j] = 0.0;
+    }
+  for (int i = 0; i < k; ++i) {
+    for (int j = i; j < k; ++j) {   // row i of U
+      double s = A[static_cast<size_t>(i) * ld + j];
+      for (int q = 0; q < i; ++q) s -= L[static_cast<size_t>(i) * ld + q] * U[static_cast<size_t>(q) * ld + j];
+      U[static_cast<size_t>(i) * ld + j] = s;
+    }
+    const double piv = U[static_cast<size_t>(i) * ld + i];
+    if (!(piv != 0.0) || !std::isfinite(piv)) return false;
+    for (int r = i + 1; r < k; ++r) {   // column i of L
+      double s = A[static_cast<size_t>(r) * ld + i];
+      for (int q = 0; q < i; ++q) s -= L[static_cast<size_t>(r) * ld + q] * U[static_cast<size_t>(q) * ld + i];
+      L[static_cast<size_t>(r) * ld + i] = s / piv;
+    }
+  }
+  return true;
+}
+
 }  // namespace
 
 struct ctaux_cpu_chain {
@@ -231,6 +261,9 @@ struct ctaux_cpu_chain {
   // block buffers
   std::vector<double> X[2], Z[2], Rt[2], Y[2], Gnn[2];   // X, Rt: ki x n0; Z, Y: n0 x kp; Gnn: ki x kp
   std::vector<double> Xi[2];     // Gamma~^{-1} (kmax x kmax, leading dimension kmax)
+  // LU growth (Sec. III B 1): Gamma~ = L U, L unit lower, U upper (kmax x kmax)
+  int growth = 0;                // 0: inversion by partitioning, 1: LU growth
+  std::vector<double> Lm[2], Um[2];
   std::vector<double> obs;
   std::vector<uint8_t> log_acc;
   std::vector<double> log_R;
@@ -325,8 +358,32 @@ int ctaux_cpu_chain::block(int64_t L) {
   std::vector<int> scur(na, 0), s0(na, 0), slot(na, -1), P;
   for (int i = 0; i < n0; ++i) scur[i] = s0[i] = spin[i];
   std::vector<double> gh[2];
-  for (int sec = 0; sec < 2; ++sec) Xi[sec].assign(static_cast<size_t>(kmax) * kmax, 0.0);
-  std::vector<double> sv(kmax), wv(kmax), v(kmax), u(kmax);
+  const bool lu = growth == 1;
+  for (int sec = 0; sec < 2; ++sec) {
+    Xi[sec].assign(static_cast<size_t>(kmax) * kmax, 0.0);
+    if (lu) {
+      Lm[sec].assign(static_cast<size_t>(kmax) * kmax, 0.0);
+      Um[sec].assign(static_cast<size_t>(kmax) * kmax, 0.0);
+    }
+  }
+  std::vector<double> sv(kmax), wv(kmax), v(kmax), u(kmax), ly[2], ux[2];
+  ly[0].assign(kmax, 0.0); ly[1].assign(kmax, 0.0); ux[0].assign(kmax, 0.0); ux[1].assign(kmax, 0.0);
+  // (Gamma~^{-1})_aa from the factors: L c = e_a, U z = c
+  auto lu_inv_diag = [&](int sec, int a, int k) {
+    const double *Lp = Lm[sec].data(), *Up = Um[sec].data();
+    std::vector<double> cz(k, 0.0);
+    for (int i = a; i < k; ++i) {
+      double c = (i == a) ? 1.0 : 0.0;
+      for (int j = a; j < i; ++j) c -= Lp[static_cast<size_t>(i) * kmax + j] * cz[j];
+      cz[i] = c;
+    }
+    for (int i = k - 1; i >= a; --i) {
+      double z = cz[i];
+      for (int j = i + 1; j < k; ++j) z -= Up[static_cast<size_t>(i) * kmax + j] * cz[j];
+      cz[i] = z / Up[static_cast<size_t>(i) * kmax + i];
+    }
+    return cz[a];
+  };
   int ncur = n0, next_cand = 0, ka = 0;
   std::vector<int64_t> cid(ki, -1);
   int64_t L_eff = L;
@@ -362,7 +419,8 @@ int ctaux_cpu_chain::block(int64_t L) {
         dp[sec] = dscale(sec, s0[p]);
         const double *xi = Xi[sec].data();
         if (a >= 0) {   // repeated change of slot a: net change from the block start
-          const double go = gh[sec][a], gn = e(sec, s_new - s0[p]) - 1.0, xaa = xi[a * kmax + a];
+          const double go = gh[sec][a], gn = e(sec, s_new - s0[p]) - 1.0;
+          const double xaa = lu ? lu_inv_diag(sec, a, ka) : xi[a * kmax + a];
           ghn[sec] = gn;
           rs[sec] = s_new == s0[p] ? xaa / (-go * dp[sec]) : (gn / go) * (1.0 + (1.0 / go - 1.0 / gn) / dp[sec] * xaa);
         } else {
@@ -371,16 +429,31 @@ int ctaux_cpu_chain::block(int64_t L) {
             wv[b] = gt(sec, p, P[b]);
           }
           double dd = gt(sec, p, p) - 1.0 / (ghn[sec] * dp[sec]);
-          for (int i = 0; i < ka; ++i) {
-            double s = 0.0, s2 = 0.0;
-            for (int j = 0; j < ka; ++j) {
-              s += xi[i * kmax + j] * sv[j];
-              s2 += wv[j] * xi[j * kmax + i];
+          if (lu) {   // L y = s, U^T x = w (Eqs. lineq1, lineq2), beta~ = d - x^T y (Eq. detrat)
+            const double *Lp = Lm[sec].data(), *Up = Um[sec].data();
+            double *y = ly[sec].data(), *x = ux[sec].data();
+            for (int i = 0; i < ka; ++i) {
+              double ys = sv[i], xs = wv[i];
+              for (int j = 0; j < i; ++j) {
+                ys -= Lp[static_cast<size_t>(i) * kmax + j] * y[j];
+                xs -= Up[static_cast<size_t>(j) * kmax + i] * x[j];
+              }
+              y[i] = ys;
+              x[i] = xs / Up[static_cast<size_t>(i) * kmax + i];
             }
-            v[i] = s;   // X s
-            u[i] = s2;  // w^T X
+            for (int i = 0; i < ka; ++i) dd -= x[i] * y[i];
+          } else {
+            for (int i = 0; i < ka; ++i) {
+              double s = 0.0, s2 = 0.0;
+              for (int j = 0; j < ka; ++j) {
+                s += xi[i * kmax + j] * sv[j];
+                s2 += wv[j] * xi[j * kmax + i];
+              }
+              v[i] = s;   // X s
+              u[i] = s2;  // w^T X
+            }
+            for (int i = 0; i < ka; ++i) dd -= wv[i] * v[i];
           }
-          for (int i = 0; i < ka; ++i) dd -= wv[i] * v[i];
           bt[sec] = dd;
           rs[sec] = -ghn[sec] * dp[sec] * dd;   // the growth on acceptance recomputes X s and w^T X
         }
@@ -400,7 +473,29 @@ int ctaux_cpu_chain::block(int64_t L) {
     if (acc) {
       accepted += 1;
       if (R < 0.0) sign = -sign;
-      if (!gz) {
+      if (!gz && lu) {
+        for (int sec = 0; sec < 2; ++sec) {
+          if (a >= 0) {   // the net change of slot a, or its removal (re-factorised below)
+            if (s_new != s0[p]) {
+              gh[sec][a] = ghn[sec];
+            } else {
+              gh[sec][a] = gh[sec][ka - 1];
+              gh[sec].pop_back();
+            }
+          } else {   // Gamma~ grows: L gains the row [x^T 1], U the column [y; beta~]
+            double *Lp = Lm[sec].data(), *Up = Um[sec].data();
+            const int k = ka;
+            for (int j = 0; j < k; ++j) {
+              Lp[static_cast<size_t>(k) * kmax + j] = ux[sec][j];
+              Up[static_cast<size_t>(j) * kmax + k] = ly[sec][j];
+            }
+            Lp[static_cast<size_t>(k) * kmax + k] = 1.0;
+            Up[static_cast<size_t>(k) * kmax + k] = bt[sec];
+            gh[sec].push_back(ghn[sec]);
+          }
+        }
+      }
+      if (!gz && !lu) {
         for (int sec = 0; sec < 2; ++sec) {
           double *xi = Xi[sec].data();
           if (a >= 0) {
@@ -448,6 +543,8 @@ int ctaux_cpu_chain::block(int64_t L) {
             gh[sec].push_back(ghn[sec]);
           }
         }
+      }
+      if (!gz) {
         if (a >= 0) {
           if (s_new == s0[p]) {
             const int last = ka - 1;
@@ -455,6 +552,21 @@ int ctaux_cpu_chain::block(int64_t L) {
             P.pop_back();
             slot[p] = -1;
             ka -= 1;
+          }
+          if (lu) {   // a changed diagonal entry or a removed slot: factorise Gamma~ again
+            std::vector<double> G(static_cast<size_t>(kmax) * kmax, 0.0);
+            for (int sec = 0; sec < 2 && rc == CTAUX_OK; ++sec) {
+              for (int i = 0; i < ka; ++i)
+                for (int j = 0; j < ka; ++j)
+                  G[static_cast<size_t>(i) * kmax + j] =
+                      gt(sec, P[i], P[j]) - (i == j ? 1.0 / (gh[sec][j] * dscale(sec, s0[P[j]])) : 0.0);
+              if (!lu_nopiv(G.data(), ka, kmax, Lm[sec].data(), Um[sec].data()))
+                rc = fail(CTAUX_ENUMERIC, "zero pivot re-factorising Gamma at proposal %lld", (long long)(done + t));
+            }
+            if (rc != CTAUX_OK) {
+              L_eff = t;
+              break;
+            }
           }
         } else {
           P.push_back(p);
@@ -735,6 +847,12 @@ int ctaux_cpu_set_config(ctaux_cpu_chain *c, int32_t n, const ctaux_vertex *v, i
 }
 
 const char *ctaux_cpu_last_error(const ctaux_cpu_chain *c) { return c ? c->err.c_str() : "null chain"; }
+
+int ctaux_cpu_set_growth(ctaux_cpu_chain *c, int32_t mode) {
+  if (!c || (mode != 0 && mode != 1)) return CTAUX_EINVAL;
+  c->growth = mode;
+  return CTAUX_OK;
+}
 
 void ctaux_cpu_destroy(ctaux_cpu_chain *c) { delete c; }
 

@@ -106,3 +106,36 @@ def test_cpu_block_independence_and_restart(cpu):
     a.run(n_prop)
     b.run(n_prop)
     assert np.array_equal(a.decisions(n_prop, n_prop)[0], b.decisions(n_prop, n_prop)[0])
+
+
+@pytest.mark.parametrize("name,make,n_prop,kmax", [
+    ("plaquette", _plaquette, 4000, 64),
+    ("plaquette_sign", hubbard_plaquette, 4000, 64),
+    ("cluster16", _cluster16, 3000, 64),
+])
+def test_lu_growth_matches_partitioning_and_oracle(cpu, name, make, n_prop, kmax):
+    """Gamma grown as LU factors (Sec. III B 1) gives the decisions of the
+    rank-1 oracle and of the growth by partitioning, ratios within rounding of
+    the partitioning form's, and the same N; repeated changes of a vertex
+    (re-factorised) occur in these runs."""
+    from paper_1010_3690_amd.ctaux import Options
+    w = make()
+    opts = Options(k_max=kmax, n_cap=1024, log_cap=n_prop, meas_every=kmax, n_tau_out=4, seed=5)
+    part = cpu.CpuChain(w, opts)
+    lu = cpu.CpuChain(w, opts)
+    lu.set_growth(1)
+    oc = OracleChain(w, seed=5, meas_every=kmax, n_tau_out=4, n_cap=1024)
+    oc.set_log(n_prop)
+    part.run(n_prop)
+    lu.run(n_prop)
+    oc.run(n_prop)
+    acc_p, R_p = part.decisions(0, n_prop)
+    acc_l, R_l = lu.decisions(0, n_prop)
+    acc_o, _ = oc.get_log(0, n_prop)
+    assert np.array_equal(acc_l, acc_o) and np.array_equal(acc_l, acc_p)
+    np.testing.assert_allclose(R_l, R_p, rtol=1e-9, atol=1e-300)
+    for sec in (0, 1):
+        Np = part.N(sec)
+        assert np.linalg.norm(lu.N(sec) - Np) / np.linalg.norm(Np) < 1e-12
+    with pytest.raises(Exception):
+        lu.set_growth(2)
