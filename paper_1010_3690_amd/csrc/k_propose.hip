@@ -403,7 +403,8 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         }
         const double raw_s = (si >= 0) ? gat(si, sj) : 0.0;
         const double raw_w = (wi >= 0) ? gat(wi, wj) : 0.0;
-        const int s0p = s0l[p];
+        // outside P an old vertex still has its block-start spin, a candidate 0
+        const int s0p = s_old;
         gh0 = sh_ev[0][s_new - s0p + 2] - sh_ev[0][s_old - s0p + 2];
         gh1 = sh_ev[1][s_new - s0p + 2] - sh_ev[1][s_old - s0p + 2];
         dp0 = sh_dsc[0][s0p + 2];   // 1 for a candidate (s0 = 0)
