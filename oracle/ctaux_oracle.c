@@ -23,7 +23,7 @@ struct oc_chain {
     /* walk parameters */
     uint64_t seed;
     uint32_t chain_id;
-    double p_flip;
+    double p_flip, p_pair;
     int32_t meas_every, n_out, n_cap;
     int64_t n_therm;
     /* state */
@@ -43,6 +43,8 @@ struct oc_chain {
     /* last proposal */
     int32_t last_type, last_p, last_site, last_s, last_acc;
     double last_tau, last_R;
+    int32_t last_p2, last_site2, last_s2;   /* second vertex of a pair proposal */
+    double last_tau2;
     /* observables */
     double *obs;
     int32_t obs_len;
@@ -97,6 +99,20 @@ void oc_draws(uint64_t seed, uint32_t chain_id, uint64_t index, double out[5]) {
         if (tag == 1) { out[2] = u53(x[0], x[1]); out[3] = u53(x[2], x[3]); }
         if (tag == 2) { out[4] = u53(x[0], x[1]); }
     }
+}
+
+/* Extra uniforms of a pair proposal: the second word pair of tag 2 (spin of
+ * the second vertex) and tag 3 (its time and its pick). */
+void oc_pair_draws(uint64_t seed, uint32_t chain_id, uint64_t index, double out[3]) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    uint32_t c2[4] = {(uint32_t)index, (uint32_t)(index >> 32), chain_id, 2};
+    oc_philox4x32_10(c2, key, x);
+    out[0] = u53(x[2], x[3]);
+    uint32_t c3[4] = {(uint32_t)index, (uint32_t)(index >> 32), chain_id, 3};
+    oc_philox4x32_10(c3, key, x);
+    out[1] = u53(x[0], x[1]);
+    out[2] = u53(x[2], x[3]);
 }
 
 /* Eq. (gamma) with the cluster factor: cosh(gamma) = 1 + beta*U*Nc/(2K). */
@@ -293,6 +309,85 @@ static void flip_commit(oc_chain *c, int sec, int p, int32_t s_new, double r) {
         for (int j = 0; j < n; ++j) NE(c, sec, i, j) += u[i] * row[j];
 }
 
+/* ---------------- pair updates (Sec. II B, Sec. IV B) ---------------------- */
+/* Two vertices v_0, v_1 inserted together enlarge N^{-1} by two rows and two
+ * columns.  By the block determinant formula the ratio det N''^{-1}/det N^{-1}
+ * is the determinant of the 2x2 Schur complement
+ *   S_ab = (N''^{-1})_{v_a v_b} - r_a N c_b,
+ * with c_b, r_a the new column of v_b and the new row of v_a (as in
+ * insert_ratio) and, from Eq. (Nmatrix),
+ *   (N''^{-1})_{v_a v_b} = delta_ab e^{V(s_a)} - G0(tau_a - tau_b)(e^{V(s_b)} - 1)
+ * (the diagonal reads G0 at 0+). */
+static double pair_insert_ratio(oc_chain *c, int sec, const double tau[2], const int32_t x[2],
+                                const int32_t s[2]) {
+    int n = c->n;
+    double *buf = (double *)malloc(sizeof(double) * 4 * (size_t)(n > 0 ? n : 1));
+    double *col[2] = {buf, buf + n}, *ncol[2] = {buf + 2 * n, buf + 3 * n};
+    for (int b = 0; b < 2; ++b) {
+        double evb = expV(c, sec, s[b]);
+        for (int i = 0; i < n; ++i)
+            col[b][i] = -oc_g0_lookup(c, sec, c->site[i], x[b], c->tau[i] - tau[b]) * (evb - 1.0);
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += NE(c, sec, i, k) * col[b][k];
+            ncol[b][i] = acc;
+        }
+    }
+    double S[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double e = (a == b ? expV(c, sec, s[a]) : 0.0) -
+                       oc_g0_lookup(c, sec, x[a], x[b], a == b ? 0.0 : tau[a] - tau[b]) *
+                           (expV(c, sec, s[b]) - 1.0);
+            double rnc = 0.0;
+            for (int j = 0; j < n; ++j) {
+                double r = -oc_g0_lookup(c, sec, x[a], c->site[j], tau[a] - c->tau[j]) *
+                           (expV(c, sec, c->s[j]) - 1.0);
+                rnc += r * ncol[b][j];
+            }
+            S[a][b] = e - rnc;
+        }
+    free(buf);
+    return S[0][0] * S[1][1] - S[0][1] * S[1][0];
+}
+
+/* Appends vertex (tau, x, s) with the next id: bordering of both sectors. */
+static int append_vertex(oc_chain *c, double tau, int32_t x, int32_t s) {
+    int n = c->n;
+    double S0 = insert_ratio(c, 0, tau, x, s), S1 = insert_ratio(c, 1, tau, x, s);
+    if (!(S0 != 0.0) || !(S1 != 0.0) || !isfinite(S0) || !isfinite(S1))
+        return fail(c, OC_ENUMERIC, "singular bordering in a pair insertion");
+    c->tau[n] = tau; c->site[n] = x; c->s[n] = s; c->id[n] = c->next_id++;
+    insert_commit(c, 0, tau, x, S0);
+    insert_commit(c, 1, tau, x, S1);
+    c->n = n + 1;
+    return OC_OK;
+}
+
+/* Removes the vertex at position p from both sectors, keeping the canonical order. */
+static void remove_vertex(oc_chain *c, int p) {
+    int n = c->n;
+    remove_commit(c, 0, p);
+    remove_commit(c, 1, p);
+    for (int i = p; i < n - 1; ++i) {
+        c->tau[i] = c->tau[i + 1]; c->site[i] = c->site[i + 1];
+        c->s[i] = c->s[i + 1]; c->id[i] = c->id[i + 1];
+    }
+    c->n = n - 1;
+}
+
+/* Removal of the vertices at positions a and b: by Jacobi's identity the
+ * ratio det N''^{-1}/det N^{-1} (rows and columns a, b deleted from N^{-1}) is
+ * the complementary minor det N[{a,b},{a,b}]. */
+static double pair_remove_ratio(const oc_chain *c, int sec, int a, int b) {
+    return NE(c, sec, a, a) * NE(c, sec, b, b) - NE(c, sec, a, b) * NE(c, sec, b, a);
+}
+
+static int32_t site_of(const oc_chain *c, double u_pick) {
+    int32_t x = (int32_t)floor((double)c->nc * u_pick);
+    return x > c->nc - 1 ? c->nc - 1 : x;
+}
+
 /* ---------------- measurement (Sec. IV D) ---------------------------------- */
 /* With T = (e^V - 1) N, the estimator is
  *   G(x tau; y 0) = G0_xy(tau) + sum_{l,k} G0_{x x_l}(tau - tau_l) T_lk G0_{x_k y}(tau_k).
@@ -469,22 +564,36 @@ static void measure(oc_chain *c) {
 }
 
 /* ---------------- the walk (Sec. II B) ------------------------------------- */
+/* Proposal mix: insertion and removal with probability (1 - p_flip - p_pair)/2
+ * each, insertion and removal of a pair of vertices (Sec. IV B) with p_pair/2
+ * each, a spin flip with p_flip.  Acceptance ratios (Eq. insprob and its
+ * detailed-balance partners), n the order before the move:
+ *   insert K/(n+1), remove n/K, pair insert K^2/((n+1)(n+2)),
+ *   pair remove n(n-1)/K^2, flip 1,
+ * each times prod_sigma det N'^{-1}_sigma / det N^{-1}_sigma.  A pair is
+ * proposed with density 2 (1/(2 beta Nc))^2 for the unordered pair and removed
+ * with probability 1/C(n+2, 2), which gives the pair factors. */
 static int step(oc_chain *c) {
     double u[5];
     int64_t idx = c->done;
     oc_draws(c->seed, c->chain_id, (uint64_t)idx, u);
     double u_type = u[0], u_acc = u[1], u_tau = u[2], u_pick = u[3], u_spin = u[4];
-    double p_ins = 0.5 * (1.0 - c->p_flip);
-    int type = u_type < p_ins ? 0 : (u_type < 2.0 * p_ins ? 1 : 2);
+    double p_one = 0.5 * (1.0 - c->p_flip - c->p_pair);
+    int type;
+    if (u_type < p_one) type = 0;
+    else if (u_type < 2.0 * p_one) type = 1;
+    else if (u_type < 2.0 * p_one + 0.5 * c->p_pair) type = 3;
+    else if (u_type < 2.0 * p_one + c->p_pair) type = 4;
+    else type = 2;
     int n = c->n;
     double R = 0.0;
     int acc = 0;
     c->last_type = type; c->last_p = -1; c->last_tau = 0; c->last_site = -1; c->last_s = 0;
+    c->last_p2 = -1; c->last_tau2 = 0; c->last_site2 = -1; c->last_s2 = 0;
     if (type == 0) {
         /* insertion: random time, site and auxiliary spin; R = K/(n+1) prod_sigma ratio */
         double tau = c->beta * u_tau;
-        int32_t x = (int32_t)floor((double)c->nc * u_pick);
-        if (x > c->nc - 1) x = c->nc - 1;
+        int32_t x = site_of(c, u_pick);
         int32_t s = u_spin < 0.5 ? -1 : 1;
         c->last_p = n; c->last_tau = tau; c->last_site = x; c->last_s = s;
         if (n + 1 > c->n_cap)
@@ -500,6 +609,49 @@ static int step(oc_chain *c) {
             insert_commit(c, 1, tau, x, S1);
             c->n = n + 1;
         }
+    } else if (type == 3) {
+        /* pair insertion: two independent (time, site, spin) draws */
+        double v[3];
+        oc_pair_draws(c->seed, c->chain_id, (uint64_t)idx, v);
+        double tau[2] = {c->beta * u_tau, c->beta * v[1]};
+        int32_t x[2] = {site_of(c, u_pick), site_of(c, v[2])};
+        int32_t s[2] = {u_spin < 0.5 ? -1 : 1, v[0] < 0.5 ? -1 : 1};
+        c->last_p = n; c->last_tau = tau[0]; c->last_site = x[0]; c->last_s = s[0];
+        c->last_p2 = n + 1; c->last_tau2 = tau[1]; c->last_site2 = x[1]; c->last_s2 = s[1];
+        if (n + 2 > c->n_cap)
+            return fail(c, OC_ECAPACITY, "order would exceed n_cap=%d", c->n_cap);
+        double S0 = pair_insert_ratio(c, 0, tau, x, s);
+        double S1 = pair_insert_ratio(c, 1, tau, x, s);
+        R = c->K * c->K / ((double)(n + 1) * (double)(n + 2)) * S0 * S1;
+        if (!isfinite(R)) return fail(c, OC_ENUMERIC, "non-finite pair insertion ratio at proposal %lld", (long long)idx);
+        if (u_acc < fabs(R)) {
+            acc = 1;
+            int rc = append_vertex(c, tau[0], x[0], s[0]);
+            if (rc) return rc;
+            rc = append_vertex(c, tau[1], x[1], s[1]);
+            if (rc) return rc;
+        }
+    } else if (type == 4) {
+        /* pair removal: an unordered pair of distinct vertices, picked by rank */
+        if (n >= 2) {
+            double v[3];
+            oc_pair_draws(c->seed, c->chain_id, (uint64_t)idx, v);
+            int32_t p1 = (int32_t)floor((double)n * u_pick);
+            if (p1 > n - 1) p1 = n - 1;
+            int32_t r2 = (int32_t)floor((double)(n - 1) * v[2]);
+            if (r2 > n - 2) r2 = n - 2;
+            int32_t p2 = r2 + (r2 >= p1 ? 1 : 0);
+            c->last_p = p1; c->last_tau = c->tau[p1]; c->last_site = c->site[p1];
+            c->last_p2 = p2; c->last_tau2 = c->tau[p2]; c->last_site2 = c->site[p2];
+            R = (double)n * (double)(n - 1) / (c->K * c->K) * pair_remove_ratio(c, 0, p1, p2) *
+                pair_remove_ratio(c, 1, p1, p2);
+            if (!isfinite(R)) return fail(c, OC_ENUMERIC, "non-finite pair removal ratio at proposal %lld", (long long)idx);
+            if (u_acc < fabs(R)) {
+                acc = 1;
+                remove_vertex(c, p1 > p2 ? p1 : p2);
+                remove_vertex(c, p1 > p2 ? p2 : p1);
+            }
+        }
     } else if (n > 0) {
         int32_t p = (int32_t)floor((double)n * u_pick);
         if (p > n - 1) p = n - 1;
@@ -511,13 +663,7 @@ static int step(oc_chain *c) {
             if (!isfinite(R)) return fail(c, OC_ENUMERIC, "non-finite removal ratio at proposal %lld", (long long)idx);
             if (u_acc < fabs(R)) {
                 acc = 1;
-                remove_commit(c, 0, p);
-                remove_commit(c, 1, p);
-                for (int i = p; i < n - 1; ++i) {
-                    c->tau[i] = c->tau[i + 1]; c->site[i] = c->site[i + 1];
-                    c->s[i] = c->s[i + 1]; c->id[i] = c->id[i + 1];
-                }
-                c->n = n - 1;
+                remove_vertex(c, p);
             }
         } else {
             /* spin flip: R = prod_sigma (1 + (1 - G_pp) lambda_sigma) */
@@ -657,6 +803,18 @@ int oc_get_state(const oc_chain *c, int64_t *proposals_done, int64_t *next_id, d
 int oc_set_state(oc_chain *c, int64_t proposals_done, int64_t next_id, double sign) {
     if (proposals_done < 0 || (sign != 1.0 && sign != -1.0)) return OC_EINVAL;
     c->done = proposals_done; c->next_id = next_id; c->sign = sign;
+    return OC_OK;
+}
+
+int oc_set_pair(oc_chain *c, double p_pair) {
+    if (!(p_pair >= 0.0 && c->p_flip + p_pair <= 1.0))
+        return fail(c, OC_EINVAL, "p_pair must be in [0, 1 - p_flip]");
+    c->p_pair = p_pair;
+    return OC_OK;
+}
+
+int oc_last_pair(const oc_chain *c, int32_t *p2, double *tau2, int32_t *site2, int32_t *s2) {
+    *p2 = c->last_p2; *tau2 = c->last_tau2; *site2 = c->last_site2; *s2 = c->last_s2;
     return OC_OK;
 }
 

@@ -96,10 +96,24 @@ int oc_set_config(oc_chain *c, int32_t n, const int64_t *id, const double *tau,
 int oc_get_state(const oc_chain *c, int64_t *proposals_done, int64_t *next_id, double *sign);
 int oc_set_state(oc_chain *c, int64_t proposals_done, int64_t next_id, double sign);
 
-/* Last processed proposal: type (0 ins, 1 rem, 2 flip), vertex position p
- * (insert: n before insertion), tau, site, new spin, signed ratio, accepted. */
+/* Last processed proposal: type (0 ins, 1 rem, 2 flip, 3 pair insertion,
+ * 4 pair removal), vertex position p (insert: n before insertion), tau, site,
+ * new spin, signed ratio, accepted.  For a pair these describe its first
+ * vertex and oc_last_pair its second (position n + 1 for a pair insertion;
+ * -1 for other types). */
 int oc_last_proposal(const oc_chain *c, int32_t *type, int32_t *p, double *tau,
                      int32_t *site, int32_t *s_new, double *R, int32_t *acc);
+int oc_last_pair(const oc_chain *c, int32_t *p2, double *tau2, int32_t *site2, int32_t *s2);
+
+/* Pair updates (Sec. IV B: Gamma grows by two rows and columns): insertion and
+ * removal of two vertices at once, each with probability p_pair/2, in place
+ * of single insertions and removals (which keep (1 - p_flip - p_pair)/2 each).
+ * Requires 0 <= p_pair <= 1 - p_flip; 0 (the default) leaves the walk as it is.
+ * A pair insertion draws its second vertex from oc_pair_draws; a pair removal
+ * picks ranks r1 = floor(n u_pick) and r2 = floor((n - 1) u_pick2), the second
+ * skipping r1 (r2 >= r1 -> r2 + 1), in ascending id order; at n < 2 it is
+ * rejected and counted. */
+int oc_set_pair(oc_chain *c, double p_pair);
 
 /* Observables. */
 int32_t oc_obs_len(const oc_chain *c);
@@ -131,6 +145,9 @@ void oc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
 /* The five uniforms of proposal `index`: u_type, u_acc, u_tau, u_pick, u_spin. */
 void oc_draws(uint64_t seed, uint32_t chain_id, uint64_t index, double out[5]);
 double oc_gamma_of(double beta, double U, double K, int32_t n_sites);
+/* The extra uniforms of a pair proposal: u_spin2 (the second word pair of tag
+ * 2), u_tau2 and u_pick2 (tag 3). */
+void oc_pair_draws(uint64_t seed, uint32_t chain_id, uint64_t index, double out[3]);
 
 #ifdef __cplusplus
 }

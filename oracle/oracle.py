@@ -62,6 +62,9 @@ def _load():
     lib.oc_get_state.argtypes = [vp, P(i64), P(i64), P(d)]
     lib.oc_set_state.argtypes = [vp, i64, i64, d]
     lib.oc_last_proposal.argtypes = [vp, P(i32), P(i32), P(d), P(i32), P(i32), P(d), P(i32)]
+    lib.oc_last_pair.argtypes = [vp, P(i32), P(d), P(i32), P(i32)]
+    lib.oc_set_pair.argtypes = [vp, d]
+    lib.oc_pair_draws.argtypes = [u64, u32, u64, vp]
     lib.oc_obs_len.restype = i32
     lib.oc_obs_len.argtypes = [vp]
     lib.oc_get_obs.argtypes = [vp, vp]
@@ -100,6 +103,14 @@ def draws(seed: int, chain: int, index: int) -> np.ndarray:
     return out
 
 
+def pair_draws(seed: int, chain: int, index: int) -> np.ndarray:
+    """u_spin2, u_tau2, u_pick2 of a pair proposal."""
+    lib = _load()
+    out = np.zeros(3)
+    lib.oc_pair_draws(seed, chain, index, _ptr(out))
+    return out
+
+
 def gamma_of(beta, U, K, n_sites) -> float:
     return _load().oc_gamma_of(beta, U, K, n_sites)
 
@@ -112,7 +123,7 @@ class OracleChain:
     """One Markov chain of the oracle."""
 
     def __init__(self, w, seed=0, chain_id=0, p_flip=0.2, meas_every=16, n_therm=0,
-                 n_tau_out=16, n_cap=4096):
+                 n_tau_out=16, n_cap=4096, p_pair=0.0):
         self.lib = _load()
         self.w = w
         self._keep = (np.ascontiguousarray(w.site_disp, np.int32),
@@ -125,6 +136,8 @@ class OracleChain:
         if not self.h:
             raise OracleError("oc_create rejected its arguments")
         self.n_tau_out = n_tau_out
+        if p_pair:
+            self._check(self.lib.oc_set_pair(self.h, p_pair))
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -220,8 +233,12 @@ class OracleChain:
         self._check(self.lib.oc_last_proposal(self.h, C.byref(t), C.byref(p), C.byref(tau),
                                               C.byref(site), C.byref(s), C.byref(R),
                                               C.byref(acc)))
+        p2, site2, s2 = C.c_int32(), C.c_int32(), C.c_int32()
+        tau2 = C.c_double()
+        self._check(self.lib.oc_last_pair(self.h, C.byref(p2), C.byref(tau2), C.byref(site2), C.byref(s2)))
         return dict(type=t.value, p=p.value, tau=tau.value, site=site.value, s_new=s.value,
-                    R=R.value, acc=acc.value)
+                    R=R.value, acc=acc.value, p2=p2.value, tau2=tau2.value, site2=site2.value,
+                    s2=s2.value)
 
     def obs(self) -> np.ndarray:
         out = np.zeros(self.lib.oc_obs_len(self.h))
