@@ -56,7 +56,7 @@ FP32_PEAK_TFS = 157.3
 N_CU = 256
 
 METRIC = "vertex updates/s + rank-k TFLOP/s, mixed/batched vs plain FP64, same GPU"
-ALL_LEGS = "plain,mixed,cfg2x128,batched,config3,config5,graph,cpu"
+ALL_LEGS = "plain,mixed,pairs,cfg2x128,batched,config3,config5,graph,cpu"
 
 
 def log(msg):
@@ -472,6 +472,11 @@ def main():
         g2.close()
         g2, d2, t2 = single_chain(ctaux, w, ctaux.CTAUX_BF16X3, args.steps, args.warmup)
         forms["mixed_bf16x3"] = form(g2, d2, t2)
+        g2.close()
+    if "pairs" in legs:
+        log("pairs_fp64 leg: the same workload with pair insertions and removals (p_pair = 0.2)")
+        g2, d2, t2 = single_chain(ctaux, w, ctaux.CTAUX_FP64, args.steps, args.warmup, p_pair=0.2)
+        forms["pairs_fp64"] = form(g2, d2, t2, {"p_pair": 0.2, "p_flip": 0.2})
         g2.close()
     if "cfg2x128" in legs:
         for name, prec in (("cfg2x128_fp64", ctaux.CTAUX_FP64), ("cfg2x128_fp32", ctaux.CTAUX_FP32)):

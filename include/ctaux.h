@@ -88,7 +88,7 @@ typedef struct {
     int32_t k_max;            /* proposals per block, 1..128                                  */
     int32_t k_cap;            /* accepted changes per block (size of Gamma), 1..64; a block
                                  ends early once Gamma is full (does not change the chain)     */
-    double p_flip;            /* P(flip); P(insert) = P(remove) = (1 - p_flip)/2              */
+    double p_flip;            /* P(flip); P(insert) = P(remove) = (1 - p_flip - p_pair)/2     */
     int32_t recompute_every;  /* most blocks between FP64 refinements of N (0 = never).  Each
                                  chain has its own interval, a power of two between 1 and the
                                  largest power of two <= recompute_every, starting at 1
@@ -127,6 +127,20 @@ typedef struct {
                                  recomputed from scratch when the step cannot recover it (see
                                  ctaux_recompute); 1 = always from scratch
                                  (ctaux_recompute_from_scratch)                               */
+    double p_pair;            /* pair updates (Sec. IV B: Gamma grows by two rows and columns):
+                                 two vertices inserted together with probability p_pair/2,
+                                 two removed together with p_pair/2; 0 <= p_pair <= 1 - p_flip
+                                 (0: single-vertex moves only).  Acceptance ratios
+                                 K^2/((n+1)(n+2)) and n(n-1)/K^2 times the two sectors'
+                                 determinant ratios.  The second vertex of a pair insertion
+                                 takes u_spin2 (second word pair of Philox tag 2) and u_tau2,
+                                 u_pick2 (tag 3); a pair removal picks ranks floor(n u_pick)
+                                 and floor((n-1) u_pick2), the second skipping the first, in
+                                 ascending id order, and is rejected (and counted) at n < 2.
+                                 Requires k_max >= 2 and k_cap >= 2.  A block ends before a
+                                 pair proposal that could overfill Gamma or the block's
+                                 k_max insertion candidates; like every block boundary this
+                                 leaves the chain unchanged                                  */
 } ctaux_opts;
 
 /* Per-chain counters. */

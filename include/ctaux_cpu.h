@@ -18,6 +18,7 @@
  * meas_every, n_therm, n_tau_out, n_cap, seed, log_cap (k_cap, precision,
  * recompute_every, gamma_tol, drift_tol, rankk_tile, drift_target,
  * n_matsubara, recompute_mode are ignored: FP64, Gamma as large as k_max).
+ * Pair updates are not built here: p_pair must be 0 (CTAUX_EINVAL otherwise).
  */
 #ifndef CTAUX_CPU_H
 #define CTAUX_CPU_H

@@ -151,6 +151,11 @@ int validate(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, c
   if (o->k_cap < 1 || o->k_cap > kMaxKcap || o->k_cap > o->k_max)
     return set_err(eb, CTAUX_EINVAL, "k_cap must be in 1..min(k_max, %d)", kMaxKcap);
   if (!(o->p_flip >= 0.0 && o->p_flip <= 1.0)) return set_err(eb, CTAUX_EINVAL, "p_flip must be in [0,1]");
+  if (!(o->p_pair >= 0.0 && o->p_flip + o->p_pair <= 1.0))
+    return set_err(eb, CTAUX_EINVAL, "p_pair must be in [0, 1 - p_flip]");
+  // a pair needs two insertion candidates and two slots of Gamma in one block
+  if (o->p_pair > 0.0 && (o->k_max < 2 || o->k_cap < 2))
+    return set_err(eb, CTAUX_EINVAL, "pair updates need k_max >= 2 and k_cap >= 2");
   if (!isfinite(o->gamma_tol) || !isfinite(o->drift_tol))
     return set_err(eb, CTAUX_EINVAL, "gamma_tol and drift_tol must be finite");
   if (o->rankk_tile != 0 && o->rankk_tile != 32 && o->rankk_tile != 64)
@@ -238,8 +243,10 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
     }
     d.ptype = cv.take<int32_t>(kmax);
     d.pspin = cv.take<int32_t>(kmax);
+    d.pspin2 = cv.take<int32_t>(kmax);
     d.pacc = cv.take<double>(kmax);
     d.ppick = cv.take<double>(kmax);
+    d.ppick2 = cv.take<double>(kmax);
     d.ctau = cv.take<double>(kmax);
     d.csite = cv.take<int32_t>(kmax);
     d.cid = cv.take<int64_t>(kmax);
@@ -289,6 +296,7 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
       d.gamma = acosh(1.0 + m.beta * m.U * nc / (2.0 * m.K));
       d.inv_h = static_cast<double>(m.n_tau - 1) / m.beta;
       d.p_flip = o->p_flip;
+      d.p_pair = o->p_pair;
       d.gamma_tol = o->gamma_tol;
       d.drift_tol = o->drift_tol;
       for (int s = 0; s < 2; ++s) {
@@ -739,6 +747,7 @@ int ctaux_create(const ctaux_model *models, int32_t n_chains, const ctaux_opts *
   }
   b.n_cu = prop.multiProcessorCount;
   b.rankk_tile = opts->rankk_tile == 32 ? 32 : 64;
+  b.pairs = opts->p_pair > 0.0 ? 1 : 0;
   b.grid_per_chain = n_chains >= 2048 ? 1 : 2048 / n_chains;
   if (b.grid_per_chain > 1024) b.grid_per_chain = 1024;
   h->recompute_every = opts->recompute_every;

@@ -735,7 +735,8 @@ int ctaux_cpu_create(const ctaux_model *m, const ctaux_opts *o, int32_t chain_id
   *out = nullptr;
   if (!(m->beta > 0) || !(m->U >= 0) || !(m->K > 0) || m->n_sites < 1 || m->n_tau < 2 || m->n_disp < 1 ||
       !m->site_disp || !m->g0_up || !m->g0_dn || o->k_max < 1 || o->k_max > 128 || o->meas_every < 1 ||
-      o->n_tau_out < 0 || o->n_cap < 1 || o->log_cap < 0 || !(o->p_flip >= 0.0 && o->p_flip <= 1.0))
+      o->n_tau_out < 0 || o->n_cap < 1 || o->log_cap < 0 || !(o->p_flip >= 0.0 && o->p_flip <= 1.0) ||
+      o->p_pair != 0.0)
     return CTAUX_EINVAL;
   for (int i = 0; i < m->n_sites * m->n_sites; ++i)
     if (m->site_disp[i] < 0 || m->site_disp[i] >= m->n_disp) return CTAUX_EINVAL;

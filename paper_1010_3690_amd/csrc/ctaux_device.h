@@ -27,7 +27,7 @@ __device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
 
 // The five uniforms of proposal `index` of a chain: counter (index lo, index
 // hi, chain, tag), key = seed; tag 0 -> (type, accept), 1 -> (tau, pick),
-// 2 -> (spin, unused).
+// 2 -> (spin, the second spin of a pair).
 __device__ __forceinline__ void proposal_uniforms(const ChainDesc &d, uint64_t index, double u[5]) {
   uint32_t c[4];
   c[0] = static_cast<uint32_t>(index); c[1] = static_cast<uint32_t>(index >> 32);
@@ -42,6 +42,21 @@ __device__ __forceinline__ void proposal_uniforms(const ChainDesc &d, uint64_t i
   c[2] = d.chain_id; c[3] = 2;
   philox4x32_10(c, d.seed_lo, d.seed_hi);
   u[4] = u53(c[0], c[1]);
+}
+
+// The extra uniforms of a pair proposal: u_spin2 (the second word pair of tag
+// 2), u_tau2 and u_pick2 (tag 3).
+__device__ __forceinline__ void pair_uniforms(const ChainDesc &d, uint64_t index, double v[3]) {
+  uint32_t c[4];
+  c[0] = static_cast<uint32_t>(index); c[1] = static_cast<uint32_t>(index >> 32);
+  c[2] = d.chain_id; c[3] = 2;
+  philox4x32_10(c, d.seed_lo, d.seed_hi);
+  v[0] = u53(c[2], c[3]);
+  c[0] = static_cast<uint32_t>(index); c[1] = static_cast<uint32_t>(index >> 32);
+  c[2] = d.chain_id; c[3] = 3;
+  philox4x32_10(c, d.seed_lo, d.seed_hi);
+  v[1] = u53(c[0], c[1]);
+  v[2] = u53(c[2], c[3]);
 }
 
 // Pointers read from the chain descriptor are generic, and generic (flat)

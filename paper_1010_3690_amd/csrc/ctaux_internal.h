@@ -44,8 +44,8 @@ struct ChainDesc {
   int32_t *s0[2];
   int64_t *id[2];
   // block proposals (decoded)
-  int32_t *ptype;          // [kmax] 0 ins, 1 rem, 2 flip
-  int32_t *pspin;          // [kmax] spin of an insertion (+-1)
+  int32_t *ptype;          // [kmax] 0 ins, 1 rem, 2 flip, 3 pair insertion, 4 pair removal
+  int32_t *pspin;          // [kmax] spin of an insertion (+-1; first vertex of a pair)
   double *pacc;            // [kmax] u_acc
   double *ppick;           // [kmax] u_pick
   double *ctau;            // [kmax] candidate times
@@ -91,6 +91,10 @@ struct ChainDesc {
   // decision log
   uint8_t *log_acc;        // [log_cap]
   double *log_R;           // [log_cap]
+  // pair proposals (Sec. IV B; the fields above keep their offsets without them)
+  double p_pair;           // pair insertions and removals, p_pair / 2 each
+  int32_t *pspin2;         // [kmax] spin of a pair insertion's second vertex
+  double *ppick2;          // [kmax] u_pick2 of a pair removal
 };
 
 struct ChainState {
@@ -194,6 +198,7 @@ struct Batch {
   int32_t precision;
   int32_t grid_per_chain;    // workgroups per chain for per-chain streaming kernels
   int32_t rankk_tile;        // rank-k output tile edge, 64 or 32
+  int32_t pairs;             // 1: pair proposals are drawn (p_pair > 0)
   ChainDesc *d_desc;         // device [n_chains]
   ChainState *d_state;       // device [n_chains]
   ChainState *d_mstate;      // device [n_chains]: the state as the last block left it, read by

@@ -16,10 +16,13 @@ void launch_set_target(const Batch &b, hipStream_t s, int64_t n_proposals) {
 }
 
 // One workgroup per chain.  Decides the block length (at most k_max, never
-// past a measurement point), decodes the block's proposals and collects the
-// insertion candidates in proposal order.
+// past a measurement point, and short enough that its insertion candidates -
+// two for a pair insertion - number at most k_max), decodes the block's
+// proposals and collects the insertion candidates in proposal order.
+// Proposal mix: insertion and removal (1 - p_flip - p_pair)/2 each, pair
+// insertion and pair removal p_pair/2 each, flip p_flip.
 __device__ void block_begin_chain(const ChainDesc &d, ChainState &st) {
-  __shared__ int sh_L, sh_active;
+  __shared__ int sh_L, sh_active, sh_cut;
   __shared__ int scan[256];
   if (threadIdx.x == 0) {
     int active = (st.status == 0 && st.done < st.target) ? 1 : 0;
@@ -38,6 +41,7 @@ __device__ void block_begin_chain(const ChainDesc &d, ChainState &st) {
     st.meas_now = 0;
     sh_L = static_cast<int>(L);
     sh_active = active;
+    sh_cut = static_cast<int>(L);
   }
   __syncthreads();
   if (!sh_active) {
@@ -46,29 +50,47 @@ __device__ void block_begin_chain(const ChainDesc &d, ChainState &st) {
   }
   const int L = sh_L;
   const int t = threadIdx.x;
-  int is_ins = 0;
-  double tau = 0.0;
-  int site = 0;
+  int ncand = 0;
+  double tau = 0.0, tau2 = 0.0;
+  int site = 0, site2 = 0;
   if (t < L) {
     double u[5];
-    proposal_uniforms(d, static_cast<uint64_t>(st.done + t), u);
-    const double p_ins = 0.5 * (1.0 - d.p_flip);
-    const int type = u[0] < p_ins ? 0 : (u[0] < 2.0 * p_ins ? 1 : 2);
+    const uint64_t index = static_cast<uint64_t>(st.done + t);
+    proposal_uniforms(d, index, u);
+    const double p_one = 0.5 * (1.0 - d.p_flip - d.p_pair);
+    int type;
+    if (u[0] < p_one) type = 0;
+    else if (u[0] < 2.0 * p_one) type = 1;
+    else if (u[0] < 2.0 * p_one + 0.5 * d.p_pair) type = 3;
+    else if (u[0] < 2.0 * p_one + d.p_pair) type = 4;
+    else type = 2;
     d.ptype[t] = type;
     d.pacc[t] = u[1];
     d.ppick[t] = u[3];
-    if (type == 0) {
+    if (type == 0 || type == 3) {
       tau = d.beta * u[2];
       site = static_cast<int>(floor(static_cast<double>(d.nc) * u[3]));
       if (site > d.nc - 1) site = d.nc - 1;
       d.pspin[t] = u[4] < 0.5 ? -1 : 1;
-      is_ins = 1;
+      ncand = 1;
     } else {
       d.pspin[t] = 0;
     }
+    if (type >= 3) {
+      double v[3];
+      pair_uniforms(d, index, v);
+      d.ppick2[t] = v[2];
+      if (type == 3) {
+        tau2 = d.beta * v[1];
+        site2 = static_cast<int>(floor(static_cast<double>(d.nc) * v[2]));
+        if (site2 > d.nc - 1) site2 = d.nc - 1;
+        d.pspin2[t] = v[0] < 0.5 ? -1 : 1;
+        ncand = 2;
+      }
+    }
   }
-  // exclusive prefix sum of the insertion flags (Hillis-Steele over 256 lanes)
-  scan[t] = is_ins;
+  // inclusive prefix sum of the candidate counts (Hillis-Steele over 256 lanes)
+  scan[t] = ncand;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
     int v = (t >= off) ? scan[t - off] : 0;
@@ -76,12 +98,23 @@ __device__ void block_begin_chain(const ChainDesc &d, ChainState &st) {
     scan[t] += v;
     __syncthreads();
   }
-  if (is_ins) {
-    const int j = scan[t] - 1;
+  // the block ends before the first proposal whose candidates would exceed k_max
+  if (t < L && scan[t] > d.kmax) atomicMin(&sh_cut, t);
+  __syncthreads();
+  const int Lc = sh_cut;
+  if (t < Lc && ncand > 0) {
+    const int j = scan[t] - ncand;
     d.ctau[j] = tau;
     d.csite[j] = site;
+    if (ncand == 2) {
+      d.ctau[j + 1] = tau2;
+      d.csite[j + 1] = site2;
+    }
   }
-  if (t == 255) st.k_ins = scan[255];
+  if (t == 0) {
+    st.L = Lc;
+    st.k_ins = Lc > 0 ? scan[Lc - 1] : 0;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_block_begin(const ChainDesc *descs, ChainState *states) {

@@ -88,7 +88,10 @@ __device__ __forceinline__ void with_even_steps(int ns, F &f) {
   else f(StepCount<16>{});
 }
 
-template <typename T>
+// PAIRS: the instantiation that also takes pair proposals (p_pair > 0); their
+// path is compiled only there, so that the loop without it keeps its register
+// allocation.
+template <typename T, bool PAIRS>
 __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainState *states) {
   const int c = blockIdx.x;
   const ChainDesc &d = descs[c];
@@ -127,6 +130,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   __shared__ double sh_dsc[2][5];                  // D = e^V / (e^V - 1) for block-start spin d = +-1
   __shared__ double sh_igd[2][27];                 // 1 / (gh D) by (s0 + 1, s_old + 1, s_new + 1)
   __shared__ double sh_beta[2][2];                 // [parity][sector]
+  __shared__ double sh_pr[2], sh_bt[2];            // pair proposals: sector ratio, beta~ of a new slot
   __shared__ double sh_gh[2][kMaxKcap];
   __shared__ double sh_pacc[kMaxKmax], sh_ppick[kMaxKmax];
   __shared__ int8_t sh_ptype[kMaxKmax], sh_pspin[kMaxKmax];
@@ -318,12 +322,134 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
     lds_barrier();
   };
 
+  // One change of vertex p (spin s_old -> s_new) of a pair proposal, applied to
+  // the X written out to LDS: multiplies sh_pr[sector] by the sector's
+  // determinant ratio and leaves X, P, gh and ka as Gamma with the change has
+  // them.  A vertex in P takes the repeated-change formulas (as above); any
+  // other vertex a new slot by partitioning, with its s, w and d gathered here:
+  // v = X s (threads 0-63 of the sector), u = X^T w (threads 64-127),
+  // beta~ = d - w.v, ratio -gh D_p beta~, then X grows by the rank-1 form of
+  // the inner loop.  The caller has checked that Gamma has room (ka < 64).
+  auto lds_change = [&](int p, int s_old, int s_new) {
+    int a = -1;
+    for (int b = 0; b < ka; ++b)
+      if (P[b] == p) {
+        a = b;
+        break;
+      }
+    if (a >= 0) {
+      const int s0p = s0l[p];
+      const double gh0 = sh_ev[0][s_new - s0p + 2] - 1.0, gh1 = sh_ev[1][s_new - s0p + 2] - 1.0;
+      const double dp = sh_dsc[sec][s0p + 2], gn = sec == 0 ? gh0 : gh1;
+      const bool remove = (s_new == s0p);
+      if (loc == 0) {
+        const double xaa = Gis[a * lg + a], go = sh_gh[sec][a];
+        sh_pr[sec] *= remove ? xaa / (-go * dp) : (gn / go) * (1.0 + (1.0 / go - 1.0 / gn) / dp * xaa);
+      }
+      repeat_update(a, remove, gn, dp);   // its first barrier follows every read above
+      if (!remove) {
+        if (tid == 0) {
+          sh_gh[0][a] = gh0;
+          sh_gh[1][a] = gh1;
+        }
+      } else {
+        const int last = ka - 1;
+        if (a != last) {   // the last slot moves into slot a (every thread writes the same value)
+          P[a] = P[last];
+          if (tid == 0) {
+            sh_gh[0][a] = sh_gh[0][last];
+            sh_gh[1][a] = sh_gh[1][last];
+          }
+        }
+        ka -= 1;
+      }
+      lds_barrier();
+      return;
+    }
+    const int k = ka;
+    const int s0p = s_old;   // outside P: the block-start spin (0 for a candidate)
+    const double gh0 = sh_ev[0][s_new - s0p + 2] - 1.0, gh1 = sh_ev[1][s_new - s0p + 2] - 1.0;
+    double *sv = vs + sec * kp, *wv = vw + sec * kp, *cv = vv + sec * kp, *rw = vu + sec * kp;
+    if (loc < 64) {
+      if (loc < k) sv[loc] = gat(P[loc], p);
+    } else if (loc - 64 < k) {
+      wv[loc - 64] = gat(p, P[loc - 64]);
+    }
+    lds_barrier();
+    if (loc < 64) {
+      double acc = 0.0;
+      if (loc < k)
+        for (int b = 0; b < k; ++b) acc = fma(Gis[loc * lg + b], sv[b], acc);
+      cv[loc] = acc;
+    } else {
+      const int b = loc - 64;
+      double acc = 0.0;
+      if (b < k)
+        for (int a2 = 0; a2 < k; ++a2) acc = fma(wv[a2], Gis[a2 * lg + b], acc);
+      rw[b] = acc;
+    }
+    lds_barrier();
+    if (loc < 64) {
+      const double sum = wave_sum((loc < k) ? wv[loc] * cv[loc] : 0.0);
+      if (loc == 0) {
+        const double igd = sh_igd[sec][(s0p + 1) * 9 + (s_old + 1) * 3 + (s_new + 1)];   // 1 / (gh D_p)
+        const double beta = gat(p, p) - 1.0 - igd - sum;
+        sh_bt[sec] = beta;
+        sh_pr[sec] *= -(sec == 0 ? gh0 : gh1) * sh_dsc[sec][s0p + 2] * beta;
+      }
+    }
+    lds_barrier();
+    const double ib = 1.0 / sh_bt[sec];
+    // X' = [[X, 0], [0, 0]] + (vt / beta~) ut^T, vt = [v; -1], ut = [u; -1]; each
+    // entry is read and written by one thread
+    for (int e = loc; e < (k + 1) * (k + 1); e += 128) {
+      const int r = e / (k + 1), c2 = e - r * (k + 1);
+      const double vr = (r < k) ? cv[r] : -1.0, uc = (c2 < k) ? rw[c2] : -1.0;
+      const double base = (r < k && c2 < k) ? Gis[r * lg + c2] : 0.0;
+      Gis[r * lg + c2] = fma(vr * ib, uc, base);
+    }
+    P[k] = p;   // every thread writes the same value
+    if (tid == 0) {
+      sh_gh[0][k] = gh0;
+      sh_gh[1][k] = gh1;
+    }
+    ka = k + 1;
+    lds_barrier();
+  };
+
   unsigned long long alive_lo = 0ull, alive_hi = 0ull;   // live candidates (bit j of candidates 0-63, 64-127)
+  // the vertex of rank r among the interacting ones in canonical (augmented-index)
+  // order, or -1; every wave computes it from the bookkeeping all threads wrote
+  // identically (pair removals; the inner loop has its own copy of these lines,
+  // which keeps the register allocation of the loop as it is without pairs)
+  auto select_rank = [&](int r) -> int {
+    if (r < n - ndead) {
+      // old vertex: least idx with idx = r + #{dead <= idx}
+      int idx = r;
+      while (true) {
+        const bool le = myDead <= idx;   // lanes past the list hold INT_MAX
+        const int nw = r + __popcll(__ballot(le));
+        if (nw == idx) break;
+        idx = nw;
+      }
+      return idx;
+    }
+    // the r2-th live candidate in index order
+    int r2 = r - (n - ndead);
+    const int c0 = __popcll(alive_lo);
+    const int wsel = (r2 < c0) ? 0 : 1;
+    const unsigned long long m = wsel ? alive_hi : alive_lo;
+    if (wsel == 1) r2 -= c0;
+    const bool hitl = ((m >> lane) & 1ull) && __popcll(m & ((1ull << lane) - 1ull)) == r2;
+    const unsigned long long hit = __ballot(hitl);
+    return hit ? n + 64 * wsel + __ffsll(static_cast<long long>(hit)) - 1 : -1;
+  };
   int why = 0;   // why the inner loop stopped: 1 capacity, 2 bookkeeping, 3 non-finite ratio, 4 Gamma full
   // The proposals run in an inner loop that handles insertions, removals and
-  // flips of vertices outside P; a repeated change of a vertex in P leaves it
-  // and is handled once below (X written out, updated in LDS, read back), so
-  // that the inner loop keeps X in registers without that path's demands.
+  // flips of vertices outside P; a repeated change of a vertex in P, and a pair
+  // proposal, leave it and are handled once below (X written out, updated in
+  // LDS, read back), so that the inner loop keeps X in registers without those
+  // paths' demands.
   int t = 0;
   while (t < L) {
     int rp = -1, p = -1, s_old = 0, s_new = 0, type = 0;
@@ -333,6 +459,10 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       const int tspin = __builtin_amdgcn_readlane(tj ? r_tspin[1] : r_tspin[0], tl);
       type = tspin & 0xff;
       u_acc = readlane_f64(tj ? r_pacc[1] : r_pacc[0], tl);
+      if (PAIRS && type >= 3) {
+        why = 5;
+        break;   // a pair proposal: handled after this loop
+      }
       p = -1;
       s_old = 0;
       s_new = 0;
@@ -347,8 +477,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       } else if (ncur == 0) {
         skip = 1;
       } else {
-        // rank r among interacting vertices in canonical (augmented-index) order;
-        // every wave computes it from the bookkeeping all threads wrote identically
+        // rank r among interacting vertices in canonical order (as select_rank)
         int r = static_cast<int>(floor(static_cast<double>(ncur) * readlane_f64(tj ? r_ppick[1] : r_ppick[0], tl)));
         if (r > ncur - 1) r = ncur - 1;
         if (r < n - ndead) {
@@ -506,6 +635,155 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       if ((gz ? nchg : ka) == kcap) {
         why = 4;
         break;
+      }
+    }
+    if constexpr (PAIRS) {
+      if (why == 5) {
+        // ---- a pair insertion (type 3) or removal (type 4) at proposal t ----
+        why = 0;
+        const int tj = t >> 6, tl = t & 63;
+        // Gamma gains up to two slots: the block ends before a pair that could overfill it
+        if ((gz ? nchg : ka) + 2 > kcap) {
+          L_eff = t;
+          break;
+        }
+        int pa0 = -1, pa1 = -1, so0 = 0, so1 = 0, sn0 = 0, sn1 = 0;
+        bool skip = false;
+        double fpre2 = 0.0;
+        if (type == 3) {
+          if (ncur + 2 > n_cap) {
+            status = -5;   // CTAUX_ECAPACITY
+            L_eff = t;
+            err_index = done0 + t;
+            break;
+          }
+          pa0 = n + next_cand;
+          pa1 = pa0 + 1;
+          sn0 = (__builtin_amdgcn_readlane(tj ? r_tspin[1] : r_tspin[0], tl) >> 8) - 1;
+          sn1 = gview(d.pspin2)[t];
+          fpre2 = Kc * Kc / (static_cast<double>(ncur + 1) * static_cast<double>(ncur + 2));
+        } else if (ncur < 2) {
+          skip = true;   // rejected, still counted
+        } else {
+          int r1 = static_cast<int>(floor(static_cast<double>(ncur) * readlane_f64(tj ? r_ppick[1] : r_ppick[0], tl)));
+          if (r1 > ncur - 1) r1 = ncur - 1;
+          int r2 = static_cast<int>(floor(static_cast<double>(ncur - 1) * gview(d.ppick2)[t]));
+          if (r2 > ncur - 2) r2 = ncur - 2;
+          if (r2 >= r1) r2 += 1;
+          pa0 = select_rank(r1);
+          pa1 = select_rank(r2);
+          if (pa0 < 0 || pa0 >= n + next_cand || pa1 < 0 || pa1 >= n + next_cand || pa0 == pa1 || scur[pa0] == 0 ||
+              scur[pa1] == 0) {   // cannot happen unless bookkeeping is broken
+            status = -4;   // CTAUX_ENUMERIC
+            L_eff = t;
+            err_index = -3;
+            break;
+          }
+          so0 = scur[pa0];
+          so1 = scur[pa1];
+          fpre2 = static_cast<double>(ncur) * static_cast<double>(ncur - 1) / (Kc * Kc);
+        }
+        if (pend) {
+          growth(pk, pbeta, pq);
+          pend = false;
+        }
+        const int ka0 = ka;
+        const bool lds_path = !skip && !gz;
+        int *Psv = reinterpret_cast<int *>(vu + 2 * kp);   // parity-1 vector buffers: free here
+        double *ghsv = vv + 2 * kp;
+        const auto xsv = gview_w(d.Rg[sec]);   // the residual's buffer, free until block end
+        double R = skip ? 0.0 : fpre2;
+        if (lds_path) {
+          write_out();
+          lds_barrier();   // also ends every read of the vector buffers by the growth
+          // X, P and gh as they are, for a rejected pair (X goes to global memory;
+          // both outcomes then read X back, so the registers need not hold it)
+          for (int e = loc; e < ka0 * ka0; e += 128) xsv[e] = Gis[(e / ka0) * lg + e % ka0];
+          for (int i = tid; i < ka0; i += 256) {
+            Psv[i] = P[i];
+            ghsv[i] = sh_gh[0][i];
+            ghsv[kp + i] = sh_gh[1][i];
+          }
+          if (tid < 2) sh_pr[tid] = 1.0;
+          __syncthreads();   // the saved X is visible to the whole workgroup
+          lds_change(pa0, so0, sn0);
+          lds_change(pa1, so1, sn1);
+          R = fpre2 * sh_pr[0] * sh_pr[1];
+          if (!(u_acc < fabs(R))) {   // rejected (or not finite): P, gh, ka and X as they were
+            for (int i = tid; i < ka0; i += 256) {
+              P[i] = Psv[i];
+              sh_gh[0][i] = ghsv[i];
+              sh_gh[1][i] = ghsv[kp + i];
+            }
+            ka = ka0;
+            // the changes touched rows and columns below ka0 + 2 at most
+            const int m = ka0 + 2 < kp ? ka0 + 2 : kp;
+            for (int e = loc; e < m * m; e += 128) {
+              const int r = e / m, c2 = e - r * m;
+              Gis[r * lg + c2] = (r < ka0 && c2 < ka0) ? xsv[r * ka0 + c2] : 0.0;
+            }
+          }
+          lds_barrier();
+          // X back to registers within this branch: between write_out and here the
+          // registers hold nothing live
+          read_back();
+          myP = (lane < ka) ? P[lane] : 0;
+        }
+        if (!isfinite(R)) {
+          status = -4;   // CTAUX_ENUMERIC
+          L_eff = t;
+          err_index = done0 + t;
+          break;
+        }
+        const int acc = (!skip && u_acc < fabs(R)) ? 1 : 0;
+        if (tid == 0) {
+          const int64_t idx = done0 + t;
+          if (idx < log_cap) {
+            log_acc[idx] = static_cast<uint8_t>(acc);
+            log_R[idx] = R;
+          }
+        }
+        if (acc) {
+          accepted += 1;
+          nchg += 2;
+          if (R < 0.0) sign = -sign;
+          if (!gz) had_repeat = true;   // Gamma~ is gathered again at block end
+          scur[pa0] = static_cast<int8_t>(sn0);   // every thread writes the same value
+          scur[pa1] = static_cast<int8_t>(sn1);
+          if (type == 3) {
+  #pragma unroll
+            for (int i = 0; i < 2; ++i) {
+              const int j = pa0 - n + i;
+              if (j < 64) alive_lo |= 1ull << j;
+              else alive_hi |= 1ull << (j - 64);
+              if (tid == 0) sh_cid[j] = next_id + i;
+            }
+            next_id += 2;
+            ncur += 2;
+          } else {
+  #pragma unroll
+            for (int i = 0; i < 2; ++i) {
+              const int pi = i ? pa1 : pa0;
+              if (pi < n) {
+                if (lane == ndead) myDead = pi;
+                ndead += 1;
+              } else {
+                const int j = pi - n;
+                if (j < 64) alive_lo &= ~(1ull << j);
+                else alive_hi &= ~(1ull << (j - 64));
+              }
+            }
+            ncur -= 2;
+          }
+        }
+        if (type == 3) next_cand += 2;
+        lds_barrier();   // the bookkeeping above before the next proposal reads it
+        ++t;
+        if ((gz ? nchg : ka) >= kcap) {   // Gamma full: the block ends here
+          L_eff = t;
+          break;
+        }
+        continue;
       }
     }
     if (why != 0) {
@@ -910,24 +1188,28 @@ static size_t propose_lds_bytes(const Batch &b) { return propose_lds_bytes(b.kca
 // so this signals a device that has less).
 int setup_propose(const Batch &b) {
   const int lds = static_cast<int>(propose_lds_bytes(b));
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_propose<double>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
-      hipFuncSetAttribute(reinterpret_cast<const void *>(k_propose<float>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-    return -1;
-  hipFuncAttributes fa;
-  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_propose<double>)) != hipSuccess ||
-      fa.sharedSizeBytes > kProposeStaticLds)
-    return -1;
+  const void *fns[4] = {reinterpret_cast<const void *>(k_propose<double, false>),
+                        reinterpret_cast<const void *>(k_propose<float, false>),
+                        reinterpret_cast<const void *>(k_propose<double, true>),
+                        reinterpret_cast<const void *>(k_propose<float, true>)};
+  for (const void *f : fns) {
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, f) != hipSuccess || fa.sharedSizeBytes > kProposeStaticLds) return -1;
+  }
   return 0;
 }
 
 void launch_propose(const Batch &b, hipStream_t s) {
   const size_t lds = propose_lds_bytes(b);
-  if (b.precision == kFP64)
-    hipLaunchKernelGGL(k_propose<double>, dim3(b.n_chains), dim3(256), lds, s, b.d_desc, b.d_state);
-  else
-    hipLaunchKernelGGL(k_propose<float>, dim3(b.n_chains), dim3(256), lds, s, b.d_desc, b.d_state);
+  const dim3 grid(b.n_chains), block(256);
+  if (b.precision == kFP64) {
+    if (b.pairs) hipLaunchKernelGGL((k_propose<double, true>), grid, block, lds, s, b.d_desc, b.d_state);
+    else hipLaunchKernelGGL((k_propose<double, false>), grid, block, lds, s, b.d_desc, b.d_state);
+  } else {
+    if (b.pairs) hipLaunchKernelGGL((k_propose<float, true>), grid, block, lds, s, b.d_desc, b.d_state);
+    else hipLaunchKernelGGL((k_propose<float, false>), grid, block, lds, s, b.d_desc, b.d_state);
+  }
 }
 
 }  // namespace ctaux

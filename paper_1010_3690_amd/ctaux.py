@@ -48,7 +48,8 @@ class _Opts(C.Structure):
                 ("n_therm", C.c_int64), ("n_tau_out", C.c_int32), ("n_cap", C.c_int32),
                 ("seed", C.c_uint64), ("log_cap", C.c_int64), ("gamma_tol", C.c_double),
                 ("drift_tol", C.c_double), ("rankk_tile", C.c_int32), ("drift_target", C.c_double),
-                ("n_matsubara", C.c_int32), ("recompute_mode", C.c_int32)]
+                ("n_matsubara", C.c_int32), ("recompute_mode", C.c_int32),
+                ("p_pair", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -140,12 +141,13 @@ class Options:
     drift_target: float = 0.0
     n_matsubara: int = 0
     recompute_mode: int = 0
+    p_pair: float = 0.0
 
     def _c(self) -> _Opts:
         return _Opts(self.k_max, self.k_cap, self.p_flip, self.recompute_every, self.precision,
                      self.meas_every, self.n_therm, self.n_tau_out, self.n_cap, self.seed, self.log_cap,
                      self.gamma_tol, self.drift_tol, self.rankk_tile, self.drift_target, self.n_matsubara,
-                     self.recompute_mode)
+                     self.recompute_mode, self.p_pair)
 
 
 def _ptr(a: np.ndarray):

@@ -65,7 +65,10 @@ def test_workspace_bytes_and_validation(lib):
                 dict(n_tau_out=4096, n_cap=65536),
                 # the proposal kernel's LDS (Gamma^-1 of both sectors plus two bytes per
                 # vertex of the augmented configuration) exceeds 160 KB
-                dict(n_cap=45000), dict(drift_target=-1.0), dict(recompute_mode=2)):
+                dict(n_cap=45000), dict(drift_target=-1.0), dict(recompute_mode=2),
+                # pair updates: p_flip + p_pair <= 1, and room for a pair in a block
+                dict(p_pair=0.9), dict(p_pair=-0.1), dict(p_pair=0.1, k_cap=1),
+                dict(p_pair=0.1, k_max=1, k_cap=1)):
         mb, ob, kb = _model_and_opts(ctaux, **bad)
         assert lib.ctaux_workspace_bytes(C.byref(mb), 1, C.byref(ob)) == 0, bad
     # a non-finite table entry is rejected
