@@ -131,6 +131,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   __shared__ double sh_igd[2][27];                 // 1 / (gh D) by (s0 + 1, s_old + 1, s_new + 1)
   __shared__ double sh_beta[2][2];                 // [parity][sector]
   __shared__ double sh_pr[2], sh_bt[2];            // pair proposals: sector ratio, beta~ of a new slot
+  __shared__ double sh_S[2][4];                    // pair proposals: 2x2 Schur complement per sector
   __shared__ double sh_gh[2][kMaxKcap];
   __shared__ double sh_pacc[kMaxKmax], sh_ppick[kMaxKmax];
   __shared__ int8_t sh_ptype[kMaxKmax], sh_pspin[kMaxKmax];
@@ -242,6 +243,31 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       for (int i = 0; i < 8; ++i) a4[i & 3] = fma(xr[c + i], o[i], a4[i & 3]);
     });
     return (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  };
+  // the same from another LDS vector, and the rank-2 growth of a pair:
+  // X_ab += f1 o1_b + f2 o2_b over the first nent entries
+  auto matvec_from = [&](const double *src, int k) -> double {
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    chunks(src, k, [&](int c, const double *o) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a4[i & 3] = fma(xr[c + i], o[i], a4[i & 3]);
+    });
+    return (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  };
+  auto growth2 = [&](int nent, double f1, const double *o1, double f2, const double *o2) {
+#pragma unroll
+    for (int c = 0; c < kMaxKcap; c += 8) {
+      if (c < nent) {
+        double a[8], b[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          a[i] = o1[c + i];
+          b[i] = o2[c + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xr[c + i] = fma(f1, a[i], fma(f2, b[i], xr[c + i]));
+      }
+    }
   };
   // X to LDS (the rows; the LDS code of repeated changes and of the block end
   // reads it there) and back
@@ -683,16 +709,83 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           so1 = scur[pa1];
           fpre2 = static_cast<double>(ncur) * static_cast<double>(ncur - 1) / (Kc * Kc);
         }
-        if (pend) {
-          growth(pk, pbeta, pq);
-          pend = false;
-        }
         const int ka0 = ka;
-        const bool lds_path = !skip && !gz;
+        // Both vertices outside P (every pair insertion; a pair removal of two
+        // vertices unchanged in this block): the two new slots at once, from X
+        // in registers.  With s1, w1 (s2, w2) the new column and row of the first
+        // (second) vertex and the 2x2 corner of Gamma~,
+        //   S = [[d1, G12], [G21, d2]] - [w1 w2]^T X [s1 s2]   (Schur complement),
+        // the sector ratio is (-gh1 D1)(-gh2 D2) det S, and on acceptance
+        //   X'' = [[X, 0], [0, 0]] + Vt S^{-1} Ut^T,  Vt = [[X s1, X s2], [-I]],
+        //   Ut = [[X^T w1, X^T w2], [-I]]   (inversion by partitioning, two rows at once).
+        // A rejected pair leaves X as it was.  Otherwise (a vertex in P) the LDS path
+        // below applies the two changes in turn.
+        const bool fresh = !skip && !gz && __ballot(lane < ka && (myP == pa0 || myP == pa1)) == 0ull;
+        const bool lds_path = !skip && !gz && !fresh;
         int *Psv = reinterpret_cast<int *>(vu + 2 * kp);   // parity-1 vector buffers: free here
         double *ghsv = vv + 2 * kp;
         const auto xsv = gview_w(d.Rg[sec]);   // the residual's buffer, free until block end
         double R = skip ? 0.0 : fpre2;
+        double rs1 = 0.0, rw1 = 0.0, rs2 = 0.0, rw2 = 0.0, m1 = 0.0, m2 = 0.0;
+        if (fresh) {
+          if (lane < ka) {
+            rs1 = gat(myP, pa0);
+            rw1 = gat(pa0, myP);
+            rs2 = gat(myP, pa1);
+            rw2 = gat(pa1, myP);
+          }
+          const double g00 = gat(pa0, pa0), g01 = gat(pa0, pa1), g10 = gat(pa1, pa0), g11 = gat(pa1, pa1);
+          if (pend) {   // while the gathers are in flight
+            growth(pk, pbeta, pq);
+            pend = false;
+          }
+          lds_barrier();   // every wave's growth has read the vector buffers
+          double *b1 = bcast, *b2 = (role == 0 ? vv : vu) + sec * kp;
+          b1[lane] = role == 0 ? rs1 : rw1;
+          b2[lane] = role == 0 ? rs2 : rw2;
+          __builtin_amdgcn_wave_barrier();
+          m1 = matvec_from(b1, ka);   // rows: (X s1)_a; columns: (X^T w1)_b
+          m2 = matvec_from(b2, ka);
+          __builtin_amdgcn_wave_barrier();   // the wave's reads of b1, b2 before it overwrites them
+          b1[lane] = (lane == ka) ? -1.0 : m1;       // vt1 (rows), ut1 (columns)
+          b2[lane] = (lane == ka + 1) ? -1.0 : m2;   // vt2, ut2
+          if (role == 0) {
+            const double t11 = wave_sum_dpp(rw1 * m1), t12 = wave_sum_dpp(rw1 * m2);
+            const double t21 = wave_sum_dpp(rw2 * m1), t22 = wave_sum_dpp(rw2 * m2);
+            if (lane == 0) {
+              sh_S[sec][0] = g00 - 1.0 - sh_igd[sec][(so0 + 1) * 9 + (so0 + 1) * 3 + (sn0 + 1)] - t11;
+              sh_S[sec][1] = g01 - t12;
+              sh_S[sec][2] = g10 - t21;
+              sh_S[sec][3] = g11 - 1.0 - sh_igd[sec][(so1 + 1) * 9 + (so1 + 1) * 3 + (sn1 + 1)] - t22;
+              // Gamma~ entries of the two slots, for the inversion at block end
+              // (a rejected pair's are overwritten later)
+              gam[ka * kcap + ka] = g00 - 1.0 - sh_igd[sec][(so0 + 1) * 9 + (so0 + 1) * 3 + (sn0 + 1)];
+              gam[ka * kcap + ka + 1] = g01;
+              gam[(ka + 1) * kcap + ka] = g10;
+              gam[(ka + 1) * kcap + ka + 1] = g11 - 1.0 - sh_igd[sec][(so1 + 1) * 9 + (so1 + 1) * 3 + (sn1 + 1)];
+            }
+            if (lane < ka) {
+              gam[lane * kcap + ka] = rs1;
+              gam[lane * kcap + ka + 1] = rs2;
+            }
+          } else if (lane < ka) {
+            gam[ka * kcap + lane] = rw1;
+            gam[(ka + 1) * kcap + lane] = rw2;
+          }
+          lds_barrier();
+          double rr[2];
+#pragma unroll
+          for (int sc = 0; sc < 2; ++sc) {
+            const double det = sh_S[sc][0] * sh_S[sc][3] - sh_S[sc][1] * sh_S[sc][2];
+            const double f0 = -(sh_ev[sc][sn0 - so0 + 2] - 1.0) * sh_dsc[sc][so0 + 2];
+            const double f1 = -(sh_ev[sc][sn1 - so1 + 2] - 1.0) * sh_dsc[sc][so1 + 2];
+            rr[sc] = f0 * f1 * det;
+          }
+          R = fpre2 * rr[0] * rr[1];
+        } else if (pend) {
+          growth(pk, pbeta, pq);
+          pend = false;
+        }
         if (lds_path) {
           write_out();
           lds_barrier();   // also ends every read of the vector buffers by the growth
@@ -747,7 +840,30 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           accepted += 1;
           nchg += 2;
           if (R < 0.0) sign = -sign;
-          if (!gz) had_repeat = true;   // Gamma~ is gathered again at block end
+          if (lds_path) had_repeat = true;   // Gamma~ is gathered again at block end
+          if (fresh) {
+            const double S0 = sh_S[sec][0], S1 = sh_S[sec][1], S2 = sh_S[sec][2], S3 = sh_S[sec][3];
+            const double id = 1.0 / (S0 * S3 - S1 * S2);
+            const double i00 = S3 * id, i01 = -S1 * id, i10 = -S2 * id, i11 = S0 * id;   // S^{-1}
+            const double e1 = (lane == ka) ? -1.0 : m1, e2 = (lane == ka + 1) ? -1.0 : m2;
+            if (role == 0) {   // row a: X''_ab += (vt_a S^{-1})_j ut_j,b
+              growth2(ka + 2, e1 * i00 + e2 * i10, vw + sec * kp, e1 * i01 + e2 * i11, vu + sec * kp);
+            } else {           // column b: X''_ab += vt_i,a (S^{-1} ut_b)_i
+              growth2(ka + 2, i00 * e1 + i01 * e2, vs + sec * kp, i10 * e1 + i11 * e2, vv + sec * kp);
+            }
+            P[ka] = pa0;   // every thread writes the same values
+            P[ka + 1] = pa1;
+            if (lane == ka) myP = pa0;
+            if (lane == ka + 1) myP = pa1;
+            if (tid == 0) {
+#pragma unroll
+              for (int sc = 0; sc < 2; ++sc) {
+                sh_gh[sc][ka] = sh_ev[sc][sn0 - so0 + 2] - 1.0;
+                sh_gh[sc][ka + 1] = sh_ev[sc][sn1 - so1 + 2] - 1.0;
+              }
+            }
+            ka += 2;
+          }
           scur[pa0] = static_cast<int8_t>(sn0);   // every thread writes the same value
           scur[pa1] = static_cast<int8_t>(sn1);
           if (type == 3) {
