@@ -265,7 +265,6 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
       d.Bc[s] = cv.take<char>(es * lda * ld);
       d.W[s] = cv.take<double>(static_cast<size_t>(n_cap) * nc);
       d.gR[s] = cv.take<double>(static_cast<size_t>(n_cap) * nc);
-      d.gL[s] = cv.take<double>(static_cast<size_t>(o->n_tau_out + 1) * nc * ld);
       d.Gxy[s] = cv.take<double>(static_cast<size_t>(o->n_tau_out + 1) * nc * nc);
     }
     d.P = cv.take<int32_t>(kcap);

@@ -71,7 +71,6 @@ struct ChainDesc {
   // measurement
   double *W[2];            // [n_cap][nc]  N gR
   double *gR[2];           // [nc][n_cap]  G0_{x_k y}(tau_k), transposed
-  double *gL[2];           // [nc*(n_out+1)][ld]  G0_{x x_l}(tau_j - tau_l)(e^{V_l} - 1), row (j, x)
   double *Gxy[2];          // [(n_out+1)][nc*nc]  row 0 = equal time
   const int32_t *cls_off;  // [n_disp+1] pairs (x*nc+y) of each table, CSR offsets
   const int32_t *cls_pairs;  // [nc*nc]

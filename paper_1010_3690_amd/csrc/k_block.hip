@@ -201,12 +201,13 @@ __device__ void block_end_chain(const ChainDesc &d, ChainState &st, ChainState &
   st.sum_ka += st.k_a;
   st.meas_now = (st.done % d.meas_every == 0 && st.done > d.n_therm) ? 1 : 0;
   if (st.meas_now) {
-    // measurement (per sector): W = N gR reads N once (2 n^2 nc flops); gL has
-    // nc (n_out + 1) n entries, each two table reads, written and read once;
-    // G = G0 + gL W (2 nc (n_out + 1) n nc flops)
+    // measurement (per sector): W = N gR reads N once (2 n^2 nc flops), gR is
+    // written and read once; G = G0 + gL W (2 nc (n_out + 1) n nc flops) with the
+    // nc (n_out + 1) n entries of gL interpolated in the product, two table reads
+    // each (counted as loads, though they mostly hit the L2)
     const double m = static_cast<double>(d.nc) * (d.n_out + 1), nc = d.nc;
     st.meas_flops += 2.0 * (2.0 * np * np * nc + 2.0 * m * np * nc);
-    st.meas_bytes += 2.0 * (es * np * np + 8.0 * (2.0 + 2.0) * m * np + 8.0 * 2.0 * np * nc);
+    st.meas_bytes += 2.0 * (es * np * np + 8.0 * 2.0 * m * np + 8.0 * 2.0 * np * nc);
   }
   mst = st;
 }

@@ -6,7 +6,8 @@
 //     (each reads N once) and Gnn = X YT^T + G0nn;
 //   - the operand B_c = Gamma~^{-1} N_a(P, map) of the rank-k update (Sec. IV C),
 //     with N_a gathered on the fly;
-//   - the measurement (Sec. IV D): W = N gR, then G(x tau_j; y 0) = G0 + gL W.
+//   - the measurement (Sec. IV D): W = N gR, then G(x tau_j; y 0) = G0 + gL W
+//     with gL interpolated from the tables inside the product.
 // A work item is a tile of 16*NRT rows and 16 columns of one product of one
 // chain (NRT covers the largest row count the product can have in the batch); items of all chains are enumerated from a per-chain prefix that
 // every workgroup builds in LDS.  Two execution modes:
@@ -319,14 +320,24 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
     const int ngroups = (Mtot + rows - 1) / rows, ntiles = (nc + 15) >> 4;
     const int sec = local / (ngroups * ntiles), rem = local - sec * ngroups * ntiles;
     const int g = rem / ntiles, c0 = (rem - g * ntiles) * 16;
-    const int m0 = g * rows, M = min(rows, Mtot - m0), ld = d.ld;
-    const auto gL = gview(d.gL[sec] + static_cast<size_t>(m0) * ld), W = gview(d.W[sec]);
+    const int m0 = g * rows, M = min(rows, Mtot - m0);
+    const auto W = gview(d.W[sec]);
     const double dt = d.beta / d.n_out;
     const auto Gxy = gview_w(d.Gxy[sec]);
     const int c = c0 + lr;
     const bool cok = c < nc;
     const int cc0 = cok ? c : 0;
-    auto afn = [=](int m, int l) { return gL[static_cast<size_t>(m) * ld + l]; };
+    // gL_{(j, x), l} = G0_{x x_l}(tau_j - tau_l) (e^{V_l} - 1), interpolated where
+    // the product needs it (never stored: a table of (n_out + 1) nc n entries
+    // would be written and read back once)
+    const auto tau = gview(d.tau[par]);
+    const auto site = gview(d.site[par]), s0 = gview(d.s0[par]);
+    const auto ev = gview(d.evd[sec]);
+    auto afn = [=](int m, int l) {
+      const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
+      const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
+      return g0_interp(d, sec, x, site[l], tj - tau[l]) * (ev[s0[l] + 2] - 1.0);
+    };
     auto bfn = [=](int l) {
       const double v = W[static_cast<size_t>(l) * nc + cc0];
       return cok ? v : 0.0;
