@@ -266,6 +266,8 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
       d.W[s] = cv.take<double>(static_cast<size_t>(n_cap) * nc);
       d.gR[s] = cv.take<double>(static_cast<size_t>(n_cap) * nc);
       d.Gxy[s] = cv.take<double>(static_cast<size_t>(o->n_tau_out + 1) * nc * nc);
+      // gL as a table only where the measurement uses one (batches of fewer than 8 chains)
+      d.gL[s] = n_chains < 8 ? cv.take<double>(static_cast<size_t>(o->n_tau_out + 1) * nc * ld) : nullptr;
     }
     d.P = cv.take<int32_t>(kcap);
     d.map = cv.take<int32_t>(n_cap + kmax);

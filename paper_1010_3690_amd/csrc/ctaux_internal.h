@@ -90,6 +90,8 @@ struct ChainDesc {
   // decision log
   uint8_t *log_acc;        // [log_cap]
   double *log_R;           // [log_cap]
+  // measurement of batches of fewer than 8 chains (null otherwise)
+  double *gL[2];           // [nc*(n_out+1)][ld]  G0_{x x_l}(tau_j - tau_l)(e^{V_l} - 1), row (j, x)
   // pair proposals (Sec. IV B; the fields above keep their offsets without them)
   double p_pair;           // pair insertions and removals, p_pair / 2 each
   int32_t *pspin2;         // [kmax] spin of a pair insertion's second vertex

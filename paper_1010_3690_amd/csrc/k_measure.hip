@@ -4,8 +4,9 @@
 //   G(x tau; y 0) = G0_xy(tau) + sum_{l,k} G0_{x x_l}(tau - tau_l) T_lk G0_{x_k y}(tau_k),
 // evaluated as W = N gR (gR_ky = G0_{x_k y}(tau_k), stored transposed), then
 // G = G0 + gL W with gL_{(x,tau), l} = G0_{x x_l}(tau - tau_l) (e^{V_l} - 1)
-// interpolated inside that product (the output times are tau = 0+ and
-// tau_j = (j - 1/2) beta / n_out, j >= 1, row j*nc + x).
+// (the output times are tau = 0+ and tau_j = (j - 1/2) beta / n_out, j >= 1,
+// row j*nc + x), tabulated first for a few chains and interpolated inside the
+// product for many.
 // Accumulated per chain: order, sign, densities and double occupancy from the
 // equal-time G (tau = 0+), and G(tau_j) averaged over the site pairs of each table.
 #include "ctaux_device.h"
@@ -31,6 +32,36 @@ __global__ __launch_bounds__(256) void k_meas_gR(const ChainDesc *descs, const C
     const int y = r / n, k = r - y * n;
     gview_w(d.gR[sec])[static_cast<size_t>(y) * d.n_cap + k] =
         g0_interp(d, sec, gview(d.site[par])[k], y, gview(d.tau[par])[k]);
+  }
+}
+
+// gL_{(j, x), l} = G0_{x x_l}(tau_j - tau_l) (e^{V_l} - 1) for the output times
+// tau_0 = 0+ and tau_j = (j - 1/2) beta / n_out, j >= 1 (row j*nc + x), as a
+// table: batches of fewer than 8 chains, whose G product splits K over the
+// waves of a workgroup and has too few items to hide interpolations in its k
+// loop (many chains interpolate gL inside the product instead).
+__global__ __launch_bounds__(256) void k_meas_gL(const ChainDesc *descs, const ChainState *states, int n_chains,
+                                                 int xcd_g) {
+  const ChainBlock cb = chain_block(xcd_g);
+  const int c = cb.c;
+  if (c >= n_chains) return;
+  const ChainDesc &d = descs[c];
+  const ChainState &st = states[c];
+  if (!st.active || !st.meas_now) return;
+  const int n = st.n, nc = d.nc, par = st.parity, ld = d.ld;
+  const int rows = nc * (d.n_out + 1);
+  const double dt = d.beta / d.n_out;
+  const int per = rows * n;   // 32-bit indices: 2 (n_out + 1) nc n < 2^31
+  const auto tau = gview(d.tau[par]);
+  const auto site = gview(d.site[par]), s0 = gview(d.s0[par]);
+  for (int e = cb.sub * 256 + threadIdx.x; e < 2 * per; e += cb.g * 256) {
+    const int sec = e >= per ? 1 : 0;
+    const int r = e - sec * per;
+    const int m = r / n, l = r - m * n;
+    const int j = m / nc, x = m - j * nc;
+    const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
+    gview_w(d.gL[sec])[static_cast<size_t>(m) * ld + l] =
+        g0_interp(d, sec, x, site[l], tj - tau[l]) * (gview(d.evd[sec])[s0[l] + 2] - 1.0);
   }
 }
 
@@ -372,9 +403,11 @@ void launch_kw_g0(const Batch &b, hipStream_t s) {
 
 void launch_measure(const Batch &b, hipStream_t s) {
   hipLaunchKernelGGL(k_meas_gR, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_mstate, b.n_chains, chain_grid_arg(b));
+  if (b.n_chains < 8)
+    hipLaunchKernelGGL(k_meas_gL, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_mstate, b.n_chains,
+                       chain_grid_arg(b));
   launch_skinny(b, s, 2);   // W = N gR
   launch_skinny(b, s, 3);   // Gxy = G0 + gL W, gL_{(x,tau), l} = G0_{x x_l}(tau - tau_l)(e^{V_l} - 1)
-                            // interpolated inside the product
   hipLaunchKernelGGL(k_meas_acc, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);
   if (b.n_mats > 0) {
     hipLaunchKernelGGL(k_meas_kw_sort, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);

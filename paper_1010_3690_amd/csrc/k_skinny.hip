@@ -7,7 +7,8 @@
 //   - the operand B_c = Gamma~^{-1} N_a(P, map) of the rank-k update (Sec. IV C),
 //     with N_a gathered on the fly;
 //   - the measurement (Sec. IV D): W = N gR, then G(x tau_j; y 0) = G0 + gL W
-//     with gL interpolated from the tables inside the product.
+//     (gL read from its table for a few chains, interpolated inside the
+//     product for many).
 // A work item is a tile of 16*NRT rows and 16 columns of one product of one
 // chain (NRT covers the largest row count the product can have in the batch); items of all chains are enumerated from a per-chain prefix that
 // every workgroup builds in LDS.  Two execution modes:
@@ -327,17 +328,6 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
     const int c = c0 + lr;
     const bool cok = c < nc;
     const int cc0 = cok ? c : 0;
-    // gL_{(j, x), l} = G0_{x x_l}(tau_j - tau_l) (e^{V_l} - 1), interpolated where
-    // the product needs it (never stored: a table of (n_out + 1) nc n entries
-    // would be written and read back once)
-    const auto tau = gview(d.tau[par]);
-    const auto site = gview(d.site[par]), s0 = gview(d.s0[par]);
-    const auto ev = gview(d.evd[sec]);
-    auto afn = [=](int m, int l) {
-      const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
-      const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
-      return g0_interp(d, sec, x, site[l], tj - tau[l]) * (ev[s0[l] + 2] - 1.0);
-    };
     auto bfn = [=](int l) {
       const double v = W[static_cast<size_t>(l) * nc + cc0];
       return cok ? v : 0.0;
@@ -347,7 +337,25 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
       const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
       Gxy[static_cast<size_t>(j) * nc * nc + x * nc + cc] = g0_interp(d, sec, x, cc, tj) + v;
     };
-    skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, nc, c0, red);
+    if constexpr (MODE == kModeSplitK) {
+      // few chains: gL from its table (k_meas_gL)
+      const auto gL = gview(d.gL[sec] + static_cast<size_t>(m0) * d.ld);
+      auto afn = [=](int m, int l) { return gL[static_cast<size_t>(m) * d.ld + l]; };
+      skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, nc, c0, red);
+    } else {
+      // many chains: gL_{(j, x), l} = G0_{x x_l}(tau_j - tau_l) (e^{V_l} - 1)
+      // interpolated where the product needs it (no table of (n_out + 1) nc n
+      // entries per sector written and read back)
+      const auto tau = gview(d.tau[par]);
+      const auto site = gview(d.site[par]), s0 = gview(d.s0[par]);
+      const auto ev = gview(d.evd[sec]);
+      auto afn = [=](int m, int l) {
+        const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
+        const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
+        return g0_interp(d, sec, x, site[l], tj - tau[l]) * (ev[s0[l] + 2] - 1.0);
+      };
+      skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, nc, c0, red);
+    }
   }
 }
 
