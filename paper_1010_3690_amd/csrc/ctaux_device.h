@@ -73,6 +73,49 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gview_w(T *p) {
   return (__attribute__((address_space(1))) T *)(p);
 }
 
+// Exclusive prefix sums pre[0..n] (pre[0] = 0) of count(i), i < n, as every
+// workgroup (NT threads) of a persistent kernel builds them in LDS to find the
+// owner of a work item.  Up to 64 entries one wave scans them with lane
+// shuffles and one barrier publishes them; more, the workgroup scans NT at a
+// time (Hillis-Steele).  pre is complete on return.
+template <int NT, typename F>
+__device__ __forceinline__ void block_prefix(int n, int *pre, F count) {
+  __shared__ int scan[NT];
+  __shared__ int carry;
+  const int tid = threadIdx.x;
+  if (n <= 64) {
+    if (tid < 64) {
+      int v = tid < n ? count(tid) : 0;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int x = __shfl_up(v, off, 64);
+        if (tid >= off) v += x;
+      }
+      if (tid < n) pre[tid + 1] = v;
+      if (tid == 0) pre[0] = 0;
+    }
+    __syncthreads();
+    return;
+  }
+  if (tid == 0) { carry = 0; pre[0] = 0; }
+  __syncthreads();
+  for (int base = 0; base < n; base += NT) {
+    const int i = base + tid;
+    scan[tid] = i < n ? count(i) : 0;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+      const int x = tid >= off ? scan[tid - off] : 0;
+      __syncthreads();
+      scan[tid] += x;
+      __syncthreads();
+    }
+    if (i < n) pre[i + 1] = carry + scan[tid];
+    __syncthreads();
+    if (tid == 0) carry += scan[NT - 1];
+    __syncthreads();
+  }
+}
+
 // Chain and sub-block of a per-chain streaming kernel.  With xcd_g = G > 0 the
 // grid is one-dimensional, 8 G ceil(C / 8) workgroups, and workgroup b serves
 // chain (b % 8) + 8 (b / 8G) as sub-block (b / 8) % G: workgroups are handed to

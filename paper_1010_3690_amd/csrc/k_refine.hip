@@ -63,32 +63,12 @@ __global__ __launch_bounds__(256) void k_ref_gemm(const ChainDesc *descs, const 
   extern __shared__ int pre[];   // [n_items + 1]
   __shared__ double As[2][64][kGK + 1];
   __shared__ double Bs[2][kGK][64 + 1];
-  __shared__ int scan[256];
-  __shared__ int carry;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nslots = (sizeof(T) == sizeof(double)) ? 2 : 3;
-  if (tid == 0) { carry = 0; pre[0] = 0; }
-  __syncthreads();
-  for (int base = 0; base < n_items; base += 256) {
-    const int q = base + tid;
-    int v = 0;
-    if (q < n_items) {
-      const int nt = (items[q].n + 63) / 64;
-      v = 2 * nt * nt;
-    }
-    scan[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const int x = tid >= off ? scan[tid - off] : 0;
-      __syncthreads();
-      scan[tid] += x;
-      __syncthreads();
-    }
-    if (q < n_items) pre[q + 1] = carry + scan[tid];
-    __syncthreads();
-    if (tid == 0) carry += scan[255];
-    __syncthreads();
-  }
+  block_prefix<256>(n_items, pre, [&](int q) {
+    const int nt = (items[q].n + 63) / 64;
+    return 2 * nt * nt;
+  });
   const int total = pre[n_items];
   const int wr = wave >> 1, wc = wave & 1, lr = lane & 15, lk = lane >> 4;
   for (int t = blockIdx.x; t < total; t += gridDim.x) {

@@ -365,27 +365,9 @@ template <typename T, int MODE, int NRT, int KIND>
 __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, const ChainState *states,
                                                         int n_chains) {
   extern __shared__ int pre[];   // [n_chains + 1]
-  __shared__ int scan[kSkThreads];
-  __shared__ int carry;
   __shared__ double red[NRT * 256];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  if (tid == 0) { carry = 0; pre[0] = 0; }
-  __syncthreads();
-  for (int base = 0; base < n_chains; base += kSkThreads) {
-    const int cc = base + tid;
-    scan[tid] = cc < n_chains ? skinny_items(descs[cc], states[cc], KIND) : 0;
-    __syncthreads();
-    for (int off = 1; off < kSkThreads; off <<= 1) {
-      const int v = tid >= off ? scan[tid - off] : 0;
-      __syncthreads();
-      scan[tid] += v;
-      __syncthreads();
-    }
-    if (cc < n_chains) pre[cc + 1] = carry + scan[tid];
-    __syncthreads();
-    if (tid == 0) carry += scan[kSkThreads - 1];
-    __syncthreads();
-  }
+  const int wave = threadIdx.x >> 6;
+  block_prefix<kSkThreads>(n_chains, pre, [&](int cc) { return skinny_items(descs[cc], states[cc], KIND); });
   const int total = pre[n_chains];
   const int first = (MODE == kModeWave) ? blockIdx.x * kSkWaves + wave : blockIdx.x;
   const int stride = (MODE == kModeWave) ? gridDim.x * kSkWaves : gridDim.x;

@@ -87,30 +87,11 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int SUB = TILE / 2, NB = SUB / 16;
   extern __shared__ int prefix[];   // [n_chains + 1]
-  __shared__ int scan[256];
-  __shared__ int carry;
-  if (threadIdx.x == 0) { carry = 0; prefix[0] = 0; }
-  __syncthreads();
-  for (int base = 0; base < n_chains; base += 256) {
-    const int cc = base + threadIdx.x;
-    int v = 0;
-    if (cc < n_chains && states[cc].active) {
-      const int nt = (states[cc].n_new + TILE - 1) / TILE;
-      v = 2 * nt * nt;
-    }
-    scan[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const int x = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
-      __syncthreads();
-      scan[threadIdx.x] += x;
-      __syncthreads();
-    }
-    if (cc < n_chains) prefix[cc + 1] = carry + scan[threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x == 0) carry += scan[255];
-    __syncthreads();
-  }
+  block_prefix<256>(n_chains, prefix, [&](int cc) {
+    if (!states[cc].active) return 0;
+    const int nt = (states[cc].n_new + TILE - 1) / TILE;
+    return 2 * nt * nt;
+  });
   const int total = prefix[n_chains];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
