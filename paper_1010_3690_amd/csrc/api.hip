@@ -251,8 +251,8 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
     d.csite = cv.take<int32_t>(kmax);
     d.cid = cv.take<int64_t>(kmax);
     for (int s = 0; s < 2; ++s) {
-      d.X[s] = cv.take<double>(static_cast<size_t>(kmax) * ld);
-      d.ZT[s] = cv.take<double>(static_cast<size_t>(kmax) * ld);
+      d.X[s] = cv.take<double>(static_cast<size_t>(align_up(kmax, 16)) * ld);   // cand_offset order
+      d.ZT[s] = cv.take<double>(static_cast<size_t>(align_up(kmax, 16)) * ld);
       d.YT[s] = cv.take<double>(static_cast<size_t>(kmax) * ld);
       d.Rt[s] = cv.take<double>(static_cast<size_t>(kmax) * ld);
       d.G0nn[s] = cv.take<double>(static_cast<size_t>(kmax) * kmax);

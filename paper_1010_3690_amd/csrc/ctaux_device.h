@@ -73,6 +73,18 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gview_w(T *p) {
   return (__attribute__((address_space(1))) T *)(p);
 }
 
+// The candidate operands X and ZT (k_max candidates x ld vertices per sector)
+// are stored in the order the skinny products' lanes read them: 16 x 16 blocks
+// of (candidate, vertex), block (vertex group g, candidate tile t) at
+// 256 (g RT + t), RT = ceil(k_max / 16), and inside a block entry (j, i) at
+// 4 (16 ((i % 16) / 4) + j % 16) + i % 4.  A lane then reads four consecutive
+// vertices of one candidate as 32 contiguous bytes, and the 64 lanes of a
+// load (16 candidates x 16 vertices) one contiguous 2 KB block, where the
+// row-major layout touched 16 cache lines per load for 32 bytes in each.
+__device__ __forceinline__ size_t cand_offset(int j, int i, int rt) {
+  return ((static_cast<size_t>(i >> 4) * rt + (j >> 4)) * 64 + (((i & 15) >> 2) << 4) + (j & 15)) * 4 + (i & 3);
+}
+
 // Exclusive prefix sums pre[0..n] (pre[0] = 0) of count(i), i < n, as every
 // workgroup (NT threads) of a persistent kernel builds them in LDS to find the
 // owner of a work item.  Up to 64 entries one wave scans them with lane

@@ -52,8 +52,8 @@ struct ChainDesc {
   int32_t *csite;          // [kmax] candidate sites
   int64_t *cid;            // [kmax] ids given to accepted candidates
   // preparation products, FP64, per sector
-  double *X[2];            // [kmax][ld]  X_ji = G0(tau_j^new - tau_i)(e^{V_i} - 1)
-  double *ZT[2];           // [kmax][ld]  ZT_ji = G0(tau_i - tau_j^new)
+  double *X[2];            // X_ji = G0(tau_j^new - tau_i)(e^{V_i} - 1), kmax x ld in cand_offset order
+  double *ZT[2];           // ZT_ji = G0(tau_i - tau_j^new), the same layout
   double *G0nn[2];         // [kmax][kmax]
   double *YT[2];           // [kmax][ld]  (N Z)^T: G of old rows, new columns
   double *Rt[2];           // [kmax][ld]  X N: rows of the augmented N for new vertices

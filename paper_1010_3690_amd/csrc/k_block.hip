@@ -128,6 +128,7 @@ void launch_block_begin(const Batch &b, hipStream_t s) {
 // G0 products for the candidates (Sec. IV A, "Preparation steps"), per sector:
 //   X_ji  = G0(tau_j^new - tau_i)(e^{V_i} - 1)   (so that Rt = X N)
 //   ZT_ji = G0(tau_i - tau_j^new)                 (so that YT = (N Z)^T)
+// (both in the blocked order of cand_offset)
 //   G0nn_jj' = G0(tau_j^new - tau_j'^new)          (0+ on the diagonal)
 __global__ __launch_bounds__(256) void k_interp(const ChainDesc *descs, const ChainState *states, int n_chains,
                                                 int xcd_g) {
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(256) void k_interp(const ChainDesc *descs, const Ch
   const int32_t *s0 = d.s0[par];
   // 32-bit index arithmetic: 2 (2 k n + k^2) < 2^31 for k <= 128, n <= 8192
   const int kn = k * n, per_sec = 2 * kn + k * k, total = 2 * per_sec;
+  const int rt = (d.kmax + 15) >> 4;   // candidate tiles of the X, ZT layout (cand_offset)
   for (int e = cb.sub * 256 + threadIdx.x; e < total; e += cb.g * 256) {
     const int sec = e >= per_sec ? 1 : 0;
     int r = e - sec * per_sec;
@@ -153,10 +155,10 @@ __global__ __launch_bounds__(256) void k_interp(const ChainDesc *descs, const Ch
       const int j = r / n, i = r - j * n;
       if (which == 0) {
         const double ev = d.evd[sec][s0[i] + 2];
-        d.X[sec][static_cast<size_t>(j) * d.ld + i] =
+        d.X[sec][cand_offset(j, i, rt)] =
             g0_interp(d, sec, d.csite[j], site[i], d.ctau[j] - tau[i]) * (ev - 1.0);
       } else {
-        d.ZT[sec][static_cast<size_t>(j) * d.ld + i] =
+        d.ZT[sec][cand_offset(j, i, rt)] =
             g0_interp(d, sec, site[i], d.csite[j], tau[i] - d.ctau[j]);
       }
     } else {

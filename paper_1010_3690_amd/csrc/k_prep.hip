@@ -19,12 +19,12 @@ __global__ __launch_bounds__(256) void k_gnn_dot(const ChainDesc *descs, const C
   const ChainDesc &d = descs[c];
   const ChainState &st = states[c];
   if (!st.active) return;
-  const int n = st.n, ki = st.k_ins, ld = d.ld, km = d.kmax;
+  const int n = st.n, ki = st.k_ins, ld = d.ld, km = d.kmax, rt = (km + 15) >> 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int per = ki * ki;
   for (int w = blockIdx.x * 4 + wave; w < 2 * per; w += gridDim.x * 4) {
     const int sec = w >= per ? 1 : 0, r = w - sec * per, m = r / ki, cc = r - m * ki;
-    const auto X = gview(d.X[sec] + static_cast<size_t>(m) * ld);
+    const auto X = gview(d.X[sec]);
     const auto YT = gview(d.YT[sec] + static_cast<size_t>(cc) * ld);
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < n; k0 += 64 * 8) {   // eight loads of each row in flight
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_gnn_dot(const ChainDesc *descs, const C
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k = k0 + 64 * i + lane;
-        x[i] = k < n ? X[k] : 0.0;
+        x[i] = k < n ? X[cand_offset(m, k, rt)] : 0.0;
         y[i] = k < n ? YT[k] : 0.0;
       }
 #pragma unroll

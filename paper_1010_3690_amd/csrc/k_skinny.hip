@@ -192,8 +192,8 @@ __device__ __forceinline__ void skinny_item(AF afn, BF bfn, OF out, int M, int K
     }
     return;
   }
-  // contiguous eighths of K, rounded to whole k-steps
-  const int chunk = (((K + kSkWaves - 1) / kSkWaves) + 3) & ~3;
+  // contiguous eighths of K, rounded to whole groups of 16 k-steps
+  const int chunk = (((K + kSkWaves - 1) / kSkWaves) + 15) & ~15;
   const int kb = wave * chunk;
   mma(kb, min(K, kb + chunk), acc);
   for (int w = 0; w < kSkWaves; ++w) {   // fixed-order reduction of the partial tiles
@@ -228,14 +228,15 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
     const int grp = local / (4 * nt), r0 = grp * kPrepRows;
     const int loc2 = local - grp * 4 * nt;
     const int job = loc2 / nt, c0 = (loc2 - job * nt) * 16, sec = job & 1, ld = d.ld;
-    const auto A = gview(((job < 2) ? d.ZT[sec] : d.X[sec]) + static_cast<size_t>(r0) * ld);
+    const auto A = gview((job < 2) ? d.ZT[sec] : d.X[sec]);
+    const int rt = (d.kmax + 15) >> 4;
     const auto N = gview(static_cast<const T *>(d.N[par][sec]));
     const auto C = gview_w(((job < 2) ? d.YT[sec] : d.Rt[sec]) + static_cast<size_t>(r0) * ld);
     const int M = min(kPrepRows, st.k_ins - r0);
     const int c = c0 + lr;
     const bool cok = c < n;
     const int cc0 = cok ? c : 0;   // in-bounds address; the value is masked
-    auto afn = [=](int m, int k) { return A[static_cast<size_t>(m) * ld + k]; };
+    auto afn = [=](int m, int k) { return A[cand_offset(r0 + m, k, rt)]; };
     auto out = [=](int m, int cc, double v) { C[static_cast<size_t>(m) * ld + cc] = v; };
     if (job < 2) {
       auto bfn = [=](int k) {
@@ -256,14 +257,15 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
     const int grp = local / (2 * nt), r0 = grp * kPrepRows;
     const int loc2 = local - grp * 2 * nt;
     const int sec = loc2 / nt, c0 = (loc2 - sec * nt) * 16, ld = d.ld, km = d.kmax;
-    const auto X = gview(d.X[sec] + static_cast<size_t>(r0) * ld), YT = gview(d.YT[sec]);
+    const auto X = gview(d.X[sec]), YT = gview(d.YT[sec]);
+    const int rt = (km + 15) >> 4;
     const auto G0nn = gview(d.G0nn[sec] + static_cast<size_t>(r0) * km);
     const auto Gnn = gview_w(d.Gnn[sec] + static_cast<size_t>(r0) * km);
     const int M = min(kPrepRows, ki - r0);
     const int c = c0 + lr;
     const bool cok = c < ki;
     const int cc0 = cok ? c : 0;
-    auto afn = [=](int m, int k) { return X[static_cast<size_t>(m) * ld + k]; };
+    auto afn = [=](int m, int k) { return X[cand_offset(r0 + m, k, rt)]; };
     auto bfn = [=](int k) {
       const double v = YT[static_cast<size_t>(cc0) * ld + k];
       return cok ? v : 0.0;
