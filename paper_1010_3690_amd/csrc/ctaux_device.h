@@ -85,6 +85,15 @@ __device__ __forceinline__ size_t cand_offset(int j, int i, int rt) {
   return ((static_cast<size_t>(i >> 4) * rt + (j >> 4)) * 64 + (((i & 15) >> 2) << 4) + (j & 15)) * 4 + (i & 3);
 }
 
+// The rank-k operand Ac (n' rows x lda columns, lda a multiple of 8) in the
+// order the update's MFMA lanes read it: blocks of 16 rows x 4 columns (one
+// k-step), block (row tile t, step s) at 64 (t S + s), S = lda / 4, and inside
+// a block entry (i, a) at 16 (a % 4) + i % 16.  A load of 64 lanes (16 rows,
+// 4 consecutive k) then reads 512 contiguous bytes.
+__device__ __forceinline__ size_t ac_offset(int i, int a, int steps) {
+  return ((static_cast<size_t>(i >> 4) * steps + (a >> 2)) << 6) + ((a & 3) << 4) + (i & 15);
+}
+
 // Exclusive prefix sums pre[0..n] (pre[0] = 0) of count(i), i < n, as every
 // workgroup (NT threads) of a persistent kernel builds them in LDS to find the
 // owner of a work item.  Up to 64 entries one wave scans them with lane

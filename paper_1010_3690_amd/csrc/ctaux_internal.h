@@ -66,7 +66,7 @@ struct ChainDesc {
   double *Rg[2];           // [kcap][kcap] residual I - Gamma~ X0 of the growth inverse
   int32_t *map;            // [n_cap] new canonical index -> augmented index
   // rank-k operands (storage type of N)
-  void *Ac[2];             // [ld rows][lda]  ((G - I) D^{-1})_{map, P}
+  void *Ac[2];             // ((G - I) D^{-1})_{map, P}, n' x lda in ac_offset order (ld x lda allocated)
   void *Bc[2];             // [lda][ld]       Gamma~^{-1} N_a(P, map)
   // measurement
   double *W[2];            // [n_cap][nc]  N gR

@@ -438,23 +438,26 @@ __global__ __launch_bounds__(256) void k_operands(const ChainDesc *descs, const 
   if (ka == 0 || np == 0) return;
   const int kpad = (ka + 7) & ~7;
   const int32_t *s0 = d.s0[par];
-  const int64_t per_sec = static_cast<int64_t>(np) * kpad;   // Ac entries per sector
+  // Ac in ac_offset order: consecutive threads write consecutive entries of a
+  // block (16 rows x one k-step); rows of the last row tile beyond n' are skipped
+  const int steps = d.lda >> 2, sk = kpad >> 2, nrt = (np + 15) >> 4;
+  const int64_t per_sec = static_cast<int64_t>(nrt) * sk * 64;   // Ac entries per sector
   const int64_t total = 2 * per_sec;
   const int *map = d.map, *P = d.P;
-  const int lda = d.lda;
   for (int64_t e = cb.sub * 256ll + threadIdx.x; e < total; e += cb.g * 256ll) {
     const int sec = static_cast<int>(e / per_sec);
-    const int64_t r = e - sec * per_sec;
+    const int r = static_cast<int>(e - sec * per_sec);
+    const int rt = r / (sk * 64), rem = r - rt * sk * 64, s = rem >> 6, l = rem & 63;
+    const int i = rt * 16 + (l & 15), a = 4 * s + (l >> 4);
+    if (i >= np) continue;
     const T *N = static_cast<const T *>(d.N[par][sec]);
-    // consecutive threads walk the k index of one row, then rows
-    const int i = static_cast<int>(r / kpad), a = static_cast<int>(r - static_cast<int64_t>(i) * kpad);
     double v = 0.0;
     if (a < ka) {
       // (G - I)_{map, P} D^{-1}: (N_a - I) for an old column, (G - I) for a candidate
       const int mi = gview(map)[i], pa = gview(P)[a];
       v = (pa < n ? na_entry<T>(d, N, n, sec, mi, pa) : g_entry<T>(d, N, s0, n, sec, mi, pa)) - (mi == pa ? 1.0 : 0.0);
     }
-    gview_w(static_cast<T *>(d.Ac[sec]))[static_cast<size_t>(i) * lda + a] = static_cast<T>(v);
+    gview_w(static_cast<T *>(d.Ac[sec]))[ac_offset(i, a, steps)] = static_cast<T>(v);
   }
 }
 

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int k = k0 + 4 * lk + e;
-            const float a = (r < np && k < ka) ? static_cast<float>(Ac[static_cast<size_t>(r) * lda + k]) : 0.f;
+            const float a = (r < np && k < ka) ? static_cast<float>(Ac[ac_offset(r, k, lda >> 2)]) : 0.f;
             short h, l;
             split_bf16(a, h, l);
             ahi[i][e] = h;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
 #pragma unroll
           for (int i = 0; i < NB; ++i) {
             const int r = row0 + i * 16 + lr;
-            av[u][i] = (kok && r < np) ? Ac[static_cast<size_t>(r) * lda + k] : T(0);
+            av[u][i] = (kok && r < np) ? Ac[ac_offset(r, k, lda >> 2)] : T(0);
           }
 #pragma unroll
           for (int j = 0; j < NB; ++j) {
