@@ -264,7 +264,7 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
       d.Ac[s] = cv.take<char>(es * ld * lda);
       d.Bc[s] = cv.take<char>(es * lda * ld);
       d.W[s] = cv.take<double>(static_cast<size_t>(n_cap) * nc);
-      d.gR[s] = cv.take<double>(static_cast<size_t>(n_cap) * nc);
+      d.gR[s] = cv.take<double>(align_up(n_cap, 16) * align_up(nc, 16));   // cand_offset order
       d.Gxy[s] = cv.take<double>(static_cast<size_t>(o->n_tau_out + 1) * nc * nc);
       // gL as a table only where the measurement uses one (batches of fewer than 8 chains)
       d.gL[s] = n_chains < 8 ? cv.take<double>(static_cast<size_t>(o->n_tau_out + 1) * nc * ld) : nullptr;

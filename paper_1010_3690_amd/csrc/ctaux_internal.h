@@ -70,7 +70,7 @@ struct ChainDesc {
   void *Bc[2];             // [lda][ld]       Gamma~^{-1} N_a(P, map)
   // measurement
   double *W[2];            // [n_cap][nc]  N gR
-  double *gR[2];           // [nc][n_cap]  G0_{x_k y}(tau_k), transposed
+  double *gR[2];           // G0_{x_k y}(tau_k), nc x n_cap in cand_offset order (rows y)
   double *Gxy[2];          // [(n_out+1)][nc*nc]  row 0 = equal time
   const int32_t *cls_off;  // [n_disp+1] pairs (x*nc+y) of each table, CSR offsets
   const int32_t *cls_pairs;  // [nc*nc]

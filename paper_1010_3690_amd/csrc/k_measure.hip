@@ -23,14 +23,15 @@ __global__ __launch_bounds__(256) void k_meas_gR(const ChainDesc *descs, const C
   const ChainDesc &d = descs[c];
   const ChainState &st = states[c];
   if (!st.active || !st.meas_now) return;
-  const int n = st.n, nc = d.nc, par = st.parity;
-  // rows y, columns k (consecutive threads write consecutive k); 32-bit indices
+  const int n = st.n, nc = d.nc, par = st.parity, rt = (nc + 15) >> 4;
+  // rows y, columns k, stored in the blocked order of cand_offset (the W product's
+  // operand order); 32-bit indices
   const int per = n * nc;
   for (int e = cb.sub * 256 + threadIdx.x; e < 2 * per; e += cb.g * 256) {
     const int sec = e >= per ? 1 : 0;
     const int r = e - sec * per;
     const int y = r / n, k = r - y * n;
-    gview_w(d.gR[sec])[static_cast<size_t>(y) * d.n_cap + k] =
+    gview_w(d.gR[sec])[cand_offset(y, k, rt)] =
         g0_interp(d, sec, gview(d.site[par])[k], y, gview(d.tau[par])[k]);
   }
 }

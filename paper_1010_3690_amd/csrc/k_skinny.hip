@@ -303,14 +303,15 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
   } else if constexpr (KIND == kSkMeasW) {
     // W[sec] = N gR as (gRT N^T)^T: C[l][y]
     const int nt = (n + 15) >> 4;
-    const int sec = local / nt, c0 = (local - sec * nt) * 16, ld = d.ld, ncap = d.n_cap, nc = d.nc;
+    const int sec = local / nt, c0 = (local - sec * nt) * 16, ld = d.ld, nc = d.nc;
     const auto gR = gview(d.gR[sec]);
     const auto N = gview(static_cast<const T *>(d.N[par][sec]));
     const auto W = gview_w(d.W[sec]);
     const int c = c0 + lr;
     const bool cok = c < n;
     const int cc0 = cok ? c : 0;
-    auto afn = [=](int m, int k) { return gR[static_cast<size_t>(m) * ncap + k]; };
+    const int rt = (nc + 15) >> 4;
+    auto afn = [=](int m, int k) { return gR[cand_offset(m, k, rt)]; };
     auto bfn = [=](int k) {
       const double v = static_cast<double>(N[static_cast<size_t>(cc0) * ld + k]);
       return cok ? v : 0.0;
