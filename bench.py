@@ -141,19 +141,27 @@ def timed_run(gb, steps, k, n_chains=1, profile_blocks=40):
 
 
 def measured_traffic(kernel, n_chains):
-    """HBM bytes per launch of `kernel` on the headline chain from the committed
-    rocprofv3 counter summary, or None when the kernel's source has changed since
-    the counters were taken (the summary records the source's SHA-256)."""
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary: the proposal loop and the rank-k update on the headline chain, the
+    measurement kernels (gR, W, G, accumulation) on the 512-chain batch.  None
+    when no entry exists for that case or the kernel's sources have changed since
+    the counters were taken (the summary records their SHA-256)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_bytes_per_launch.txt")
-    src = {"propose": "k_propose.hip", "rankk": "k_update.hip"}.get(kernel)
-    if n_chains != 1 or src is None or not os.path.exists(path):
+    key, srcs = {("propose", 1): ("propose", ["k_propose.hip"]),
+                 ("rankk", 1): ("rankk", ["k_update.hip"]),
+                 ("measure", 512): ("measure_batched512", ["k_measure.hip", "k_skinny.hip"])}.get(
+                     (kernel, n_chains), (None, None))
+    if key is None or not os.path.exists(path):
         return None
-    with open(os.path.join(ROOT, "paper_1010_3690_amd", "csrc", src), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for src in srcs:
+        with open(os.path.join(ROOT, "paper_1010_3690_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()
     for line in open(path):
         parts = line.split()
-        if len(parts) == 3 and not line.startswith("#") and parts[0] == kernel and parts[2] == sha:
+        if len(parts) == 3 and not line.startswith("#") and parts[0] == key and parts[2] == sha:
             return float(parts[1])
     return None
 
@@ -176,7 +184,7 @@ def roofline(d):
         key = {"rankk": "rankk_bytes", "prep": "prep_bytes", "measure": "meas_bytes"}[name]
         achieved = d[key] / max(launches, 1) / avg_s / 1e9
         out.update({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None})
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, n_chains)})
     else:
         # The proposal loop is one workgroup per chain running k dependent
         # proposals; its work per launch is the O(k_a^2) Gamma^{-1} arithmetic

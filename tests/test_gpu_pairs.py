@@ -132,3 +132,35 @@ def test_pair_batch_of_chains():
         oc.run(n_prop)
         _compare(gb, oc, n_prop, chain=c)
         _compare_obs(gb.obs(c), oc.obs())
+
+
+def test_pair_fp32_storage():
+    """Pairs with N stored in FP32 (the float instantiation of the pair path):
+    the first 1200 decisions equal the oracle's (ratios to FP32 rounding), and
+    after 4000 proposals N is within 1e-4 of the FP64 inverse of the chain's
+    own configuration; a refinement restores it to FP32 rounding."""
+    ctaux = _ctaux()
+    w = _cluster16()
+    n_first = 1200
+    opts = _opts(ctaux, 4000, k_cap=48, n_cap=1024, precision=ctaux.CTAUX_FP32, p_pair=0.4)
+    gb = ctaux.CtauxBatch([w], opts)
+    oc = _oracle(w, opts)
+    gb.run(n_first)
+    oc.run(n_first)
+    acc_g, R_g = gb.decisions(0, 0, n_first)
+    acc_o, R_o = oc.get_log(0, n_first)
+    assert np.array_equal(acc_g, acc_o)
+    np.testing.assert_allclose(R_g, R_o, rtol=1e-3, atol=1e-300)
+    gb.run(4000 - n_first)
+    ids, tau, site, s = gb.config(0)
+    ref_chain = OracleChain(w, n_cap=1024)
+    ref_chain.set_config(ids, tau, site, s)
+    errs = []
+    for sec in (0, 1):
+        ref = np.linalg.inv(ref_chain.Minv(sec))
+        errs.append(np.linalg.norm(gb.N(0, sec) - ref) / np.linalg.norm(ref))
+    assert max(errs) < 1e-4, errs
+    gb.recompute()
+    for sec in (0, 1):
+        ref = np.linalg.inv(ref_chain.Minv(sec))
+        assert np.linalg.norm(gb.N(0, sec) - ref) / np.linalg.norm(ref) < 1e-6
