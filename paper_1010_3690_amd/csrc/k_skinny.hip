@@ -352,10 +352,14 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
       const auto tau = gview(d.tau[par]);
       const auto site = gview(d.site[par]), s0 = gview(d.s0[par]);
       const auto ev = gview(d.evd[sec]);
-      auto afn = [=](int m, int l) {
-        const int mm = m0 + m, j = mm / nc, x = mm - j * nc;
-        const double tj = j == 0 ? 0.0 : (static_cast<double>(j - 1) + 0.5) * dt;
-        return g0_interp(d, sec, x, site[l], tj - tau[l]) * (ev[s0[l] + 2] - 1.0);
+      // one row tile: lane l supplies row l % 16 for every k (wave_mma_kv), so its
+      // output time and site are fixed for the item and computed once here (a
+      // masked row beyond M takes any in-range values)
+      static_assert(NRT == 1, "one row tile per G item");
+      const int mm = m0 + (lr < M ? lr : 0), jr = mm / nc, xr = mm - jr * nc;
+      const double tjr = jr == 0 ? 0.0 : (static_cast<double>(jr - 1) + 0.5) * dt;
+      auto afn = [=](int, int l) {
+        return g0_interp(d, sec, xr, site[l], tjr - tau[l]) * (ev[s0[l] + 2] - 1.0);
       };
       skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, nc, c0, red);
     }
