@@ -156,15 +156,20 @@ __device__ __forceinline__ ChainBlock chain_block(int xcd_g) {
 // Bare propagator G0_{xy}(dtau): linear interpolation on the uniform grid,
 // dtau in (-beta, beta); dtau < 0 uses G0(dtau) = -G0(dtau + beta); dtau = 0
 // reads the 0+ entry.
-__device__ __forceinline__ double g0_interp(const ChainDesc &d, int sec, int x, int y, double dtau) {
-  const auto tab = gview(d.g0[sec] + static_cast<int64_t>(gview(d.site_disp)[x * d.nc + y]) * d.n_tau);
+// The same on one table (n_tau points, spacing 1 / inv_h, period beta).
+__device__ __forceinline__ double interp_table(const __attribute__((address_space(1))) double *tab, double beta,
+                                               double inv_h, int n_tau, double dtau) {
   double sgn = 1.0;
-  if (dtau < 0.0) { dtau += d.beta; sgn = -1.0; }
-  double xx = dtau * d.inv_h;
+  if (dtau < 0.0) { dtau += beta; sgn = -1.0; }
+  double xx = dtau * inv_h;
   int m = static_cast<int>(floor(xx));
-  m = m < 0 ? 0 : (m > d.n_tau - 2 ? d.n_tau - 2 : m);
+  m = m < 0 ? 0 : (m > n_tau - 2 ? n_tau - 2 : m);
   double w = xx - static_cast<double>(m);
   return sgn * ((1.0 - w) * tab[m] + w * tab[m + 1]);
+}
+__device__ __forceinline__ double g0_interp(const ChainDesc &d, int sec, int x, int y, double dtau) {
+  const auto tab = gview(d.g0[sec] + static_cast<int64_t>(gview(d.site_disp)[x * d.nc + y]) * d.n_tau);
+  return interp_table(tab, d.beta, d.inv_h, d.n_tau, dtau);
 }
 
 

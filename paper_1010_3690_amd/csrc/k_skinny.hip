@@ -218,8 +218,10 @@ __device__ __forceinline__ void skinny_item(AF afn, BF bfn, OF out, int M, int K
   lds_barrier();   // red is reused by the next item
 }
 
+// Inlined into each kernel: as a function of its own (kind 4 is called from two
+// kernels) its lambdas and operand arrays would live in scratch memory.
 template <typename T, int MODE, int NRT, int KIND>
-__device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int local, double *red) {
+__device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int local, double *red) {
   const int lane = threadIdx.x & 63, lr = lane & 15;
   const int n = st.n, par = st.parity;
   if constexpr (KIND == kSkPrep) {
@@ -342,8 +344,9 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
     };
     if constexpr (MODE == kModeSplitK) {
       // few chains: gL from its table (k_meas_gL)
-      const auto gL = gview(d.gL[sec] + static_cast<size_t>(m0) * d.ld);
-      auto afn = [=](int m, int l) { return gL[static_cast<size_t>(m) * d.ld + l]; };
+      const int ld = d.ld;
+      const auto gL = gview(d.gL[sec] + static_cast<size_t>(m0) * ld);
+      auto afn = [=](int m, int l) { return gL[static_cast<size_t>(m) * ld + l]; };
       skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, nc, c0, red);
     } else {
       // many chains: gL_{(j, x), l} = G0_{x x_l}(tau_j - tau_l) (e^{V_l} - 1)
@@ -358,8 +361,15 @@ __device__ void skinny_dispatch(const ChainDesc &d, const ChainState &st, int lo
       static_assert(NRT == 1, "one row tile per G item");
       const int mm = m0 + (lr < M ? lr : 0), jr = mm / nc, xr = mm - jr * nc;
       const double tjr = jr == 0 ? 0.0 : (static_cast<double>(jr - 1) + 0.5) * dt;
+      // the functor captures the table parameters, not the chain descriptor (a
+      // copy of which would sit in scratch memory)
+      const auto g0s = gview(d.g0[sec]);
+      const auto sdrow = gview(d.site_disp) + xr * nc;
+      const int ntau = d.n_tau;
+      const double beta = d.beta, inv_h = d.inv_h;
       auto afn = [=](int, int l) {
-        return g0_interp(d, sec, xr, site[l], tjr - tau[l]) * (ev[s0[l] + 2] - 1.0);
+        const auto tab = g0s + static_cast<int64_t>(sdrow[site[l]]) * ntau;
+        return interp_table(tab, beta, inv_h, ntau, tjr - tau[l]) * (ev[s0[l] + 2] - 1.0);
       };
       skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, nc, c0, red);
     }
