@@ -269,6 +269,14 @@ size_t layout(const ctaux_model *models, int32_t n_chains, const ctaux_opts *o, 
       // gL as a table only where the measurement uses one (batches of fewer than 8 chains)
       d.gL[s] = n_chains < 8 ? cv.take<double>(static_cast<size_t>(o->n_tau_out + 1) * nc * ld) : nullptr;
     }
+    {
+      // time-ordered vertex records of the measurement (batches of 8 chains or more)
+      const size_t nm = n_chains >= 8 ? static_cast<size_t>(n_cap) : 1;
+      d.mpos = cv.take<int32_t>(nm);
+      d.mtau = cv.take<double>(nm);
+      d.msite = cv.take<int32_t>(nm);
+      d.mfac = cv.take<double>(2 * nm);
+    }
     d.P = cv.take<int32_t>(kcap);
     d.map = cv.take<int32_t>(n_cap + kmax);
     d.obs_len = 8 + 2 * m.n_disp * o->n_tau_out;

@@ -92,6 +92,13 @@ struct ChainDesc {
   double *log_R;           // [log_cap]
   // measurement of batches of fewer than 8 chains (null otherwise)
   double *gL[2];           // [nc*(n_out+1)][ld]  G0_{x x_l}(tau_j - tau_l)(e^{V_l} - 1), row (j, x)
+  // measurement of batches of 8 chains or more: vertices in order of their time
+  // (stable by 128 time buckets), so that the interpolations of gL for
+  // consecutive vertices read neighbouring table entries
+  int32_t *mpos;           // [n_cap] position of vertex l in that order
+  double *mtau;            // [n_cap] tau of the vertex at each position
+  int32_t *msite;          // [n_cap] its site
+  double *mfac;            // [n_cap] e^{V} - 1 of its sector 0 and 1 ([2][n_cap])
   // pair proposals (Sec. IV B; the fields above keep their offsets without them)
   double p_pair;           // pair insertions and removals, p_pair / 2 each
   int32_t *pspin2;         // [kmax] spin of a pair insertion's second vertex

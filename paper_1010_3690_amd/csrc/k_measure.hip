@@ -66,6 +66,61 @@ __global__ __launch_bounds__(256) void k_meas_gL(const ChainDesc *descs, const C
   }
 }
 
+// Time order of the vertices for the measurement of many chains (one workgroup
+// per chain): a stable sort into 128 buckets of tau (ascending index within a
+// bucket, so the order does not depend on thread timing); records the position
+// of every vertex and, per position, its tau, site and e^{V} - 1 of both
+// sectors.  The G product then interpolates consecutive vertices from
+// neighbouring table entries.
+constexpr int kTauBuckets = 128;
+__global__ __launch_bounds__(256) void k_meas_tsort(const ChainDesc *descs, const ChainState *states) {
+  __shared__ int cnt[kTauBuckets], run[kTauBuckets], chunk_b[256];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const ChainDesc &d = descs[c];
+  const ChainState &st = states[c];
+  if (!st.active || !st.meas_now) return;
+  const int n = st.n, par = st.parity;
+  const auto tau = gview(d.tau[par]);
+  const auto site = gview(d.site[par]), s0 = gview(d.s0[par]);
+  const double scale = kTauBuckets / d.beta;
+  auto bucket = [&](int i) { return min(kTauBuckets - 1, static_cast<int>(tau[i] * scale)); };
+  for (int b = tid; b < kTauBuckets; b += 256) cnt[b] = 0;
+  __syncthreads();
+  for (int i = tid; i < n; i += 256) atomicAdd(&cnt[bucket(i)], 1);   // integer counts: any order
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int b = 0; b < kTauBuckets; ++b) {
+      run[b] = acc;
+      acc += cnt[b];
+    }
+  }
+  __syncthreads();
+  for (int base = 0; base < n; base += 256) {
+    const int i = base + tid;
+    const int bi = i < n ? bucket(i) : -1;
+    chunk_b[tid] = bi;
+    __syncthreads();
+    if (i < n) {
+      int r = 0;
+      for (int j = 0; j < tid; ++j) r += chunk_b[j] == bi;
+      const int pos = run[bi] + r;
+      gview_w(d.mpos)[i] = pos;
+      gview_w(d.mtau)[pos] = tau[i];
+      gview_w(d.msite)[pos] = site[i];
+      gview_w(d.mfac)[pos] = gview(d.evd[0])[s0[i] + 2] - 1.0;
+      gview_w(d.mfac)[d.n_cap + pos] = gview(d.evd[1])[s0[i] + 2] - 1.0;
+    }
+    __syncthreads();
+    if (tid < kTauBuckets) {
+      int add = 0;
+      for (int j = 0; j < 256; ++j) add += chunk_b[j] == tid;
+      run[tid] += add;
+    }
+    __syncthreads();
+  }
+}
+
 // Accumulate the observables of one measurement (one workgroup per chain).
 __global__ __launch_bounds__(256) void k_meas_acc(const ChainDesc *descs, const ChainState *states) {
   const int c = blockIdx.x;
@@ -407,6 +462,8 @@ void launch_measure(const Batch &b, hipStream_t s) {
   if (b.n_chains < 8)
     hipLaunchKernelGGL(k_meas_gL, chain_grid(b), dim3(256), 0, s, b.d_desc, b.d_mstate, b.n_chains,
                        chain_grid_arg(b));
+  else
+    hipLaunchKernelGGL(k_meas_tsort, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);
   launch_skinny(b, s, 2);   // W = N gR
   launch_skinny(b, s, 3);   // Gxy = G0 + gL W, gL_{(x,tau), l} = G0_{x x_l}(tau - tau_l)(e^{V_l} - 1)
   hipLaunchKernelGGL(k_meas_acc, dim3(b.n_chains), dim3(256), 0, s, b.d_desc, b.d_mstate);

@@ -318,8 +318,15 @@ __device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainS
       const double v = static_cast<double>(N[static_cast<size_t>(cc0) * ld + k]);
       return cok ? v : 0.0;
     };
-    auto out = [=](int m, int cc, double v) { W[static_cast<size_t>(cc) * nc + m] = v; };
-    skinny_item<MODE, NRT, 0, true>(afn, bfn, out, nc, n, n, c0, red);
+    if constexpr (MODE == kModeWave) {
+      // many chains: row l of W at the time-ordered position of vertex l
+      const auto pos = gview(d.mpos);
+      auto out = [=](int m, int cc, double v) { W[static_cast<size_t>(pos[cc]) * nc + m] = v; };
+      skinny_item<MODE, NRT, 0, true>(afn, bfn, out, nc, n, n, c0, red);
+    } else {
+      auto out = [=](int m, int cc, double v) { W[static_cast<size_t>(cc) * nc + m] = v; };
+      skinny_item<MODE, NRT, 0, true>(afn, bfn, out, nc, n, n, c0, red);
+    }
   } else {
     // Gxy: rows m = j*nc + x (j = 0: tau = 0+, j >= 1: tau_{j-1}); item = 16*kMeasGRt rows x 16 columns y
     const int nc = d.nc, Mtot = nc * (d.n_out + 1), rows = 16 * kMeasGRt;
@@ -352,9 +359,9 @@ __device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainS
       // many chains: gL_{(j, x), l} = G0_{x x_l}(tau_j - tau_l) (e^{V_l} - 1)
       // interpolated where the product needs it (no table of (n_out + 1) nc n
       // entries per sector written and read back)
-      const auto tau = gview(d.tau[par]);
-      const auto site = gview(d.site[par]), s0 = gview(d.s0[par]);
-      const auto ev = gview(d.evd[sec]);
+      // the sum over vertices runs in time order (k_meas_tsort; W is stored in it)
+      const auto mtau = gview(d.mtau), mfac = gview(d.mfac + sec * d.n_cap);
+      const auto msite = gview(d.msite);
       // one row tile: lane l supplies row l % 16 for every k (wave_mma_kv), so its
       // output time and site are fixed for the item and computed once here (a
       // masked row beyond M takes any in-range values)
@@ -367,9 +374,9 @@ __device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainS
       const auto sdrow = gview(d.site_disp) + xr * nc;
       const int ntau = d.n_tau;
       const double beta = d.beta, inv_h = d.inv_h;
-      auto afn = [=](int, int l) {
-        const auto tab = g0s + static_cast<int64_t>(sdrow[site[l]]) * ntau;
-        return interp_table(tab, beta, inv_h, ntau, tjr - tau[l]) * (ev[s0[l] + 2] - 1.0);
+      auto afn = [=](int, int k) {
+        const auto tab = g0s + static_cast<int64_t>(sdrow[msite[k]]) * ntau;
+        return interp_table(tab, beta, inv_h, ntau, tjr - mtau[k]) * mfac[k];
       };
       skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, nc, c0, red);
     }
