@@ -527,37 +527,81 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
           const unsigned long long hit = __ballot(hitl);
           if (hit) p = n + 64 * wsel + __ffsll(static_cast<long long>(hit)) - 1;
         }
-        if (p < 0 || p >= n + next_cand || scur[p] == 0) {   // cannot happen unless bookkeeping is broken
+        if (p < 0 || p >= n + next_cand) {   // cannot happen unless bookkeeping is broken
           why = 2;
           break;
         }
-        s_old = scur[p];
-        s_new = (type == 1) ? 0 : -s_old;
       }
 
-      // prefactor of the acceptance ratio (Eq. insprob), computed while the
-      // gathers below are in flight
-      fpre = (type == 0) ? Kc / static_cast<double>(ncur + 1)
-                         : (type == 1 ? static_cast<double>(ncur) / Kc : 1.0);
+      // The gathers go out first; the spins, the liveness check and the
+      // prefactor are worked out while they are in flight.
       double gh0 = 0.0, gh1 = 0.0, dp0 = 1.0, dp1 = 1.0;
-      if (!skip && !gz) {
+      double raw_s, raw_w;   // set (and read) only on the path with gathers
+      const bool gath = !skip && !gz;
+      if (gath) {
         if (type != 0) {
           const unsigned long long hit = __ballot(lane < ka && myP == p);
-          if (hit) {
-            rp = __ffsll(static_cast<long long>(hit)) - 1;
-            break;   // a repeated change: handled after this loop
+          if (hit) rp = __ffsll(static_cast<long long>(hit)) - 1;   // a repeated change: handled after this loop
+        }
+        if (rp < 0) {
+          // ---- issue the gathers: lane b < k_a takes s_b = G(P_b, p) and
+          // w_b = G(p, P_b), lane 63 (never a slot while proposing) G_pp ----
+          if constexpr (std::is_same<T, double>::value) {
+            // every lane loads (lanes past k_a other than 63 take G_pp and drop
+            // it): with i = P_b (or p) and j = p, the four blocks of the
+            // augmented G are N[i][j], Rt[i-n][j], YT[j-n][i] and Gnn[i-n][j-n];
+            // p decides (for the whole wave) which pair of blocks a gather
+            // reads, i < n (per lane) which of the two
+            const int gi = (lane < ka) ? myP : p;
+            const bool ic = gi < n;
+            const unsigned gl = static_cast<unsigned>(ic ? gi : gi - n);
+            std::remove_const_t<decltype(Rts)> sb0, sb1, wb0, wb1;
+            unsigned sm0, sm1, wm1;
+            if (p < n) {
+              sb0 = Nsec + p;                                    // N[i][p]
+              sb1 = Rts + p;                                     // Rt[i-n][p]
+              sm0 = ld;
+              sm1 = ld;
+              wb0 = Nsec + static_cast<size_t>(p) * ld;          // N[p][i]
+              wb1 = YTs + p;                                     // YT[i-n][p]
+              wm1 = ld;
+            } else {
+              sb0 = YTs + static_cast<size_t>(p - n) * ld;       // YT[p-n][i]
+              sb1 = Gnns + (p - n);                              // Gnn[i-n][p-n]
+              sm0 = 1;
+              sm1 = kmax;
+              wb0 = Rts + static_cast<size_t>(p - n) * ld;       // Rt[p-n][i]
+              wb1 = Gnns + static_cast<size_t>(p - n) * kmax;    // Gnn[p-n][i-n]
+              wm1 = 1;
+            }
+            raw_s = *((ic ? sb0 : sb1) + static_cast<uint64_t>(gl) * (ic ? sm0 : sm1));
+            raw_w = *((ic ? wb0 : wb1) + static_cast<uint64_t>(gl) * (ic ? 1u : wm1));
+          } else {
+            int si = -1, sj = -1, wi = -1, wj = -1;
+            if (lane < ka) {
+              si = myP; sj = p; wi = p; wj = myP;
+            } else if (lane == 63) {
+              si = p; sj = p;
+            }
+            raw_s = (si >= 0) ? gat(si, sj) : 0.0;
+            raw_w = (wi >= 0) ? gat(wi, wj) : 0.0;
           }
         }
-        // ---- issue the gathers: lane b < k_a takes s_b = G(P_b, p) and
-        // w_b = G(p, P_b), lane 63 (never a slot while proposing) takes G_pp ----
-        int si = -1, sj = -1, wi = -1, wj = -1;
-        if (lane < ka) {
-          si = myP; sj = p; wi = p; wj = myP;
-        } else if (lane == 63) {
-          si = p; sj = p;
+      }
+      if (type != 0 && !skip) {
+        const int sc = scur[p];
+        if (sc == 0) {   // cannot happen unless bookkeeping is broken
+          why = 2;
+          break;
         }
-        const double raw_s = (si >= 0) ? gat(si, sj) : 0.0;
-        const double raw_w = (wi >= 0) ? gat(wi, wj) : 0.0;
+        s_old = sc;
+        s_new = (type == 1) ? 0 : -s_old;
+      }
+      // prefactor of the acceptance ratio (Eq. insprob)
+      fpre = (type == 0) ? Kc / static_cast<double>(ncur + 1)
+                         : (type == 1 ? static_cast<double>(ncur) / Kc : 1.0);
+      if (rp >= 0) break;
+      if (gath) {
         // outside P an old vertex still has its block-start spin, a candidate 0
         const int s0p = s_old;
         gh0 = sh_ev[0][s_new - s0p + 2] - sh_ev[0][s_old - s0p + 2];
