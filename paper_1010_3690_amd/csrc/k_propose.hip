@@ -40,7 +40,7 @@
 // waves 1 and 3 its columns (lane b: column b), zero beyond k_a.  Every wave
 // gathers both s and w of its sector (one load each per lane, in flight
 // together); a row wave forms v = X s and beta~ = d - w.v, a column wave
-// u = X^T w, each from registers and an LDS broadcast of its own vector.  One
+// u = X^T w, each from registers and its own vector read across lanes.  One
 // barrier per proposal publishes the two sectors' beta~ (and v, u for the
 // growth); it orders LDS only, so the global stores of the loop (the recorded
 // Gamma entries, the decision log) stay in flight until the full barrier
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
   double xr[kMaxKcap];
 #pragma unroll
   for (int i = 0; i < kMaxKcap; ++i) xr[i] = 0.0;
-  double *bcast = (role == 0 ? vs : vw) + sec * kp;   // this wave's s (rows) or w (columns)
+  double *bcast = (role == 0 ? vs : vw) + sec * kp;   // this wave's vector buffer (pair proposals)
   double myv = 0.0;   // v_a (rows) or u_b (columns) of the last proposal with gathers
   int q = 0;          // parity of the proposals with gathers
   int pq = 0;         // parity of the proposal whose growth is owed
@@ -234,17 +234,24 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
       for (int i = 0; i < 8; ++i) xr[c + i] = fma(f, o[i], xr[c + i]);
     });
   };
-  // row a . s (rows) or column b . w (columns) over k entries: four
-  // accumulators, the broadcast vector read from LDS
-  auto matvec = [&](int k) -> double {
+  // row a . s (rows) or column b . w (columns) over k entries, four
+  // accumulators; the vector is held by the wave itself, entry b in lane b, and
+  // read with readlane, eight entries at a time (no LDS round trip)
+  auto matvec_lanes = [&](double vec, int k) -> double {
     double a4[4] = {0.0, 0.0, 0.0, 0.0};
-    chunks(bcast, k, [&](int c, const double *o) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) a4[i & 3] = fma(xr[c + i], o[i], a4[i & 3]);
-    });
+    for (int c = 0; c < kMaxKcap; c += 8) {
+      if (c < k) {
+        double o[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = readlane_f64(vec, c + i);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a4[i & 3] = fma(xr[c + i], o[i], a4[i & 3]);
+      }
+    }
     return (a4[0] + a4[1]) + (a4[2] + a4[3]);
   };
-  // the same from another LDS vector, and the rank-2 growth of a pair:
+  // the same from an LDS vector, and the rank-2 growth of a pair:
   // X_ab += f1 o1_b + f2 o2_b over the first nent entries
   auto matvec_from = [&](const double *src, int k) -> double {
     double a4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -617,7 +624,6 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         const double igd = sh_igd[sec][(s0p + 1) * 9 + (s_old + 1) * 3 + (s_new + 1)];   // 1 / (gh D_p)
         const double dd = raw_s - 1.0 - igd;   // d, in lane 63
         const double sv = (lane < ka) ? raw_s : 0.0, wv = (lane < ka) ? raw_w : 0.0;
-        bcast[lane] = (role == 0) ? sv : wv;
         // record row / column ka of Gamma~ for the inversion at block end (a
         // rejected proposal's entries are overwritten by the next one)
         if (role == 0) {
@@ -626,8 +632,7 @@ __global__ __launch_bounds__(256) void k_propose(const ChainDesc *descs, ChainSt
         } else if (lane < ka) {
           gam[ka * kcap + lane] = wv;
         }
-        __builtin_amdgcn_wave_barrier();   // the wave's LDS stores before its loads
-        myv = matvec(ka);
+        myv = matvec_lanes((role == 0) ? sv : wv, ka);
         if (role == 0) {
           const double beta = readlane_f64(dd, 63) - wave_sum_dpp(wv * myv);
           if (lane == 0) sh_beta[q][sec] = beta;
