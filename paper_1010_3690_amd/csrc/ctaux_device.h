@@ -153,6 +153,29 @@ __device__ __forceinline__ ChainBlock chain_block(int xcd_g) {
   return ChainBlock{(b & 7) + 8 * (slot / xcd_g), slot % xcd_g, xcd_g};
 }
 
+// A worker's share of the items of a persistent grid (workers: the waves of a
+// workgroup in wave mode, else the workgroup itself).  Workgroups are handed to
+// the eight XCDs round-robin; with a grid of 8 G workgroups the items are dealt
+// to the XCDs in chunks of kItemChunk consecutive items (chunk c to XCD c % 8),
+// so that neighbouring items, which share a chain's operands and tables, meet
+// in one L2 while chains of uneven cost still spread over all XCDs.  The
+// worker's k-th item is item(k) for k = first, first + stride, ...; items grow
+// with k, so a loop stops at the first item(k) >= total.  Another grid size,
+// or chunked = false, takes items b * workers + w + k * G * workers.
+constexpr int kItemChunk = 32;
+struct ItemSpan {
+  int first, stride, x;   // x < 0: no XCD mapping
+  __device__ int item(int k) const {
+    if (x < 0) return k;
+    return ((k / kItemChunk) * 8 + x) * kItemChunk + (k % kItemChunk);
+  }
+};
+__device__ __forceinline__ ItemSpan xcd_items(int workers, int w, bool chunked = true) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if ((G & 7) || !chunked) return ItemSpan{b * workers + w, G * workers, -1};
+  return ItemSpan{(b >> 3) * workers + w, (G >> 3) * workers, b & 7};
+}
+
 // Bare propagator G0_{xy}(dtau): linear interpolation on the uniform grid,
 // dtau in (-beta, beta); dtau < 0 uses G0(dtau) = -G0(dtau + beta); dtau = 0
 // reads the 0+ entry.

@@ -71,7 +71,10 @@ __global__ __launch_bounds__(256) void k_ref_gemm(const ChainDesc *descs, const 
   });
   const int total = pre[n_items];
   const int wr = wave >> 1, wc = wave & 1, lr = lane & 15, lk = lane >> 4;
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+  const ItemSpan span = xcd_items(1, 0);   // neighbouring tiles on one XCD
+  for (int k = span.first;; k += span.stride) {
+    const int t = span.item(k);
+    if (t >= total) break;
     int lo = 0, hi = n_items;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;

@@ -393,9 +393,13 @@ __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, c
   const int wave = threadIdx.x >> 6;
   block_prefix<kSkThreads>(n_chains, pre, [&](int cc) { return skinny_items(descs[cc], states[cc], KIND); });
   const int total = pre[n_chains];
-  const int first = (MODE == kModeWave) ? blockIdx.x * kSkWaves + wave : blockIdx.x;
-  const int stride = (MODE == kModeWave) ? gridDim.x * kSkWaves : gridDim.x;
-  for (int item = first; item < total; item += stride) {
+  // the preparation products' items are dealt one by one (chunks cost them more
+  // in balance than they save in L2 hits)
+  constexpr bool chunked = KIND != kSkPrep;
+  const ItemSpan span = (MODE == kModeWave) ? xcd_items(kSkWaves, wave, chunked) : xcd_items(1, 0, chunked);
+  for (int k = span.first;; k += span.stride) {
+    const int item = span.item(k);
+    if (item >= total) break;
     int lo = 0, hi = n_chains;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;

@@ -96,7 +96,10 @@ __global__ __launch_bounds__(256) void k_rankk(const ChainDesc *descs, const Cha
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+  const ItemSpan span = xcd_items(1, 0);   // neighbouring tiles on one XCD
+  for (int k = span.first;; k += span.stride) {
+    const int t = span.item(k);
+    if (t >= total) break;
     // chain owning tile t (prefix is non-decreasing)
     int lo = 0, hi = n_chains;
     while (hi - lo > 1) {
