@@ -35,18 +35,29 @@ constexpr int kPrepRows = 32;             // rows (candidates) per preparation i
 enum SkinnyKind : int { kSkPrep = 0, kSkGnn = 1, kSkMeasW = 2, kSkMeasG = 3, kSkAsmB = 4 };
 enum SkinnyMode : int { kModeSplitK = 0, kModeWave = 1 };
 
-// Work items of one chain for a kind (0 when the chain does not take part).
-__device__ __forceinline__ int skinny_items(const ChainDesc &d, const ChainState &st, int kind) {
+// Column tiles of 16 per item.  In wave mode the preparation and measurement
+// products with up to two row tiles take two, so that each A operand loaded
+// (candidate rows, gR, or the interpolated gL) serves two MFMA tiles; split-K
+// items keep one (a few chains need the items for parallelism), and so do more
+// row tiles (their operand registers would spill).
+template <int MODE, int KIND, int NRT>
+constexpr int skinny_cols() {
+  return (MODE == kModeWave && NRT <= 2 && (KIND == kSkPrep || KIND == kSkMeasW || KIND == kSkMeasG)) ? 2 : 1;
+}
+
+// Work items of one chain for a kind (0 when the chain does not take part);
+// cols: column tiles of 16 per item.
+__device__ __forceinline__ int skinny_items(const ChainDesc &d, const ChainState &st, int kind, int cols = 1) {
   if (!st.active) return 0;
-  const int n = st.n;
+  const int n = st.n, w = 16 * cols;
   const int rg = (st.k_ins + kPrepRows - 1) / kPrepRows;   // row groups of the candidates
-  if (kind == kSkPrep) return st.k_ins > 0 ? 4 * rg * ((n + 15) >> 4) : 0;
+  if (kind == kSkPrep) return st.k_ins > 0 ? 4 * rg * ((n + w - 1) / w) : 0;
   if (kind == kSkGnn) return st.k_ins > 0 ? 2 * rg * ((st.k_ins + 15) >> 4) : 0;
   if (kind == kSkAsmB) return (st.k_a > 0 && st.n_new > 0) ? 2 * ((st.n_new + 15) >> 4) : 0;
   if (!st.meas_now) return 0;
-  if (kind == kSkMeasW) return 2 * ((n + 15) >> 4);
+  if (kind == kSkMeasW) return 2 * ((n + w - 1) / w);
   const int mtot = d.nc * (d.n_out + 1), rows = 16 * kMeasGRt;
-  return 2 * ((mtot + rows - 1) / rows) * ((d.nc + 15) >> 4);
+  return 2 * ((mtot + rows - 1) / rows) * ((d.nc + w - 1) / w);
 }
 
 // acc[r] += A(16r + m, k) B(k, c) for k in [k_begin, k_end), this wave only.
@@ -163,6 +174,101 @@ __device__ __forceinline__ void wave_mma_kv(AF afn, BF bfn, int M, int k_begin, 
   }
 }
 
+// As wave_mma_kv over k in [0, K) for NCT column tiles of 16 (the lane's column
+// of tile t is c0 + 16 t + l % 16): each A operand loaded serves NCT MFMAs.
+// bfn(k, t) returns B(k, c) for the lane's column of tile t (0 outside).
+template <int NRT, int U, int NCT, typename AF, typename BF>
+__device__ __forceinline__ void wave_mma_kv_cols(AF afn, BF bfn, int M, int K, v4d (&acc)[NRT][NCT]) {
+  static_assert(U % 4 == 0, "whole groups of four k-steps");
+  constexpr int G = U / 4;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  double b0[G][4][NCT], a0[G][4][NRT], b1[G][4][NCT], a1[G][4][NRT];
+  auto load = [&](double (&bv)[G][4][NCT], double (&av)[G][4][NRT], int k0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int kb = k0 + 16 * g + 4 * lk;
+      if (kb + 3 < K) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int t = 0; t < NCT; ++t) bv[g][i][t] = bfn(kb + i, t);
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) {
+          const int m = r * 16 + lr;
+          const bool mok = m < M;
+          const int mc = mok ? m : 0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double v = afn(mc, kb + i);
+            av[g][i][r] = mok ? v : 0.0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = kb + i;
+          const bool kok = k < K;
+#pragma unroll
+          for (int t = 0; t < NCT; ++t) bv[g][i][t] = kok ? bfn(k, t) : 0.0;
+#pragma unroll
+          for (int r = 0; r < NRT; ++r) {
+            const int m = r * 16 + lr;
+            av[g][i][r] = (kok && m < M) ? afn(m, k) : 0.0;
+          }
+        }
+      }
+    }
+  };
+  auto mma = [&](const double (&bv)[G][4][NCT], const double (&av)[G][4][NRT]) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < NRT; ++r)
+#pragma unroll
+          for (int t = 0; t < NCT; ++t)
+            acc[r][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g][i][r], bv[g][i][t], acc[r][t], 0, 0, 0);
+  };
+  constexpr int S = 16 * G;
+  int k0 = 0;
+  if (K <= 0) return;
+  load(b0, a0, k0);
+  while (true) {
+    load(b1, a1, k0 + S);
+    mma(b0, a0);
+    k0 += S;
+    if (k0 >= K) break;
+    load(b0, a0, k0 + S);
+    mma(b1, a1);
+    k0 += S;
+    if (k0 >= K) break;
+  }
+}
+
+// One wave-mode item of NCT column tiles: C rows [0, M), columns [c0, c0 + 16 NCT),
+// handed to out(m, c, value); operands stored along k (wave_mma_kv_cols).
+template <int NRT, int NCT, typename AF, typename BF, typename OF>
+__device__ __forceinline__ void skinny_item_cols(AF afn, BF bfn, OF out, int M, int K, int Ncols, int c0) {
+  v4d acc[NRT][NCT];
+#pragma unroll
+  for (int r = 0; r < NRT; ++r)
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) acc[r][t] = v4d{0.0, 0.0, 0.0, 0.0};
+  wave_mma_kv_cols<NRT, 4, NCT>(afn, bfn, M, K, acc);
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < NRT; ++r)
+#pragma unroll
+    for (int t = 0; t < NCT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = r * 16 + (lane >> 4) + 4 * q;   // FP64 16x16x4 accumulator: row l/16 + 4q
+        const int cc = c0 + 16 * t + (lane & 15);
+        if (m < M && cc < Ncols) out(m, cc, acc[r][t][q]);
+      }
+}
+
 // One item: C tile rows [0, M), columns [c0, c0 + 16), handed to out(m, c, value).
 // UO overrides the k-steps per batch (0: the default for NRT).
 // KV: operands stored along k, loaded four k at a time (wave_mma_kv; up to four
@@ -226,10 +332,11 @@ __device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainS
   const int n = st.n, par = st.parity;
   if constexpr (KIND == kSkPrep) {
     // per row group of candidates: items 0..2nt-1 YT[sec] = ZT N^T, 2nt..4nt-1 Rt[sec] = X N
-    const int nt = (n + 15) >> 4;
+    constexpr int NC = skinny_cols<MODE, KIND, NRT>();
+    const int nt = (n + 16 * NC - 1) / (16 * NC);
     const int grp = local / (4 * nt), r0 = grp * kPrepRows;
     const int loc2 = local - grp * 4 * nt;
-    const int job = loc2 / nt, c0 = (loc2 - job * nt) * 16, sec = job & 1, ld = d.ld;
+    const int job = loc2 / nt, c0 = (loc2 - job * nt) * 16 * NC, sec = job & 1, ld = d.ld;
     const auto A = gview((job < 2) ? d.ZT[sec] : d.X[sec]);
     const int rt = (d.kmax + 15) >> 4;
     const auto N = gview(static_cast<const T *>(d.N[par][sec]));
@@ -240,7 +347,24 @@ __device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainS
     const int cc0 = cok ? c : 0;   // in-bounds address; the value is masked
     auto afn = [=](int m, int k) { return A[cand_offset(r0 + m, k, rt)]; };
     auto out = [=](int m, int cc, double v) { C[static_cast<size_t>(m) * ld + cc] = v; };
-    if (job < 2) {
+    if constexpr (NC > 1) {
+      // column tile t: column c0 + 16 t + l % 16 (clamped in-bounds, masked)
+      if (job < 2) {
+        auto bfn = [=](int k, int t) {
+          const int ct = c + 16 * t, cs = ct < n ? ct : 0;
+          const double v = static_cast<double>(N[static_cast<size_t>(cs) * ld + k]);
+          return ct < n ? v : 0.0;
+        };
+        skinny_item_cols<NRT, NC>(afn, bfn, out, M, n, n, c0);
+      } else {
+        auto bfn = [=](int k, int t) {
+          const int ct = c + 16 * t, cs = ct < n ? ct : 0;
+          const double v = static_cast<double>(N[static_cast<size_t>(k) * ld + cs]);
+          return ct < n ? v : 0.0;
+        };
+        skinny_item_cols<NRT, NC>(afn, bfn, out, M, n, n, c0);
+      }
+    } else if (job < 2) {
       auto bfn = [=](int k) {
         const double v = static_cast<double>(N[static_cast<size_t>(cc0) * ld + k]);
         return cok ? v : 0.0;
@@ -304,8 +428,9 @@ __device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainS
     skinny_item<MODE, NRT, UB>(afn, bfn, out, kpad, ka, np, c0, red);
   } else if constexpr (KIND == kSkMeasW) {
     // W[sec] = N gR as (gRT N^T)^T: C[l][y]
-    const int nt = (n + 15) >> 4;
-    const int sec = local / nt, c0 = (local - sec * nt) * 16, ld = d.ld, nc = d.nc;
+    constexpr int NC = skinny_cols<MODE, KIND, NRT>();
+    const int nt = (n + 16 * NC - 1) / (16 * NC);
+    const int sec = local / nt, c0 = (local - sec * nt) * 16 * NC, ld = d.ld, nc = d.nc;
     const auto gR = gview(d.gR[sec]);
     const auto N = gview(static_cast<const T *>(d.N[par][sec]));
     const auto W = gview_w(d.W[sec]);
@@ -322,17 +447,27 @@ __device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainS
       // many chains: row l of W at the time-ordered position of vertex l
       const auto pos = gview(d.mpos);
       auto out = [=](int m, int cc, double v) { W[static_cast<size_t>(pos[cc]) * nc + m] = v; };
-      skinny_item<MODE, NRT, 0, true>(afn, bfn, out, nc, n, n, c0, red);
+      if constexpr (NC > 1) {
+        auto bfn2 = [=](int k, int t) {
+          const int ct = c + 16 * t, cs = ct < n ? ct : 0;
+          const double v = static_cast<double>(N[static_cast<size_t>(cs) * ld + k]);
+          return ct < n ? v : 0.0;
+        };
+        skinny_item_cols<NRT, NC>(afn, bfn2, out, nc, n, n, c0);
+      } else {
+        skinny_item<MODE, NRT, 0, true>(afn, bfn, out, nc, n, n, c0, red);
+      }
     } else {
       auto out = [=](int m, int cc, double v) { W[static_cast<size_t>(cc) * nc + m] = v; };
       skinny_item<MODE, NRT, 0, true>(afn, bfn, out, nc, n, n, c0, red);
     }
   } else {
     // Gxy: rows m = j*nc + x (j = 0: tau = 0+, j >= 1: tau_{j-1}); item = 16*kMeasGRt rows x 16 columns y
+    constexpr int NC = skinny_cols<MODE, KIND, NRT>();
     const int nc = d.nc, Mtot = nc * (d.n_out + 1), rows = 16 * kMeasGRt;
-    const int ngroups = (Mtot + rows - 1) / rows, ntiles = (nc + 15) >> 4;
+    const int ngroups = (Mtot + rows - 1) / rows, ntiles = (nc + 16 * NC - 1) / (16 * NC);
     const int sec = local / (ngroups * ntiles), rem = local - sec * ngroups * ntiles;
-    const int g = rem / ntiles, c0 = (rem - g * ntiles) * 16;
+    const int g = rem / ntiles, c0 = (rem - g * ntiles) * 16 * NC;
     const int m0 = g * rows, M = min(rows, Mtot - m0);
     const auto W = gview(d.W[sec]);
     const double dt = d.beta / d.n_out;
@@ -378,7 +513,12 @@ __device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainS
         const auto tab = g0s + static_cast<int64_t>(sdrow[msite[k]]) * ntau;
         return interp_table(tab, beta, inv_h, ntau, tjr - mtau[k]) * mfac[k];
       };
-      skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, nc, c0, red);
+      auto bfn2 = [=](int l, int t) {
+        const int ct = c + 16 * t, cs = ct < nc ? ct : 0;
+        const double v = W[static_cast<size_t>(l) * nc + cs];
+        return ct < nc ? v : 0.0;
+      };
+      skinny_item_cols<NRT, NC>(afn, bfn2, out, M, n, nc, c0);
     }
   }
 }
@@ -391,7 +531,8 @@ __global__ __launch_bounds__(kSkThreads) void k_skinny(const ChainDesc *descs, c
   extern __shared__ int pre[];   // [n_chains + 1]
   __shared__ double red[NRT * 256];
   const int wave = threadIdx.x >> 6;
-  block_prefix<kSkThreads>(n_chains, pre, [&](int cc) { return skinny_items(descs[cc], states[cc], KIND); });
+  block_prefix<kSkThreads>(n_chains, pre,
+                           [&](int cc) { return skinny_items(descs[cc], states[cc], KIND, skinny_cols<MODE, KIND, NRT>()); });
   const int total = pre[n_chains];
   // the preparation products' items are dealt one by one (chunks cost them more
   // in balance than they save in L2 hits)
