@@ -35,14 +35,17 @@ constexpr int kPrepRows = 32;             // rows (candidates) per preparation i
 enum SkinnyKind : int { kSkPrep = 0, kSkGnn = 1, kSkMeasW = 2, kSkMeasG = 3, kSkAsmB = 4 };
 enum SkinnyMode : int { kModeSplitK = 0, kModeWave = 1 };
 
-// Column tiles of 16 per item.  In wave mode the preparation and measurement
-// products with up to two row tiles take two, so that each A operand loaded
-// (candidate rows, gR, or the interpolated gL) serves two MFMA tiles; split-K
+// Column tiles of 16 per item.  In wave mode the preparation (and G_nn) and
+// measurement products with up to two row tiles take two, so that each A operand
+// loaded (candidate rows, gR, or the interpolated gL) serves two MFMA tiles; split-K
 // items keep one (a few chains need the items for parallelism), and so do more
 // row tiles (their operand registers would spill).
 template <int MODE, int KIND, int NRT>
 constexpr int skinny_cols() {
-  return (MODE == kModeWave && NRT <= 2 && (KIND == kSkPrep || KIND == kSkMeasW || KIND == kSkMeasG)) ? 2 : 1;
+  return (MODE == kModeWave && NRT <= 2 &&
+          (KIND == kSkPrep || KIND == kSkGnn || KIND == kSkMeasW || KIND == kSkMeasG))
+             ? 2
+             : 1;
 }
 
 // Work items of one chain for a kind (0 when the chain does not take part);
@@ -52,7 +55,7 @@ __device__ __forceinline__ int skinny_items(const ChainDesc &d, const ChainState
   const int n = st.n, w = 16 * cols;
   const int rg = (st.k_ins + kPrepRows - 1) / kPrepRows;   // row groups of the candidates
   if (kind == kSkPrep) return st.k_ins > 0 ? 4 * rg * ((n + w - 1) / w) : 0;
-  if (kind == kSkGnn) return st.k_ins > 0 ? 2 * rg * ((st.k_ins + 15) >> 4) : 0;
+  if (kind == kSkGnn) return st.k_ins > 0 ? 2 * rg * ((st.k_ins + w - 1) / w) : 0;
   if (kind == kSkAsmB) return (st.k_a > 0 && st.n_new > 0) ? 2 * ((st.n_new + 15) >> 4) : 0;
   if (!st.meas_now) return 0;
   if (kind == kSkMeasW) return 2 * ((n + w - 1) / w);
@@ -379,10 +382,11 @@ __device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainS
     }
   } else if constexpr (KIND == kSkGnn) {
     // Gnn[sec] = X YT^T + G0nn (K = 0 still writes Gnn = G0nn), per row group
-    const int ki = st.k_ins, nt = (ki + 15) >> 4;
+    constexpr int NC = skinny_cols<MODE, KIND, NRT>();
+    const int ki = st.k_ins, nt = (ki + 16 * NC - 1) / (16 * NC);
     const int grp = local / (2 * nt), r0 = grp * kPrepRows;
     const int loc2 = local - grp * 2 * nt;
-    const int sec = loc2 / nt, c0 = (loc2 - sec * nt) * 16, ld = d.ld, km = d.kmax;
+    const int sec = loc2 / nt, c0 = (loc2 - sec * nt) * 16 * NC, ld = d.ld, km = d.kmax;
     const auto X = gview(d.X[sec]), YT = gview(d.YT[sec]);
     const int rt = (km + 15) >> 4;
     const auto G0nn = gview(d.G0nn[sec] + static_cast<size_t>(r0) * km);
@@ -399,7 +403,16 @@ __device__ __forceinline__ void skinny_dispatch(const ChainDesc &d, const ChainS
     auto out = [=](int m, int cc, double v) {
       Gnn[static_cast<size_t>(m) * km + cc] = v + G0nn[static_cast<size_t>(m) * km + cc];
     };
-    skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, ki, c0, red);
+    if constexpr (NC > 1) {
+      auto bfn2 = [=](int k, int t) {
+        const int ct = c + 16 * t, cs = ct < ki ? ct : 0;
+        const double v = YT[static_cast<size_t>(cs) * ld + k];
+        return ct < ki ? v : 0.0;
+      };
+      skinny_item_cols<NRT, NC>(afn, bfn2, out, M, n, ki, c0);
+    } else {
+      skinny_item<MODE, NRT, 0, true>(afn, bfn, out, M, n, ki, c0, red);
+    }
   } else if constexpr (KIND == kSkAsmB) {
     // Bc[sec] = Gamma~^{-1} N_a(P, map): rows a < kpad (zero beyond k_a), K = k_a
     const int np = st.n_new, ka = st.k_a, kpad = (ka + 7) & ~7, nt = (np + 15) >> 4;
