@@ -542,8 +542,8 @@ def main():
 
     def config5():
         from ctaux_inputs import dca_cubic
-        w5 = dca_cubic(beta=6.0, U=8.0, K=3500.0, n_tau=8192)
-        log("config5_fp32: 3D Nc = 100, 8 chains, order ~5000")
+        w5 = dca_cubic(beta=6.0, U=8.0, K=4300.0, n_tau=8192)
+        log("config5_fp32: 3D Nc = 100, 8 chains, order ~5000-6000")
         opts = _opts(ctaux, ctaux.CTAUX_FP32, n_cap=8192, k=128, recompute_every=32, n_tau_out=8,
                      drift_tol=mixed_tol)
         g5, d5, t5 = many_chains(ctaux, [w5] * 8, opts, 16, 200, 20)
