@@ -54,9 +54,9 @@ __global__ __launch_bounds__(256) void k_ref_build(const ChainDesc *descs, const
 }
 
 // C = alpha A B + diag I on 64x64 tiles, FP64 MFMA 16x16x4, K staged through LDS
-// in chunks of 32 with the next chunk's loads in flight during the current
+// in chunks of kGK with the next chunk's loads in flight during the current
 // chunk's MFMAs.  mode 0: R = I - M N;  mode 1: T = N R (into M's slot).
-constexpr int kGK = 32;
+constexpr int kGK = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void k_ref_gemm(const ChainDesc *descs, const ChainState *states,
                                                   const RefineItem *items, int n_items, double *pool, int mode) {
@@ -106,14 +106,15 @@ __global__ __launch_bounds__(256) void k_ref_gemm(const ChainDesc *descs, const 
     const int ldb = mode == 0 ? ldn : n;
     const auto C = gview_w(mode == 0 ? Rs : Ms);
     const double alpha = mode == 0 ? -1.0 : 1.0, diag = mode == 0 ? 1.0 : 0.0;
-    // staging: thread tid loads row tid/4 of the A chunk (8 consecutive k) and
-    // row tid/8 of the B chunk (8 consecutive columns)
-    const int ar = tid >> 2, ak = (tid & 3) * 8;
-    const int bk = tid >> 3, bc = (tid & 7) * 8;
-    double ra[8], rb[8];
+    // staging: thread tid loads row tid/4 of the A chunk (kGV consecutive k) and
+    // row tid/(64/kGV) of the B chunk (kGV consecutive columns)
+    constexpr int kGV = kGK / 4;
+    const int ar = tid >> 2, ak = (tid & 3) * kGV;
+    const int bk = tid / (64 / kGV), bc = (tid % (64 / kGV)) * kGV;
+    double ra[kGV], rb[kGV];
     auto load = [&](int k0) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < kGV; ++i) {
         const int r = r0 + ar, k = k0 + ak + i;
         ra[i] = (r < n && k < n) ? A[static_cast<size_t>(r) * lda + k] : 0.0;
         const int kb = k0 + bk, cc = c0 + bc + i;
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void k_ref_gemm(const ChainDesc *descs, const 
     };
     auto store = [&](int buf) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < kGV; ++i) {
         As[buf][ar][ak + i] = ra[i];
         Bs[buf][bk][bc + i] = rb[i];
       }
