@@ -9,9 +9,12 @@
 //   - the measurement (Sec. IV D): W = N gR, then G(x tau_j; y 0) = G0 + gL W
 //     (gL read from its table for a few chains, interpolated inside the
 //     product for many).
-// A work item is a tile of 16*NRT rows and 16 columns of one product of one
-// chain (NRT covers the largest row count the product can have in the batch); items of all chains are enumerated from a per-chain prefix that
-// every workgroup builds in LDS.  Two execution modes:
+// A work item is a tile of 16*NRT rows and 16 columns (two tiles of 16 for
+// some products in wave mode, skinny_cols) of one product of one chain (NRT
+// covers the largest row count the product can have in the batch); items of
+// all chains are enumerated from a per-chain prefix that every workgroup
+// builds in LDS, and dealt to the XCDs in chunks (xcd_items).  Two execution
+// modes:
 //   - split-K: the 8 waves of a workgroup share one item, each taking one
 //     contiguous eighth of K, and their partial tiles are summed in LDS in a
 //     fixed order (few chains with long K: keeps the GPU busy);
