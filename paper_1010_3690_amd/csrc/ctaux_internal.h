@@ -156,7 +156,7 @@ struct RefineItem {
   int64_t off;
 };
 int refine_slots(int precision);           // n x n scratch blocks per sector
-size_t refine_red_doubles(int n_items);    // partial sums for the drift of n_items chains
+size_t refine_red_doubles(int n_chains);   // partial sums for the drift of a batch of n_chains chains
 // pool doubles one chain of order n needs for a refinement (Newton slots of both
 // sectors, then the from-scratch elimination's scratch of both sectors)
 size_t refine_need_doubles(int n, int precision);

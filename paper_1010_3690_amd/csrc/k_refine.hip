@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_ref_apply(const ChainDesc *descs, const
 // (last_drift, max_drift, the drift_tol check); every pass leaves its drift in
 // pass_drift for the host's decision on one more step.
 __global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const RefineItem *items, int n_items,
-                             const double *red, int pass, int scratch) {
+                             const double *red, int nb, int pass, int scratch) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_items) return;
   const int c = items[q].chain;
@@ -220,8 +220,8 @@ __global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const R
   double drift = 0.0;
   for (int sec = 0; sec < 2; ++sec) {
     double a = 0.0, b = 0.0;
-    const double *r = red + (static_cast<size_t>(q) * 2 + sec) * kRefBlocks * 2;
-    for (int i = 0; i < kRefBlocks; ++i) {
+    const double *r = red + (static_cast<size_t>(q) * 2 + sec) * nb * 2;   // nb partials per sector
+    for (int i = 0; i < nb; ++i) {
       a += r[2 * i];
       b += r[2 * i + 1];
     }
@@ -257,20 +257,26 @@ size_t refine_need_doubles(int n, int precision) {
   return 2 * (static_cast<size_t>(refine_slots(precision)) * n * n + inv_scratch_doubles(n));
 }
 
-size_t refine_red_doubles(int n_items) { return static_cast<size_t>(n_items) * 2 * kRefBlocks * 2; }
+// Workgroups per chain of the elementwise kernels (the table build of M, the
+// update N + T with its partial sums, the from-scratch store): kRefBlocks for
+// batches of 8 chains or more; fewer chains take more, so that their n^2
+// entries spread over the GPU.
+static int elem_blocks(int n_chains) { return n_chains >= 8 ? kRefBlocks : (n_chains >= 2 ? 256 : 512); }
+
+size_t refine_red_doubles(int n_chains) { return static_cast<size_t>(n_chains) * 2 * elem_blocks(n_chains) * 2; }
 
 template <typename T>
 static void launch_group_t(const Batch &b, hipStream_t s, const RefineItem *items, int n_items, int pass) {
-  hipLaunchKernelGGL(k_ref_build<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
-                     b.r_pool);
+  const int nb = elem_blocks(b.n_chains);
+  hipLaunchKernelGGL(k_ref_build<T>, dim3(nb, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items, b.r_pool);
   const size_t lds = sizeof(int) * (n_items + 1);
   for (int mode = 0; mode < 2; ++mode)
     hipLaunchKernelGGL(k_ref_gemm<T>, dim3(b.n_cu * 2), dim3(256), lds, s, b.d_desc, b.d_state, items, n_items,
                        b.r_pool, mode);
-  hipLaunchKernelGGL(k_ref_apply<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
-                     b.r_pool, b.r_red);
+  hipLaunchKernelGGL(k_ref_apply<T>, dim3(nb, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items, b.r_pool,
+                     b.r_red);
   hipLaunchKernelGGL(k_ref_reduce, dim3((n_items + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items,
-                     b.r_red, pass, 0);
+                     b.r_red, nb, pass, 0);
 }
 
 // After the elimination: N <- M^{-1} in canonical order, N[i][j] = W[perm[i]][pos(j)]
@@ -317,13 +323,13 @@ __global__ __launch_bounds__(256) void k_ref_scratch_store(const ChainDesc *desc
 template <typename T>
 static void launch_scratch_t(const Batch &b, hipStream_t s, const RefineItem *items, const InvItem *inv, int n_items,
                              int n_max, int pass) {
-  hipLaunchKernelGGL(k_ref_build<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
-                     b.r_pool);
+  const int nb = elem_blocks(b.n_chains);
+  hipLaunchKernelGGL(k_ref_build<T>, dim3(nb, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items, b.r_pool);
   launch_invert(s, inv, 2 * n_items, n_max, b.n_cu);
-  hipLaunchKernelGGL(k_ref_scratch_store<T>, dim3(kRefBlocks, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items,
-                     inv, b.r_red);
+  hipLaunchKernelGGL(k_ref_scratch_store<T>, dim3(nb, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items, inv,
+                     b.r_red);
   hipLaunchKernelGGL(k_ref_reduce, dim3((n_items + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items,
-                     b.r_red, pass, 1);
+                     b.r_red, nb, pass, 1);
 }
 
 void launch_scratch_group(const Batch &b, hipStream_t s, const RefineItem *items, const InvItem *inv, int n_items,
