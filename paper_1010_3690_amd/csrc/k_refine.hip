@@ -207,13 +207,15 @@ __global__ __launch_bounds__(256) void k_ref_apply(const ChainDesc *descs, const
   }
 }
 
-// Drift of every chain of the group (partial sums in a fixed order).
+// Drift of every chain of the group, one wave per chain: lane l sums partials
+// l, l + 64, ... and the lanes are summed on the DPP network (a fixed order).
 // pass 0 records the drift the chain accumulated since its last refinement
 // (last_drift, max_drift, the drift_tol check); every pass leaves its drift in
 // pass_drift for the host's decision on one more step.
-__global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const RefineItem *items, int n_items,
-                             const double *red, int nb, int pass, int scratch) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64) void k_ref_reduce(const ChainDesc *descs, ChainState *states,
+                                                   const RefineItem *items, int n_items, const double *red, int nb,
+                                                   int pass, int scratch) {
+  const int q = blockIdx.x, lane = threadIdx.x;
   if (q >= n_items) return;
   const int c = items[q].chain;
   ChainState &st = states[c];
@@ -221,14 +223,17 @@ __global__ void k_ref_reduce(const ChainDesc *descs, ChainState *states, const R
   for (int sec = 0; sec < 2; ++sec) {
     double a = 0.0, b = 0.0;
     const double *r = red + (static_cast<size_t>(q) * 2 + sec) * nb * 2;   // nb partials per sector
-    for (int i = 0; i < nb; ++i) {
+    for (int i = lane; i < nb; i += 64) {
       a += r[2 * i];
       b += r[2 * i + 1];
     }
+    a = wave_sum_dpp(a);
+    b = wave_sum_dpp(b);
     const double dr = (b > 0.0) ? sqrt(a / b) : 0.0;
     if (!isfinite(dr)) drift = INFINITY;
     else if (dr > drift) drift = dr;
   }
+  if (lane != 0) return;
   st.pass_drift = drift;
   if (scratch) st.scratch_recomputes += 1;
   // A Newton step that left a non-finite N is repaired by a from-scratch
@@ -275,8 +280,8 @@ static void launch_group_t(const Batch &b, hipStream_t s, const RefineItem *item
                        b.r_pool, mode);
   hipLaunchKernelGGL(k_ref_apply<T>, dim3(nb, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items, b.r_pool,
                      b.r_red);
-  hipLaunchKernelGGL(k_ref_reduce, dim3((n_items + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items,
-                     b.r_red, nb, pass, 0);
+  hipLaunchKernelGGL(k_ref_reduce, dim3(n_items), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items, b.r_red, nb,
+                     pass, 0);
 }
 
 // After the elimination: N <- M^{-1} in canonical order, N[i][j] = W[perm[i]][pos(j)]
@@ -328,8 +333,8 @@ static void launch_scratch_t(const Batch &b, hipStream_t s, const RefineItem *it
   launch_invert(s, inv, 2 * n_items, n_max, b.n_cu);
   hipLaunchKernelGGL(k_ref_scratch_store<T>, dim3(nb, n_items), dim3(256), 0, s, b.d_desc, b.d_state, items, inv,
                      b.r_red);
-  hipLaunchKernelGGL(k_ref_reduce, dim3((n_items + 63) / 64), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items,
-                     b.r_red, nb, pass, 1);
+  hipLaunchKernelGGL(k_ref_reduce, dim3(n_items), dim3(64), 0, s, b.d_desc, b.d_state, items, n_items, b.r_red, nb,
+                     pass, 1);
 }
 
 void launch_scratch_group(const Batch &b, hipStream_t s, const RefineItem *items, const InvItem *inv, int n_items,
